@@ -1,0 +1,224 @@
+/*
+ * lens_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU implementation of what the GPU
+ * library computes, used only by tests/, by __graft_entry__.smoke() and by
+ * the cpu_baseline leg of bench.py.  Nothing in the product path may link,
+ * load or call it.  It shares no code, header or table with the GPU library.
+ *
+ * What it computes (Jimenez-Vicente & Mediavilla 2022, "Fast Multipole
+ * Method for Gravitational Lensing"):
+ *
+ *  - oracle_deflect: the thin-lens lens equation for N point lenses, eq. (1)
+ *    of Section 1, in its real-vector form
+ *        alpha(x) = sum_i m_i (x - x_i) / |x - x_i|^2,
+ *    with the smooth convergence kappa_s and shear gamma that the footnote to
+ *    eq. (1) and step 3 of the map driver (Section 2.4) add:
+ *        y1 = (1 - kappa_s - gamma) x1 - alpha1
+ *        y2 = (1 - kappa_s + gamma) x2 - alpha2
+ *    (shear along the x1 axis; the paper fixes only |gamma|).  Units are
+ *    Einstein radii of unit mass.  This is the plain O(N_* x N_x) definition
+ *    the FMM approximates (Section 1, after eq. 1).  Sums run in star index
+ *    order with Neumaier compensation.  A ray that coincides exactly with a
+ *    star is singular; that pair is skipped and counted.
+ *
+ *  - oracle_jacobian: the deflection Jacobian d(alpha)/d(x) at each ray,
+ *        J = sum_i m_i ( I/r^2 - 2 d d^T / r^4 ),   d = x - x_i,
+ *    i.e. the derivative of eq. (1); the complex form of the same thing is
+ *    f'(z) = -sum_i m_i/(z - z_i)^2, which Appendix A says the expansions
+ *    provide without numerical derivatives.
+ *
+ *  - oracle_bin: inverse ray shooting (Section 2.3): each mapped ray adds one
+ *    count to the source-plane pixel it lands in.  Pixel (u, v) of an
+ *    npix x npix map of side `side` whose lower-left corner is (y1min, y2min)
+ *    is the half-open square [y1min + u/S, y1min + (u+1)/S) x [...),
+ *    S = npix/side, decided as u = floor((y1 - y1min) * S) with one rounding
+ *    per operation.  Rays outside the map are dropped.
+ *
+ *  - oracle_grad: the gradient of a scalar loss L(y) with respect to the star
+ *    positions and masses, given G_k = dL/dy_k, from differentiating eq. (1):
+ *        dL/dx_i = m_i sum_k ( G_k / r^2 - 2 d (d . G_k) / r^4 )
+ *        dL/dm_i = - sum_k (d . G_k) / r^2,           d = x_k - x_i.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (see build.py);
+ * contraction is off so every product and sum rounds once, as written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Neumaier (improved Kahan-Babuska) compensated accumulation. */
+typedef struct { double s, c; } nsum;
+
+static inline void nadd(nsum *a, double v) {
+  double t = a->s + v;
+  if (fabs(a->s) >= fabs(v))
+    a->c += (a->s - t) + v;
+  else
+    a->c += (v - t) + a->s;
+  a->s = t;
+}
+
+static inline double nval(const nsum *a) { return a->s + a->c; }
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+static void set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
+/*
+ * Deflect n_rays rays (rxy[k][2]) by n_stars point lenses (sxy[i][2], sm[i]).
+ * Writes y_out[k][2] (may be NULL) and alpha_out[k][2] (may be NULL).
+ * *n_coincident (may be NULL) receives the number of skipped (ray == star)
+ * pairs.  nthreads <= 0 keeps the OpenMP default.  Returns 0, or -1 on a
+ * negative size.
+ */
+int oracle_deflect(int64_t n_stars, const double *sxy, const double *sm,
+                   double kappa_s, double gamma, int64_t n_rays,
+                   const double *rxy, double *y_out, double *alpha_out,
+                   int64_t *n_coincident, int nthreads) {
+  if (n_stars < 0 || n_rays < 0) return -1;
+  set_threads(nthreads);
+  int64_t skipped = 0;
+  const double c1 = (1.0 - kappa_s) - gamma;
+  const double c2 = (1.0 - kappa_s) + gamma;
+#pragma omp parallel for schedule(static) reduction(+ : skipped)
+  for (int64_t k = 0; k < n_rays; ++k) {
+    const double x1 = rxy[2 * k], x2 = rxy[2 * k + 1];
+    nsum a1 = {0.0, 0.0}, a2 = {0.0, 0.0};
+    for (int64_t i = 0; i < n_stars; ++i) {
+      const double d1 = x1 - sxy[2 * i];
+      const double d2 = x2 - sxy[2 * i + 1];
+      const double r2 = d1 * d1 + d2 * d2;
+      if (r2 == 0.0) {
+        ++skipped;
+        continue;
+      }
+      const double w = sm[i] / r2;
+      nadd(&a1, w * d1);
+      nadd(&a2, w * d2);
+    }
+    const double al1 = nval(&a1), al2 = nval(&a2);
+    if (alpha_out) {
+      alpha_out[2 * k] = al1;
+      alpha_out[2 * k + 1] = al2;
+    }
+    if (y_out) {
+      y_out[2 * k] = c1 * x1 - al1;
+      y_out[2 * k + 1] = c2 * x2 - al2;
+    }
+  }
+  if (n_coincident) *n_coincident = skipped;
+  return 0;
+}
+
+/*
+ * Deflection Jacobian at each ray: jac_out[k][3] = (J11, J12, J22) of
+ * d(alpha)/d(x).  Coincident pairs are skipped.  Returns 0 or -1.
+ */
+int oracle_jacobian(int64_t n_stars, const double *sxy, const double *sm,
+                    int64_t n_rays, const double *rxy, double *jac_out,
+                    int nthreads) {
+  if (n_stars < 0 || n_rays < 0) return -1;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n_rays; ++k) {
+    const double x1 = rxy[2 * k], x2 = rxy[2 * k + 1];
+    nsum j11 = {0, 0}, j12 = {0, 0}, j22 = {0, 0};
+    for (int64_t i = 0; i < n_stars; ++i) {
+      const double d1 = x1 - sxy[2 * i];
+      const double d2 = x2 - sxy[2 * i + 1];
+      const double r2 = d1 * d1 + d2 * d2;
+      if (r2 == 0.0) continue;
+      const double w = sm[i] / r2;
+      const double w2 = 2.0 * w / r2;
+      nadd(&j11, w - w2 * d1 * d1);
+      nadd(&j12, -w2 * d1 * d2);
+      nadd(&j22, w - w2 * d2 * d2);
+    }
+    jac_out[3 * k] = nval(&j11);
+    jac_out[3 * k + 1] = nval(&j12);
+    jac_out[3 * k + 2] = nval(&j22);
+  }
+  return 0;
+}
+
+/*
+ * Inverse-ray-shooting binning of n mapped rays y[k][2] into counts[v*npix+u]
+ * (accumulated, +=).  Returns the number of rays that landed in the map, or
+ * -1 on bad arguments, or -2 if a pixel count would exceed INT32_MAX.
+ */
+int64_t oracle_bin(int64_t n, const double *y, double y1min, double y2min,
+                   double side, int32_t npix, int32_t *counts) {
+  if (n < 0 || npix <= 0 || !(side > 0.0)) return -1;
+  const double S = (double)npix / side;
+  const int64_t np2 = (int64_t)npix * npix;
+  int64_t *acc = (int64_t *)calloc((size_t)np2, sizeof(int64_t));
+  if (!acc) return -1;
+  int64_t landed = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double t1 = (y[2 * k] - y1min) * S;
+    const double t2 = (y[2 * k + 1] - y2min) * S;
+    if (!(t1 >= 0.0) || !(t2 >= 0.0)) continue; /* also drops NaN */
+    const double f1 = floor(t1), f2 = floor(t2);
+    if (f1 >= (double)npix || f2 >= (double)npix) continue;
+    acc[(int64_t)f2 * npix + (int64_t)f1] += 1;
+    ++landed;
+  }
+  int rc = 0;
+  for (int64_t q = 0; q < np2; ++q) {
+    const int64_t v = (int64_t)counts[q] + acc[q];
+    if (v > INT32_MAX) rc = -2;
+    else counts[q] = (int32_t)v;
+  }
+  free(acc);
+  return rc ? rc : landed;
+}
+
+/*
+ * Gradient of a loss L with respect to star positions and masses given
+ * grad_y[k][2] = dL/dy_k.  Writes grad_xy[i][2] and grad_m[i].  Coincident
+ * pairs are skipped (their term is singular).  Returns 0 or -1.
+ */
+int oracle_grad(int64_t n_stars, const double *sxy, const double *sm,
+                int64_t n_rays, const double *rxy, const double *grad_y,
+                double *grad_xy, double *grad_m, int nthreads) {
+  if (n_stars < 0 || n_rays < 0) return -1;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n_stars; ++i) {
+    const double s1 = sxy[2 * i], s2 = sxy[2 * i + 1];
+    nsum gx = {0, 0}, gy = {0, 0}, gm = {0, 0};
+    for (int64_t k = 0; k < n_rays; ++k) {
+      const double d1 = rxy[2 * k] - s1;
+      const double d2 = rxy[2 * k + 1] - s2;
+      const double r2 = d1 * d1 + d2 * d2;
+      if (r2 == 0.0) continue;
+      const double g1 = grad_y[2 * k], g2 = grad_y[2 * k + 1];
+      const double dg = d1 * g1 + d2 * g2;
+      const double inv = 1.0 / r2;
+      const double two = 2.0 * dg * inv * inv;
+      nadd(&gx, g1 * inv - two * d1);
+      nadd(&gy, g2 * inv - two * d2);
+      nadd(&gm, -dg * inv);
+    }
+    grad_xy[2 * i] = sm[i] * nval(&gx);
+    grad_xy[2 * i + 1] = sm[i] * nval(&gy);
+    grad_m[i] = nval(&gm);
+  }
+  return 0;
+}

@@ -1,0 +1,368 @@
+"""Pins for the FP64 oracle: each test checks it against something other than
+itself -- closed forms, exact rational arithmetic, Gauss's law, Laurent
+moments, the paper's printed worked numbers, finite differences and scaling
+invariants -- chosen so that a dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails at least one of them."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------ exact arithmetic
+
+def _exact_alpha(stars, masses, ray):
+    """Eq. 1 of the paper in exact rational arithmetic; also returns the sum
+    of the terms' magnitudes, which bounds the effect of per-term rounding."""
+    x1, x2 = Fraction(ray[0]), Fraction(ray[1])
+    a1 = a2 = Fraction(0)
+    mag = Fraction(0)
+    for (s1, s2), m in zip(stars, masses):
+        d1, d2 = x1 - Fraction(s1), x2 - Fraction(s2)
+        r2 = d1 * d1 + d2 * d2
+        if r2 == 0:
+            continue
+        a1 += Fraction(m) * d1 / r2
+        a2 += Fraction(m) * d2 / r2
+        mag += abs(Fraction(m) * d1 / r2) + abs(Fraction(m) * d2 / r2)
+    return a1, a2, float(mag)
+
+
+def test_tiny_inputs_match_exact_rationals():
+    rng = np.random.default_rng(11)
+    stars = rng.uniform(-3, 3, (7, 2))
+    masses = rng.uniform(-0.5, 2.0, 7)          # a negative mass too: any finite value is allowed
+    rays = rng.uniform(-4, 4, (9, 2))
+    rays[0] = stars[3]                          # a ray exactly on a star: pair skipped and counted
+    ks, g = 0.125, -0.375
+    y, al, skipped = oracle.deflect(stars, masses, rays, ks, g)
+    assert skipped == 1
+    for k in range(len(rays)):
+        e1, e2, mag = _exact_alpha(stars, masses, rays[k])
+        ey1 = (1 - Fraction(ks) - Fraction(g)) * Fraction(rays[k, 0]) - e1
+        ey2 = (1 - Fraction(ks) + Fraction(g)) * Fraction(rays[k, 1]) - e2
+        # each term rounds ~5 times; the compensated sum adds ~1 ulp
+        eps = 2.0 ** -52
+        assert abs(al[k, 0] - float(e1)) <= 6 * eps * mag + eps * abs(float(e1))
+        assert abs(al[k, 1] - float(e2)) <= 6 * eps * mag + eps * abs(float(e2))
+        ys = mag + abs(rays[k]).sum() * 2
+        assert abs(y[k, 0] - float(ey1)) <= 8 * eps * ys
+        assert abs(y[k, 1] - float(ey2)) <= 8 * eps * ys
+
+
+def test_empty_star_field_and_no_rays():
+    rays = np.array([[1.5, -2.0], [0.0, 0.0]])
+    y, al, _ = oracle.deflect(np.zeros((0, 2)), np.zeros(0), rays, 0.25, 0.5)
+    assert np.all(al == 0.0)
+    np.testing.assert_array_equal(y[:, 0], (1 - 0.25 - 0.5) * rays[:, 0])
+    np.testing.assert_array_equal(y[:, 1], (1 - 0.25 + 0.5) * rays[:, 1])
+    y, al, _ = oracle.deflect(np.ones((3, 2)), np.ones(3), np.zeros((0, 2)))
+    assert y.shape == (0, 2)
+
+
+# ------------------------------------------------------------------ point lens
+
+@pytest.mark.parametrize("m", [1.0, 0.37, 4.2])
+def test_point_lens_images_map_back_to_source(m):
+    """A point lens of mass m at c has two images of a source at offset u along
+    u's direction, at distances (|u| +- sqrt(|u|^2 + 4m))/2 from c."""
+    c = np.array([0.75, -1.25])
+    rng = np.random.default_rng(3)
+    srcs = rng.uniform(-3, 3, (50, 2))
+    imgs, want = [], []
+    for s in srcs:
+        u = s - c
+        un = np.hypot(*u)
+        e = u / un
+        for sgn in (+1, -1):
+            imgs.append(c + e * (un + sgn * math.sqrt(un * un + 4 * m)) / 2)
+            want.append(s)
+    y, _, _ = oracle.deflect(c[None, :], np.array([m]), np.array(imgs))
+    np.testing.assert_allclose(y, np.array(want), rtol=0, atol=1e-13)
+
+
+def test_point_lens_irs_counts_follow_magnification():
+    """IRS counts in a small source pixel ~ mu(u) * pixel area / ray cell area
+    with mu(u) = (u^2+2)/(u sqrt(u^2+4)) for a unit point lens."""
+    g = wl.Grid(x0=-4.0, y0=-4.0, dx=2.0 ** -9, dy=2.0 ** -9, nx=4096, ny=4096)
+    rays = g.rays()
+    y, _, _ = oracle.deflect(np.zeros((1, 2)), np.ones(1), rays)
+    # a 16x16 map of side 0.4 centred on (u0, 0): check the central pixels
+    u0 = 0.8
+    side, npix = 0.4, 16
+    counts, _ = oracle.bin_rays(y, u0 - side / 2, -side / 2, side, npix)
+    pix = side / npix
+    # aggregate a 4x4 block of pixels around (u0, 0) to beat down grid noise
+    block = counts[6:10, 6:10].sum()
+    # integrate mu over the block numerically (fine midpoint rule)
+    t = (np.arange(400) + 0.5) / 400
+    uu = u0 - 2 * pix + 4 * pix * t
+    vv = -2 * pix + 4 * pix * t
+    U, V = np.meshgrid(uu, vv)
+    r = np.hypot(U, V)
+    mu = (r * r + 2) / (r * np.sqrt(r * r + 4))
+    expect = mu.mean() * (4 * pix) ** 2 / (g.dx * g.dy)
+    assert abs(block - expect) / expect < 0.01
+
+
+def test_point_lens_annulus_preimage_area():
+    """Rays landing at source radius u in [u1, u2] come from an image-plane
+    area pi[u2 sqrt(u2^2+4m) - u1 sqrt(u1^2+4m)] (both images together)."""
+    m = 1.0
+    g = wl.Grid(x0=-3.0, y0=-3.0, dx=2.0 ** -8, dy=2.0 ** -8, nx=1536, ny=1536)
+    y, _, _ = oracle.deflect(np.zeros((1, 2)), np.array([m]), g.rays())
+    u = np.hypot(y[:, 0], y[:, 1])
+    u1, u2 = 0.3, 0.9
+    area = np.count_nonzero((u >= u1) & (u < u2)) * g.dx * g.dy
+    expect = math.pi * (u2 * math.sqrt(u2 ** 2 + 4 * m) - u1 * math.sqrt(u1 ** 2 + 4 * m))
+    assert abs(area - expect) / expect < 2e-3
+
+
+# --------------------------------------------------------------- Chang-Refsdal
+
+@pytest.mark.parametrize("gamma", [0.2, 0.3, 0.6])
+def test_chang_refsdal_cusps(gamma):
+    """Unit point lens plus shear gamma (kappa_s=0): the critical points on the
+    axes, x1 = 1/sqrt(1+gamma) and x2 = 1/sqrt(1-gamma), map to the caustic
+    cusps y1 = -2 gamma/sqrt(1+gamma) and y2 = 2 gamma/sqrt(1-gamma), and the
+    Jacobian determinant vanishes there."""
+    pts = np.array([[1 / math.sqrt(1 + gamma), 0.0], [0.0, 1 / math.sqrt(1 - gamma)]])
+    y, _, _ = oracle.deflect(np.zeros((1, 2)), np.ones(1), pts, 0.0, gamma)
+    np.testing.assert_allclose(y[0], [-2 * gamma / math.sqrt(1 + gamma), 0.0], atol=1e-14)
+    np.testing.assert_allclose(y[1], [0.0, 2 * gamma / math.sqrt(1 - gamma)], atol=1e-14)
+    J = oracle.jacobian(np.zeros((1, 2)), np.ones(1), pts)
+    for k in range(2):
+        A = np.diag([1 - gamma, 1 + gamma]) - np.array([[J[k, 0], J[k, 1]], [J[k, 1], J[k, 2]]])
+        assert abs(np.linalg.det(A)) < 1e-13
+
+
+def test_chang_refsdal_jacobian_closed_form():
+    """det A = (1-kappa_s)^2 - |gamma - m / conj(z)^2|^2 for a point lens of mass m at 0."""
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-2, 2, (200, 2))
+    m, ks, g = 0.8, 0.15, 0.4
+    J = oracle.jacobian(np.zeros((1, 2)), np.array([m]), pts)
+    A11 = (1 - ks - g) - J[:, 0]
+    A22 = (1 - ks + g) - J[:, 2]
+    A12 = -J[:, 1]
+    det = A11 * A22 - A12 * A12
+    z = pts[:, 0] + 1j * pts[:, 1]
+    expect = (1 - ks) ** 2 - np.abs(g - m / np.conj(z) ** 2) ** 2
+    np.testing.assert_allclose(det, expect, rtol=1e-12, atol=1e-12)
+
+
+def test_jacobian_matches_finite_differences():
+    f = wl.random_field(12, 3.0, seed=8, masses="powerlaw")
+    rng = np.random.default_rng(9)
+    pts = rng.uniform(-2.5, 2.5, (30, 2))
+    J = oracle.jacobian(f.xy, f.m, pts)
+    h = 1e-6
+    for c in range(2):
+        e = np.zeros(2)
+        e[c] = h
+        _, ap, _ = oracle.deflect(f.xy, f.m, pts + e)
+        _, am, _ = oracle.deflect(f.xy, f.m, pts - e)
+        fd = (ap - am) / (2 * h)
+        Jc = np.stack([J[:, 0], J[:, 1]], 1) if c == 0 else np.stack([J[:, 1], J[:, 2]], 1)
+        np.testing.assert_allclose(fd, Jc, rtol=1e-5, atol=1e-5)
+
+
+# ----------------------------------------------------------------- Gauss's law
+
+def test_gauss_flux_through_circle():
+    """The flux of alpha through a circle is 2 pi times the enclosed mass, so
+    the mean normal component over the circle is M_in/rho and the mean
+    tangential component is 0 (2-D Gauss's law for eq. 1)."""
+    rng = np.random.default_rng(21)
+    rho = 2.0
+    xy = wl.uniform_disk(rng, 400, 4.0)
+    r = np.hypot(xy[:, 0], xy[:, 1])
+    keep = np.abs(r - rho) > 0.25
+    xy = xy[keep]
+    m = rng.uniform(0.2, 1.5, xy.shape[0])
+    n = 4096
+    th = 2 * math.pi * np.arange(n) / n
+    nrm = np.stack([np.cos(th), np.sin(th)], 1)
+    _, al, _ = oracle.deflect(xy, m, rho * nrm)
+    normal = (al * nrm).sum(1).mean()
+    tang = (al[:, 1] * nrm[:, 0] - al[:, 0] * nrm[:, 1]).mean()
+    m_in = m[np.hypot(xy[:, 0], xy[:, 1]) < rho].sum()
+    assert abs(normal - m_in / rho) < 1e-10 * (m.sum() / rho)
+    assert abs(tang) < 1e-10 * (m.sum() / rho)
+
+
+def test_uniform_disk_mean_field():
+    """Inside a uniform disk of point masses the deflection averages to
+    kappa_* x with kappa_* = sum(m)/R^2 (the reading used for the workloads)."""
+    f = wl.random_field(20000, 20.0, seed=13)
+    rng = np.random.default_rng(14)
+    # the flux identity gives the mean over a circle exactly; the disk's
+    # enclosed mass fluctuates, so compare with kappa_* times radius loosely
+    n = 1024
+    rho = 10.0
+    th = 2 * math.pi * np.arange(n) / n
+    nrm = np.stack([np.cos(th), np.sin(th)], 1)
+    _, al, _ = oracle.deflect(f.xy, f.m, rho * nrm)
+    normal = (al * nrm).sum(1).mean()
+    assert abs(normal - f.kappa_star * rho) / (f.kappa_star * rho) < 0.02
+    del rng
+
+
+# ------------------------------------------------------------------- far field
+
+def test_far_field_laurent_moments():
+    """Far from a compact cluster alpha = conj(sum_k M_k / z^(k+1)) with the
+    exact moments M_k = sum_i m_i z_i^k (the multipole form of Appendix A)."""
+    rng = np.random.default_rng(4)
+    xy = rng.uniform(-1, 1, (50, 2))
+    m = rng.uniform(0.1, 2.0, 50)
+    zi = xy[:, 0] + 1j * xy[:, 1]
+    th = rng.uniform(0, 2 * math.pi, 64)
+    z = 40.0 * np.exp(1j * th)
+    series = np.zeros_like(z)
+    for k in range(40):
+        series += np.sum(m * zi ** k) / z ** (k + 1)
+    _, al, _ = oracle.deflect(xy, m, np.stack([z.real, z.imag], 1))
+    got = al[:, 0] + 1j * al[:, 1]
+    np.testing.assert_allclose(got, np.conj(series), rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------- macro magnification
+
+def test_macro_magnification_printed_values():
+    """With no lenses the map is linear; its Jacobian gives mu = 1/det, which
+    must reproduce the paper's printed worked values."""
+    cases = json.load(open(os.path.join(GOLDEN, "macro_magnification.json")))["cases"]
+    pts = np.array([[0.3, -0.7], [1.9, 2.2]])
+    for c in cases:
+        h = 0.5
+        y0, _, _ = oracle.deflect(np.zeros((0, 2)), np.zeros(0), pts, c["kappa"], c["gamma"])
+        y1, _, _ = oracle.deflect(np.zeros((0, 2)), np.zeros(0), pts + [h, 0], c["kappa"], c["gamma"])
+        y2, _, _ = oracle.deflect(np.zeros((0, 2)), np.zeros(0), pts + [0, h], c["kappa"], c["gamma"])
+        A = np.stack([(y1 - y0) / h, (y2 - y0) / h], -1)    # [n, 2, 2]
+        mu = 1.0 / np.linalg.det(A)
+        tol = 0.5 * 10 ** (math.floor(math.log10(abs(c["mu"]))) - c["printed_digits"] + 1)
+        assert np.all(np.abs(mu - c["mu"]) <= tol), (c, mu)
+
+
+def test_macro_magnification_irs_counts():
+    """IRS under the smooth field alone: counts per pixel = |mu| * pixel area /
+    ray cell area, up to the grid's edge effects (kappa=gamma=0.3, mu=2.5)."""
+    g = wl.Grid(x0=-8.0, y0=-8.0, dx=2.0 ** -6, dy=2.0 ** -6, nx=1024, ny=1024)
+    y, _, _ = oracle.deflect(np.zeros((0, 2)), np.zeros(0), g.rays(), 0.3, 0.3)
+    counts, landed = oracle.bin_rays(y, -0.5, -0.5, 1.0, 4)
+    expect = 2.5 * 0.25 ** 2 / (g.dx * g.dy)
+    assert abs(counts.mean() - expect) / expect < 0.02
+    assert landed == counts.sum()
+
+
+# --------------------------------------------------------------------- binning
+
+def test_binning_half_open_pixels():
+    pts = np.array([
+        [-1.0, -1.0],          # lower-left corner: pixel (0, 0)
+        [-0.5, -1.0],          # exactly on the edge between u=0 and u=1 -> u=1
+        [1.0, 0.0],            # upper map edge in y1: outside (half-open)
+        [0.999999, 0.999999],  # last pixel
+        [-1.0000001, 0.0],     # just left of the map: dropped
+        [np.nan, 0.0],         # NaN: dropped
+        [0.0, -0.5],           # u = 2, v = 1
+        [-0.5 - 2.0 ** -40, 0.5 - 2.0 ** -40],   # just below both edges: u = 0, v = 2
+    ])
+    counts, landed = oracle.bin_rays(pts, -1.0, -1.0, 2.0, 4)
+    want = np.zeros((4, 4), np.int32)
+    want[0, 0] = 1
+    want[0, 1] = 1
+    want[3, 3] = 1
+    want[1, 2] = 1
+    want[2, 0] = 1
+    np.testing.assert_array_equal(counts, want)
+    assert landed == 5
+    counts2, _ = oracle.bin_rays(pts, -1.0, -1.0, 2.0, 4, counts=counts)
+    np.testing.assert_array_equal(counts2, 2 * want)
+
+
+def test_binning_overflow_is_reported():
+    c = np.zeros((2, 2), np.int32)
+    c[0, 0] = np.iinfo(np.int32).max
+    with pytest.raises(OverflowError):
+        oracle.bin_rays(np.array([[0.1, 0.1]]), 0.0, 0.0, 1.0, 2, counts=c)
+
+
+# -------------------------------------------------------------------- gradient
+
+def _loss(f, rays, t, xy=None, m=None):
+    y, _, _ = oracle.deflect(f.xy if xy is None else xy, f.m if m is None else m, rays,
+                             f.kappa_s, f.gamma)
+    return float(((y - t) ** 2).sum()), y
+
+
+def test_gradient_matches_central_differences():
+    f = wl.random_field(6, 2.0, seed=31, masses="powerlaw", kappa_s=0.1, gamma=0.2)
+    rng = np.random.default_rng(32)
+    rays = rng.uniform(-2.5, 2.5, (40, 2))
+    t = rng.uniform(-2, 2, (40, 2))
+    L0, y = _loss(f, rays, t)
+    G = 2 * (y - t)
+    gxy, gm = oracle.grad(f.xy, f.m, rays, G)
+    h = 1e-6
+    for i in range(f.n):
+        for c in range(2):
+            xp = f.xy.copy()
+            xp[i, c] += h
+            xm = f.xy.copy()
+            xm[i, c] -= h
+            fd = (_loss(f, rays, t, xy=xp)[0] - _loss(f, rays, t, xy=xm)[0]) / (2 * h)
+            assert abs(fd - gxy[i, c]) <= 1e-6 * max(1.0, abs(gxy[i, c]))
+        mp = f.m.copy()
+        mp[i] += h
+        mm = f.m.copy()
+        mm[i] -= h
+        fd = (_loss(f, rays, t, m=mp)[0] - _loss(f, rays, t, m=mm)[0]) / (2 * h)
+        assert abs(fd - gm[i]) <= 1e-6 * max(1.0, abs(gm[i]))
+
+
+def test_gradient_invariants():
+    """Mass homogeneity: sum_i m_i dL/dm_i = -sum_k G_k . alpha_k.
+    Translation: moving every star by e equals moving every ray by -e, so
+    sum_i dL/dx_i = sum_k J(x_k) G_k with J the deflection Jacobian."""
+    f = wl.random_field(30, 3.0, seed=41, masses="powerlaw")
+    rng = np.random.default_rng(42)
+    rays = rng.uniform(-3, 3, (200, 2))
+    G = rng.standard_normal((200, 2))
+    gxy, gm = oracle.grad(f.xy, f.m, rays, G)
+    _, al, _ = oracle.deflect(f.xy, f.m, rays)
+    lhs = (f.m * gm).sum()
+    rhs = -(G * al).sum()
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(G * al).sum()
+    J = oracle.jacobian(f.xy, f.m, rays)
+    t1 = (J[:, 0] * G[:, 0] + J[:, 1] * G[:, 1]).sum()
+    t2 = (J[:, 1] * G[:, 0] + J[:, 2] * G[:, 1]).sum()
+    scale = np.abs(J).sum() * np.abs(G).max()
+    assert abs(gxy[:, 0].sum() - t1) <= 1e-12 * scale
+    assert abs(gxy[:, 1].sum() - t2) <= 1e-12 * scale
+
+
+# ------------------------------------------------------------------ workloads
+
+def test_workload_readings():
+    f, g, mp = wl.config1()
+    assert f.n == 1000 and abs(f.kappa_star - 1000 / 26.6 ** 2) < 1e-12
+    assert g.dx == 10 / 512 and g.rays()[0, 0] == -5 + 0.5 * 10 / 512
+    f2, g2 = wl.config2(n_stars=20000, n_side=256)
+    assert abs(f2.m.mean() - 1.0) < 1e-12
+    assert 0.44 < f2.m.min() and f2.m.max() < 4.5
+    assert abs(f2.kappa_star - 0.4) < 1e-12
+    # dyadic grid: every coordinate is exact, so any evaluation order agrees
+    r = g2.rays()
+    i = np.arange(g2.n) % g2.nx
+    assert np.all(r[:, 0] == g2.x0 + (i + 0.5) * g2.dx)
+    assert (g2.dx * 2 ** 20) == round(g2.dx * 2 ** 20)
