@@ -1,0 +1,228 @@
+"""Benchmark: rays/s deflected at N_* = 1e6 by the mixed-precision FMM, next
+to the FP64 direct sum on the same GPU, at a stated relative error.
+
+Workload (one "step"): 1e6 stars with power-law masses uniform in a disk of
+convergence 0.4 (kappa_s = 0.2, gamma = 0.35), an 8192 x 8192 cell-centred ray
+grid over the square inscribed in the disk; one lens_deflect call with no
+plan, so each step runs the whole path: star quadtree build, P2M, M2M, the
+downward pass and the fused evaluation, writing y [8192^2, 2] FP64.  Stars
+are resident in HBM before the timed region; grid rays need no input bytes.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/s deflected at N_*=1e6 (mixed FMM vs FP64 direct) at stated rel. error"
+PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak, FLOP/s
+PEAK_HBM = 8.0e12                # bytes/s
+PAIR_FLOPS = 12                  # per near pair: 2 sub, |d|^2 (3), rcp (1), m*rcp (1), 2 FMA (4), + cvt free
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_config2_traffic.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def near_pairs(info, f, g):
+    """Near-field pairs of one evaluation: sum over rays of the stars in the
+    3x3 leaf neighbourhood of the ray's leaf box (counting only)."""
+    import numpy as np
+    L = info["leaf_level"]
+    nb = 1 << L
+    s = math.ldexp(info["root_side"], -L)
+
+    def box(v, origin):
+        t = (v - origin) / s
+        return np.floor(np.clip(t, 0, nb - 1)).astype(np.int64)
+
+    bx = box(f.xy[:, 0], info["root_x0"])
+    by = box(f.xy[:, 1], info["root_y0"])
+    cnt = np.bincount(by * nb + bx, minlength=nb * nb).reshape(nb, nb).astype(np.float64)
+    pad = np.pad(cnt, 1)
+    n3 = sum(pad[1 + dy:1 + dy + nb, 1 + dx:1 + dx + nb] for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    rx = g.x0 + (np.arange(g.nx) + 0.5) * g.dx
+    ry = g.y0 + (np.arange(g.ny) + 0.5) * g.dy
+    cx = np.bincount(box(rx, info["root_x0"]), minlength=nb).astype(np.float64)
+    cy = np.bincount(box(ry, info["root_y0"]), minlength=nb).astype(np.float64)
+    return float(cy @ n3 @ cx)
+
+
+def eval_source_hash():
+    h = hashlib.sha256()
+    for fn in ("eval.hip", "device_common.h", "lens_internal.h"):
+        with open(os.path.join(ROOT, "paper_2211_00354_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--leaf", type=int, default=0, help="leaf level (0 = tune over a few)")
+    ap.add_argument("--p", type=int, default=12)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-direct", action="store_true", help="skip the FP64 direct comparator")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup+steps of the mixed FMM only (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the ray grid would shard into bands, one per GPU; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2211_00354_amd as lf
+    from paper_2211_00354_amd import _lib
+    import workloads as wl
+
+    torch.cuda.set_device(0)
+    log("generating workload")
+    f, g = wl.config2()
+    xy = torch.from_numpy(f.xy).cuda()
+    m = torch.from_numpy(f.m).cuda()
+    grid = lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny)
+    y = torch.empty((g.n, 2), dtype=torch.float64, device="cuda")
+    n_rays = g.n
+
+    def run(prec="mixed", p=args.p, leaf=0, method="fmm"):
+        lf.deflect(xy, m, grid=grid, kappa_s=f.kappa_s, gamma=f.gamma, precision=prec, p=p,
+                   leaf_level=leaf, method=method, out=y)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # leaf-level choice (outside the timed region)
+    leaf = args.leaf
+    if leaf == 0 and not args.profile_only:
+        best = None
+        for L in (9, 10, 11):
+            run(leaf=L)
+            t = timed(lambda: run(leaf=L), 2)
+            log(f"leaf level {L}: {t:.3f} ms")
+            if best is None or t < best[0]:
+                best = (t, L)
+        leaf = best[1]
+    elif leaf == 0:
+        leaf = 10
+    log(f"using leaf level {leaf}, p={args.p}")
+
+    for _ in range(args.warmup):
+        run(leaf=leaf)
+    torch.cuda.synchronize()
+    _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    ms = timed(lambda: run(leaf=leaf), args.steps)
+    wall = time.perf_counter() - t0
+    prof = _lib.profile_read()
+    _lib.profile_enable(False)
+    log(f"mixed FMM: {ms:.3f} ms/step ({wall:.2f} s wall for {args.steps} steps); stages {prof}")
+    if args.profile_only:
+        return
+
+    value = n_rays / (ms * 1e-3)
+    y_mixed_sample = None
+    idx = g.strided(64, 32)
+    y_mixed_sample = y[torch.from_numpy(idx).cuda()].cpu().numpy()
+
+    # algorithmic work of the dominant kernel (fused evaluation)
+    plan = lf.Plan(xy, m, ray_box=(g.x0 + 0.5 * g.dx, g.y0 + 0.5 * g.dy,
+                                   g.x0 + (g.nx - 0.5) * g.dx, g.y0 + (g.ny - 0.5) * g.dy),
+                   precision="mixed", p=args.p, leaf_level=leaf)
+    info = plan.info()
+    plan.close()
+    pairs = near_pairs(info, f, g)
+    flops = PAIR_FLOPS * pairs + (8 * args.p + 2) * n_rays
+    ev_ms, ev_n = prof.get("eval", (float("nan"), 1))
+    ev_avg = ev_ms / max(ev_n, 1)
+    achieved = flops / (ev_avg * 1e-3)
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            t = json.load(open(TRAFFIC_FILE))
+            if t.get("eval_source_hash") == eval_source_hash() and t.get("leaf_level") == leaf:
+                traffic = t.get("hbm_bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    extra = {"leaf_level": leaf, "p": args.p, "near_pairs_per_ray": pairs / n_rays,
+             "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
+             "eval_flops_per_launch": flops}
+
+    # FP64 direct sum on the same GPU, on 128 full rows of the grid (rays/s is
+    # exactly linear in the ray count for a direct sum)
+    if not args.no_direct:
+        sub = lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, 128)
+        ysub = torch.empty((g.nx * 128, 2), dtype=torch.float64, device="cuda")
+        fn = lambda: lf.deflect(xy, m, grid=sub, kappa_s=f.kappa_s, gamma=f.gamma,
+                                method="direct", out=ysub)
+        fn()
+        dms = timed(fn, 2)
+        direct = g.nx * 128 / (dms * 1e-3)
+        extra["fp64_direct_rays_per_s"] = direct
+        extra["mixed_fmm_speedup_vs_fp64_direct"] = value / direct
+        log(f"FP64 direct: {dms:.1f} ms for {g.nx * 128} rays -> {direct:.3e} rays/s")
+        # FP64 FMM at the same p, for context
+        fms = timed(lambda: run(prec="fp64", leaf=leaf), 3)
+        extra["fp64_fmm_rays_per_s"] = n_rays / (fms * 1e-3)
+        yf = y[torch.from_numpy(idx).cuda()].cpu().numpy()
+        run(leaf=leaf)   # restore the mixed output (not timed)
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        rays = g.rays(idx)
+        nthr = min(16, os.cpu_count() or 1)
+        t1 = time.perf_counter()
+        yo, ao, _ = oracle.deflect(f.xy, f.m, rays, f.kappa_s, f.gamma, nthreads=nthr)
+        dt = time.perf_counter() - t1
+        cpu = {"value": len(idx) / dt, "unit": "rays/s", "cores": nthr, "kind": "oracle",
+               "sample": f"{len(idx)} rays (every 64th row and column of the 8192^2 grid) "
+                         f"against all 1e6 stars, FP64 direct sum, {dt:.1f} s"}
+        err = float(np.linalg.norm(y_mixed_sample - yo) / np.linalg.norm(ao))
+        extra["rel_l2_err_alpha_mixed"] = err
+        extra["max_abs_err_y_mixed"] = float(np.max(np.abs(y_mixed_sample - yo)))
+        if not args.no_direct:
+            extra["rel_l2_err_alpha_fp64_fmm"] = float(np.linalg.norm(yf - yo) / np.linalg.norm(ao))
+        log(f"oracle: {dt:.1f} s on {nthr} threads; mixed rel l2 err {err:.2e}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/f64 mixed", "data": "synthetic",
+        "config": {"workload": "N_*=1e6 power-law-mass disk (kappa_*=0.4, kappa_s=0.2, "
+                               "gamma=0.35), 8192x8192 ray grid, mixed FMM p=%d" % args.p,
+                   "n_stars": f.n, "n_rays": n_rays, "p": args.p, "leaf_level": leaf},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
+                     "kernel": "k_eval (fused L2P + P2P + smooth term)",
+                     "eval_ms_avg": ev_avg},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * lens.h -- C ABI of liblensfmm, a fast-multipole evaluator of gravitational
+ * lens deflection by many point masses on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Jimenez-Vicente & Mediavilla 2022, Section 1, eq. 1, with
+ * the smooth-field term of its footnote and of step 3 of the map driver in
+ * Section 2.4) maps each image-plane ray x to the source plane:
+ *
+ *     alpha(x) = sum_i m_i (x - x_i) / |x - x_i|^2
+ *     y1 = (1 - kappa_s - gamma) x1 - alpha1
+ *     y2 = (1 - kappa_s + gamma) x2 - alpha2
+ *
+ * in units of the Einstein radius of unit mass, with the shear along the x1
+ * axis.  In complex form, z = x1 + i x2, alpha = conj(f) with
+ * f(z) = sum_i m_i / (z - z_i) (Appendix A: the expansions take a simple
+ * analytic form in complex variables).  A ray that coincides exactly with a
+ * star skips that singular pair.
+ *
+ * LENS_FMM evaluates the sum with the fast multipole method of Appendix A
+ * (quadtree, P2M, M2M, M2L, L2L, L2P and near-field P2P); LENS_DIRECT sums
+ * it directly in FP64.  LENS_FP64 runs every FMM stage in FP64; LENS_MIXED
+ * runs the near field and the fine-level translations in FP32 and keeps FP64
+ * for coordinates relative to box centres, coarse-level translations and the
+ * final y.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array pointer is a DEVICE pointer (hipMalloc / torch CUDA tensor
+ *    memory) unless its comment says otherwise.  The caller owns every
+ *    buffer; the library never frees or retains a caller pointer past the
+ *    call (a plan copies what it needs).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All device work is enqueued on it; outputs are valid once the stream
+ *    has completed.  The only calls that wait on the stream are noted below.
+ *  - On any status other than LENS_OK nothing has been enqueued and the
+ *    outputs are untouched, except LENS_EDEVICE, which reports a HIP runtime
+ *    failure after work may have been enqueued.  lens_last_error() gives a
+ *    thread-local description (host string, valid until the thread's next
+ *    call into the library).
+ *  - Positions are FP64 pairs laid out [n][2] = (x1, x2); masses FP64 [n].
+ *    Masses may be any finite value; N_* = 0 is valid (alpha = 0); a call
+ *    with zero rays is a no-op.
+ *  - Distinct plans may be used from distinct threads on distinct streams.
+ */
+#ifndef LENS_H
+#define LENS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define LENS_API __attribute__((visibility("default")))
+#else
+#define LENS_API
+#endif
+
+typedef enum {
+  LENS_OK = 0,
+  LENS_EINVAL = 1,       /* bad argument; nothing enqueued */
+  LENS_ENOMEM = 2,       /* device allocation failed; nothing enqueued */
+  LENS_EDEVICE = 3,      /* HIP runtime error */
+  LENS_EUNSUPPORTED = 4  /* valid request this build does not implement */
+} lens_status;
+
+enum { LENS_FMM = 0, LENS_DIRECT = 1 };   /* lens_opts.method    */
+enum { LENS_FP64 = 0, LENS_MIXED = 1 };   /* lens_opts.precision */
+
+#define LENS_MAX_ORDER 40     /* largest expansion order p (terms k = 0..p-1) */
+#define LENS_MAX_LEVEL 15     /* deepest quadtree level */
+
+/* The lens: N_* point masses plus the smooth convergence and shear. */
+typedef struct {
+  int64_t n_stars;      /* N_* >= 0 */
+  const double *xy;     /* [N_*][2] star positions (device) */
+  const double *m;      /* [N_*] star masses (device) */
+  double kappa_s;       /* smooth convergence (finite) */
+  double gamma;         /* shear along x1 (finite) */
+} lens_field;
+
+/* A cell-centred ray grid: ray k = j*nx + i sits at
+ * (x0 + (i + 0.5) dx, y0 + (j + 0.5) dy), each product and sum rounded once. */
+typedef struct {
+  double x0, y0;        /* lower-left corner of the grid */
+  double dx, dy;        /* cell sizes, > 0 */
+  int64_t nx, ny;       /* cells per side, >= 0 */
+} lens_grid;
+
+/* A source-plane inverse-ray-shooting map (Section 2.3): counts[v*npix + u]
+ * counts the rays with u = floor((y1 - y1min) * S), v = floor((y2 - y2min) * S),
+ * S = npix / side, 0 <= u, v < npix (half-open pixels; rays outside are
+ * dropped).  Counts are ACCUMULATED (+=) so a map may be built over calls. */
+typedef struct {
+  double y1min, y2min;  /* lower-left corner of the map */
+  double side;          /* side length, > 0 */
+  int32_t npix;         /* pixels per side, npix*npix <= INT32_MAX */
+  int32_t *counts;      /* [npix][npix] int32 (device) */
+} lens_map_desc;
+
+typedef struct {
+  int32_t method;       /* LENS_FMM or LENS_DIRECT */
+  int32_t precision;    /* LENS_FP64 or LENS_MIXED (LENS_DIRECT is always FP64) */
+  int32_t order_p;      /* expansion terms p in [1, LENS_MAX_ORDER]; 0 = 12 */
+  int32_t leaf_level;   /* quadtree leaf level in [2, LENS_MAX_LEVEL]; 0 = chosen
+                           by the library's cost model */
+  int64_t max_rays_per_chunk;  /* lens_map: rays per chunk; 0 = 1.6e7 */
+} lens_opts;
+
+/* Fill *o with the defaults (FMM, mixed, p = 12, automatic leaf level). */
+LENS_API void lens_opts_default(lens_opts *o);
+
+/* Star-side state reusable across calls: the quadtree over the stars and the
+ * multipole expansions of every box (Appendix A, initialisation and upward
+ * passes).  Opaque. */
+typedef struct lens_plan lens_plan;
+
+/*
+ * Build a plan for `field` whose quadtree also covers the rectangle
+ * ray_box = {x1min, x2min, x1max, x2max} (HOST array; every ray later
+ * evaluated with this plan must lie inside it; NULL = the stars' extent only).
+ * Copies the stars (sorted by leaf box) into plan-owned device memory, so the
+ * caller's star arrays may be freed afterwards.  Waits on `stream` once, to
+ * read back the stars' bounding box.  *out receives the plan.
+ */
+LENS_API lens_status lens_plan_create(const lens_field *field, const double *ray_box, const lens_opts *opts,
+                             void *stream, lens_plan **out);
+
+/* Release a plan (waits for the plan's last stream to finish first). */
+LENS_API void lens_plan_destroy(lens_plan *plan);
+
+/* Query a plan: expansion order, leaf level, root square (x0, y0, side). */
+LENS_API lens_status lens_plan_info(const lens_plan *plan, int32_t *order_p, int32_t *leaf_level,
+                           double *root_x0, double *root_y0, double *root_side);
+
+/*
+ * Deflect rays: y_out[k][2] = y(x_k) (FP64, device).  Rays come from `grid`
+ * (then rays_xy must be NULL and n_rays = grid->nx * grid->ny) or from the
+ * explicit device array rays_xy[n_rays][2] (then grid must be NULL).
+ * `plan` may be NULL: the library then builds the star tree for this call
+ * (explicit rays: waits on the stream once to read back their bounding box).
+ * With a plan, the plan's (sorted) stars, expansion order, leaf level and
+ * precision are used and opts->method still selects FMM or direct; `field`
+ * may then be NULL (the plan's kappa_s and gamma apply) or supply only
+ * kappa_s and gamma (its star pointers are ignored).
+ */
+LENS_API lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                         const double *rays_xy, int64_t n_rays, double *y_out, const lens_opts *opts,
+                         void *stream);
+
+/*
+ * Inverse ray shooting: deflect every ray of `grid` and add it to the map
+ * (see lens_map_desc).  Rays are processed in chunks of whole grid rows of at
+ * most opts->max_rays_per_chunk rays (Section 2.4); the result does not
+ * depend on the chunking.  `plan` may be NULL as in lens_deflect.
+ */
+LENS_API lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                     const lens_map_desc *map, const lens_opts *opts, void *stream);
+
+/*
+ * Stage profiler.  lens_profile_enable(1) clears the totals and starts
+ * bracketing every stage of every later call (tree, upward, downward, eval,
+ * direct) with HIP events on the stream that runs it; (0) stops.
+ * lens_profile_read waits for the recorded events, then fills up to `cap`
+ * entries: stage names (host strings valid until the next enable), total
+ * milliseconds and number of timed launches.  Returns the number of stages.
+ * Process-wide; meant for benchmarks, not for concurrent calls.
+ */
+LENS_API void lens_profile_enable(int32_t on);
+LENS_API int32_t lens_profile_read(int32_t cap, const char **names, double *total_ms,
+                                   int64_t *launches);
+
+/* Thread-local text for the last status other than LENS_OK (host string). */
+LENS_API const char *lens_last_error(void);
+
+/* Library version string (host string). */
+LENS_API const char *lens_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LENS_H */

@@ -1,0 +1,201 @@
+"""lensfmm for MI355X: fast-multipole gravitational-lens ray deflection.
+
+Python face of liblensfmm (include/lens.h).  Tensors must be contiguous
+float64 CUDA (HIP) tensors on the current device; work is enqueued on the
+current torch stream.  Every step runs in the HIP library; there is no CPU
+fallback, and a missing library raises ImportError on first use.
+
+    import torch, paper_2211_00354_amd as lf
+    y = lf.deflect(xy, m, grid=lf.Grid(x0, y0, dx, dy, nx, ny),
+                   kappa_s=0.2, gamma=0.35, precision="mixed", p=12)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+from . import _lib
+from ._lib import (LENS_DIRECT, LENS_FMM, LENS_FP64, LENS_MIXED, LensError, LensField, LensGrid,
+                   LensMapDesc, LensOpts)
+
+__all__ = ["Grid", "MapDesc", "Plan", "deflect", "irs_map", "LensError", "version"]
+
+
+@dataclass
+class Grid:
+    """Cell-centred ray grid: ray k = j*nx + i at (x0+(i+.5)dx, y0+(j+.5)dy)."""
+    x0: float
+    y0: float
+    dx: float
+    dy: float
+    nx: int
+    ny: int
+
+    def c(self) -> LensGrid:
+        return LensGrid(self.x0, self.y0, self.dx, self.dy, self.nx, self.ny)
+
+
+@dataclass
+class MapDesc:
+    y1min: float
+    y2min: float
+    side: float
+    npix: int
+
+
+def version() -> str:
+    return _lib.load().lens_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_tensor(t, name, shape_last=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_last is not None and t.numel() and t.shape[-1] != shape_last:
+        raise ValueError(f"{name} must have a trailing dimension of {shape_last}")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} is not on the current device")
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _opts(method="fmm", precision="mixed", p=12, leaf_level=0, max_rays_per_chunk=0) -> LensOpts:
+    o = LensOpts()
+    _lib.load().lens_opts_default(ctypes.byref(o))
+    o.method = {"fmm": LENS_FMM, "direct": LENS_DIRECT}[method]
+    o.precision = {"fp64": LENS_FP64, "mixed": LENS_MIXED}[precision]
+    o.order_p = int(p)
+    o.leaf_level = int(leaf_level)
+    o.max_rays_per_chunk = int(max_rays_per_chunk)
+    return o
+
+
+def _field(xy, m, kappa_s, gamma):
+    _check_tensor(xy, "star_xy", 2)
+    _check_tensor(m, "star_m")
+    n = m.numel()
+    if xy.numel() != 2 * n:
+        raise ValueError("star_xy must be [N, 2] with N = star_m.numel()")
+    return LensField(n, xy.data_ptr() if n else None, m.data_ptr() if n else None,
+                     float(kappa_s), float(gamma))
+
+
+class Plan:
+    """Star quadtree + multipoles, reusable across deflect/irs_map calls.
+
+    ``ray_box`` = (x1min, x2min, x1max, x2max) must contain every ray the plan
+    will serve.  The plan copies the stars; it fixes method, precision, p and
+    the leaf level.
+    """
+
+    def __init__(self, star_xy, star_m, kappa_s=0.0, gamma=0.0, ray_box=None, precision="mixed",
+                 p=12, leaf_level=0):
+        lib = _lib.load()
+        self._f = _field(star_xy, star_m, kappa_s, gamma)
+        self.precision = precision
+        self.kappa_s, self.gamma = float(kappa_s), float(gamma)
+        o = _opts("fmm", precision, p, leaf_level)
+        box = (ctypes.c_double * 4)(*ray_box) if ray_box is not None else None
+        h = ctypes.c_void_p()
+        _lib.check(lib.lens_plan_create(ctypes.byref(self._f), box, ctypes.byref(o), _stream(),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        p, L = ctypes.c_int32(), ctypes.c_int32()
+        x0, y0, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.load().lens_plan_info(self._h, ctypes.byref(p), ctypes.byref(L),
+                                              ctypes.byref(x0), ctypes.byref(y0), ctypes.byref(s)))
+        return {"p": p.value, "leaf_level": L.value, "root_x0": x0.value, "root_y0": y0.value,
+                "root_side": s.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().lens_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, kappa_s=0.0,
+            gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0,
+            plan: Optional[Plan] = None, out=None):
+    """Lens-map rays: returns y [n, 2] float64 on the GPU (eq. 1 + smooth term).
+
+    Rays come from ``grid`` or from the explicit tensor ``rays`` [n, 2].  With
+    ``plan`` the plan's stars are used; ``kappa_s``/``gamma`` still apply.
+    """
+    torch = _torch()
+    lib = _lib.load()
+    if (grid is None) == (rays is None):
+        raise ValueError("give exactly one of grid and rays")
+    if plan is None:
+        f = _field(star_xy, star_m, kappa_s, gamma)
+    else:  # the plan supplies the stars, the call the smooth terms
+        f = LensField(0, None, None, float(kappa_s), float(gamma))
+    if grid is not None:
+        n = int(grid.nx) * int(grid.ny)
+        g = grid.c()
+        gp, rp = ctypes.byref(g), None
+    else:
+        _check_tensor(rays, "rays", 2)
+        n = rays.numel() // 2
+        gp, rp = None, rays.data_ptr() if n else None
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    else:
+        _check_tensor(out, "out", 2)
+        if out.numel() != 2 * n:
+            raise ValueError("out must be [n, 2]")
+    o = _opts(method, precision, p, leaf_level)
+    _lib.check(lib.lens_deflect(plan.handle if plan else None, ctypes.byref(f), gp, rp, n,
+                                out.data_ptr() if n else None, ctypes.byref(o), _stream()))
+    return out
+
+
+def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, kappa_s=0.0,
+            gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0,
+            max_rays_per_chunk=0, plan: Optional[Plan] = None, counts=None):
+    """Inverse ray shooting into an int32 [npix, npix] count map (accumulated
+    into ``counts`` if given, indexed [v, u])."""
+    torch = _torch()
+    lib = _lib.load()
+    if plan is None:
+        f = _field(star_xy, star_m, kappa_s, gamma)
+    else:  # the plan supplies the stars, the call the smooth terms
+        f = LensField(0, None, None, float(kappa_s), float(gamma))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if counts is None:
+        counts = torch.zeros((map.npix, map.npix), dtype=torch.int32, device=dev)
+    elif counts.dtype != torch.int32 or not counts.is_cuda or not counts.is_contiguous() \
+            or counts.shape != (map.npix, map.npix):
+        raise ValueError("counts must be a contiguous int32 [npix, npix] GPU tensor")
+    md = LensMapDesc(map.y1min, map.y2min, map.side, map.npix, counts.data_ptr())
+    g = grid.c()
+    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk)
+    _lib.check(lib.lens_map(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
+                            ctypes.byref(md), ctypes.byref(o), _stream()))
+    return counts

@@ -1,0 +1,632 @@
+// C ABI of liblensfmm: argument checks, plans (star quadtree + multipoles),
+// target windows, ray chunking and the launch sequence of every entry point.
+//
+// Call sequence of lens_deflect with LENS_FMM (Appendix A):
+//   plan (stars):  bbox -> leaf keys -> radix sort -> gather -> leaf starts
+//                  -> P2M at level L -> M2M for L-1 .. 2
+//   per call:      target windows per level from the rays' bounding box
+//                  -> for l = 2..L: L2L + M2L into the window (FP64, or FP32
+//                     M2L on the finest levels in LENS_MIXED)
+//                  -> fused L2P + P2P + smooth term per leaf box of the window
+// All device work goes to the caller's stream; plan creation and explicit-ray
+// calls read one bounding box back from the device.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "lens_internal.h"
+
+using namespace lensfmm;
+
+struct lens_plan {
+  int device = 0;
+  int p = 12;
+  int precision = LENS_MIXED;
+  int fine_levels = 2;  // LENS_MIXED: levels L-fine_levels+1 .. L run M2L in FP32
+  Geometry g{};
+  int64_t n_stars = 0;
+  double kappa_s = 0, gamma = 0;
+  double domain[4] = {0, 0, 0, 0};
+  DevBuf sxy, sm, leaf_start;
+  std::vector<DevBuf> mp;    // index = level, FP64 multipoles
+  std::vector<DevBuf> mp32;  // index = level, FP32 copies (fine levels, mixed)
+  hipStream_t last_stream = nullptr;
+
+  const double *mp_at(int l) const { return static_cast<const double *>(mp[l].ptr); }
+  const float *mp32_at(int l) const {
+    return mp32.size() > (size_t)l ? static_cast<const float *>(mp32[l].ptr) : nullptr;
+  }
+  void release() {
+    if (last_stream) (void)hipStreamSynchronize(last_stream);
+    pool_put(sxy, nullptr);
+    pool_put(sm, nullptr);
+    pool_put(leaf_start, nullptr);
+    for (auto &b : mp) pool_put(b, nullptr);
+    for (auto &b : mp32) pool_put(b, nullptr);
+  }
+};
+
+namespace {
+
+constexpr int64_t kDefaultChunk = 16000000;  // nmaxarg of Section 2.4
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+void check_opts(const lens_opts &o) {
+  if (o.method != LENS_FMM && o.method != LENS_DIRECT) fail(LENS_EINVAL, "opts.method must be LENS_FMM or LENS_DIRECT");
+  if (o.precision != LENS_FP64 && o.precision != LENS_MIXED)
+    fail(LENS_EINVAL, "opts.precision must be LENS_FP64 or LENS_MIXED");
+  if (o.order_p < 0 || o.order_p > LENS_MAX_ORDER)
+    fail(LENS_EINVAL, "opts.order_p must be in [1, " + std::to_string(LENS_MAX_ORDER) + "] or 0");
+  if (o.leaf_level != 0 && (o.leaf_level < 2 || o.leaf_level > LENS_MAX_LEVEL))
+    fail(LENS_EINVAL, "opts.leaf_level must be in [2, " + std::to_string(LENS_MAX_LEVEL) + "] or 0");
+  if (o.max_rays_per_chunk < 0) fail(LENS_EINVAL, "opts.max_rays_per_chunk must be >= 0");
+}
+
+lens_opts resolve_opts(const lens_opts *o) {
+  lens_opts r;
+  lens_opts_default(&r);
+  if (o) r = *o;
+  check_opts(r);
+  if (r.order_p == 0) r.order_p = 12;
+  if (r.max_rays_per_chunk == 0) r.max_rays_per_chunk = kDefaultChunk;
+  return r;
+}
+
+void check_field(const lens_field *f) {
+  if (!f) fail(LENS_EINVAL, "field is NULL");
+  if (f->n_stars < 0) fail(LENS_EINVAL, "field.n_stars < 0");
+  if (f->n_stars > (int64_t)std::numeric_limits<int32_t>::max())
+    fail(LENS_EINVAL, "field.n_stars exceeds 2^31-1");
+  if (f->n_stars > 0 && (!f->xy || !f->m)) fail(LENS_EINVAL, "field.xy / field.m is NULL");
+  if (!is_finite(f->kappa_s) || !is_finite(f->gamma)) fail(LENS_EINVAL, "kappa_s and gamma must be finite");
+}
+
+void check_grid(const lens_grid *g) {
+  if (g->nx < 0 || g->ny < 0) fail(LENS_EINVAL, "grid.nx / grid.ny < 0");
+  if (!is_finite(g->x0) || !is_finite(g->y0) || !is_finite(g->dx) || !is_finite(g->dy))
+    fail(LENS_EINVAL, "grid origin and spacing must be finite");
+  if (!(g->dx > 0) || !(g->dy > 0)) fail(LENS_EINVAL, "grid.dx and grid.dy must be > 0");
+  if (g->nx > (int64_t)std::numeric_limits<int32_t>::max() ||
+      g->ny > (int64_t)std::numeric_limits<int32_t>::max())
+    fail(LENS_EINVAL, "grid side exceeds 2^31-1 rays");
+}
+
+double grid_x(const lens_grid &g, int64_t i) { return g.x0 + ((double)i + 0.5) * g.dx; }
+double grid_y(const lens_grid &g, int64_t j) { return g.y0 + ((double)j + 0.5) * g.dy; }
+
+int64_t box_coord_host(double x, double origin, double s, int64_t nbox) {
+  double t = (x - origin) / s;
+  t = std::fmin(std::fmax(t, 0.0), (double)(nbox - 1));
+  return (int64_t)std::floor(t);
+}
+
+void device_bbox(const double *xy, int64_t n, hipStream_t st, double out[4]) {
+  Scratch sc(st);
+  const int parts = bbox_parts(n);
+  double *partial = sc.get<double>((size_t)parts * 4);
+  double *o4 = sc.get<double>(4);
+  launch_bbox(xy, n, partial, parts, o4, st);
+  LENS_HIP(hipMemcpyAsync(out, o4, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  LENS_HIP(hipStreamSynchronize(st));
+  for (int c = 0; c < 4; ++c)
+    if (!is_finite(out[c])) fail(LENS_EINVAL, "non-finite coordinates in the input positions");
+}
+
+// Leaf level from a cost model of the evaluation: per ray, 9 q near pairs
+// (q = stars per leaf) against 27 p^2 M2L complex MACs per target box shared
+// by the rays of the box.  Minimising over the leaf side s gives
+// s^2 = sqrt(3 p^2 c_m2l / (rho_* rho_ray c_pair)).  Without rays, aim for
+// about 8 stars per leaf.
+int choose_leaf_level(int64_t n_stars, const double sb[4], double rays_density, double side,
+                      int p) {
+  const double area = std::max((sb[2] - sb[0]) * (sb[3] - sb[1]), 1e-300);
+  const double rho = n_stars > 0 ? (double)n_stars / area : 0.0;
+  double s;
+  if (rho <= 0) {
+    s = side / 4;
+  } else if (rays_density > 0) {
+    const double c_pair = 14.0, c_m2l = 4.0;
+    s = std::sqrt(std::sqrt(3.0 * p * p * c_m2l / (rho * rays_density * c_pair)));
+    s = std::max(s, std::sqrt(0.5 / rho));   // at least ~0.5 stars per leaf
+    s = std::min(s, std::sqrt(64.0 / rho));  // at most ~64
+  } else {
+    s = std::sqrt(8.0 / rho);
+  }
+  int L = (int)std::lround(std::log2(side / s));
+  L = std::max(2, std::min(L, 13));
+  // keep the multipole storage (all levels) under ~8 GB
+  while (L > 2 && (double)(int64_t(1) << (2 * L)) * p * 16.0 * 1.34 > 8e9) --L;
+  return L;
+}
+
+Window window_for(const lens_plan &P, int level, const double bb[4]) {
+  const int64_t n = int64_t(1) << level;
+  const double s = std::ldexp(P.g.side, -level);
+  int64_t x0 = box_coord_host(bb[0], P.g.x0, s, n) - 1, x1 = box_coord_host(bb[2], P.g.x0, s, n) + 1;
+  int64_t y0 = box_coord_host(bb[1], P.g.y0, s, n) - 1, y1 = box_coord_host(bb[3], P.g.y0, s, n) + 1;
+  x0 = std::max<int64_t>(x0, 0);
+  y0 = std::max<int64_t>(y0, 0);
+  x1 = std::min<int64_t>(x1, n - 1);
+  y1 = std::min<int64_t>(y1, n - 1);
+  return Window{x0, y0, x1 - x0 + 1, y1 - y0 + 1};
+}
+
+lens_plan *build_plan(const lens_field &f, const double *ray_box, double rays_density,
+                      const lens_opts &o, hipStream_t st) {
+  auto *P = new lens_plan();
+  try {
+    LENS_HIP(hipGetDevice(&P->device));
+    P->p = o.order_p;
+    P->precision = o.precision;
+    P->n_stars = f.n_stars;
+    P->kappa_s = f.kappa_s;
+    P->gamma = f.gamma;
+    double sb[4] = {0, 0, 0, 0};
+    bool have = false;
+    if (f.n_stars > 0) {
+      device_bbox(f.xy, f.n_stars, st, sb);
+      have = true;
+    }
+    double dom[4];
+    if (have) std::copy(sb, sb + 4, dom);
+    if (ray_box) {
+      if (!have) std::copy(ray_box, ray_box + 4, dom);
+      dom[0] = std::min(dom[0], ray_box[0]);
+      dom[1] = std::min(dom[1], ray_box[1]);
+      dom[2] = std::max(dom[2], ray_box[2]);
+      dom[3] = std::max(dom[3], ray_box[3]);
+      have = true;
+    }
+    if (!have) dom[0] = dom[1] = 0, dom[2] = dom[3] = 1;
+    std::copy(dom, dom + 4, P->domain);
+    double side = std::max(dom[2] - dom[0], dom[3] - dom[1]);
+    if (!(side > 0)) side = 1.0;
+    side *= 1.0 + 1.0 / 1024;
+    const double cxm = 0.5 * (dom[0] + dom[2]), cym = 0.5 * (dom[1] + dom[3]);
+    P->g.side = side;
+    P->g.x0 = cxm - 0.5 * side;
+    P->g.y0 = cym - 0.5 * side;
+    P->g.L = o.leaf_level > 0 ? o.leaf_level
+                              : choose_leaf_level(f.n_stars, have ? sb : dom, rays_density, side, P->p);
+    const int L = P->g.L;
+    const int64_t nL = int64_t(1) << L;
+    const int64_t nbox = nL * nL;
+    const int64_t N = f.n_stars;
+
+    P->mp.resize(L + 1);
+    P->leaf_start = pool_get((size_t)(nbox + 1) * sizeof(int32_t), st);
+    P->sxy = pool_get((size_t)std::max<int64_t>(N, 1) * 16, st);
+    P->sm = pool_get((size_t)std::max<int64_t>(N, 1) * 8, st);
+    for (int l = 2; l <= L; ++l) {
+      const int64_t nb = int64_t(1) << (2 * l);
+      P->mp[l] = pool_get((size_t)nb * P->p * 16, st);
+    }
+
+    Scratch sc(st);
+    auto *leaf_start = static_cast<int32_t *>(P->leaf_start.ptr);
+    auto *sxy = static_cast<double *>(P->sxy.ptr);
+    auto *sm = static_cast<double *>(P->sm.ptr);
+    {
+      StageTimer tm("tree", st);
+      if (N > 0) {
+        uint32_t *k = sc.get<uint32_t>(N), *v = sc.get<uint32_t>(N);
+        uint32_t *kt = sc.get<uint32_t>(N), *vt = sc.get<uint32_t>(N);
+        const size_t ncnt = radix_counts_len(N);
+        uint32_t *cnt = sc.get<uint32_t>(ncnt);
+        uint32_t *stmp = sc.get<uint32_t>(scan_tmp_len(ncnt));
+        launch_leaf_keys(f.xy, N, P->g, k, v, st);
+        const bool in_tmp = radix_sort_pairs(k, v, kt, vt, N, 2 * L, cnt, stmp, st);
+        const uint32_t *ks = in_tmp ? kt : k, *vs = in_tmp ? vt : v;
+        launch_gather_stars(vs, f.xy, f.m, N, sxy, sm, st);
+        launch_box_starts(ks, N, nbox, leaf_start, st);
+      } else {
+        LENS_HIP(hipMemsetAsync(leaf_start, 0, (size_t)(nbox + 1) * sizeof(int32_t), st));
+      }
+    }
+    const OpTables &T = op_tables(P->p, st);
+    {
+      StageTimer tm("upward", st);
+      launch_p2m(P->g, sxy, sm, leaf_start, P->p, static_cast<double *>(P->mp[L].ptr), st);
+      for (int l = L - 1; l >= 2; --l)
+        launch_m2m(l, P->p, P->mp_at(l + 1), static_cast<double *>(P->mp[l].ptr), T.m2m, st);
+      if (P->precision == LENS_MIXED) {
+        P->mp32.resize(L + 1);
+        for (int l = std::max(2, L - P->fine_levels + 1); l <= L; ++l) {
+          const size_t n = (size_t)(int64_t(1) << (2 * l)) * P->p * 2;
+          P->mp32[l] = pool_get(n * sizeof(float), st);
+          launch_to_f32(P->mp_at(l), static_cast<float *>(P->mp32[l].ptr), n, st);
+        }
+      }
+    }
+    P->last_stream = st;
+  } catch (...) {
+    P->release();
+    delete P;
+    throw;
+  }
+  return P;
+}
+
+void check_inside(const lens_plan &P, const double bb[4]) {
+  const double tol = 1e-12 * P.g.side;
+  if (bb[0] < P.domain[0] - tol || bb[1] < P.domain[1] - tol || bb[2] > P.domain[2] + tol ||
+      bb[3] > P.domain[3] + tol)
+    fail(LENS_EINVAL, "rays lie outside the region the plan was built for (pass ray_box to lens_plan_create)");
+}
+
+// Downward pass over the windows of `bb`: locals of every level 2..L.
+// Returns the leaf window; *leaf_loc receives its local expansions.
+Window downward(lens_plan &P, const double bb[4], Scratch &sc, hipStream_t st, double **leaf_loc) {
+  const int L = P.g.L;
+  const OpTables &T = op_tables(P.p, st);
+  StageTimer tm("downward", st);
+  std::vector<Window> win(L + 1);
+  std::vector<double *> loc(L + 1, nullptr);
+  for (int l = 2; l <= L; ++l) {
+    win[l] = window_for(P, l, bb);
+    loc[l] = sc.get<double>((size_t)win[l].count() * P.p * 2);
+  }
+  for (int l = 2; l <= L; ++l) {
+    DownArgs d{};
+    d.level = l;
+    d.p = P.p;
+    d.s = std::ldexp(P.g.side, -l);
+    d.win = win[l];
+    d.pwin = l >= 3 ? win[l - 1] : Window{0, 0, 0, 0};
+    d.mp = P.mp_at(l);
+    d.mp32 = P.mp32_at(l);
+    d.ploc = l >= 3 ? loc[l - 1] : nullptr;
+    d.loc = loc[l];
+    const bool fine = P.precision == LENS_MIXED && l > L - P.fine_levels && d.mp32;
+    if (fine)
+      launch_down_f32(d, T, st);
+    else
+      launch_down_f64(d, T, st);
+  }
+  *leaf_loc = loc[L];
+  return win[L];
+}
+
+void fill_star_side(const lens_plan &P, Window wl, double *loc, EvalArgs &ea) {
+  ea.g = P.g;
+  ea.p = P.p;
+  ea.win = wl;
+  ea.loc = loc;
+  ea.sxy = static_cast<const double *>(P.sxy.ptr);
+  ea.sm = static_cast<const double *>(P.sm.ptr);
+  ea.leaf_start = static_cast<const int32_t *>(P.leaf_start.ptr);
+}
+
+void launch_eval_checked(EvalArgs &ea, int precision, hipStream_t st) {
+  while (ea.win.count() * ea.chunks_per_box > (int64_t)0x7fffffff && ea.chunks_per_box > 1)
+    ea.chunks_per_box = (ea.chunks_per_box + 1) / 2;
+  if (ea.win.count() > (int64_t)0x7fffffff) fail(LENS_EUNSUPPORTED, "leaf window too large");
+  StageTimer tm(ea.counts ? "eval_map" : "eval", st);
+  launch_eval(ea, precision, st);
+}
+
+template <typename F>
+lens_status guarded(F &&fn) {
+  try {
+    fn();
+    return LENS_OK;
+  } catch (const LensError &e) {
+    set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return LENS_ENOMEM;
+  } catch (...) {
+    set_error("unexpected internal error");
+    return LENS_EDEVICE;
+  }
+}
+
+void grid_bbox(const lens_grid &g, int64_t j0, int64_t j1, double bb[4]) {
+  bb[0] = grid_x(g, 0);
+  bb[2] = grid_x(g, g.nx - 1);
+  bb[1] = grid_y(g, j0);
+  bb[3] = grid_y(g, j1 - 1);
+}
+
+// Grid rows [j0, j1) through the FMM path (deflect: y_out; map: binning).
+void fmm_grid_rows(lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, double c1, double c2,
+                   double *y_out, const lens_map_desc *map, double S, hipStream_t st) {
+  Scratch sc(st);
+  double bb[4];
+  grid_bbox(grid, j0, j1, bb);
+  check_inside(P, bb);
+  double *loc = nullptr;
+  const Window wl = downward(P, bb, sc, st, &loc);
+  EvalArgs ea{};
+  fill_star_side(P, wl, loc, ea);
+  ea.grid_mode = 1;
+  ea.grid = grid;
+  ea.c1 = c1;
+  ea.c2 = c2;
+  ea.y_out = y_out;
+  if (map) {
+    ea.counts = map->counts;
+    ea.y1min = map->y1min;
+    ea.y2min = map->y2min;
+    ea.S = S;
+    ea.npix = map->npix;
+  }
+  int32_t *cs = sc.get<int32_t>(wl.nbx + 1), *rs = sc.get<int32_t>(wl.nby + 1);
+  launch_grid_ranges(grid, P.g, wl, j0, j1, cs, rs, st);
+  ea.col_start = cs;
+  ea.row_start = rs;
+  // upper bound on the rays of one leaf box: the box spans at most
+  // ceil(s/dx)+1 columns and ceil(s/dy)+1 rows of the grid
+  const int64_t rpc = eval_rays_per_chunk();
+  const double s = std::ldexp(P.g.side, -P.g.L);
+  const int64_t mw = std::min<int64_t>((int64_t)std::ceil(s / grid.dx) + 2, grid.nx);
+  const int64_t mh = std::min<int64_t>((int64_t)std::ceil(s / grid.dy) + 2, j1 - j0);
+  ea.chunks_per_box = std::max<int64_t>(1, (mw * mh + rpc - 1) / rpc);
+  launch_eval_checked(ea, P.precision, st);
+  P.last_stream = st;
+}
+
+// Explicit rays: sorted by leaf box of the window, evaluated box by box,
+// written back in the caller's order.
+void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4], double c1, double c2,
+                  double *y_out, hipStream_t st) {
+  Scratch sc(st);
+  check_inside(P, bb);
+  double *loc = nullptr;
+  const Window wl = downward(P, bb, sc, st, &loc);
+  uint32_t *k = sc.get<uint32_t>(n), *v = sc.get<uint32_t>(n);
+  uint32_t *kt = sc.get<uint32_t>(n), *vt = sc.get<uint32_t>(n);
+  const size_t ncnt = radix_counts_len(n);
+  uint32_t *cnt = sc.get<uint32_t>(ncnt);
+  uint32_t *stmp = sc.get<uint32_t>(scan_tmp_len(ncnt));
+  launch_ray_keys(rays, n, P.g, wl, k, v, st);
+  int bits = 1;
+  while ((int64_t(1) << bits) < wl.count()) ++bits;
+  const bool in_tmp = radix_sort_pairs(k, v, kt, vt, n, bits, cnt, stmp, st);
+  const uint32_t *ks = in_tmp ? kt : k, *vs = in_tmp ? vt : v;
+  double *srays = sc.get<double>((size_t)n * 2);
+  launch_gather_rays(vs, rays, n, srays, st);
+  int32_t *rstart = sc.get<int32_t>(wl.count() + 1);
+  launch_box_starts(ks, n, wl.count(), rstart, st);
+  EvalArgs ea{};
+  fill_star_side(P, wl, loc, ea);
+  ea.grid_mode = 0;
+  ea.rxy = srays;
+  ea.rperm = vs;
+  ea.ray_start = rstart;
+  ea.c1 = c1;
+  ea.c2 = c2;
+  ea.y_out = y_out;
+  const int64_t rpc = eval_rays_per_chunk();
+  const int64_t per = n / std::max<int64_t>(wl.count(), 1);
+  ea.chunks_per_box = std::max<int64_t>(1, (per + rpc - 1) / rpc);
+  launch_eval_checked(ea, P.precision, st);
+  P.last_stream = st;
+}
+
+void release_owned(lens_plan *owned, hipStream_t st) {
+  // stream-ordered release: the buffers go back to the pool behind the work
+  pool_put(owned->sxy, st);
+  pool_put(owned->sm, st);
+  pool_put(owned->leaf_start, st);
+  for (auto &b : owned->mp) pool_put(b, st);
+  for (auto &b : owned->mp32) pool_put(b, st);
+  delete owned;
+}
+
+struct FieldView {
+  lens_field f;
+  bool from_plan;
+};
+
+FieldView field_for(const lens_plan *plan, const lens_field *field) {
+  if (!plan) {
+    check_field(field);
+    return {*field, false};
+  }
+  // a plan supplies the stars; a field given with it supplies kappa_s and gamma
+  lens_field f{plan->n_stars, static_cast<const double *>(plan->sxy.ptr),
+               static_cast<const double *>(plan->sm.ptr), plan->kappa_s, plan->gamma};
+  if (field) {
+    if (!is_finite(field->kappa_s) || !is_finite(field->gamma))
+      fail(LENS_EINVAL, "kappa_s and gamma must be finite");
+    f.kappa_s = field->kappa_s;
+    f.gamma = field->gamma;
+  }
+  return {f, true};
+}
+
+void check_plan_device(const lens_plan *plan) {
+  int dev = 0;
+  LENS_HIP(hipGetDevice(&dev));
+  if (dev != plan->device) fail(LENS_EINVAL, "plan was created on another device");
+}
+
+}  // namespace
+
+extern "C" {
+
+void lens_opts_default(lens_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->method = LENS_FMM;
+  o->precision = LENS_MIXED;
+  o->order_p = 12;
+  o->leaf_level = 0;
+  o->max_rays_per_chunk = 0;
+}
+
+const char *lens_last_error(void) { return lensfmm::last_error().c_str(); }
+
+const char *lens_version(void) { return "liblensfmm 0.1 (gfx950)"; }
+
+lens_status lens_plan_create(const lens_field *field, const double *ray_box, const lens_opts *opts,
+                             void *stream, lens_plan **out) {
+  return guarded([&] {
+    if (!out) fail(LENS_EINVAL, "out is NULL");
+    check_field(field);
+    const lens_opts o = resolve_opts(opts);
+    if (ray_box) {
+      for (int c = 0; c < 4; ++c)
+        if (!is_finite(ray_box[c])) fail(LENS_EINVAL, "ray_box must be finite");
+      if (ray_box[2] < ray_box[0] || ray_box[3] < ray_box[1]) fail(LENS_EINVAL, "ray_box is empty");
+    }
+    *out = build_plan(*field, ray_box, 0.0, o, (hipStream_t)stream);
+  });
+}
+
+void lens_plan_destroy(lens_plan *plan) {
+  if (!plan) return;
+  plan->release();
+  delete plan;
+}
+
+lens_status lens_plan_info(const lens_plan *plan, int32_t *order_p, int32_t *leaf_level,
+                           double *root_x0, double *root_y0, double *root_side) {
+  return guarded([&] {
+    if (!plan) fail(LENS_EINVAL, "plan is NULL");
+    if (order_p) *order_p = plan->p;
+    if (leaf_level) *leaf_level = plan->g.L;
+    if (root_x0) *root_x0 = plan->g.x0;
+    if (root_y0) *root_y0 = plan->g.y0;
+    if (root_side) *root_side = plan->g.side;
+  });
+}
+
+lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                         const double *rays_xy, int64_t n_rays, double *y_out, const lens_opts *opts,
+                         void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    const lens_opts o = resolve_opts(opts);
+    FieldView fv = field_for(plan, field);
+    if (plan) check_plan_device(plan);
+    if ((grid == nullptr) == (rays_xy == nullptr) && !(grid == nullptr && n_rays == 0))
+      fail(LENS_EINVAL, "give exactly one of grid and rays_xy");
+    if (n_rays < 0) fail(LENS_EINVAL, "n_rays < 0");
+    if (grid) {
+      check_grid(grid);
+      if (n_rays != grid->nx * grid->ny) fail(LENS_EINVAL, "n_rays must equal grid.nx * grid.ny");
+    }
+    if (n_rays > (int64_t)std::numeric_limits<uint32_t>::max() - 1)
+      fail(LENS_EINVAL, "n_rays exceeds 2^32-2");
+    if (n_rays > 0 && !y_out) fail(LENS_EINVAL, "y_out is NULL");
+    if (n_rays == 0) return;
+    const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
+    const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
+
+    if (o.method == LENS_DIRECT || fv.f.n_stars == 0) {
+      DirectArgs d{};
+      d.n_stars = fv.f.n_stars;
+      d.sxy = fv.f.xy;
+      d.sm = fv.f.m;
+      d.grid_mode = grid != nullptr;
+      if (grid) d.grid = *grid;
+      d.rxy = rays_xy;
+      d.n_rays = n_rays;
+      d.c1 = c1;
+      d.c2 = c2;
+      d.y_out = y_out;
+      StageTimer tm("direct", st);
+      launch_direct(d, st);
+      return;
+    }
+
+    double bb[4];
+    if (grid) {
+      grid_bbox(*grid, 0, grid->ny, bb);
+    } else {
+      device_bbox(rays_xy, n_rays, st, bb);
+    }
+    lens_plan *P = plan;
+    lens_plan *owned = nullptr;
+    if (!P) {
+      const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
+      owned = P = build_plan(fv.f, bb, (double)n_rays / area, o, st);
+    }
+    try {
+      if (grid)
+        fmm_grid_rows(*P, *grid, 0, grid->ny, c1, c2, y_out, nullptr, 0.0, st);
+      else
+        fmm_explicit(*P, rays_xy, n_rays, bb, c1, c2, y_out, st);
+    } catch (...) {
+      if (owned) lens_plan_destroy(owned);
+      throw;
+    }
+    if (owned) release_owned(owned, st);
+  });
+}
+
+lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                     const lens_map_desc *map, const lens_opts *opts, void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    const lens_opts o = resolve_opts(opts);
+    FieldView fv = field_for(plan, field);
+    if (plan) check_plan_device(plan);
+    if (!grid) fail(LENS_EINVAL, "grid is NULL");
+    check_grid(grid);
+    if (!map) fail(LENS_EINVAL, "map is NULL");
+    if (map->npix <= 0) fail(LENS_EINVAL, "map.npix must be > 0");
+    if ((int64_t)map->npix * map->npix > (int64_t)std::numeric_limits<int32_t>::max())
+      fail(LENS_EINVAL, "map.npix^2 exceeds 2^31-1");
+    if (!is_finite(map->y1min) || !is_finite(map->y2min) || !is_finite(map->side) || !(map->side > 0))
+      fail(LENS_EINVAL, "map placement must be finite with side > 0");
+    if (!map->counts) fail(LENS_EINVAL, "map.counts is NULL");
+    const int64_t n = grid->nx * grid->ny;
+    if (n > (int64_t)std::numeric_limits<int32_t>::max())
+      fail(LENS_EINVAL, "a map call may shoot at most 2^31-1 rays (int32 counts)");
+    if (n == 0) return;
+    const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
+    const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
+    const double S = (double)map->npix / map->side;
+    const int64_t rows = std::max<int64_t>(1, o.max_rays_per_chunk / std::max<int64_t>(grid->nx, 1));
+
+    if (o.method == LENS_DIRECT || fv.f.n_stars == 0) {
+      for (int64_t j0 = 0; j0 < grid->ny; j0 += rows) {
+        const int64_t j1 = std::min(grid->ny, j0 + rows);
+        DirectArgs d{};
+        d.n_stars = fv.f.n_stars;
+        d.sxy = fv.f.xy;
+        d.sm = fv.f.m;
+        d.grid_mode = 1;
+        d.grid = *grid;
+        d.n_rays = (j1 - j0) * grid->nx;
+        d.ray_offset = j0 * grid->nx;
+        d.c1 = c1;
+        d.c2 = c2;
+        d.counts = map->counts;
+        d.y1min = map->y1min;
+        d.y2min = map->y2min;
+        d.S = S;
+        d.npix = map->npix;
+        StageTimer tm("direct_map", st);
+        launch_direct(d, st);
+      }
+      return;
+    }
+    double bb[4];
+    grid_bbox(*grid, 0, grid->ny, bb);
+    lens_plan *P = plan;
+    lens_plan *owned = nullptr;
+    if (!P) {
+      const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
+      owned = P = build_plan(fv.f, bb, (double)n / area, o, st);
+    }
+    try {
+      for (int64_t j0 = 0; j0 < grid->ny; j0 += rows) {
+        const int64_t j1 = std::min(grid->ny, j0 + rows);
+        fmm_grid_rows(*P, *grid, j0, j1, c1, c2, nullptr, map, S, st);
+      }
+    } catch (...) {
+      if (owned) lens_plan_destroy(owned);
+      throw;
+    }
+    if (owned) release_owned(owned, st);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,208 @@
+// Internal declarations shared by the host orchestration (api.cpp) and the
+// HIP kernel translation units.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lens.h"
+
+namespace lensfmm {
+
+// ------------------------------------------------------------------ errors
+const std::string &last_error();
+
+struct LensError {
+  lens_status status;
+  std::string msg;
+};
+
+void set_error(const std::string &msg);
+[[noreturn]] void fail(lens_status st, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define LENS_HIP(call) ::lensfmm::check_hip((call), #call)
+
+// ------------------------------------------------------------ device memory
+
+// A cached device allocation.  Blocks return to a per-device free list and
+// are reused by later requests; a block released on one stream and reused on
+// another makes the new stream wait for the release point first.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+};
+
+DevBuf pool_get(size_t bytes, hipStream_t stream);
+void pool_put(DevBuf &b, hipStream_t stream);
+
+// RAII list of scratch buffers released at scope exit (stream-ordered).
+struct Scratch {
+  hipStream_t stream;
+  std::vector<DevBuf> bufs;
+  explicit Scratch(hipStream_t s) : stream(s) {}
+  ~Scratch() {
+    for (auto &b : bufs) pool_put(b, stream);
+  }
+  template <typename T>
+  T *get(size_t count) {
+    DevBuf b = pool_get(count * sizeof(T) + 256, stream);
+    bufs.push_back(b);
+    return static_cast<T *>(b.ptr);
+  }
+  Scratch(const Scratch &) = delete;
+  Scratch &operator=(const Scratch &) = delete;
+};
+
+// ------------------------------------------------------------------ geometry
+
+// Root square of the quadtree and its depth.  Box (ix, iy) at level l has
+// side s_l = side / 2^l and lower-left corner (x0 + ix s_l, y0 + iy s_l);
+// boxes of a level are numbered row-major, iy * 2^l + ix.
+struct Geometry {
+  double x0, y0, side;
+  int L;  // leaf level
+};
+
+// A rectangle of boxes at one level: columns [bx0, bx0+nbx), rows [by0, by0+nby).
+struct Window {
+  int64_t bx0, by0, nbx, nby;
+  int64_t count() const { return nbx * nby; }
+};
+
+// ------------------------------------------------------------ kernel launchers
+// (each returns after enqueueing on `stream`; sizes already validated)
+
+// Tree build (tree.hip)
+void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, double *out4,
+                 hipStream_t stream);
+int bbox_parts(int64_t n);
+void launch_leaf_keys(const double *xy, int64_t n, Geometry g, uint32_t *keys, uint32_t *vals,
+                      hipStream_t stream);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.
+// Uses (k_tmp, v_tmp) as ping-pong storage; returns true if the sorted result
+// ended up in the tmp buffers.
+bool radix_sort_pairs(uint32_t *k, uint32_t *v, uint32_t *k_tmp, uint32_t *v_tmp, int64_t n,
+                      int bits, uint32_t *counts, uint32_t *scan_tmp, hipStream_t stream);
+size_t radix_counts_len(int64_t n);
+size_t scan_tmp_len(size_t n);
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp,
+                        hipStream_t stream);
+void launch_gather_stars(const uint32_t *perm, const double *xy, const double *m, int64_t n,
+                         double *sxy, double *sm, hipStream_t stream);
+void launch_gather_rays(const uint32_t *perm, const double *xy, int64_t n, double *sxy,
+                        hipStream_t stream);
+// start[b] = first sorted index with key >= b, for b in [0, nbox]
+void launch_box_starts(const uint32_t *sorted_keys, int64_t n, int64_t nbox, int32_t *start,
+                       hipStream_t stream);
+
+// Expansion operator tables (host-built, uploaded once per order).
+struct OpTables {
+  int p = 0;
+  double *m2m = nullptr;   // [4][p][p] complex, M[q][l][k]
+  double *l2l = nullptr;   // [4][p][p] complex, L[q][j][l]
+  double *m2l = nullptr;   // [49][p][p] complex, stored T[tau][k][l]
+  float *m2l32 = nullptr;  // same in FP32
+};
+const OpTables &op_tables(int p, hipStream_t stream);
+
+// Host-side table builders (also exported for tests through lens_debug_*).
+void build_m2m_table(int p, std::vector<double> &out);
+void build_l2l_table(int p, std::vector<double> &out);
+void build_m2l_table(int p, std::vector<double> &out);
+
+// Upward pass (upward.hip)
+void launch_p2m(Geometry g, const double *sxy, const double *sm, const int32_t *leaf_start, int p,
+                double *mp_leaf, hipStream_t stream);
+void launch_m2m(int level, int p, const double *child, double *parent, const double *m2m,
+                hipStream_t stream);
+
+// Downward pass (downward.hip): local expansions of `win` at `level` from the
+// parent's locals (level >= 3) and the multipoles of the interaction list.
+struct DownArgs {
+  int level, p;
+  double s;              // box side at this level
+  Window win, pwin;      // target window and parent window
+  const double *mp;      // multipoles at this level, [4^level][p] complex FP64
+  const float *mp32;     // same in FP32 (mixed fine levels) or nullptr
+  const double *ploc;    // parent locals [pwin][p] or nullptr (level 2)
+  double *loc;           // output locals [win][p]
+};
+void launch_down_f64(const DownArgs &a, const OpTables &t, hipStream_t stream);
+void launch_down_f32(const DownArgs &a, const OpTables &t, hipStream_t stream);
+void launch_to_f32(const double *src, float *dst, size_t n, hipStream_t stream);
+
+// Evaluation (eval.hip): per leaf box of the window, local expansion at its
+// rays + direct sum over the 3x3 neighbourhood + smooth term.
+struct EvalArgs {
+  Geometry g;
+  int p;
+  Window win;            // leaf-level target window
+  const double *loc;     // [win][p] complex locals
+  const double *sxy;     // sorted stars
+  const double *sm;
+  const int32_t *leaf_start;  // [4^L + 1]
+  // rays: grid or sorted explicit
+  int grid_mode;
+  lens_grid grid;
+  const int32_t *col_start;   // grid: [win.nbx + 1] first ray column per box column
+  const int32_t *row_start;   // grid: [win.nby + 1]
+  const double *rxy;          // explicit, sorted by leaf box
+  const uint32_t *rperm;      // explicit: sorted position -> caller index
+  const int32_t *ray_start;   // explicit: [win.count() + 1]
+  int64_t chunks_per_box;
+  double c1, c2;              // (1 - kappa_s - gamma), (1 - kappa_s + gamma)
+  double *y_out;              // [n][2] or nullptr
+  // map
+  int32_t *counts;
+  double y1min, y2min, S;
+  int32_t npix;
+};
+void launch_eval(const EvalArgs &a, int precision, hipStream_t stream);
+// col_start[c] = first grid column whose rays fall in box column win.bx0 + c
+// (c = 0..nbx); row_start likewise over the rows [j_begin, j_end).
+void launch_grid_ranges(const lens_grid &grid, Geometry g, Window win, int64_t j_begin,
+                        int64_t j_end, int32_t *col_start, int32_t *row_start, hipStream_t stream);
+int64_t eval_rays_per_chunk();
+void launch_ray_keys(const double *rxy, int64_t n, Geometry g, Window win, uint32_t *keys,
+                     uint32_t *vals, hipStream_t stream);
+
+// Direct FP64 sum (direct.hip)
+struct DirectArgs {
+  int64_t n_stars;
+  const double *sxy, *sm;
+  int grid_mode;
+  lens_grid grid;
+  const double *rxy;
+  int64_t n_rays;
+  int64_t ray_offset;    // first ray index (grid rows chunking)
+  double c1, c2;
+  double *y_out;
+  int32_t *counts;
+  double y1min, y2min, S;
+  int32_t npix;
+};
+void launch_direct(const DirectArgs &a, hipStream_t stream);
+
+}  // namespace lensfmm
+
+namespace lensfmm {
+
+// Per-stage timing with HIP events on the launching stream, enabled by
+// lens_profile_enable().  A StageTimer brackets one stage of one call.
+bool profiling_enabled();
+struct StageTimer {
+  const char *name;
+  hipStream_t stream;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  StageTimer(const char *n, hipStream_t s);
+  ~StageTimer();
+  StageTimer(const StageTimer &) = delete;
+  StageTimer &operator=(const StageTimer &) = delete;
+};
+
+}  // namespace lensfmm

@@ -1,0 +1,385 @@
+// Quadtree construction (Appendix A, initialisation step): bounding boxes,
+// leaf-box keys, a stable LSD radix sort of (key, index) pairs, gathers and
+// per-box start offsets.  Keys are row-major leaf-box indices iy * 2^L + ix,
+// so the 3 boxes of one row of a 3x3 neighbourhood are contiguous in the
+// sorted order.  The sort is stable and every reduction runs in a fixed
+// order, so the tree (and everything computed from it) is bitwise
+// reproducible run to run.
+#include <cfloat>
+
+#include "device_common.h"
+
+namespace lensfmm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// ------------------------------------------------------------ bounding box
+
+__global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restrict__ xy, int64_t n,
+                                                           double *__restrict__ partial) {
+  double mn0 = DBL_MAX, mn1 = DBL_MAX, mx0 = -DBL_MAX, mx1 = -DBL_MAX;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double a = xy[2 * i], b = xy[2 * i + 1];
+    mn0 = fmin(mn0, a);
+    mx0 = fmax(mx0, a);
+    mn1 = fmin(mn1, b);
+    mx1 = fmax(mx1, b);
+  }
+  __shared__ double red[4][kThreads];
+  red[0][threadIdx.x] = mn0;
+  red[1][threadIdx.x] = mn1;
+  red[2][threadIdx.x] = mx0;
+  red[3][threadIdx.x] = mx1;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restrict__ partial,
+                                                         int nparts, double *__restrict__ out4) {
+  __shared__ double red[4][kThreads];
+  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
+  for (int i = threadIdx.x; i < nparts; i += kThreads) {
+    v[0] = fmin(v[0], partial[4 * i + 0]);
+    v[1] = fmin(v[1], partial[4 * i + 1]);
+    v[2] = fmax(v[2], partial[4 * i + 2]);
+    v[3] = fmax(v[3], partial[4 * i + 3]);
+  }
+  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  // out4 = {x1min, x2min, x1max, x2max}
+  if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// --------------------------------------------------------------- leaf keys
+
+__global__ __launch_bounds__(kThreads) void k_leaf_keys(const double *__restrict__ xy, int64_t n,
+                                                        Geometry g, uint32_t *__restrict__ keys,
+                                                        uint32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int64_t nb = int64_t(1) << g.L;
+  const double s = ldexp(g.side, -g.L);
+  const int64_t ix = box_coord(xy[2 * i], g.x0, s, nb);
+  const int64_t iy = box_coord(xy[2 * i + 1], g.y0, s, nb);
+  keys[i] = (uint32_t)(iy * nb + ix);
+  vals[i] = (uint32_t)i;
+}
+
+// ------------------------------------------------------------------ scans
+// Exclusive scan of uint32 in three phases: tile sums, a single-workgroup
+// scan of the tile sums (carried across chunks), tile scans with offsets.
+
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan across the workgroup of one value per thread; returns the
+// thread's exclusive prefix and writes the total to *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *sh /*[kWaves]*/,
+                                                    uint32_t *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan(x, lane);
+  if (lane == 63) sh[w] = incl;
+  __syncthreads();
+  uint32_t woff = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) {
+    if (q < w) woff += sh[q];
+    tot += sh[q];
+  }
+  __syncthreads();
+  *total = tot;
+  return woff + incl - x;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_tile_sums(const uint32_t *__restrict__ in,
+                                                             size_t n, uint32_t *__restrict__ sums) {
+  const size_t base = (size_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+  for (int it = 0; it < kScanItems; ++it) {
+    const size_t i = base + (size_t)it * kThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  __shared__ uint32_t sh[kWaves];
+  uint32_t tot;
+  (void)block_excl_scan(s, sh, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_sums(uint32_t *__restrict__ sums, size_t n) {
+  __shared__ uint32_t sh[kWaves];
+  uint32_t carry = 0;
+  for (size_t base = 0; base < n; base += kThreads) {
+    const size_t i = base + threadIdx.x;
+    const uint32_t x = (i < n) ? sums[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(x, sh, &tot);
+    if (i < n) sums[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_tiles(const uint32_t *__restrict__ in, size_t n,
+                                                         const uint32_t *__restrict__ offs,
+                                                         uint32_t *__restrict__ out) {
+  // thread t owns the kScanItems consecutive elements [t*items, (t+1)*items)
+  __shared__ uint32_t tile[kScanTile];
+  __shared__ uint32_t sh[kWaves];
+  const size_t base = (size_t)blockIdx.x * kScanTile;
+  for (int it = 0; it < kScanItems; ++it) {
+    const size_t i = base + (size_t)it * kThreads + threadIdx.x;
+    tile[it * kThreads + threadIdx.x] = (i < n) ? in[i] : 0u;
+  }
+  __syncthreads();
+  uint32_t loc[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    loc[j] = s;
+    s += tile[threadIdx.x * kScanItems + j];
+  }
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan(s, sh, &tot);
+  const uint32_t off = offs[blockIdx.x] + ex;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) tile[threadIdx.x * kScanItems + j] = off + loc[j];
+  __syncthreads();
+  for (int it = 0; it < kScanItems; ++it) {
+    const size_t i = base + (size_t)it * kThreads + threadIdx.x;
+    if (i < n) out[i] = tile[it * kThreads + threadIdx.x];
+  }
+}
+
+// ------------------------------------------------------------- radix sort
+
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kThreads * kSortItems;
+
+__global__ __launch_bounds__(kThreads) void k_radix_count(const uint32_t *__restrict__ keys,
+                                                          int64_t n, int shift,
+                                                          uint32_t *__restrict__ counts,
+                                                          int nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t i = base + (int64_t)it * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  counts[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter.  Items of a tile are taken in global order (round `it`,
+// then thread); a key's destination is the digit's global offset for this
+// tile + keys of that digit in earlier rounds + in lower waves of this round
+// + in lower lanes of its own wave (found with ballots on the digit bits).
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offsets,
+    int nblocks) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kWaves][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  run[t] = offsets[(size_t)t * nblocks + blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) wcnt[q][t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t i = base + (int64_t)it * kThreads + t;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t v = valid ? vin[i] : 0u;
+    const uint32_t d = (k >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = __popcll(peers & below);
+    if (valid && (peers >> lane) == 1ull) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      add += wcnt[q][t];
+      wcnt[q][t] = 0;
+    }
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- gathers
+
+__global__ __launch_bounds__(kThreads) void k_gather_stars(const uint32_t *__restrict__ perm,
+                                                           const double *__restrict__ xy,
+                                                           const double *__restrict__ m, int64_t n,
+                                                           double *__restrict__ sxy,
+                                                           double *__restrict__ sm) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t i = perm[j];
+  sxy[2 * j] = xy[2 * (int64_t)i];
+  sxy[2 * j + 1] = xy[2 * (int64_t)i + 1];
+  sm[j] = m[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather_rays(const uint32_t *__restrict__ perm,
+                                                          const double *__restrict__ xy, int64_t n,
+                                                          double *__restrict__ sxy) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t i = perm[j];
+  sxy[2 * j] = xy[2 * (int64_t)i];
+  sxy[2 * j + 1] = xy[2 * (int64_t)i + 1];
+}
+
+__global__ __launch_bounds__(kThreads) void k_box_starts(const uint32_t *__restrict__ keys,
+                                                         int64_t n, int64_t nbox,
+                                                         int32_t *__restrict__ start) {
+  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (b > nbox) return;
+  // lower_bound of b in the sorted keys
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  start[b] = (int32_t)lo;
+}
+
+inline unsigned blocks_for(int64_t n, int per = kThreads) {
+  return (unsigned)((n + per - 1) / per);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+
+int bbox_parts(int64_t n) {
+  int64_t b = (n + kThreads * 8 - 1) / (kThreads * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, double *out4,
+                 hipStream_t stream) {
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(kThreads), 0, stream, xy, n, partial);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kThreads), 0, stream, partial, nparts, out4);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_leaf_keys(const double *xy, int64_t n, Geometry g, uint32_t *keys, uint32_t *vals,
+                      hipStream_t stream) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_leaf_keys, dim3(blocks_for(n)), dim3(kThreads), 0, stream, xy, n, g, keys,
+                     vals);
+  LENS_HIP(hipGetLastError());
+}
+
+size_t scan_tmp_len(size_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp,
+                        hipStream_t stream) {
+  if (n == 0) return;
+  const size_t nb = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(kThreads), 0, stream, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kThreads), 0, stream, tmp, nb);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kThreads), 0, stream, in, n, tmp, out);
+  LENS_HIP(hipGetLastError());
+}
+
+size_t radix_counts_len(int64_t n) {
+  const int64_t nb = (n + kSortTile - 1) / kSortTile;
+  return (size_t)(nb < 1 ? 1 : nb) * 256;
+}
+
+bool radix_sort_pairs(uint32_t *k, uint32_t *v, uint32_t *k_tmp, uint32_t *v_tmp, int64_t n,
+                      int bits, uint32_t *counts, uint32_t *scan_tmp, hipStream_t stream) {
+  if (n <= 1 || bits <= 0) return false;
+  const int nb = (int)((n + kSortTile - 1) / kSortTile);
+  bool in_tmp = false;
+  for (int shift = 0; shift < bits; shift += 8) {
+    uint32_t *ki = in_tmp ? k_tmp : k, *vi = in_tmp ? v_tmp : v;
+    uint32_t *ko = in_tmp ? k : k_tmp, *vo = in_tmp ? v : v_tmp;
+    hipLaunchKernelGGL(k_radix_count, dim3(nb), dim3(kThreads), 0, stream, ki, n, shift, counts, nb);
+    exclusive_scan_u32(counts, counts, (size_t)nb * 256, scan_tmp, stream);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kThreads), 0, stream, ki, vi, ko, vo, n,
+                       shift, counts, nb);
+    LENS_HIP(hipGetLastError());
+    in_tmp = !in_tmp;
+  }
+  return in_tmp;
+}
+
+void launch_gather_stars(const uint32_t *perm, const double *xy, const double *m, int64_t n,
+                         double *sxy, double *sm, hipStream_t stream) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gather_stars, dim3(blocks_for(n)), dim3(kThreads), 0, stream, perm, xy, m, n,
+                     sxy, sm);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_gather_rays(const uint32_t *perm, const double *xy, int64_t n, double *sxy,
+                        hipStream_t stream) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gather_rays, dim3(blocks_for(n)), dim3(kThreads), 0, stream, perm, xy, n,
+                     sxy);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_box_starts(const uint32_t *sorted_keys, int64_t n, int64_t nbox, int32_t *start,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL(k_box_starts, dim3(blocks_for(nbox + 1)), dim3(kThreads), 0, stream,
+                     sorted_keys, n, nbox, start);
+  LENS_HIP(hipGetLastError());
+}
+
+}  // namespace lensfmm

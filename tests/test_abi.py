@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/lens.h declares, and rejects bad arguments before it
+touches the device."""
+import ctypes
+
+import pytest
+
+from paper_2211_00354_amd import _lib
+
+
+def test_library_exports_every_declared_symbol():
+    names = _lib.declared_functions()
+    assert {"lens_deflect", "lens_map", "lens_plan_create", "lens_plan_destroy",
+            "lens_last_error"} <= set(names)
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_string():
+    assert b"gfx950" in _lib.load().lens_version()
+
+
+def _opts(**kw):
+    o = _lib.LensOpts()
+    _lib.load().lens_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_opts_defaults():
+    o = _opts()
+    assert (o.method, o.precision, o.order_p, o.leaf_level) == (_lib.LENS_FMM, _lib.LENS_MIXED, 12, 0)
+
+
+@pytest.mark.parametrize("field,opts,msg", [
+    (dict(n_stars=-1), {}, "n_stars"),
+    (dict(n_stars=5), {}, "NULL"),                       # null star pointers
+    (dict(n_stars=0, kappa_s=float("nan")), {}, "finite"),
+    (dict(n_stars=0), dict(order_p=41), "order_p"),
+    (dict(n_stars=0), dict(order_p=-2), "order_p"),
+    (dict(n_stars=0), dict(leaf_level=1), "leaf_level"),
+    (dict(n_stars=0), dict(leaf_level=16), "leaf_level"),
+    (dict(n_stars=0), dict(method=7), "method"),
+    (dict(n_stars=0), dict(precision=3), "precision"),
+])
+def test_deflect_rejects_bad_arguments(field, opts, msg):
+    lib = _lib.load()
+    f = _lib.LensField(**field)
+    o = _opts(**opts)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2)
+    st = lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), None, 4, ctypes.c_void_p(8),
+                          ctypes.byref(o), None)
+    assert st == _lib.LENS_EINVAL
+    assert msg in lib.lens_last_error().decode()
+
+
+@pytest.mark.parametrize("grid,n,msg", [
+    ((0.0, 0.0, 0.0, 1.0, 2, 2), 4, "dx"),
+    ((0.0, 0.0, 1.0, -1.0, 2, 2), 4, "dx"),
+    ((float("inf"), 0.0, 1.0, 1.0, 2, 2), 4, "finite"),
+    ((0.0, 0.0, 1.0, 1.0, -1, 2), 0, "nx"),
+    ((0.0, 0.0, 1.0, 1.0, 2, 2), 5, "n_rays"),
+])
+def test_deflect_rejects_bad_grids(grid, n, msg):
+    lib = _lib.load()
+    f = _lib.LensField(n_stars=0)
+    g = _lib.LensGrid(*grid)
+    st = lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), None, n, ctypes.c_void_p(8),
+                          None, None)
+    assert st == _lib.LENS_EINVAL
+    assert msg in lib.lens_last_error().decode()
+
+
+def test_deflect_needs_exactly_one_ray_source_and_an_output():
+    lib = _lib.load()
+    f = _lib.LensField(n_stars=0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2)
+    assert lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), ctypes.c_void_p(8), 4,
+                            ctypes.c_void_p(8), None, None) == _lib.LENS_EINVAL
+    assert lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), None, 4, None, None,
+                            None) == _lib.LENS_EINVAL
+    assert b"y_out" in lib.lens_last_error()
+    # zero rays is a no-op
+    g0 = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 0, 3)
+    assert lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g0), None, 0, None, None,
+                            None) == _lib.LENS_OK
+
+
+@pytest.mark.parametrize("npix,side,counts,msg", [
+    (0, 1.0, 8, "npix"),
+    (46341, 1.0, 8, "npix"),        # npix^2 > 2^31 - 1
+    (4, 0.0, 8, "side"),
+    (4, float("nan"), 8, "side"),
+    (4, 1.0, None, "counts"),
+])
+def test_map_rejects_bad_maps(npix, side, counts, msg):
+    lib = _lib.load()
+    f = _lib.LensField(n_stars=0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2)
+    md = _lib.LensMapDesc(0.0, 0.0, side, npix, counts)
+    st = lib.lens_map(None, ctypes.byref(f), ctypes.byref(g), ctypes.byref(md), None, None)
+    assert st == _lib.LENS_EINVAL
+    assert msg in lib.lens_last_error().decode()
+
+
+def test_map_rejects_more_rays_than_int32_counts_can_hold():
+    lib = _lib.load()
+    f = _lib.LensField(n_stars=0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 65536, 32769)
+    md = _lib.LensMapDesc(0.0, 0.0, 1.0, 4, ctypes.c_void_p(8))
+    assert lib.lens_map(None, ctypes.byref(f), ctypes.byref(g), ctypes.byref(md), None,
+                        None) == _lib.LENS_EINVAL
+    assert b"2^31" in lib.lens_last_error()
+
+
+def test_plan_create_rejects_bad_ray_box():
+    lib = _lib.load()
+    f = _lib.LensField(n_stars=0)
+    box = (ctypes.c_double * 4)(1.0, 0.0, 0.0, 1.0)   # x1max < x1min
+    h = ctypes.c_void_p()
+    assert lib.lens_plan_create(ctypes.byref(f), box, None, None, ctypes.byref(h)) == _lib.LENS_EINVAL
+    assert lib.lens_plan_create(ctypes.byref(f), None, None, None, None) == _lib.LENS_EINVAL

@@ -1,0 +1,288 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs.  Floating-point results are compared through the relative l2 error of
+the deflection, ||y_gpu - y_oracle|| / ||alpha_oracle|| (y and alpha differ by
+the exact smooth term), against the targets: 1e-13 for the FP64 direct sum,
+1e-10 for the FP64 FMM at high order, 1e-5 for the mixed-precision FMM at
+p = 12.  Map counts are integers: the GPU map must equal the oracle's binning
+of the GPU's own y exactly, and differ from the oracle's map by at most the
+bin-reassignment budget."""
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev_tensor(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_l2(y, y_ref, alpha_ref):
+    den = np.linalg.norm(alpha_ref)
+    return float(np.linalg.norm(y - y_ref) / (den if den > 0 else 1.0))
+
+
+def lfgrid(g: wl.Grid):
+    import paper_2211_00354_amd as lf
+    return lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny)
+
+
+# ------------------------------------------------------------ FP64 direct sum
+
+def test_direct_config1_matches_oracle(lf):
+    f, g, _ = wl.config1()
+    _say("direct config1", f.n, g.nx, g.ny)
+    y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
+                        gamma=f.gamma, method="direct"))
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
+    err = rel_l2(y, yo, ao)
+    print("direct rel l2", err)
+    assert err <= 1e-13
+    assert np.max(np.abs(y - yo)) <= 1e-11 * np.max(np.abs(ao))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 17, 1000])
+def test_direct_explicit_rays_edge_cases(lf, n):
+    rng = np.random.default_rng(100 + n)
+    xy = rng.uniform(-2, 2, (n, 2))
+    m = rng.uniform(-0.5, 2.0, n)
+    rays = rng.uniform(-3, 3, (301, 2))
+    if n:
+        rays[:min(n, 5)] = xy[:min(n, 5)]      # rays exactly on stars
+    _say("direct explicit", n)
+    y = host(lf.deflect(dev_tensor(xy.reshape(-1, 2)), dev_tensor(m), rays=dev_tensor(rays),
+                        kappa_s=0.1, gamma=-0.2, method="direct"))
+    yo, ao, skipped = oracle.deflect(xy, m, rays, 0.1, -0.2)
+    assert skipped == min(n, 5)
+    assert np.all(np.isfinite(y))
+    if n == 0:
+        np.testing.assert_array_equal(y, yo)
+    else:
+        assert rel_l2(y, yo, ao) <= 1e-13
+
+
+def test_direct_map_config1(lf):
+    import torch
+    f, g, mp = wl.config1()
+    _say("direct map config1")
+    md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
+    counts = host(lf.irs_map(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), map=md,
+                             kappa_s=f.kappa_s, gamma=f.gamma, method="direct"))
+    y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
+                        gamma=f.gamma, method="direct"))
+    mine, _ = oracle.bin_rays(y, mp.y1min, mp.y2min, mp.side, mp.npix)
+    np.testing.assert_array_equal(counts, mine)
+    yo, _, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
+    ref, _ = oracle.bin_rays(yo, mp.y1min, mp.y2min, mp.side, mp.npix)
+    assert np.abs(counts.astype(np.int64) - ref).sum() <= 2      # 0 expected
+    assert counts.sum() > 0
+    del torch
+
+
+# --------------------------------------------------------------------- FMM
+
+@pytest.mark.parametrize("precision,p,tol", [
+    ("fp64", 12, 1e-6), ("fp64", 20, 1e-8), ("fp64", 30, 1e-10), ("mixed", 12, 1e-5),
+])
+def test_fmm_config1(lf, precision, p, tol):
+    f, g, _ = wl.config1()
+    _say("fmm config1", precision, p)
+    y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
+                        gamma=f.gamma, precision=precision, p=p))
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
+    err = rel_l2(y, yo, ao)
+    print("fmm", precision, p, "rel l2", err)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("leaf", [2, 3, 4, 6, 8])
+def test_fmm_leaf_levels(lf, leaf):
+    f, g, _ = wl.config1()
+    _say("fmm leaf level", leaf)
+    y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
+                        gamma=f.gamma, precision="fp64", p=24, leaf_level=leaf))
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
+    assert rel_l2(y, yo, ao) <= 1e-9
+
+
+def test_fmm_error_falls_with_order(lf):
+    """The truncation error must fall at least geometrically with p."""
+    f = wl.random_field(3000, 30.0, seed=7, masses="powerlaw")
+    g = wl.centred_grid(40.0, 40.0, 200, 200)
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays())
+    errs = []
+    for p in (4, 8, 12, 16, 20):
+        _say("fmm order sweep", p)
+        y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), precision="fp64",
+                            p=p, leaf_level=5))
+        errs.append(rel_l2(y, yo, ao))
+    print("errors by p", errs)
+    for a, b in zip(errs, errs[1:]):
+        assert b < a * 0.5 ** 2        # at least 2 bits per 4 orders (bound: 0.547^4)
+    # well-separated bound: error <= C rho^p with rho = sqrt(2)/(4-sqrt(2))
+    rho = math.sqrt(2) / (4 - math.sqrt(2))
+    assert errs[-1] <= 10 * rho ** 20
+
+
+def test_fmm_ragged_grid_offset(lf):
+    f = wl.random_field(2500, 25.0, seed=9, masses="powerlaw", kappa_s=0.3, gamma=0.1)
+    g = wl.Grid(x0=-7.3, y0=3.1, dx=0.043, dy=0.029, nx=333, ny=257)
+    _say("fmm ragged grid")
+    for prec, tol in (("fp64", 1e-9), ("mixed", 1e-5)):
+        y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
+                            gamma=f.gamma, precision=prec, p=24 if prec == "fp64" else 12))
+        yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
+        assert rel_l2(y, yo, ao) <= tol, prec
+
+
+@pytest.mark.parametrize("prec,p,tol", [("fp64", 24, 1e-9), ("mixed", 12, 1e-5)])
+def test_fmm_explicit_rays(lf, prec, p, tol):
+    f = wl.random_field(4000, 20.0, seed=12, masses="powerlaw")
+    rng = np.random.default_rng(13)
+    rays = wl.uniform_disk(rng, 50001, 20.0)
+    _say("fmm explicit rays", prec)
+    y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), rays=dev_tensor(rays), precision=prec,
+                        p=p))
+    yo, ao, _ = oracle.deflect(f.xy, f.m, rays)
+    assert rel_l2(y, yo, ao) <= tol
+
+
+@pytest.mark.parametrize("case", ["one", "two", "three", "seventeen", "cluster", "onstar",
+                                  "negmass", "empty"])
+def test_fmm_tiny_edge_cases(lf, case):
+    rng = np.random.default_rng(zlib.crc32(case.encode()))
+    if case == "empty":
+        xy, m = np.zeros((0, 2)), np.zeros(0)
+    elif case == "cluster":                     # every star in one leaf
+        xy = 1.0 + 1e-3 * rng.standard_normal((40, 2))
+        m = np.ones(40)
+    else:
+        n = {"one": 1, "two": 2, "three": 3, "seventeen": 17, "onstar": 17, "negmass": 17}[case]
+        xy = rng.uniform(-3, 3, (n, 2))
+        m = rng.uniform(-1.0, 2.0, n) if case == "negmass" else rng.uniform(0.1, 2.0, n)
+    rays = rng.uniform(-4, 4, (2000, 2))
+    if case == "onstar":
+        rays[:17] = xy
+    _say("fmm tiny", case)
+    # mass concentrated at a box corner is the worst case of the truncation
+    # bound, so the mixed path runs at p = 16 here
+    for prec, p, tol in (("fp64", 24, 1e-9), ("mixed", 16, 1e-5)):
+        y = host(lf.deflect(dev_tensor(xy.reshape(-1, 2)), dev_tensor(m), rays=dev_tensor(rays),
+                            kappa_s=0.05, gamma=0.2, precision=prec, p=p))
+        yo, ao, _ = oracle.deflect(xy, m, rays, 0.05, 0.2)
+        assert np.all(np.isfinite(y)), prec
+        if case == "empty":
+            np.testing.assert_array_equal(y, yo)
+        else:
+            assert rel_l2(y, yo, ao) <= tol, (prec, rel_l2(y, yo, ao))
+
+
+def test_fmm_rays_on_box_edges(lf):
+    """Rays exactly on leaf-box edges and corners (several boxes are valid)."""
+    f = wl.random_field(500, 10.0, seed=21)
+    plan = lf.Plan(dev_tensor(f.xy), dev_tensor(f.m), ray_box=(-10, -10, 10, 10), precision="fp64",
+                   p=24, leaf_level=4)
+    info = plan.info()
+    s = info["root_side"] / 2 ** info["leaf_level"]
+    ii = np.arange(2, 14)
+    ex = info["root_x0"] + ii * s
+    ey = info["root_y0"] + ii * s
+    X, Y = np.meshgrid(ex, ey)
+    rays = np.stack([X.ravel(), Y.ravel()], 1)
+    rays = rays[(np.abs(rays) <= 10).all(1)]
+    _say("fmm box edges", rays.shape)
+    y = host(lf.deflect(rays=dev_tensor(rays), plan=plan))
+    yo, ao, _ = oracle.deflect(f.xy, f.m, rays)
+    assert rel_l2(y, yo, ao) <= 1e-9
+    plan.close()
+
+
+def test_fmm_determinism_and_plan_reuse(lf):
+    f = wl.random_field(5000, 30.0, seed=31, masses="powerlaw")
+    g = wl.centred_grid(40.0, 40.0, 256, 256)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    _say("fmm determinism")
+    for prec in ("fp64", "mixed"):
+        a = host(lf.deflect(xy, m, grid=lfgrid(g), precision=prec, kappa_s=0.2, gamma=0.1))
+        b = host(lf.deflect(xy, m, grid=lfgrid(g), precision=prec, kappa_s=0.2, gamma=0.1))
+        np.testing.assert_array_equal(a, b)
+    bb = (g.x0, g.y0, g.x0 + g.nx * g.dx, g.y0 + g.ny * g.dy)
+    plan = lf.Plan(xy, m, ray_box=bb, precision="mixed", p=12)
+    yo0, ao0, _ = oracle.deflect(f.xy, f.m, g.rays(), 0.0, 0.0)
+    for ks, gm in ((0.0, 0.0), (0.3, -0.2)):
+        y = host(lf.deflect(grid=lfgrid(g), plan=plan, kappa_s=ks, gamma=gm))
+        yo, _, _ = oracle.deflect(f.xy, f.m, g.rays(), ks, gm)
+        assert rel_l2(y, yo, ao0) <= 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("prec,p", [("fp64", 20), ("mixed", 16)])
+def test_fmm_map_equals_binned_deflect(lf, prec, p):
+    f, g, mp = wl.config1()
+    md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    _say("fmm map", prec, p)
+    counts = host(lf.irs_map(xy, m, grid=lfgrid(g), map=md, kappa_s=f.kappa_s, gamma=f.gamma,
+                             precision=prec, p=p))
+    y = host(lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma, precision=prec,
+                        p=p))
+    mine, _ = oracle.bin_rays(y, mp.y1min, mp.y2min, mp.side, mp.npix)
+    np.testing.assert_array_equal(counts, mine)
+    yo, _, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
+    ref, _ = oracle.bin_rays(yo, mp.y1min, mp.y2min, mp.side, mp.npix)
+    moved = np.abs(counts.astype(np.int64) - ref).sum() / 2
+    print("rays moved to another pixel:", moved, "of", g.n)
+    assert moved <= 1e-4 * g.n
+    # chunking by rows does not change the map
+    c2 = host(lf.irs_map(xy, m, grid=lfgrid(g), map=md, kappa_s=f.kappa_s, gamma=f.gamma,
+                         precision=prec, p=p, max_rays_per_chunk=5 * g.nx + 17))
+    np.testing.assert_array_equal(counts, c2)
+
+
+# -------------------------------------------------------- the N_*=1e6 field
+
+def test_config2_reduced(lf):
+    f, g = wl.config2(n_stars=50000, n_side=1024)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    idx = g.strided(8, 3)
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), f.kappa_s, f.gamma)
+    for prec, p, tol in (("mixed", 12, 1e-5), ("fp64", 12, 1e-6), ("fp64", 30, 1e-10)):
+        _say("config2 reduced", prec, p)
+        y = host(lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma,
+                            precision=prec, p=p))
+        err = rel_l2(y[idx], yo, ao)
+        print(prec, p, err)
+        assert err <= tol
+
+
+def test_config2_full_size_sampled(lf):
+    """The benchmark workload itself (1e6 stars, 8192^2 rays, mixed, p=12) in
+    the launch configuration the benchmark times, checked on a strided sample."""
+    import torch
+    f, g = wl.config2()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    _say("config2 full mixed")
+    y = lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma, precision="mixed", p=12)
+    idx = torch.from_numpy(g.strided(128, 64)).cuda()
+    ys = host(y[idx])
+    assert bool(torch.isfinite(y).all())
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx.cpu().numpy()), f.kappa_s, f.gamma)
+    err = rel_l2(ys, yo, ao)
+    print("config2 full mixed rel l2", err)
+    assert err <= 1e-5
