@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--no-direct", action="store_true", help="skip the FP64 direct comparator")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps of the mixed FMM only (for rocprofv3)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="with --profile-only: also run one device-to-device copy of this many "
+                         "MiB, the reference for scaling FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -139,6 +142,13 @@ def main():
     _lib.profile_enable(False)
     log(f"mixed FMM: {ms:.3f} ms/step ({wall:.2f} s wall for {args.steps} steps); stages {prof}")
     if args.profile_only:
+        if args.calib_copy_mib:
+            n = args.calib_copy_mib * (1 << 20) // 4
+            src = torch.ones(n, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"calibration copy: {args.calib_copy_mib} MiB read + written")
         return
 
     value = n_rays / (ms * 1e-3)
@@ -147,9 +157,8 @@ def main():
     y_mixed_sample = y[torch.from_numpy(idx).cuda()].cpu().numpy()
 
     # algorithmic work of the dominant kernel (fused evaluation)
-    plan = lf.Plan(xy, m, ray_box=(g.x0 + 0.5 * g.dx, g.y0 + 0.5 * g.dy,
-                                   g.x0 + (g.nx - 0.5) * g.dx, g.y0 + (g.ny - 0.5) * g.dy),
-                   precision="mixed", p=args.p, leaf_level=leaf)
+    # the same tree the timed calls build (grid-aligned, same leaf level)
+    plan = lf.Plan(xy, m, grid=grid, precision="mixed", p=args.p, leaf_level=leaf)
     info = plan.info()
     plan.close()
     pairs = near_pairs(info, f, g)
@@ -167,6 +176,7 @@ def main():
             traffic = None
 
     extra = {"leaf_level": leaf, "p": args.p, "near_pairs_per_ray": pairs / n_rays,
+             "leaf_box_side": math.ldexp(info["root_side"], -leaf),
              "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
              "eval_flops_per_launch": flops}
 

@@ -119,13 +119,17 @@ typedef struct lens_plan lens_plan;
 /*
  * Build a plan for `field` whose quadtree also covers the rectangle
  * ray_box = {x1min, x2min, x1max, x2max} (HOST array; every ray later
- * evaluated with this plan must lie inside it; NULL = the stars' extent only).
- * Copies the stars (sorted by leaf box) into plan-owned device memory, so the
- * caller's star arrays may be freed afterwards.  Waits on `stream` once, to
- * read back the stars' bounding box.  *out receives the plan.
+ * evaluated with this plan must lie inside it; NULL = the stars' extent only)
+ * and, if `grid` is not NULL, every ray of that grid.  With a grid, leaf boxes
+ * are aligned with its cells where the spacings allow (a leaf box then holds
+ * a whole number of 64-ray waves).  Copies the stars (sorted by leaf box) into
+ * plan-owned device memory, so the caller's star arrays may be freed
+ * afterwards.  Waits on `stream` once, to read back the stars' bounding box.
+ * *out receives the plan.
  */
-LENS_API lens_status lens_plan_create(const lens_field *field, const double *ray_box, const lens_opts *opts,
-                             void *stream, lens_plan **out);
+LENS_API lens_status lens_plan_create(const lens_field *field, const double *ray_box,
+                                      const lens_grid *grid, const lens_opts *opts, void *stream,
+                                      lens_plan **out);
 
 /* Release a plan (waits for the plan's last stream to finish first). */
 LENS_API void lens_plan_destroy(lens_plan *plan);

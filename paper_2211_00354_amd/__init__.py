@@ -97,21 +97,23 @@ def _field(xy, m, kappa_s, gamma):
 class Plan:
     """Star quadtree + multipoles, reusable across deflect/irs_map calls.
 
-    ``ray_box`` = (x1min, x2min, x1max, x2max) must contain every ray the plan
-    will serve.  The plan copies the stars; it fixes method, precision, p and
-    the leaf level.
+    ``ray_box`` = (x1min, x2min, x1max, x2max) and/or ``grid`` must contain
+    every ray the plan will serve; with ``grid`` the leaf boxes are aligned
+    with its cells where possible.  The plan copies the stars; it fixes
+    precision, p and the leaf level.
     """
 
-    def __init__(self, star_xy, star_m, kappa_s=0.0, gamma=0.0, ray_box=None, precision="mixed",
-                 p=12, leaf_level=0):
+    def __init__(self, star_xy, star_m, kappa_s=0.0, gamma=0.0, ray_box=None, grid=None,
+                 precision="mixed", p=12, leaf_level=0):
         lib = _lib.load()
         self._f = _field(star_xy, star_m, kappa_s, gamma)
         self.precision = precision
         self.kappa_s, self.gamma = float(kappa_s), float(gamma)
         o = _opts("fmm", precision, p, leaf_level)
         box = (ctypes.c_double * 4)(*ray_box) if ray_box is not None else None
+        g = ctypes.byref(grid.c()) if grid is not None else None
         h = ctypes.c_void_p()
-        _lib.check(lib.lens_plan_create(ctypes.byref(self._f), box, ctypes.byref(o), _stream(),
+        _lib.check(lib.lens_plan_create(ctypes.byref(self._f), box, g, ctypes.byref(o), _stream(),
                                         ctypes.byref(h)))
         self._h = h
 

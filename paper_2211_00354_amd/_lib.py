@@ -68,7 +68,7 @@ def load(path: str = LIB_PATH):
     P, V, I64, I32, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     lib.lens_opts_default.argtypes = [P(LensOpts)]
     lib.lens_opts_default.restype = None
-    lib.lens_plan_create.argtypes = [P(LensField), P(D), P(LensOpts), V, P(V)]
+    lib.lens_plan_create.argtypes = [P(LensField), P(D), P(LensGrid), P(LensOpts), V, P(V)]
     lib.lens_plan_create.restype = ctypes.c_int
     lib.lens_plan_destroy.argtypes = [V]
     lib.lens_plan_destroy.restype = None

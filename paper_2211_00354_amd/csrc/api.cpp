@@ -114,31 +114,92 @@ void device_bbox(const double *xy, int64_t n, hipStream_t st, double out[4]) {
     if (!is_finite(out[c])) fail(LENS_EINVAL, "non-finite coordinates in the input positions");
 }
 
-// Leaf level from a cost model of the evaluation: per ray, 9 q near pairs
-// (q = stars per leaf) against 27 p^2 M2L complex MACs per target box shared
-// by the rays of the box.  Minimising over the leaf side s gives
-// s^2 = sqrt(3 p^2 c_m2l / (rho_* rho_ray c_pair)).  Without rays, aim for
-// about 8 stars per leaf.
-int choose_leaf_level(int64_t n_stars, const double sb[4], double rays_density, double side,
-                      int p) {
-  const double area = std::max((sb[2] - sb[0]) * (sb[3] - sb[1]), 1e-300);
-  const double rho = n_stars > 0 ? (double)n_stars / area : 0.0;
+// Cost model of the evaluation per ray, in VALU lane-instructions: 9 q near
+// pairs at ~12 each (q = stars per leaf) plus the leaf-level M2L, 27 p^2
+// complex MACs per target box at ~6 each (MFMA), shared by the box's rays.
+constexpr double kCostPair = 12.0, kCostM2L = 6.0;
+
+double eval_cost(double rho, double s, double rays_per_box, int p) {
+  return kCostPair * 9.0 * rho * s * s + kCostM2L * 27.0 * p * p / std::max(rays_per_box, 1.0);
+}
+
+// Leaf side minimising eval_cost for a ray density rho_ray (no alignment):
+// s^4 = 27 p^2 c_m2l / (9 rho rho_ray c_pair).  Without rays, ~8 stars per leaf.
+double preferred_leaf_side(double rho, double rays_density, double side, int p) {
   double s;
   if (rho <= 0) {
     s = side / 4;
   } else if (rays_density > 0) {
-    const double c_pair = 14.0, c_m2l = 4.0;
-    s = std::sqrt(std::sqrt(3.0 * p * p * c_m2l / (rho * rays_density * c_pair)));
+    s = std::sqrt(std::sqrt(27.0 * p * p * kCostM2L / (9.0 * rho * rays_density * kCostPair)));
     s = std::max(s, std::sqrt(0.5 / rho));   // at least ~0.5 stars per leaf
     s = std::min(s, std::sqrt(64.0 / rho));  // at most ~64
   } else {
     s = std::sqrt(8.0 / rho);
   }
-  int L = (int)std::lround(std::log2(side / s));
+  return s;
+}
+
+int level_for_side(double side, double s, int p) {
+  int L = (int)std::ceil(std::log2(side / s) - 1e-9);
   L = std::max(2, std::min(L, 13));
   // keep the multipole storage (all levels) under ~8 GB
   while (L > 2 && (double)(int64_t(1) << (2 * L)) * p * 16.0 * 1.34 > 8e9) --L;
   return L;
+}
+
+double star_density(int64_t n_stars, const double sb[4]) {
+  const double area = std::max((sb[2] - sb[0]) * (sb[3] - sb[1]), 1e-300);
+  return n_stars > 0 ? (double)n_stars / area : 0.0;
+}
+
+// Root placement with leaf boxes aligned to a ray grid: a leaf box spans kx
+// grid columns and ky rows (kx dx == ky dy exactly) and kx*ky is a multiple of
+// 64, so every interior box holds whole waves of rays.  With leaf_level given,
+// the smallest such box that lets 2^L boxes cover the domain; otherwise the
+// candidate with the lowest eval_cost.  Returns false if no candidate fits.
+bool aligned_geometry(const lens_grid &g, const double dom[4], int leaf_level, double rho, int p,
+                      Geometry *out) {
+  struct Cand {
+    double s;
+    int kx, ky;
+  };
+  std::vector<Cand> cands;
+  for (int kx = 1; kx <= 64; ++kx) {
+    const long ky = std::lround((double)kx * g.dx / g.dy);
+    if (ky < 1 || ky > 64 || (double)ky * g.dy != (double)kx * g.dx) continue;
+    if ((kx * ky) % 64 != 0 || kx * ky > 1024) continue;
+    cands.push_back({(double)kx * g.dx, kx, (int)ky});
+  }
+  std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.s < b.s; });
+  const double w = dom[2] - dom[0], h = dom[3] - dom[1];
+  bool found = false;
+  double best_cost = 0;
+  for (const Cand &c : cands) {
+    // boxes to the left of / below the grid origin needed to reach the domain
+    const double mx = std::max(0.0, std::ceil((g.x0 - dom[0]) / c.s));
+    const double my = std::max(0.0, std::ceil((g.y0 - dom[1]) / c.s));
+    const double x0 = g.x0 - mx * c.s, y0 = g.y0 - my * c.s;
+    const double need = std::max(dom[2] - x0, dom[3] - y0) * (1.0 + 1e-12);
+    int L = 2;
+    while (L < 13 && std::ldexp(c.s, L) <= need) ++L;
+    if (std::ldexp(c.s, L) <= need) continue;
+    if (leaf_level > 0) {
+      if (L > leaf_level) continue;  // box too small for this depth
+      L = leaf_level;
+      *out = Geometry{x0, y0, std::ldexp(c.s, L), L};
+      return true;  // smallest fitting box
+    }
+    if ((double)(int64_t(1) << (2 * L)) * p * 16.0 * 1.34 > 8e9) continue;
+    const double cost = eval_cost(rho, c.s, (double)c.kx * c.ky, p);
+    if (!found || cost < best_cost) {
+      found = true;
+      best_cost = cost;
+      *out = Geometry{x0, y0, std::ldexp(c.s, L), L};
+    }
+  }
+  (void)w;
+  (void)h;
+  return found;
 }
 
 Window window_for(const lens_plan &P, int level, const double bb[4]) {
@@ -153,8 +214,8 @@ Window window_for(const lens_plan &P, int level, const double bb[4]) {
   return Window{x0, y0, x1 - x0 + 1, y1 - y0 + 1};
 }
 
-lens_plan *build_plan(const lens_field &f, const double *ray_box, double rays_density,
-                      const lens_opts &o, hipStream_t st) {
+lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_grid *align,
+                      double rays_density, const lens_opts &o, hipStream_t st) {
   auto *P = new lens_plan();
   try {
     LENS_HIP(hipGetDevice(&P->device));
@@ -184,12 +245,19 @@ lens_plan *build_plan(const lens_field &f, const double *ray_box, double rays_de
     double side = std::max(dom[2] - dom[0], dom[3] - dom[1]);
     if (!(side > 0)) side = 1.0;
     side *= 1.0 + 1.0 / 1024;
-    const double cxm = 0.5 * (dom[0] + dom[2]), cym = 0.5 * (dom[1] + dom[3]);
-    P->g.side = side;
-    P->g.x0 = cxm - 0.5 * side;
-    P->g.y0 = cym - 0.5 * side;
-    P->g.L = o.leaf_level > 0 ? o.leaf_level
-                              : choose_leaf_level(f.n_stars, have ? sb : dom, rays_density, side, P->p);
+    const double rho = star_density(f.n_stars, have ? sb : dom);
+    bool aligned = false;
+    if (align && align->nx > 0 && align->ny > 0 && f.n_stars > 0)
+      aligned = aligned_geometry(*align, dom, o.leaf_level, rho, P->p, &P->g);
+    if (!aligned) {
+      const double cxm = 0.5 * (dom[0] + dom[2]), cym = 0.5 * (dom[1] + dom[3]);
+      P->g.side = side;
+      P->g.x0 = cxm - 0.5 * side;
+      P->g.y0 = cym - 0.5 * side;
+      P->g.L = o.leaf_level > 0
+                   ? o.leaf_level
+                   : level_for_side(side, preferred_leaf_side(rho, rays_density, side, P->p), P->p);
+    }
     const int L = P->g.L;
     const int64_t nL = int64_t(1) << L;
     const int64_t nbox = nL * nL;
@@ -228,16 +296,21 @@ lens_plan *build_plan(const lens_field &f, const double *ray_box, double rays_de
     const OpTables &T = op_tables(P->p, st);
     {
       StageTimer tm("upward", st);
-      launch_p2m(P->g, sxy, sm, leaf_start, P->p, static_cast<double *>(P->mp[L].ptr), st);
-      for (int l = L - 1; l >= 2; --l)
-        launch_m2m(l, P->p, P->mp_at(l + 1), static_cast<double *>(P->mp[l].ptr), T.m2m, st);
-      if (P->precision == LENS_MIXED) {
-        P->mp32.resize(L + 1);
-        for (int l = std::max(2, L - P->fine_levels + 1); l <= L; ++l) {
-          const size_t n = (size_t)(int64_t(1) << (2 * l)) * P->p * 2;
-          P->mp32[l] = pool_get(n * sizeof(float), st);
-          launch_to_f32(P->mp_at(l), static_cast<float *>(P->mp32[l].ptr), n, st);
-        }
+      // LENS_MIXED: the fine levels also get FP32 copies for their M2L
+      P->mp32.resize(L + 1);
+      auto f32_at = [&](int l) -> float * {
+        if (P->precision != LENS_MIXED || l <= L - P->fine_levels) return nullptr;
+        const size_t n = (size_t)(int64_t(1) << (2 * l)) * P->p * 2;
+        P->mp32[l] = pool_get(n * sizeof(float), st);
+        return static_cast<float *>(P->mp32[l].ptr);
+      };
+      const int direct_levels = 3;  // levels L, L-1, L-2 from the stars
+      for (int l = L; l >= 2; --l) {
+        double *out = static_cast<double *>(P->mp[l].ptr);
+        if (l > L - direct_levels)
+          launch_p2m(P->g, l, sxy, sm, leaf_start, P->p, out, f32_at(l), st);
+        else
+          launch_m2m(l, P->p, P->mp_at(l + 1), out, f32_at(l), T.m2m, st);
       }
     }
     P->last_stream = st;
@@ -258,32 +331,59 @@ void check_inside(const lens_plan &P, const double bb[4]) {
 
 // Downward pass over the windows of `bb`: locals of every level 2..L.
 // Returns the leaf window; *leaf_loc receives its local expansions.
+// Levels >= 3 among the two finest run M2L and L2L in one fused kernel,
+// in order; the coarser ones run M2L batched, then the L2L sweep.
 Window downward(lens_plan &P, const double bb[4], Scratch &sc, hipStream_t st, double **leaf_loc) {
   const int L = P.g.L;
   const OpTables &T = op_tables(P.p, st);
   StageTimer tm("downward", st);
   std::vector<Window> win(L + 1);
   std::vector<double *> loc(L + 1, nullptr);
+  auto is_f32 = [&](int l) {
+    return P.precision == LENS_MIXED && l > L - P.fine_levels && P.mp32_at(l) != nullptr;
+  };
+  auto level_of = [&](int l) {
+    return M2LLevel{l, std::ldexp(P.g.side, -l), win[l],
+                    is_f32(l) ? (const void *)P.mp32_at(l) : (const void *)P.mp_at(l), loc[l],
+                    nullptr, Window{0, 0, 0, 0}};
+  };
+  const int first_fused = std::max(3, L - 1);
+  M2LBatch coarse, fine;
+  coarse.p = fine.p = P.p;
   for (int l = 2; l <= L; ++l) {
     win[l] = window_for(P, l, bb);
     loc[l] = sc.get<double>((size_t)win[l].count() * P.p * 2);
   }
-  for (int l = 2; l <= L; ++l) {
+  for (int l = 2; l < first_fused && l <= L; ++l) {
+    M2LBatch &b = is_f32(l) ? fine : coarse;
+    b.lv[b.count++] = level_of(l);
+  }
+  launch_m2l_batch(coarse, T, false, st);
+  launch_m2l_batch(fine, T, true, st);
+  auto l2l = [&](int l) {
     DownArgs d{};
     d.level = l;
     d.p = P.p;
     d.s = std::ldexp(P.g.side, -l);
     d.win = win[l];
-    d.pwin = l >= 3 ? win[l - 1] : Window{0, 0, 0, 0};
-    d.mp = P.mp_at(l);
-    d.mp32 = P.mp32_at(l);
-    d.ploc = l >= 3 ? loc[l - 1] : nullptr;
+    d.pwin = win[l - 1];
+    d.ploc = loc[l - 1];
     d.loc = loc[l];
-    const bool fine = P.precision == LENS_MIXED && l > L - P.fine_levels && d.mp32;
-    if (fine)
-      launch_down_f32(d, T, st);
-    else
-      launch_down_f64(d, T, st);
+    launch_l2l(d, T, st);
+  };
+  for (int l = 3; l < first_fused && l <= L; ++l) l2l(l);
+  for (int l = first_fused; l <= L; ++l) {
+    M2LBatch one;
+    one.p = P.p;
+    one.count = 1;
+    one.lv[0] = level_of(l);
+    one.lv[0].ploc = loc[l - 1];
+    one.lv[0].pwin = win[l - 1];
+    if (!launch_m2l_l2l(one, T, is_f32(l), st)) {
+      one.lv[0].ploc = nullptr;
+      launch_m2l_batch(one, T, is_f32(l), st);
+      l2l(l);
+    }
   }
   *leaf_loc = loc[L];
   return win[L];
@@ -358,13 +458,18 @@ void fmm_grid_rows(lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, 
   launch_grid_ranges(grid, P.g, wl, j0, j1, cs, rs, st);
   ea.col_start = cs;
   ea.row_start = rs;
-  // upper bound on the rays of one leaf box: the box spans at most
-  // ceil(s/dx)+1 columns and ceil(s/dy)+1 rows of the grid
-  const int64_t rpc = eval_rays_per_chunk();
+  // a leaf box of side s holds k grid columns when s = k dx, else at most
+  // floor(s/dx) + 1 (rows likewise); a longer box chunk is still processed
+  // whole by the kernel, only less efficiently
   const double s = std::ldexp(P.g.side, -P.g.L);
-  const int64_t mw = std::min<int64_t>((int64_t)std::ceil(s / grid.dx) + 2, grid.nx);
-  const int64_t mh = std::min<int64_t>((int64_t)std::ceil(s / grid.dy) + 2, j1 - j0);
-  ea.chunks_per_box = std::max<int64_t>(1, (mw * mh + rpc - 1) / rpc);
+  auto per_box = [&](double step, int64_t cap) {
+    const double r = s / step;
+    const double k = std::round(r);
+    const int64_t n = std::fabs(r - k) < 1e-9 * r ? (int64_t)k : (int64_t)std::floor(r) + 1;
+    return std::max<int64_t>(1, std::min(n, cap));
+  };
+  eval_shape(per_box(grid.dx, grid.nx) * per_box(grid.dy, j1 - j0), &ea.rays_per_lane,
+             &ea.chunks_per_box);
   launch_eval_checked(ea, P.precision, st);
   P.last_stream = st;
 }
@@ -400,9 +505,9 @@ void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4
   ea.c1 = c1;
   ea.c2 = c2;
   ea.y_out = y_out;
-  const int64_t rpc = eval_rays_per_chunk();
-  const int64_t per = n / std::max<int64_t>(wl.count(), 1);
-  ea.chunks_per_box = std::max<int64_t>(1, (per + rpc - 1) / rpc);
+  // explicit rays: shape for the mean box occupancy; fuller boxes loop
+  const int64_t per = (n + wl.count() - 1) / std::max<int64_t>(wl.count(), 1);
+  eval_shape(std::max<int64_t>(per, 1), &ea.rays_per_lane, &ea.chunks_per_box);
   launch_eval_checked(ea, P.precision, st);
   P.last_stream = st;
 }
@@ -463,18 +568,32 @@ const char *lens_last_error(void) { return lensfmm::last_error().c_str(); }
 
 const char *lens_version(void) { return "liblensfmm 0.1 (gfx950)"; }
 
-lens_status lens_plan_create(const lens_field *field, const double *ray_box, const lens_opts *opts,
-                             void *stream, lens_plan **out) {
+lens_status lens_plan_create(const lens_field *field, const double *ray_box, const lens_grid *grid,
+                             const lens_opts *opts, void *stream, lens_plan **out) {
   return guarded([&] {
     if (!out) fail(LENS_EINVAL, "out is NULL");
     check_field(field);
     const lens_opts o = resolve_opts(opts);
+    double gbox[4];
+    if (grid) {
+      check_grid(grid);
+      if (grid->nx > 0 && grid->ny > 0) {
+        grid_bbox(*grid, 0, grid->ny, gbox);
+        if (ray_box) {
+          gbox[0] = std::min(gbox[0], ray_box[0]);
+          gbox[1] = std::min(gbox[1], ray_box[1]);
+          gbox[2] = std::max(gbox[2], ray_box[2]);
+          gbox[3] = std::max(gbox[3], ray_box[3]);
+        }
+        ray_box = gbox;
+      }
+    }
     if (ray_box) {
       for (int c = 0; c < 4; ++c)
         if (!is_finite(ray_box[c])) fail(LENS_EINVAL, "ray_box must be finite");
       if (ray_box[2] < ray_box[0] || ray_box[3] < ray_box[1]) fail(LENS_EINVAL, "ray_box is empty");
     }
-    *out = build_plan(*field, ray_box, 0.0, o, (hipStream_t)stream);
+    *out = build_plan(*field, ray_box, grid, 0.0, o, (hipStream_t)stream);
   });
 }
 
@@ -545,7 +664,7 @@ lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_gr
     lens_plan *owned = nullptr;
     if (!P) {
       const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
-      owned = P = build_plan(fv.f, bb, (double)n_rays / area, o, st);
+      owned = P = build_plan(fv.f, bb, grid, (double)n_rays / area, o, st);
     }
     try {
       if (grid)
@@ -614,7 +733,7 @@ lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *
     lens_plan *owned = nullptr;
     if (!P) {
       const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
-      owned = P = build_plan(fv.f, bb, (double)n / area, o, st);
+      owned = P = build_plan(fv.f, bb, grid, (double)n / area, o, st);
     }
     try {
       for (int64_t j0 = 0; j0 < grid->ny; j0 += rows) {

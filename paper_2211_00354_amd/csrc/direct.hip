@@ -5,7 +5,7 @@
 // Each workgroup holds kThreads*R rays in registers (R per thread) and
 // streams the stars through LDS in tiles; every star is read back as a
 // wave-uniform broadcast and applied to the R rays of each thread.  Pairs
-// with |x - x_i| = 0 are skipped.  The reciprocal is the hardware estimate
+// with |x - x_i| = 0 contribute exactly zero.  The reciprocal is the hardware estimate
 // refined by two Newton-Raphson steps.
 #include "device_common.h"
 
@@ -52,10 +52,13 @@ __global__ __launch_bounds__(kThreads) void k_direct(DirectArgs a) {
       const double sx = tx[k], sy = ty[k], m = tm[k];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
+        // a coincident pair has dx = dy = 0: the tiny term keeps its weight
+        // finite, so it adds exactly zero (no other pair closer than ~1e-92
+        // is affected)
         const double dx = rx[r] - sx;
         const double dy = ry[r] - sy;
-        const double r2 = fma(dx, dx, dy * dy);
-        const double w = r2 > 0.0 ? m * rcp_f64(r2) : 0.0;
+        const double r2 = fma(dx, dx, fma(dy, dy, 0x1p-664));
+        const double w = m * rcp_f64(r2);
         ax[r] = fma(w, dx, ax[r]);
         ay[r] = fma(w, dy, ay[r]);
       }

@@ -2,194 +2,207 @@
 // field (Section 2.4, step 3) and, for maps, inverse-ray-shooting binning
 // (Section 2.3).
 //
-// One workgroup serves one chunk of the rays of one leaf box of the target
-// window:
-//   * the stars of the box's 3x3 neighbourhood (three contiguous row ranges of
-//     the sorted star array) are staged once in LDS and read back as
-//     wave-uniform broadcasts by every ray of the workgroup;
+// Work unit = one chunk of up to 64*R rays of one leaf box of the target
+// window, handled by one wave (a 64-thread workgroup):
+//   * the stars of the box's 3x3 neighbourhood (three contiguous row ranges
+//     of the sorted star array) and the box's local expansion are the same
+//     for every lane, so they are read with wave-uniform scalar loads into
+//     SGPRs and used directly as VALU operands -- every star is fetched once
+//     per wave and shared by all 64*R rays;
 //   * near field: alpha_near = sum m (x - x_i)/|x - x_i|^2 over those stars,
 //     pair differences formed in FP64, then (LENS_MIXED) rounded to FP32 for
 //     the square, reciprocal and accumulation;
-//   * far field: the box's local expansion f(z) = sum_l b~_l w^l,
-//     w = (z - c)/s, by Horner in FP64, alpha_far = conj(f);
+//   * far field: f(z) = sum_l b~_l w^l, w = (z - c)/s, by Horner in FP64,
+//     alpha_far = conj(f);
 //   * y = (1-kappa_s-gamma, 1-kappa_s+gamma) * x - alpha in FP64, written as
 //     [n][2] or binned into the map with an integer atomic.
+// Units are spread over a bounded grid; consecutive units (neighbouring
+// boxes, which share stars) go to the same XCD so that they share its L2.
 #include "device_common.h"
 
 namespace lensfmm {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kStarTile = 768;
+constexpr int kWave = 64;
+constexpr int kXcd = 8;
+constexpr int kThreads = 256;  // helper kernels
 
-template <bool MIXED>
-struct StarTile {
-  double x[kStarTile], y[kStarTile];
-  typename std::conditional<MIXED, float, double>::type m[kStarTile];
-};
+
+// One star against the R rays of a lane.  A coincident pair (dx = dy = 0)
+// contributes exactly zero: the tiny term keeps its weight finite (for any
+// |m| below ~1e18 in FP32, ~1e108 in FP64) and it multiplies dx = dy = 0,
+// so no branch or select is needed; the tiny term changes no other pair
+// unless the two points are closer than ~1e-7 (FP32) or ~1e-92 (FP64).
+template <bool MIXED, int R, typename A>
+__device__ __forceinline__ void pair_update(const double (&rx)[R], const double (&ry)[R], double sx,
+                                            double sy, double mm, A (&ax)[R], A (&ay)[R]) {
+  if constexpr (MIXED) {
+    const float m = (float)mm;
+    constexpr float tiny = 0x1p-66f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float dx = (float)(rx[r] - sx);
+      const float dy = (float)(ry[r] - sy);
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, tiny));
+      const float w = m * rcp_f32(r2);
+      ax[r] = fmaf(w, dx, ax[r]);
+      ay[r] = fmaf(w, dy, ay[r]);
+    }
+  } else {
+    constexpr double tiny = 0x1p-664;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double dx = rx[r] - sx;
+      const double dy = ry[r] - sy;
+      const double r2 = fma(dx, dx, fma(dy, dy, tiny));
+      const double w = mm * rcp_f64(r2);
+      ax[r] = fma(w, dx, ax[r]);
+      ay[r] = fma(w, dy, ay[r]);
+    }
+  }
+}
 
 template <int PMAX, bool MIXED, bool MAP, bool GRID, int R>
-__global__ __launch_bounds__(kThreads) void k_eval(EvalArgs a) {
-  using real = typename std::conditional<MIXED, float, double>::type;
-  __shared__ StarTile<MIXED> st;
-  __shared__ cplx sloc[PMAX];
-
-  const int tid = threadIdx.x;
-  const int64_t CH = a.chunks_per_box;
-  const int64_t b = (int64_t)blockIdx.x / CH;
-  const int64_t c0 = (int64_t)blockIdx.x % CH;
-  const int64_t bxw = b % a.win.nbx, byw = b / a.win.nbx;
-  const int64_t gx = a.win.bx0 + bxw, gy = a.win.by0 + byw;
-
-  // rays of this box
-  int64_t nr, i0 = 0, j0 = 0, W = 1, r0 = 0;
-  if (GRID) {
-    i0 = a.col_start[bxw];
-    W = a.col_start[bxw + 1] - i0;
-    j0 = a.row_start[byw];
-    nr = W * (a.row_start[byw + 1] - j0);
-  } else {
-    r0 = a.ray_start[b];
-    nr = a.ray_start[b + 1] - r0;
-  }
-  constexpr int64_t RPC = (int64_t)kThreads * R;  // rays per chunk
-  if (nr == 0 || c0 * RPC >= nr) return;          // uniform over the workgroup
-
-  // 3x3 neighbourhood: up to three row ranges of the sorted stars
+__global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__restrict__ loc,
+                                                const double *__restrict__ sxy,
+                                                const double *__restrict__ sm,
+                                                const int32_t *__restrict__ leaf_start,
+                                                const int32_t *__restrict__ col_start,
+                                                const int32_t *__restrict__ row_start,
+                                                const double *__restrict__ rxy,
+                                                const uint32_t *__restrict__ rperm,
+                                                const int32_t *__restrict__ ray_start,
+                                                double *__restrict__ y_out,
+                                                int32_t *__restrict__ counts) {
+  const int lane = threadIdx.x;
+  // unit counts fit in 31 bits (checked at launch)
+  const uint32_t CH = (uint32_t)a.chunks_per_box;
+  const uint32_t nbx = (uint32_t)a.win.nbx;
+  const uint32_t nunits = (uint32_t)(a.win.count() * CH);
+  // XCD-aware virtual block id: blocks dispatched to one XCD (blockIdx % 8)
+  // take a contiguous range of units in each sweep of the grid.
+  const uint32_t G = gridDim.x;
+  const uint32_t per_xcd = G / kXcd;
+  const uint32_t vb = (G % kXcd == 0) ? (blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd : blockIdx.x;
   const int64_t nL = int64_t(1) << a.g.L;
-  int32_t rs[3], rn[3];
-  int32_t nn = 0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int64_t row = gy - 1 + d;
-    rs[d] = 0;
-    rn[d] = 0;
-    if (row >= 0 && row < nL) {
-      const int64_t cx0 = gx > 0 ? gx - 1 : 0;
-      const int64_t cx1 = gx + 1 < nL ? gx + 1 : nL - 1;
-      rs[d] = a.leaf_start[row * nL + cx0];
-      rn[d] = a.leaf_start[row * nL + cx1 + 1] - rs[d];
-    }
-    nn += rn[d];
-  }
-
   const double s = ldexp(a.g.side, -a.g.L);
   const double inv_s = 1.0 / s;
-  const double cx = a.g.x0 + ((double)gx + 0.5) * s;
-  const double cy = a.g.y0 + ((double)gy + 0.5) * s;
   const int p = a.p;
-  if (tid < p) {
-    const double *lb = a.loc + 2 * b * p;
-    sloc[tid] = {lb[2 * tid], lb[2 * tid + 1]};
-  }
+  constexpr int RPC = kWave * R;
 
-  auto stage = [&](int32_t base, int32_t cnt) {
-    for (int32_t t = tid; t < cnt; t += kThreads) {
-      int32_t k = base + t;
-      int32_t gi;
-      if (k < rn[0]) {
-        gi = rs[0] + k;
-      } else if (k < rn[0] + rn[1]) {
-        gi = rs[1] + (k - rn[0]);
-      } else {
-        gi = rs[2] + (k - rn[0] - rn[1]);
-      }
-      st.x[t] = a.sxy[2 * (int64_t)gi];
-      st.y[t] = a.sxy[2 * (int64_t)gi + 1];
-      st.m[t] = (real)a.sm[gi];
-    }
-  };
+  for (uint32_t u = vb; u < nunits; u += G) {
+    const uint32_t b = CH == 1 ? u : u / CH;
+    const uint32_t c0 = u - b * CH;
+    const uint32_t byw = b / nbx, bxw = b - byw * nbx;
+    const int64_t gx = a.win.bx0 + bxw, gy = a.win.by0 + byw;
 
-  const bool single = nn <= kStarTile;
-  if (single) stage(0, nn);
-  __syncthreads();
-
-  for (int64_t c = c0; c * RPC < nr; c += CH) {
-    double rx[R], ry[R];
-    real ax[R], ay[R];
-    bool act[R];
-    int64_t oidx[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t idx = c * RPC + (int64_t)r * kThreads + tid;
-      act[r] = idx < nr;
-      const int64_t id = act[r] ? idx : 0;
-      if (GRID) {
-        const int64_t i = i0 + id % W, j = j0 + id / W;
-        rx[r] = grid_coord(a.grid.x0, a.grid.dx, i);
-        ry[r] = grid_coord(a.grid.y0, a.grid.dy, j);
-        oidx[r] = j * a.grid.nx + i;
-      } else {
-        rx[r] = a.rxy[2 * (r0 + id)];
-        ry[r] = a.rxy[2 * (r0 + id) + 1];
-        oidx[r] = a.rperm ? (int64_t)a.rperm[r0 + id] : r0 + id;
-      }
-      ax[r] = 0;
-      ay[r] = 0;
-    }
-
-    auto accumulate = [&](int32_t cnt) {
-      for (int32_t k = 0; k < cnt; ++k) {
-        const double sx = st.x[k], sy = st.y[k];
-        const real m = st.m[k];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (MIXED) {
-            const float dx = (float)(rx[r] - sx);
-            const float dy = (float)(ry[r] - sy);
-            const float r2 = fmaf(dx, dx, dy * dy);
-            const float w = r2 > 0.f ? (float)m * rcp_f32(r2) : 0.f;
-            ax[r] = fmaf(w, dx, (float)ax[r]);
-            ay[r] = fmaf(w, dy, (float)ay[r]);
-          } else {
-            const double dx = rx[r] - sx;
-            const double dy = ry[r] - sy;
-            const double r2 = fma(dx, dx, dy * dy);
-            const double w = r2 > 0.0 ? (double)m * rcp_f64(r2) : 0.0;
-            ax[r] = fma(w, dx, (double)ax[r]);
-            ay[r] = fma(w, dy, (double)ay[r]);
-          }
-        }
-      }
-    };
-
-    if (single) {
-      accumulate(nn);
+    int32_t nr, i0 = 0, j0 = 0, W = 1, r0 = 0;
+    if (GRID) {
+      i0 = col_start[bxw];
+      W = col_start[bxw + 1] - i0;
+      j0 = row_start[byw];
+      nr = W * (row_start[byw + 1] - j0);
     } else {
-      for (int32_t base = 0; base < nn; base += kStarTile) {
-        const int32_t cnt = nn - base < kStarTile ? nn - base : kStarTile;
-        __syncthreads();
-        stage(base, cnt);
-        __syncthreads();
-        accumulate(cnt);
+      r0 = ray_start[b];
+      nr = ray_start[b + 1] - r0;
+    }
+    if (nr == 0 || (int64_t)c0 * (GRID ? (nr + (int64_t)CH - 1) / (int64_t)CH : RPC) >= nr)
+      continue;  // uniform
+
+    int32_t rs[3], re[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t row = gy - 1 + d;
+      rs[d] = 0;
+      re[d] = 0;
+      if (row >= 0 && row < nL) {
+        const int64_t cx0 = gx > 0 ? gx - 1 : 0;
+        const int64_t cx1 = gx + 1 < nL ? gx + 1 : nL - 1;
+        rs[d] = leaf_start[row * nL + cx0];
+        re[d] = leaf_start[row * nL + cx1 + 1];
       }
     }
+    const double cx = a.g.x0 + ((double)gx + 0.5) * s;
+    const double cy = a.g.y0 + ((double)gy + 0.5) * s;
+    cplx lc[PMAX];
+    const double *lb = loc + 2 * (int64_t)b * p;
+#pragma unroll
+    for (int l = 0; l < PMAX; ++l) lc[l] = (l < p) ? cplx{lb[2 * l], lb[2 * l + 1]} : cplx{0.0, 0.0};
+
+    // grid rays: the box's rays split evenly over its CH units; explicit rays:
+    // chunks of RPC rays, a box's extra chunks looped over by its units.  A
+    // chunk longer than RPC is processed RPC rays at a time.
+    const int32_t csz = GRID ? (int32_t)((nr + (int32_t)CH - 1) / (int32_t)CH) : RPC;
+    for (uint32_t c = c0; (int64_t)c * csz < nr; c += CH)
+    for (int32_t base = (int32_t)c * csz, cend = min(nr, base + csz); base < cend; base += RPC) {
+      double rx[R], ry[R];
+      using acc_t = typename std::conditional<MIXED, float, double>::type;
+      acc_t ax[R], ay[R];
+      int64_t oidx[R];
+      bool act[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int32_t idx = base + r * kWave + lane;
+        act[r] = idx < cend;
+        const int32_t id = act[r] ? idx : 0;
+        if (GRID) {
+          const int32_t q = id / W;
+          const int64_t i = i0 + (id - q * W), j = j0 + q;
+          rx[r] = grid_coord(a.grid.x0, a.grid.dx, i);
+          ry[r] = grid_coord(a.grid.y0, a.grid.dy, j);
+          oidx[r] = j * a.grid.nx + i;
+        } else {
+          rx[r] = rxy[2 * ((int64_t)r0 + id)];
+          ry[r] = rxy[2 * ((int64_t)r0 + id) + 1];
+          oidx[r] = rperm ? (int64_t)rperm[r0 + id] : (int64_t)r0 + id;
+        }
+        ax[r] = 0;
+        ay[r] = 0;
+      }
 
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      // far field by Horner on the rescaled local expansion
-      const cplx w = {(rx[r] - cx) * inv_s, (ry[r] - cy) * inv_s};
-      cplx f = {0.0, 0.0};
+      for (int d = 0; d < 3; ++d) {
+        int32_t i = rs[d];
+        // four stars per step: their scalar loads issue together
+        for (; i + 4 <= re[d]; i += 4) {
+          double sx[4], sy[4], mm[4];
 #pragma unroll
-      for (int l = PMAX - 1; l >= 0; --l)
-        if (l < p) f = cmad(f, w, sloc[l]);
-      const double al1 = f.re + (double)ax[r];
-      const double al2 = (double)ay[r] - f.im;
-      const double y1 = a.c1 * rx[r] - al1;
-      const double y2 = a.c2 * ry[r] - al2;
-      if (!act[r]) continue;
-      if (MAP) {
-        const double t1 = (y1 - a.y1min) * a.S;
-        const double t2 = (y2 - a.y2min) * a.S;
-        if (t1 >= 0.0 && t2 >= 0.0) {
-          const double f1 = floor(t1), f2 = floor(t2);
-          if (f1 < (double)a.npix && f2 < (double)a.npix)
-            atomicAdd(&a.counts[(int64_t)f2 * a.npix + (int64_t)f1], 1);
+          for (int q = 0; q < 4; ++q) {
+            sx[q] = sxy[2 * (int64_t)(i + q)];
+            sy[q] = sxy[2 * (int64_t)(i + q) + 1];
+            mm[q] = sm[i + q];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) pair_update<MIXED, R>(rx, ry, sx[q], sy[q], mm[q], ax, ay);
         }
-      } else {
-        a.y_out[2 * oidx[r]] = y1;
-        a.y_out[2 * oidx[r] + 1] = y2;
+        for (; i < re[d]; ++i)
+          pair_update<MIXED, R>(rx, ry, sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i], ax, ay);
+      }
+
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const cplx w = {(rx[r] - cx) * inv_s, (ry[r] - cy) * inv_s};
+        cplx f = {0.0, 0.0};
+#pragma unroll
+        for (int l = PMAX - 1; l >= 0; --l)
+          if (l < p) f = cmad(f, w, lc[l]);
+        const double al1 = f.re + (double)ax[r];
+        const double al2 = (double)ay[r] - f.im;
+        const double y1 = a.c1 * rx[r] - al1;
+        const double y2 = a.c2 * ry[r] - al2;
+        if (!act[r]) continue;
+        if (MAP) {
+          const double t1 = (y1 - a.y1min) * a.S;
+          const double t2 = (y2 - a.y2min) * a.S;
+          if (t1 >= 0.0 && t2 >= 0.0) {
+            const double f1 = floor(t1), f2 = floor(t2);
+            if (f1 < (double)a.npix && f2 < (double)a.npix)
+              atomicAdd(&counts[(int64_t)f2 * a.npix + (int64_t)f1], 1);
+          }
+        } else {
+          *reinterpret_cast<double2 *>(y_out + 2 * oidx[r]) = make_double2(y1, y2);
+        }
       }
     }
   }
@@ -230,12 +243,26 @@ __global__ __launch_bounds__(kThreads) void k_ray_keys(const double *__restrict_
   vals[i] = (uint32_t)i;
 }
 
+constexpr int64_t kMaxEvalBlocks = 256 * 32 * 4;  // CUs x waves per CU x sweeps in flight
+
+template <int PM, bool MIXED, bool MAP, bool GRID, int R>
+void eval_launch_r(const EvalArgs &a, hipStream_t stream) {
+  const int64_t units = a.win.count() * a.chunks_per_box;
+  int64_t nblk = units < kMaxEvalBlocks ? units : kMaxEvalBlocks;
+  if (nblk > kXcd) nblk = nblk / kXcd * kXcd;
+  hipLaunchKernelGGL((k_eval<PM, MIXED, MAP, GRID, R>), dim3((unsigned)nblk), dim3(kWave), 0, stream,
+                     a, a.loc, a.sxy, a.sm, a.leaf_start, a.col_start, a.row_start, a.rxy, a.rperm,
+                     a.ray_start, a.y_out, a.counts);
+}
+
 template <int PM, bool MIXED, bool MAP, bool GRID>
 void eval_launch(const EvalArgs &a, hipStream_t stream) {
-  constexpr int R = 2;
-  const int64_t nblk = a.win.count() * a.chunks_per_box;
-  hipLaunchKernelGGL((k_eval<PM, MIXED, MAP, GRID, R>), dim3((unsigned)nblk), dim3(kThreads), 0,
-                     stream, a);
+  switch (a.rays_per_lane) {
+    case 1: eval_launch_r<PM, MIXED, MAP, GRID, 1>(a, stream); break;
+    case 2: eval_launch_r<PM, MIXED, MAP, GRID, 2>(a, stream); break;
+    case 3: eval_launch_r<PM, MIXED, MAP, GRID, 3>(a, stream); break;
+    default: eval_launch_r<PM, MIXED, MAP, GRID, 4>(a, stream); break;
+  }
 }
 
 template <int PM>
@@ -257,7 +284,23 @@ void eval_dispatch(const EvalArgs &a, int precision, hipStream_t stream) {
 
 }  // namespace
 
-int64_t eval_rays_per_chunk() { return (int64_t)kThreads * 2; }
+// Rays per lane R and units per box CH for boxes of at most max_rays rays:
+// the fewest lane slots 64*R*CH, ties going to the larger R (fewer units).
+void eval_shape(int64_t max_rays, int *R, int64_t *CH) {
+  int best_r = 1;
+  int64_t best_ch = 1, best_slots = -1;
+  for (int r = 1; r <= 4; ++r) {
+    const int64_t ch = (max_rays + kWave * r - 1) / (kWave * r);
+    const int64_t slots = ch * kWave * r;
+    if (best_slots < 0 || slots <= best_slots) {
+      best_slots = slots;
+      best_r = r;
+      best_ch = ch < 1 ? 1 : ch;
+    }
+  }
+  *R = best_r;
+  *CH = best_ch;
+}
 
 void launch_eval(const EvalArgs &a, int precision, hipStream_t stream) {
   if (a.win.count() == 0) return;

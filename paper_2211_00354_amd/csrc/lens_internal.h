@@ -71,7 +71,7 @@ struct Geometry {
 // A rectangle of boxes at one level: columns [bx0, bx0+nbx), rows [by0, by0+nby).
 struct Window {
   int64_t bx0, by0, nbx, nby;
-  int64_t count() const { return nbx * nby; }
+  __host__ __device__ int64_t count() const { return nbx * nby; }
 };
 
 // ------------------------------------------------------------ kernel launchers
@@ -107,6 +107,11 @@ struct OpTables {
   double *l2l = nullptr;   // [4][p][p] complex, L[q][j][l]
   double *m2l = nullptr;   // [49][p][p] complex, stored T[tau][k][l]
   float *m2l32 = nullptr;  // same in FP32
+  // M2L as MFMA B fragments: [49][ks][nt][64 lanes]
+  int ks = 0, nt = 0;
+  double *bfrag64 = nullptr;
+  float *bfrag32 = nullptr;
+  double *l2l_frag = nullptr;  // L2L as FP64 MFMA B fragments: [4][ks][nt][64]
 };
 const OpTables &op_tables(int p, hipStream_t stream);
 
@@ -114,12 +119,15 @@ const OpTables &op_tables(int p, hipStream_t stream);
 void build_m2m_table(int p, std::vector<double> &out);
 void build_l2l_table(int p, std::vector<double> &out);
 void build_m2l_table(int p, std::vector<double> &out);
+void build_m2l_bfrag(int p, std::vector<double> &out, int &ks_count, int &nt_count);
+void build_l2l_bfrag(int p, int ks_count, int nt_count, std::vector<double> &out);
 
 // Upward pass (upward.hip)
-void launch_p2m(Geometry g, const double *sxy, const double *sm, const int32_t *leaf_start, int p,
-                double *mp_leaf, hipStream_t stream);
-void launch_m2m(int level, int p, const double *child, double *parent, const double *m2m,
-                hipStream_t stream);
+// (mp32 outputs are optional FP32 copies of the same coefficients)
+void launch_p2m(Geometry g, int level, const double *sxy, const double *sm,
+                const int32_t *leaf_start, int p, double *mp, float *mp32, hipStream_t stream);
+void launch_m2m(int level, int p, const double *child, double *parent, float *parent32,
+                const double *m2m, hipStream_t stream);
 
 // Downward pass (downward.hip): local expansions of `win` at `level` from the
 // parent's locals (level >= 3) and the multipoles of the interaction list.
@@ -132,8 +140,31 @@ struct DownArgs {
   const double *ploc;    // parent locals [pwin][p] or nullptr (level 2)
   double *loc;           // output locals [win][p]
 };
-void launch_down_f64(const DownArgs &a, const OpTables &t, hipStream_t stream);
-void launch_down_f32(const DownArgs &a, const OpTables &t, hipStream_t stream);
+// loc += L2L(parent locals), FP64 (levels >= 3).
+void launch_l2l(const DownArgs &a, const OpTables &t, hipStream_t stream);
+
+// M2L of several levels in one launch: loc = (1/s) sum over the interaction
+// list (FP64 or FP32 arithmetic); runs on MFMA when the order's tile fits the
+// LDS budget, else on VALU (one launch per level).
+constexpr int kMaxBatchLevels = LENS_MAX_LEVEL + 1;
+struct M2LLevel {
+  int level;
+  double s;
+  Window win;
+  const void *mp;       // multipoles of the level, FP64 or FP32
+  double *loc;
+  const double *ploc;   // fused L2L: parent locals (window pwin), or nullptr
+  Window pwin;
+};
+struct M2LBatch {
+  int count = 0, p = 0;
+  M2LLevel lv[kMaxBatchLevels];
+  int64_t tile_begin[kMaxBatchLevels + 1];
+};
+void launch_m2l_batch(M2LBatch &b, const OpTables &t, bool fp32, hipStream_t stream);
+// One level with L2L fused: loc = (1/s) M2L + L2L(ploc), the L2L part on FP64
+// MFMA; returns false (nothing launched) if the order has no MFMA tile.
+bool launch_m2l_l2l(M2LBatch &b, const OpTables &t, bool fp32, hipStream_t stream);
 void launch_to_f32(const double *src, float *dst, size_t n, hipStream_t stream);
 
 // Evaluation (eval.hip): per leaf box of the window, local expansion at its
@@ -154,7 +185,8 @@ struct EvalArgs {
   const double *rxy;          // explicit, sorted by leaf box
   const uint32_t *rperm;      // explicit: sorted position -> caller index
   const int32_t *ray_start;   // explicit: [win.count() + 1]
-  int64_t chunks_per_box;
+  int64_t chunks_per_box;     // units (waves) per leaf box
+  int rays_per_lane;          // R: rays held per lane (1..4), 64*R rays per unit
   double c1, c2;              // (1 - kappa_s - gamma), (1 - kappa_s + gamma)
   double *y_out;              // [n][2] or nullptr
   // map
@@ -167,7 +199,7 @@ void launch_eval(const EvalArgs &a, int precision, hipStream_t stream);
 // (c = 0..nbx); row_start likewise over the rows [j_begin, j_end).
 void launch_grid_ranges(const lens_grid &grid, Geometry g, Window win, int64_t j_begin,
                         int64_t j_end, int32_t *col_start, int32_t *row_start, hipStream_t stream);
-int64_t eval_rays_per_chunk();
+void eval_shape(int64_t max_rays, int *R, int64_t *CH);
 void launch_ray_keys(const double *rxy, int64_t n, Geometry g, Window win, uint32_t *keys,
                      uint32_t *vals, hipStream_t stream);
 

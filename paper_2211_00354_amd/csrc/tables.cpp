@@ -112,6 +112,62 @@ void build_m2l_table(int p, std::vector<double> &out) {
     }
 }
 
+// M2L operators as MFMA B fragments.  The complex product b~_l += T[l][c] a~_c
+// is written as a real GEMM over interleaved (re, im) coefficients,
+// b[2l+o] += sum_{2c+i} B[2c+i][2l+o] a[2c+i], with
+//   B[2c][2l] = Re T,  B[2c+1][2l] = -Im T,  B[2c][2l+1] = Im T,  B[2c+1][2l+1] = Re T,
+// zero-padded to ks_count*4 rows and nt_count*16 columns.  For each offset t,
+// K-step ks and N-tile nt, the 64 values are stored in lane order of the
+// 16x16x4 MFMA B operand (lane l holds B[4 ks + l/16][16 nt + l%16]).
+// K-steps compiled for order p: the smallest of {2,4,6,8,10,12,16,20} >= p/2.
+int m2l_ksteps(int p) {
+  const int need = (p + 1) / 2;
+  for (int k : {2, 4, 6, 8, 10, 12, 16, 20})
+    if (k >= need) return k;
+  return 20;
+}
+
+void build_m2l_bfrag(int p, std::vector<double> &out, int &ks_count, int &nt_count) {
+  std::vector<double> T;
+  build_m2l_table(p, T);
+  ks_count = m2l_ksteps(p);
+  nt_count = (ks_count + 3) / 4;
+  out.assign((size_t)49 * ks_count * nt_count * 64, 0.0);
+  for (int t = 0; t < 49; ++t)
+    for (int ks = 0; ks < ks_count; ++ks)
+      for (int nt = 0; nt < nt_count; ++nt)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int k = 4 * ks + lane / 16, n = 16 * nt + lane % 16;
+          const int c = k / 2, pin = k % 2, l = n / 2, pout = n % 2;
+          if (c >= p || l >= p) continue;
+          const size_t o = (((size_t)t * p + c) * p + l) * 2;
+          const double tr = T[o], ti = T[o + 1];
+          const double v = pin == 0 ? (pout == 0 ? tr : ti) : (pout == 0 ? -ti : tr);
+          out[(((size_t)t * ks_count + ks) * nt_count + nt) * 64 + lane] = v;
+        }
+}
+
+// L2L operators as MFMA B fragments, one per child quadrant q, same layout
+// and padding as the M2L fragments: b'[2j+o] += sum_{2l+i} B[2l+i][2j+o] b[2l+i]
+// with the complex L[q][j][l] (zero for l < j) in real form.
+void build_l2l_bfrag(int p, int ks_count, int nt_count, std::vector<double> &out) {
+  std::vector<double> Lt;
+  build_l2l_table(p, Lt);
+  out.assign((size_t)4 * ks_count * nt_count * 64, 0.0);
+  for (int q = 0; q < 4; ++q)
+    for (int ks = 0; ks < ks_count; ++ks)
+      for (int nt = 0; nt < nt_count; ++nt)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int k = 4 * ks + lane / 16, n = 16 * nt + lane % 16;
+          const int l = k / 2, pin = k % 2, j = n / 2, pout = n % 2;
+          if (l >= p || j >= p || l < j) continue;
+          const size_t o = (((size_t)q * p + l) * p + j) * 2;
+          const double tr = Lt[o], ti = Lt[o + 1];
+          const double v = pin == 0 ? (pout == 0 ? tr : ti) : (pout == 0 ? -ti : tr);
+          out[(((size_t)q * ks_count + ks) * nt_count + nt) * 64 + lane] = v;
+        }
+}
+
 namespace {
 std::mutex g_tab_mu;
 std::map<std::pair<int, int>, OpTables> g_tabs;
@@ -144,6 +200,13 @@ const OpTables &op_tables(int p, hipStream_t stream) {
   t.m2l = upload(h);
   std::vector<float> hf(h.begin(), h.end());
   t.m2l32 = upload(hf);
+  std::vector<double> bf;
+  build_m2l_bfrag(p, bf, t.ks, t.nt);
+  t.bfrag64 = upload(bf);
+  std::vector<float> bf32(bf.begin(), bf.end());
+  t.bfrag32 = upload(bf32);
+  build_l2l_bfrag(p, t.ks, t.nt, bf);
+  t.l2l_frag = upload(bf);
   return g_tabs.emplace(key, t).first->second;  // device tables live until exit
 }
 

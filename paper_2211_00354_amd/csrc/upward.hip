@@ -1,7 +1,9 @@
 // Upward pass (Appendix A, upward passes 1 and 2): P2M forms the order-p
 // multipole of every leaf box from its stars; M2M shifts the four children's
-// multipoles to their parent's centre, level by level toward the root.
-// Both run in FP64 (they touch each star once and each box once).
+// multipoles to their parent's centre, level by level toward the root.  The
+// two levels above the leaves are also formed straight from the stars (a
+// star then enters three expansions), which replaces the two largest M2M
+// sweeps with passes over the stars.  Everything runs in FP64.
 //
 // Coefficients are box-size rescaled: a~_k = sum_{i in box} m_i w_i^k,
 // w_i = (z_i - c)/s, stored box-major as [box][p] complex (re, im).
@@ -13,81 +15,85 @@ namespace {
 
 constexpr int kThreads = 256;
 
-template <int PMAX>
-__global__ __launch_bounds__(kThreads) void k_p2m(Geometry g, const double *__restrict__ sxy,
+// P2M at `level` (<= L) straight from the stars: one thread per (box,
+// coefficient k), so consecutive threads write consecutive coefficients.  A
+// box at `level` covers 2^(L-level) rows of leaf boxes, each a contiguous
+// range of the sorted stars.  w^k by binary powering.
+__global__ __launch_bounds__(kThreads) void k_p2m(Geometry g, int level,
+                                                  const double *__restrict__ sxy,
                                                   const double *__restrict__ sm,
                                                   const int32_t *__restrict__ leaf_start, int p,
-                                                  double *__restrict__ mp) {
-  const int64_t nb = int64_t(1) << g.L;
-  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (b >= nb * nb) return;
+                                                  double *__restrict__ mp, float *__restrict__ mp32) {
+  const int64_t nb = int64_t(1) << level;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= nb * nb * p) return;
+  const int64_t b = idx / p;
+  const int k = (int)(idx - b * p);
   const int64_t ix = b % nb, iy = b / nb;
-  const double s = ldexp(g.side, -g.L);
+  const double s = ldexp(g.side, -level);
   const double inv_s = 1.0 / s;
   const double cx = g.x0 + ((double)ix + 0.5) * s;
   const double cy = g.y0 + ((double)iy + 0.5) * s;
-  cplx acc[PMAX];
-#pragma unroll
-  for (int k = 0; k < PMAX; ++k) acc[k] = {0.0, 0.0};
-  const int32_t i0 = leaf_start[b], i1 = leaf_start[b + 1];
-  for (int32_t i = i0; i < i1; ++i) {
-    const cplx w = {(sxy[2 * (int64_t)i] - cx) * inv_s, (sxy[2 * (int64_t)i + 1] - cy) * inv_s};
-    cplx pw = {sm[i], 0.0};
-#pragma unroll
-    for (int k = 0; k < PMAX; ++k) {
-      acc[k].re += pw.re;
-      acc[k].im += pw.im;
-      pw = cmul(pw, w);
+  const int sh = g.L - level;
+  const int64_t nL = int64_t(1) << g.L;
+  const int64_t span = int64_t(1) << sh;
+  cplx acc = {0.0, 0.0};
+  for (int64_t r = 0; r < span; ++r) {
+    const int64_t row = (iy << sh) + r;
+    const int32_t i0 = leaf_start[row * nL + (ix << sh)];
+    const int32_t i1 = leaf_start[row * nL + (ix << sh) + span];
+    for (int32_t i = i0; i < i1; ++i) {
+      const cplx w = {(sxy[2 * (int64_t)i] - cx) * inv_s, (sxy[2 * (int64_t)i + 1] - cy) * inv_s};
+      cplx pw = {1.0, 0.0}, base = w;
+      for (int e = k; e; e >>= 1) {
+        if (e & 1) pw = cmul(pw, base);
+        base = cmul(base, base);
+      }
+      const double m = sm[i];
+      acc.re = fma(m, pw.re, acc.re);
+      acc.im = fma(m, pw.im, acc.im);
     }
   }
-  double *out = mp + 2 * b * p;
-#pragma unroll
-  for (int k = 0; k < PMAX; ++k)
-    if (k < p) {
-      out[2 * k] = acc[k].re;
-      out[2 * k + 1] = acc[k].im;
-    }
+  mp[2 * idx] = acc.re;
+  mp[2 * idx + 1] = acc.im;
+  if (mp32) {
+    mp32[2 * idx] = (float)acc.re;
+    mp32[2 * idx + 1] = (float)acc.im;
+  }
 }
 
-// parent box (ix, iy) at `level`; child quadrant q = a + 2c is the child
-// (2ix + a, 2iy + c) at level + 1.  Table layout M[q][k][l] (complex).
-template <int PMAX>
+// One thread per (parent box at `level`, output coefficient l); child
+// quadrant q = a + 2c is the child (2ix + a, 2iy + c) at level + 1.  Table
+// layout M[q][k][l] (complex, zero for k > l).
 __global__ __launch_bounds__(kThreads) void k_m2m(int level, int p,
                                                   const double *__restrict__ child,
                                                   double *__restrict__ parent,
+                                                  float *__restrict__ parent32,
                                                   const double *__restrict__ tab) {
   const int64_t nb = int64_t(1) << level;
-  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (b >= nb * nb) return;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= nb * nb * p) return;
+  const int64_t b = idx / p;
+  const int l = (int)(idx - b * p);
   const int64_t ix = b % nb, iy = b / nb;
   const int64_t ncb = nb * 2;
-  cplx acc[PMAX];
-#pragma unroll
-  for (int l = 0; l < PMAX; ++l) acc[l] = {0.0, 0.0};
+  cplx acc = {0.0, 0.0};
   for (int q = 0; q < 4; ++q) {
     const int64_t cb = (2 * iy + (q >> 1)) * ncb + (2 * ix + (q & 1));
     const double *src = child + 2 * cb * p;
     const double *t = tab + (size_t)q * p * p * 2;
-#pragma unroll
-    for (int k = 0; k < PMAX; ++k) {
-      if (k < p) {
-        const cplx a = {src[2 * k], src[2 * k + 1]};
-#pragma unroll
-        for (int l = k; l < PMAX; ++l)
-          if (l < p) {
-            const cplx m = {t[((size_t)k * p + l) * 2], t[((size_t)k * p + l) * 2 + 1]};
-            acc[l] = cmad(m, a, acc[l]);
-          }
-      }
+    for (int k = 0; k <= l; ++k) {
+      const cplx a = {src[2 * k], src[2 * k + 1]};
+      const cplx m = {t[((size_t)k * p + l) * 2], t[((size_t)k * p + l) * 2 + 1]};
+      acc = cmad(m, a, acc);
     }
   }
-  double *out = parent + 2 * b * p;
-#pragma unroll
-  for (int l = 0; l < PMAX; ++l)
-    if (l < p) {
-      out[2 * l] = acc[l].re;
-      out[2 * l + 1] = acc[l].im;
-    }
+  parent[2 * idx] = acc.re;
+  parent[2 * idx + 1] = acc.im;
+  if (parent32) {
+    parent32[2 * idx] = (float)acc.re;
+    parent32[2 * idx + 1] = (float)acc.im;
+  }
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -95,19 +101,19 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 }  // namespace
 
 
-void launch_p2m(Geometry g, const double *sxy, const double *sm, const int32_t *leaf_start, int p,
-                double *mp_leaf, hipStream_t stream) {
-  const int64_t nb = int64_t(1) << g.L;
-  LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL(k_p2m<PM>, dim3(blocks_for(nb * nb)), dim3(kThreads), 0,
-                                           stream, g, sxy, sm, leaf_start, p, mp_leaf));
+void launch_p2m(Geometry g, int level, const double *sxy, const double *sm,
+                const int32_t *leaf_start, int p, double *mp, float *mp32, hipStream_t stream) {
+  const int64_t nb = int64_t(1) << level;
+  hipLaunchKernelGGL(k_p2m, dim3(blocks_for(nb * nb * p)), dim3(kThreads), 0, stream, g, level, sxy,
+                     sm, leaf_start, p, mp, mp32);
   LENS_HIP(hipGetLastError());
 }
 
-void launch_m2m(int level, int p, const double *child, double *parent, const double *m2m,
-                hipStream_t stream) {
+void launch_m2m(int level, int p, const double *child, double *parent, float *parent32,
+                const double *m2m, hipStream_t stream) {
   const int64_t nb = int64_t(1) << level;
-  LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL(k_m2m<PM>, dim3(blocks_for(nb * nb)), dim3(kThreads), 0,
-                                           stream, level, p, child, parent, m2m));
+  hipLaunchKernelGGL(k_m2m, dim3(blocks_for(nb * nb * p)), dim3(kThreads), 0, stream, level, p,
+                     child, parent, parent32, m2m);
   LENS_HIP(hipGetLastError());
 }
 

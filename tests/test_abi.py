@@ -120,5 +120,9 @@ def test_plan_create_rejects_bad_ray_box():
     f = _lib.LensField(n_stars=0)
     box = (ctypes.c_double * 4)(1.0, 0.0, 0.0, 1.0)   # x1max < x1min
     h = ctypes.c_void_p()
-    assert lib.lens_plan_create(ctypes.byref(f), box, None, None, ctypes.byref(h)) == _lib.LENS_EINVAL
-    assert lib.lens_plan_create(ctypes.byref(f), None, None, None, None) == _lib.LENS_EINVAL
+    assert lib.lens_plan_create(ctypes.byref(f), box, None, None, None,
+                                ctypes.byref(h)) == _lib.LENS_EINVAL
+    assert lib.lens_plan_create(ctypes.byref(f), None, None, None, None, None) == _lib.LENS_EINVAL
+    g = _lib.LensGrid(0.0, 0.0, -1.0, 1.0, 2, 2)
+    assert lib.lens_plan_create(ctypes.byref(f), None, ctypes.byref(g), None, None,
+                                ctypes.byref(h)) == _lib.LENS_EINVAL
