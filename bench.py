@@ -71,7 +71,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--leaf", type=int, default=0, help="leaf level (0 = tune over a few)")
+    ap.add_argument("--leaf", type=int, default=0, help="leaf level (0 = the library's choice)")
+    ap.add_argument("--tune", action="store_true", help="time leaf levels 9-11 and use the fastest")
     ap.add_argument("--p", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-direct", action="store_true", help="skip the FP64 direct comparator")
@@ -116,9 +117,10 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    # leaf-level choice (outside the timed region)
+    # leaf level: the library's cost model (leaf_level 0), or --leaf, or the
+    # fastest of a few with --tune (outside the timed region)
     leaf = args.leaf
-    if leaf == 0 and not args.profile_only:
+    if args.tune:
         best = None
         for L in (9, 10, 11):
             run(leaf=L)
@@ -127,9 +129,7 @@ def main():
             if best is None or t < best[0]:
                 best = (t, L)
         leaf = best[1]
-    elif leaf == 0:
-        leaf = 10
-    log(f"using leaf level {leaf}, p={args.p}")
+    log(f"leaf level {leaf or 'auto'}, p={args.p}")
 
     for _ in range(args.warmup):
         run(leaf=leaf)
@@ -143,12 +143,17 @@ def main():
     log(f"mixed FMM: {ms:.3f} ms/step ({wall:.2f} s wall for {args.steps} steps); stages {prof}")
     if args.profile_only:
         if args.calib_copy_mib:
+            # known-size reference kernels for the FETCH_SIZE / WRITE_SIZE
+            # counters: two fills write 2 x N bytes; the second evicts the
+            # first from the 256 MB Infinity Cache; the sum then reads N bytes
             n = args.calib_copy_mib * (1 << 20) // 4
-            src = torch.ones(n, dtype=torch.float32, device="cuda")
-            dst = torch.empty_like(src)
-            dst.copy_(src)
+            a = torch.ones(n, dtype=torch.float32, device="cuda")
+            b = torch.ones(n, dtype=torch.float32, device="cuda")
             torch.cuda.synchronize()
-            log(f"calibration copy: {args.calib_copy_mib} MiB read + written")
+            a.sum().item()
+            del a, b
+            log(f"calibration: 2 fills of {args.calib_copy_mib} MiB, one sum over "
+                f"{args.calib_copy_mib} MiB")
         return
 
     value = n_rays / (ms * 1e-3)
@@ -161,6 +166,7 @@ def main():
     plan = lf.Plan(xy, m, grid=grid, precision="mixed", p=args.p, leaf_level=leaf)
     info = plan.info()
     plan.close()
+    leaf = info["leaf_level"]
     pairs = near_pairs(info, f, g)
     flops = PAIR_FLOPS * pairs + (8 * args.p + 2) * n_rays
     ev_ms, ev_n = prof.get("eval", (float("nan"), 1))
