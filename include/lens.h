@@ -175,6 +175,25 @@ LENS_API void lens_profile_enable(int32_t on);
 LENS_API int32_t lens_profile_read(int32_t cap, const char **names, double *total_ms,
                                    int64_t *launches);
 
+/*
+ * Adjoint of lens_deflect with respect to the lenses: given
+ * grad_y[k][2] = dL/dy_k for the rays of `grid` (rays_xy NULL) or of
+ * rays_xy[n_rays][2] (grid NULL), writes
+ *     grad_xy[i][2] = dL/d(x_i),  grad_m[i] = dL/dm_i      (FP64, device)
+ * for every star of `field` (kappa_s and gamma do not enter).  With
+ * g_k = dL/dy1_k + i dL/dy2_k and h(z) = sum_k g_k / (z - z_k):
+ * dL/dm_i = Re h(z_i) and dL/dx_i + i dL/dy_i = m_i conj(h'(z_i)), from
+ * differentiating eq. 1.  LENS_FMM evaluates h and h' by the fast multipole
+ * method with the rays as sources (complex charges) and the stars as
+ * targets; LENS_DIRECT sums them directly in FP64.  A ray exactly on a star
+ * is skipped, as in the forward map.  Waits on `stream` to read back the
+ * bounding boxes of the stars and the rays (FMM).
+ */
+LENS_API lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid,
+                                           const double *rays_xy, int64_t n_rays,
+                                           const double *grad_y, double *grad_xy, double *grad_m,
+                                           const lens_opts *opts, void *stream);
+
 /* Thread-local text for the last status other than LENS_OK (host string). */
 LENS_API const char *lens_last_error(void);
 

@@ -19,7 +19,8 @@ from . import _lib
 from ._lib import (LENS_DIRECT, LENS_FMM, LENS_FP64, LENS_MIXED, LensError, LensField, LensGrid,
                    LensMapDesc, LensOpts)
 
-__all__ = ["Grid", "MapDesc", "Plan", "deflect", "irs_map", "LensError", "version"]
+__all__ = ["Grid", "MapDesc", "Plan", "deflect", "deflect_backward", "irs_map", "LensDeflect",
+           "LensError", "version"]
 
 
 @dataclass
@@ -201,3 +202,74 @@ def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
     _lib.check(lib.lens_map(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
                             ctypes.byref(md), ctypes.byref(o), _stream()))
     return counts
+
+
+def deflect_backward(star_xy, star_m, grad_y, grid: Optional[Grid] = None, rays=None,
+                     method="fmm", precision="mixed", p=12, leaf_level=0):
+    """Gradient of a loss with respect to the lenses: given grad_y = dL/dy
+    [n, 2] for the rays of ``grid`` or ``rays``, returns (dL/d star_xy [N, 2],
+    dL/d star_m [N]) as float64 GPU tensors."""
+    torch = _torch()
+    lib = _lib.load()
+    if (grid is None) == (rays is None):
+        raise ValueError("give exactly one of grid and rays")
+    f = _field(star_xy, star_m, 0.0, 0.0)
+    if grid is not None:
+        n = int(grid.nx) * int(grid.ny)
+        g = grid.c()
+        gp, rp = ctypes.byref(g), None
+    else:
+        _check_tensor(rays, "rays", 2)
+        n = rays.numel() // 2
+        gp, rp = None, rays.data_ptr() if n else None
+    _check_tensor(grad_y, "grad_y", 2)
+    if grad_y.numel() != 2 * n:
+        raise ValueError("grad_y must be [n, 2]")
+    dev = torch.device("cuda", torch.cuda.current_device())
+    gxy = torch.empty((f.n_stars, 2), dtype=torch.float64, device=dev)
+    gm = torch.empty((f.n_stars,), dtype=torch.float64, device=dev)
+    o = _opts(method, precision, p, leaf_level)
+    _lib.check(lib.lens_deflect_backward(ctypes.byref(f), gp, rp, n,
+                                         grad_y.data_ptr() if n else None,
+                                         gxy.data_ptr() if f.n_stars else None,
+                                         gm.data_ptr() if f.n_stars else None, ctypes.byref(o),
+                                         _stream()))
+    return gxy, gm
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class LensDeflect(torch.autograd.Function):
+        """y = lens map of the rays (eq. 1 + smooth term) as a differentiable
+        function of the star positions and masses.  Rays are a Grid (pass it
+        as ``grid``) or a tensor (``rays``, treated as a constant)."""
+
+        @staticmethod
+        def forward(ctx, star_xy, star_m, rays=None, grid=None, kappa_s=0.0, gamma=0.0,
+                    method="fmm", precision="mixed", p=12, leaf_level=0):
+            y = deflect(star_xy, star_m, grid=grid, rays=rays, kappa_s=kappa_s, gamma=gamma,
+                        method=method, precision=precision, p=p, leaf_level=leaf_level)
+            ctx.save_for_backward(star_xy, star_m, rays if rays is not None else star_m)
+            ctx.has_rays = rays is not None
+            ctx.cfg = (grid, method, precision, p, leaf_level)
+            return y
+
+        @staticmethod
+        def backward(ctx, grad_y):
+            star_xy, star_m, rays = ctx.saved_tensors
+            grid, method, precision, p, leaf_level = ctx.cfg
+            gxy, gm = deflect_backward(star_xy, star_m, grad_y.contiguous(), grid=grid,
+                                       rays=rays if ctx.has_rays else None, method=method,
+                                       precision=precision, p=p, leaf_level=leaf_level)
+            return gxy, gm, None, None, None, None, None, None, None, None
+
+    return LensDeflect
+
+
+def __getattr__(name):
+    if name == "LensDeflect":
+        fn = _autograd_function()
+        globals()["LensDeflect"] = fn
+        return fn
+    raise AttributeError(name)

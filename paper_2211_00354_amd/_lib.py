@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH):
     lib.lens_last_error.restype = ctypes.c_char_p
     lib.lens_version.argtypes = []
     lib.lens_version.restype = ctypes.c_char_p
+    lib.lens_deflect_backward.argtypes = [P(LensField), P(LensGrid), V, I64, V, V, V, P(LensOpts), V]
+    lib.lens_deflect_backward.restype = ctypes.c_int
     lib.lens_profile_enable.argtypes = [I32]
     lib.lens_profile_enable.restype = None
     lib.lens_profile_read.argtypes = [I32, P(ctypes.c_char_p), P(D), P(I64)]

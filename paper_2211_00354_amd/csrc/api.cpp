@@ -24,6 +24,7 @@ struct lens_plan {
   int p = 12;
   int precision = LENS_MIXED;
   int fine_levels = 2;  // LENS_MIXED: levels L-fine_levels+1 .. L run M2L in FP32
+  int qdim = 1;         // charge components per source: 1 (masses) or 2 (complex)
   Geometry g{};
   int64_t n_stars = 0;
   double kappa_s = 0, gamma = 0;
@@ -214,9 +215,13 @@ Window window_for(const lens_plan &P, int level, const double bb[4]) {
   return Window{x0, y0, x1 - x0 + 1, y1 - y0 + 1};
 }
 
+// Sources are f.xy with charges f.m (real), or, if qc is given, the complex
+// charges qc[n][2] (the adjoint's rays).
 lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_grid *align,
-                      double rays_density, const lens_opts &o, hipStream_t st) {
+                      double rays_density, const lens_opts &o, hipStream_t st,
+                      const double *qc = nullptr) {
   auto *P = new lens_plan();
+  P->qdim = qc ? 2 : 1;
   try {
     LENS_HIP(hipGetDevice(&P->device));
     P->p = o.order_p;
@@ -266,7 +271,7 @@ lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_gri
     P->mp.resize(L + 1);
     P->leaf_start = pool_get((size_t)(nbox + 1) * sizeof(int32_t), st);
     P->sxy = pool_get((size_t)std::max<int64_t>(N, 1) * 16, st);
-    P->sm = pool_get((size_t)std::max<int64_t>(N, 1) * 8, st);
+    P->sm = pool_get((size_t)std::max<int64_t>(N, 1) * 8 * P->qdim, st);
     for (int l = 2; l <= L; ++l) {
       const int64_t nb = int64_t(1) << (2 * l);
       P->mp[l] = pool_get((size_t)nb * P->p * 16, st);
@@ -287,7 +292,7 @@ lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_gri
         launch_leaf_keys(f.xy, N, P->g, k, v, st);
         const bool in_tmp = radix_sort_pairs(k, v, kt, vt, N, 2 * L, cnt, stmp, st);
         const uint32_t *ks = in_tmp ? kt : k, *vs = in_tmp ? vt : v;
-        launch_gather_stars(vs, f.xy, f.m, N, sxy, sm, st);
+        launch_gather_stars(vs, f.xy, qc ? qc : f.m, P->qdim, N, sxy, sm, st);
         launch_box_starts(ks, N, nbox, leaf_start, st);
       } else {
         LENS_HIP(hipMemsetAsync(leaf_start, 0, (size_t)(nbox + 1) * sizeof(int32_t), st));
@@ -308,7 +313,7 @@ lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_gri
       for (int l = L; l >= 2; --l) {
         double *out = static_cast<double *>(P->mp[l].ptr);
         if (l > L - direct_levels)
-          launch_p2m(P->g, l, sxy, sm, leaf_start, P->p, out, f32_at(l), st);
+          launch_p2m(P->g, l, sxy, sm, P->qdim, leaf_start, P->p, out, f32_at(l), st);
         else
           launch_m2m(l, P->p, P->mp_at(l + 1), out, f32_at(l), T.m2m, st);
       }
@@ -745,6 +750,89 @@ lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *
       throw;
     }
     if (owned) release_owned(owned, st);
+  });
+}
+
+lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid,
+                                  const double *rays_xy, int64_t n_rays, const double *grad_y,
+                                  double *grad_xy, double *grad_m, const lens_opts *opts,
+                                  void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    const lens_opts o = resolve_opts(opts);
+    check_field(field);
+    if ((grid == nullptr) == (rays_xy == nullptr) && !(grid == nullptr && n_rays == 0))
+      fail(LENS_EINVAL, "give exactly one of grid and rays_xy");
+    if (n_rays < 0) fail(LENS_EINVAL, "n_rays < 0");
+    if (grid) {
+      check_grid(grid);
+      if (n_rays != grid->nx * grid->ny) fail(LENS_EINVAL, "n_rays must equal grid.nx * grid.ny");
+    }
+    if (n_rays > (int64_t)std::numeric_limits<int32_t>::max())
+      fail(LENS_EINVAL, "n_rays exceeds 2^31-1");
+    const int64_t N = field->n_stars;
+    if (N == 0) return;
+    if (!grad_xy || !grad_m) fail(LENS_EINVAL, "grad_xy / grad_m is NULL");
+    if (n_rays > 0 && !grad_y) fail(LENS_EINVAL, "grad_y is NULL");
+    if (n_rays == 0) {
+      LENS_HIP(hipMemsetAsync(grad_xy, 0, (size_t)N * 16, st));
+      LENS_HIP(hipMemsetAsync(grad_m, 0, (size_t)N * 8, st));
+      return;
+    }
+    Scratch sc(st);
+    const double *rays = rays_xy;
+    if (grid) {
+      double *r = sc.get<double>((size_t)n_rays * 2);
+      launch_grid_rays(*grid, r, st);
+      rays = r;
+    }
+    if (o.method == LENS_DIRECT) {
+      StageTimer tm("direct_adjoint", st);
+      launch_direct_adj(N, field->xy, field->m, n_rays, rays, grad_y, grad_xy, grad_m, st);
+      return;
+    }
+    // sources: the rays with complex charges g_k; targets: the stars
+    double tb[4];
+    device_bbox(field->xy, N, st, tb);
+    const double area = std::max((tb[2] - tb[0]) * (tb[3] - tb[1]), 1e-300);
+    lens_field src{n_rays, rays, nullptr, 0.0, 0.0};
+    lens_plan *P = build_plan(src, tb, nullptr, (double)N / area, o, st, grad_y);
+    try {
+      double *loc = nullptr;
+      const Window wl = downward(*P, tb, sc, st, &loc);
+      uint32_t *k = sc.get<uint32_t>(N), *v = sc.get<uint32_t>(N);
+      uint32_t *kt = sc.get<uint32_t>(N), *vt = sc.get<uint32_t>(N);
+      const size_t ncnt = radix_counts_len(N);
+      uint32_t *cnt = sc.get<uint32_t>(ncnt);
+      uint32_t *stmp = sc.get<uint32_t>(scan_tmp_len(ncnt));
+      double *txy = sc.get<double>((size_t)N * 2), *tm = sc.get<double>((size_t)N);
+      int32_t *tstart = sc.get<int32_t>(wl.count() + 1);
+      {
+        StageTimer tmr("adjoint_targets", st);
+        launch_ray_keys(field->xy, N, P->g, wl, k, v, st);
+        int bits = 1;
+        while ((int64_t(1) << bits) < wl.count()) ++bits;
+        const bool in_tmp = radix_sort_pairs(k, v, kt, vt, N, bits, cnt, stmp, st);
+        const uint32_t *ks = in_tmp ? kt : k;
+        v = in_tmp ? vt : v;
+        launch_gather_stars(v, field->xy, field->m, 1, N, txy, tm, st);
+        launch_box_starts(ks, N, wl.count(), tstart, st);
+      }
+      EvalArgs ea{};
+      fill_star_side(*P, wl, loc, ea);
+      const int64_t per = (N + wl.count() - 1) / std::max<int64_t>(wl.count(), 1);
+      ea.chunks_per_box =
+          std::max<int64_t>(1, (per + adj_targets_per_unit() - 1) / adj_targets_per_unit());
+      while (wl.count() * ea.chunks_per_box > (int64_t)0x7fffffff && ea.chunks_per_box > 1)
+        ea.chunks_per_box = (ea.chunks_per_box + 1) / 2;
+      AdjArgs d{static_cast<const double *>(P->sm.ptr), txy, tm, v, tstart, grad_xy, grad_m};
+      StageTimer tme("eval_adjoint", st);
+      launch_eval_adj(ea, d, P->precision, st);
+    } catch (...) {
+      lens_plan_destroy(P);
+      throw;
+    }
+    release_owned(P, st);
   });
 }
 

@@ -92,8 +92,10 @@ size_t radix_counts_len(int64_t n);
 size_t scan_tmp_len(size_t n);
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp,
                         hipStream_t stream);
-void launch_gather_stars(const uint32_t *perm, const double *xy, const double *m, int64_t n,
-                         double *sxy, double *sm, hipStream_t stream);
+// sources (stars, or rays with complex charges) sorted by leaf box:
+// positions [n][2] and charges [n][qdim] (qdim 1: real masses; 2: complex)
+void launch_gather_stars(const uint32_t *perm, const double *xy, const double *q, int qdim,
+                         int64_t n, double *sxy, double *sq, hipStream_t stream);
 void launch_gather_rays(const uint32_t *perm, const double *xy, int64_t n, double *sxy,
                         hipStream_t stream);
 // start[b] = first sorted index with key >= b, for b in [0, nbox]
@@ -124,7 +126,7 @@ void build_l2l_bfrag(int p, int ks_count, int nt_count, std::vector<double> &out
 
 // Upward pass (upward.hip)
 // (mp32 outputs are optional FP32 copies of the same coefficients)
-void launch_p2m(Geometry g, int level, const double *sxy, const double *sm,
+void launch_p2m(Geometry g, int level, const double *sxy, const double *sq, int qdim,
                 const int32_t *leaf_start, int p, double *mp, float *mp32, hipStream_t stream);
 void launch_m2m(int level, int p, const double *child, double *parent, float *parent32,
                 const double *m2m, hipStream_t stream);
@@ -202,6 +204,23 @@ void launch_grid_ranges(const lens_grid &grid, Geometry g, Window win, int64_t j
 void eval_shape(int64_t max_rays, int *R, int64_t *CH);
 void launch_ray_keys(const double *rxy, int64_t n, Geometry g, Window win, uint32_t *keys,
                      uint32_t *vals, hipStream_t stream);
+
+// Adjoint (adjoint.hip): gradients at stars from rays with complex charges
+struct AdjArgs {
+  const double *sq;       // sorted source charges [n][2] (complex g_k)
+  const double *txy;      // targets (stars) sorted by window box
+  const double *tm;       // their masses
+  const uint32_t *tperm;  // sorted position -> caller's star index
+  const int32_t *tstart;  // [win.count() + 1]
+  double *grad_xy;        // [N][2]
+  double *grad_m;         // [N]
+};
+void launch_eval_adj(const EvalArgs &a, const AdjArgs &d, int precision, hipStream_t stream);
+void launch_direct_adj(int64_t n_stars, const double *star_xy, const double *star_m, int64_t n_rays,
+                       const double *rays_xy, const double *grad_y, double *grad_xy,
+                       double *grad_m, hipStream_t stream);
+void launch_grid_rays(const lens_grid &g, double *out, hipStream_t stream);
+int64_t adj_targets_per_unit();
 
 // Direct FP64 sum (direct.hip)
 struct DirectArgs {

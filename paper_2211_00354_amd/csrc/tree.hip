@@ -254,17 +254,18 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 
 // ----------------------------------------------------------------- gathers
 
+// sources sorted by leaf box: positions and qdim charge components each
 __global__ __launch_bounds__(kThreads) void k_gather_stars(const uint32_t *__restrict__ perm,
                                                            const double *__restrict__ xy,
-                                                           const double *__restrict__ m, int64_t n,
-                                                           double *__restrict__ sxy,
-                                                           double *__restrict__ sm) {
+                                                           const double *__restrict__ q, int qdim,
+                                                           int64_t n, double *__restrict__ sxy,
+                                                           double *__restrict__ sq) {
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (j >= n) return;
-  const uint32_t i = perm[j];
-  sxy[2 * j] = xy[2 * (int64_t)i];
-  sxy[2 * j + 1] = xy[2 * (int64_t)i + 1];
-  sm[j] = m[i];
+  const int64_t i = perm[j];
+  sxy[2 * j] = xy[2 * i];
+  sxy[2 * j + 1] = xy[2 * i + 1];
+  for (int c = 0; c < qdim; ++c) sq[qdim * j + c] = q[qdim * i + c];
 }
 
 __global__ __launch_bounds__(kThreads) void k_gather_rays(const uint32_t *__restrict__ perm,
@@ -359,11 +360,11 @@ bool radix_sort_pairs(uint32_t *k, uint32_t *v, uint32_t *k_tmp, uint32_t *v_tmp
   return in_tmp;
 }
 
-void launch_gather_stars(const uint32_t *perm, const double *xy, const double *m, int64_t n,
-                         double *sxy, double *sm, hipStream_t stream) {
+void launch_gather_stars(const uint32_t *perm, const double *xy, const double *q, int qdim,
+                         int64_t n, double *sxy, double *sq, hipStream_t stream) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_gather_stars, dim3(blocks_for(n)), dim3(kThreads), 0, stream, perm, xy, m, n,
-                     sxy, sm);
+  hipLaunchKernelGGL(k_gather_stars, dim3(blocks_for(n)), dim3(kThreads), 0, stream, perm, xy, q,
+                     qdim, n, sxy, sq);
   LENS_HIP(hipGetLastError());
 }
 

@@ -1,5 +1,6 @@
 // Upward pass (Appendix A, upward passes 1 and 2): P2M forms the order-p
-// multipole of every leaf box from its stars; M2M shifts the four children's
+// multipole of every leaf box from its sources (stars with real masses, or
+// rays with complex charges for the adjoint); M2M shifts the four children's
 // multipoles to their parent's centre, level by level toward the root.  The
 // two levels above the leaves are also formed straight from the stars (a
 // star then enters three expansions), which replaces the two largest M2M
@@ -19,9 +20,10 @@ constexpr int kThreads = 256;
 // coefficient k), so consecutive threads write consecutive coefficients.  A
 // box at `level` covers 2^(L-level) rows of leaf boxes, each a contiguous
 // range of the sorted stars.  w^k by binary powering.
+template <int QDIM>
 __global__ __launch_bounds__(kThreads) void k_p2m(Geometry g, int level,
                                                   const double *__restrict__ sxy,
-                                                  const double *__restrict__ sm,
+                                                  const double *__restrict__ sq,
                                                   const int32_t *__restrict__ leaf_start, int p,
                                                   double *__restrict__ mp, float *__restrict__ mp32) {
   const int64_t nb = int64_t(1) << level;
@@ -49,9 +51,13 @@ __global__ __launch_bounds__(kThreads) void k_p2m(Geometry g, int level,
         if (e & 1) pw = cmul(pw, base);
         base = cmul(base, base);
       }
-      const double m = sm[i];
-      acc.re = fma(m, pw.re, acc.re);
-      acc.im = fma(m, pw.im, acc.im);
+      if (QDIM == 1) {
+        const double m = sq[i];
+        acc.re = fma(m, pw.re, acc.re);
+        acc.im = fma(m, pw.im, acc.im);
+      } else {
+        acc = cmad(cplx{sq[2 * (int64_t)i], sq[2 * (int64_t)i + 1]}, pw, acc);
+      }
     }
   }
   mp[2 * idx] = acc.re;
@@ -101,11 +107,15 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 }  // namespace
 
 
-void launch_p2m(Geometry g, int level, const double *sxy, const double *sm,
+void launch_p2m(Geometry g, int level, const double *sxy, const double *sq, int qdim,
                 const int32_t *leaf_start, int p, double *mp, float *mp32, hipStream_t stream) {
   const int64_t nb = int64_t(1) << level;
-  hipLaunchKernelGGL(k_p2m, dim3(blocks_for(nb * nb * p)), dim3(kThreads), 0, stream, g, level, sxy,
-                     sm, leaf_start, p, mp, mp32);
+  if (qdim == 2)
+    hipLaunchKernelGGL(k_p2m<2>, dim3(blocks_for(nb * nb * p)), dim3(kThreads), 0, stream, g, level,
+                       sxy, sq, leaf_start, p, mp, mp32);
+  else
+    hipLaunchKernelGGL(k_p2m<1>, dim3(blocks_for(nb * nb * p)), dim3(kThreads), 0, stream, g, level,
+                       sxy, sq, leaf_start, p, mp, mp32);
   LENS_HIP(hipGetLastError());
 }
 

@@ -286,3 +286,94 @@ def test_config2_full_size_sampled(lf):
     err = rel_l2(ys, yo, ao)
     print("config2 full mixed rel l2", err)
     assert err <= 1e-5
+
+
+# ------------------------------------------------------------------- adjoint
+
+def _adjoint_case(n_clusters=40, per=25, n_rays=20000, seed=55):
+    f, rays, tn = wl.config5(n_clusters=n_clusters, per_cluster=per, n_rays=n_rays, seed=seed)
+    f.m[:] = np.random.default_rng(seed + 1).uniform(0.5, 1.5, f.n)
+    yo, ao, _ = oracle.deflect(f.xy, f.m, rays)
+    t = yo + tn
+    G = 2 * (yo - t)                     # dL/dy of L = sum |y - t|^2 at the oracle's y
+    gxy, gm = oracle.grad(f.xy, f.m, rays, G)
+    return f, rays, G, gxy, gm
+
+
+def _grad_err(g, g_ref):
+    return float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
+
+
+def test_adjoint_direct_matches_oracle(lf):
+    f, rays, G, gxy, gm = _adjoint_case()
+    _say("adjoint direct")
+    a, b = lf.deflect_backward(dev_tensor(f.xy), dev_tensor(f.m), dev_tensor(G),
+                               rays=dev_tensor(rays), method="direct")
+    assert _grad_err(host(a), gxy) <= 1e-12
+    assert _grad_err(host(b), gm) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,p,tol", [("fp64", 24, 1e-9), ("fp64", 12, 1e-5), ("mixed", 12, 1e-5)])
+def test_adjoint_fmm_matches_oracle(lf, prec, p, tol):
+    f, rays, G, gxy, gm = _adjoint_case()
+    _say("adjoint fmm", prec, p)
+    a, b = lf.deflect_backward(dev_tensor(f.xy), dev_tensor(f.m), dev_tensor(G),
+                               rays=dev_tensor(rays), precision=prec, p=p)
+    ea, eb = _grad_err(host(a), gxy), _grad_err(host(b), gm)
+    print("adjoint", prec, p, "grad_xy", ea, "grad_m", eb)
+    assert ea <= tol and eb <= tol
+
+
+def test_adjoint_grid_rays_and_edge_cases(lf):
+    f = wl.random_field(300, 5.0, seed=61, masses="powerlaw")
+    g = wl.Grid(x0=-6.0, y0=-5.5, dx=0.05, dy=0.07, nx=211, ny=157)
+    rays = g.rays()
+    rays_on = rays.copy()
+    G = np.random.default_rng(62).standard_normal((g.n, 2))
+    gxy, gm = oracle.grad(f.xy, f.m, rays, G)
+    _say("adjoint grid")
+    for method, tol in (("direct", 1e-12), ("fmm", 1e-5)):
+        a, b = lf.deflect_backward(dev_tensor(f.xy), dev_tensor(f.m), dev_tensor(G),
+                                   grid=lfgrid(g), method=method, precision="fp64", p=16)
+        assert _grad_err(host(a), gxy) <= tol, method
+        assert _grad_err(host(b), gm) <= tol, method
+    # a star exactly on a ray: its pair is skipped on both sides
+    xy = f.xy.copy()
+    xy[0] = rays_on[1234]
+    gxy2, gm2 = oracle.grad(xy, f.m, rays, G)
+    a, b = lf.deflect_backward(dev_tensor(xy), dev_tensor(f.m), dev_tensor(G), grid=lfgrid(g),
+                               method="fmm", precision="fp64", p=20)
+    assert np.all(np.isfinite(host(a))) and _grad_err(host(a), gxy2) <= 1e-6
+    # no rays: zero gradients; no stars: empty outputs
+    a, b = lf.deflect_backward(dev_tensor(f.xy), dev_tensor(f.m), dev_tensor(np.zeros((0, 2))),
+                               rays=dev_tensor(np.zeros((0, 2))))
+    assert np.all(host(a) == 0) and np.all(host(b) == 0)
+
+
+def test_adjoint_invariants_and_autograd(lf):
+    import torch
+    f, rays, G, gxy, gm = _adjoint_case(n_clusters=20, per=10, n_rays=3000, seed=71)
+    xy = torch.tensor(f.xy, device="cuda", requires_grad=True)
+    m = torch.tensor(f.m, device="cuda", requires_grad=True)
+    r = dev_tensor(rays)
+    _say("adjoint autograd")
+    y = lf.LensDeflect.apply(xy, m, r, None, 0.0, 0.0, "fmm", "fp64", 24)
+    t = torch.tensor(oracle.deflect(f.xy, f.m, rays)[0] + 0.01, device="cuda")
+    loss = ((y - t) ** 2).sum()
+    loss.backward()
+    Gt = host(2 * (y.detach() - t))
+    gx_ref, gm_ref = oracle.grad(f.xy, f.m, rays, Gt)
+    assert _grad_err(host(xy.grad), gx_ref) <= 1e-8
+    assert _grad_err(host(m.grad), gm_ref) <= 1e-8
+    # mass homogeneity: sum m dL/dm = -sum G . alpha
+    _, al, _ = oracle.deflect(f.xy, f.m, rays)
+    lhs = float((f.m * host(m.grad)).sum())
+    rhs = -float((Gt * al).sum())
+    assert abs(lhs - rhs) <= 1e-8 * np.abs(Gt * al).sum()
+    # torch.autograd.gradcheck on a tiny FP64 direct case
+    xs = torch.tensor(np.random.default_rng(3).uniform(-1, 1, (4, 2)), device="cuda",
+                      requires_grad=True)
+    ms = torch.tensor([0.5, 1.0, 1.5, 0.7], dtype=torch.float64, device="cuda", requires_grad=True)
+    rs = dev_tensor(np.random.default_rng(4).uniform(-2, 2, (30, 2)))
+    fn = lambda a, b: lf.LensDeflect.apply(a, b, rs, None, 0.1, 0.2, "direct")
+    assert torch.autograd.gradcheck(fn, (xs, ms), eps=1e-6, atol=1e-6, rtol=1e-5)
