@@ -194,6 +194,27 @@ LENS_API lens_status lens_deflect_backward(const lens_field *field, const lens_g
                                            const double *grad_y, double *grad_xy, double *grad_m,
                                            const lens_opts *opts, void *stream);
 
+/*
+ * Inverse ray shooting for n_fields independent fields in one call: the rays
+ * of grids[i] lensed by fields[i] are added into maps[i] (see lens_map).
+ * fields, grids and maps are HOST arrays of n_fields structs (their data
+ * pointers are device pointers); one opts applies to every field (NULL =
+ * defaults; the leaf level is chosen per field).  All fields' work --
+ * tree builds, expansions, downward passes and binned evaluations -- is
+ * allocated up front and captured once as a HIP graph whose branches run
+ * the fields concurrently; the graph is cached (a few batches) by the
+ * arrays, sizes and parameters, and replayed by later calls while every
+ * field's stars stay inside its captured quadtree.  Waits on `stream` once
+ * per call, to read back the fields' bounding boxes.  Fields may differ in
+ * N_*, kappa_s, gamma, grid and map.
+ */
+LENS_API lens_status lens_map_batched(int32_t n_fields, const lens_field *fields,
+                                      const lens_grid *grids, const lens_map_desc *maps,
+                                      const lens_opts *opts, void *stream);
+
+/* Release the cached batch graphs and their device buffers (waits for them). */
+LENS_API void lens_release_cached(void);
+
 /* Thread-local text for the last status other than LENS_OK (host string). */
 LENS_API const char *lens_last_error(void);
 

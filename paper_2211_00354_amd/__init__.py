@@ -19,8 +19,8 @@ from . import _lib
 from ._lib import (LENS_DIRECT, LENS_FMM, LENS_FP64, LENS_MIXED, LensError, LensField, LensGrid,
                    LensMapDesc, LensOpts)
 
-__all__ = ["Grid", "MapDesc", "Plan", "deflect", "deflect_backward", "irs_map", "LensDeflect",
-           "LensError", "version"]
+__all__ = ["Grid", "MapDesc", "Plan", "deflect", "deflect_backward", "irs_map", "irs_map_batched",
+           "LensDeflect", "LensError", "release_cached", "version"]
 
 
 @dataclass
@@ -202,6 +202,40 @@ def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
     _lib.check(lib.lens_map(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
                             ctypes.byref(md), ctypes.byref(o), _stream()))
     return counts
+
+
+def irs_map_batched(fields, grids, maps, counts=None, method="fmm", precision="mixed", p=12,
+                    leaf_level=0):
+    """Inverse ray shooting for many independent fields in one captured HIP
+    graph.  ``fields`` is a list of (star_xy, star_m, kappa_s, gamma);
+    ``grids``/``maps`` lists of Grid/MapDesc; returns the list of int32 count
+    maps (accumulated into ``counts`` if given)."""
+    torch = _torch()
+    lib = _lib.load()
+    n = len(fields)
+    if not (len(grids) == len(maps) == n):
+        raise ValueError("fields, grids and maps must have the same length")
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if counts is None:
+        counts = [torch.zeros((mp.npix, mp.npix), dtype=torch.int32, device=dev) for mp in maps]
+    fa = (LensField * max(n, 1))()
+    ga = (LensGrid * max(n, 1))()
+    ma = (LensMapDesc * max(n, 1))()
+    for k, ((xy, m, ks, gm), g, mp, c) in enumerate(zip(fields, grids, maps, counts)):
+        fa[k] = _field(xy, m, ks, gm)
+        ga[k] = g.c()
+        if c.dtype != torch.int32 or not c.is_cuda or not c.is_contiguous() \
+                or c.shape != (mp.npix, mp.npix):
+            raise ValueError("counts must be contiguous int32 [npix, npix] GPU tensors")
+        ma[k] = LensMapDesc(mp.y1min, mp.y2min, mp.side, mp.npix, c.data_ptr())
+    o = _opts(method, precision, p, leaf_level)
+    _lib.check(lib.lens_map_batched(n, fa, ga, ma, ctypes.byref(o), _stream()))
+    return counts
+
+
+def release_cached():
+    """Free the cached batch graphs and their buffers."""
+    _lib.load().lens_release_cached()
 
 
 def deflect_backward(star_xy, star_m, grad_y, grid: Optional[Grid] = None, rays=None,

@@ -84,6 +84,10 @@ def load(path: str = LIB_PATH):
     lib.lens_version.restype = ctypes.c_char_p
     lib.lens_deflect_backward.argtypes = [P(LensField), P(LensGrid), V, I64, V, V, V, P(LensOpts), V]
     lib.lens_deflect_backward.restype = ctypes.c_int
+    lib.lens_map_batched.argtypes = [I32, P(LensField), P(LensGrid), P(LensMapDesc), P(LensOpts), V]
+    lib.lens_map_batched.restype = ctypes.c_int
+    lib.lens_release_cached.argtypes = []
+    lib.lens_release_cached.restype = None
     lib.lens_profile_enable.argtypes = [I32]
     lib.lens_profile_enable.restype = None
     lib.lens_profile_read.argtypes = [I32, P(ctypes.c_char_p), P(D), P(I64)]

@@ -14,6 +14,8 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <memory>
+#include <mutex>
 
 #include "lens_internal.h"
 
@@ -32,19 +34,23 @@ struct lens_plan {
   DevBuf sxy, sm, leaf_start;
   std::vector<DevBuf> mp;    // index = level, FP64 multipoles
   std::vector<DevBuf> mp32;  // index = level, FP32 copies (fine levels, mixed)
+  DevBuf keys, vals, keys_tmp, vals_tmp, cnt, scan_tmp;  // tree-build scratch
   hipStream_t last_stream = nullptr;
 
   const double *mp_at(int l) const { return static_cast<const double *>(mp[l].ptr); }
   const float *mp32_at(int l) const {
     return mp32.size() > (size_t)l ? static_cast<const float *>(mp32[l].ptr) : nullptr;
   }
+  // return every buffer to the pool, ordered after the work on `st`
+  void put_all(hipStream_t st) {
+    for (DevBuf *b : {&sxy, &sm, &leaf_start, &keys, &vals, &keys_tmp, &vals_tmp, &cnt, &scan_tmp})
+      pool_put(*b, st);
+    for (auto &b : mp) pool_put(b, st);
+    for (auto &b : mp32) pool_put(b, st);
+  }
   void release() {
     if (last_stream) (void)hipStreamSynchronize(last_stream);
-    pool_put(sxy, nullptr);
-    pool_put(sm, nullptr);
-    pool_put(leaf_start, nullptr);
-    for (auto &b : mp) pool_put(b, nullptr);
-    for (auto &b : mp32) pool_put(b, nullptr);
+    put_all(nullptr);
   }
 };
 
@@ -215,110 +221,129 @@ Window window_for(const lens_plan &P, int level, const double bb[4]) {
   return Window{x0, y0, x1 - x0 + 1, y1 - y0 + 1};
 }
 
+// Plan phase 1 (host): domain = star bounding box sb (if any) united with
+// ray_box, root square and leaf level (aligned with `align` if possible).
+void plan_geometry(lens_plan *P, int64_t n_sources, const double *sb, const double *ray_box,
+                   const lens_grid *align, double rays_density, const lens_opts &o) {
+  P->p = o.order_p;
+  P->precision = o.precision;
+  P->n_stars = n_sources;
+  bool have = sb != nullptr;
+  double dom[4];
+  if (have) std::copy(sb, sb + 4, dom);
+  if (ray_box) {
+    if (!have) std::copy(ray_box, ray_box + 4, dom);
+    dom[0] = std::min(dom[0], ray_box[0]);
+    dom[1] = std::min(dom[1], ray_box[1]);
+    dom[2] = std::max(dom[2], ray_box[2]);
+    dom[3] = std::max(dom[3], ray_box[3]);
+    have = true;
+  }
+  if (!have) dom[0] = dom[1] = 0, dom[2] = dom[3] = 1;
+  std::copy(dom, dom + 4, P->domain);
+  double side = std::max(dom[2] - dom[0], dom[3] - dom[1]);
+  if (!(side > 0)) side = 1.0;
+  side *= 1.0 + 1.0 / 1024;
+  const double rho = star_density(n_sources, sb ? sb : dom);
+  bool aligned = false;
+  if (align && align->nx > 0 && align->ny > 0 && n_sources > 0)
+    aligned = aligned_geometry(*align, dom, o.leaf_level, rho, P->p, &P->g);
+  if (!aligned) {
+    const double cxm = 0.5 * (dom[0] + dom[2]), cym = 0.5 * (dom[1] + dom[3]);
+    P->g.side = side;
+    P->g.x0 = cxm - 0.5 * side;
+    P->g.y0 = cym - 0.5 * side;
+    P->g.L = o.leaf_level > 0
+                 ? o.leaf_level
+                 : level_for_side(side, preferred_leaf_side(rho, rays_density, side, P->p), P->p);
+  }
+}
+
+// Plan phase 2: every device buffer the tree build and the upward pass use.
+void plan_alloc(lens_plan *P, hipStream_t st) {
+  const int L = P->g.L;
+  const int64_t nbox = int64_t(1) << (2 * L);
+  const int64_t N = std::max<int64_t>(P->n_stars, 1);
+  P->mp.resize(L + 1);
+  P->mp32.resize(L + 1);
+  P->leaf_start = pool_get((size_t)(nbox + 1) * sizeof(int32_t), st);
+  P->sxy = pool_get((size_t)N * 16, st);
+  P->sm = pool_get((size_t)N * 8 * P->qdim, st);
+  for (DevBuf *b : {&P->keys, &P->vals, &P->keys_tmp, &P->vals_tmp})
+    *b = pool_get((size_t)N * sizeof(uint32_t), st);
+  const size_t ncnt = radix_counts_len(N);
+  P->cnt = pool_get(ncnt * sizeof(uint32_t), st);
+  P->scan_tmp = pool_get(scan_tmp_len(ncnt) * sizeof(uint32_t), st);
+  for (int l = 2; l <= L; ++l) {
+    const size_t n = (size_t)(int64_t(1) << (2 * l)) * P->p * 2;
+    P->mp[l] = pool_get(n * sizeof(double), st);
+    // LENS_MIXED: the fine levels also get FP32 copies for their M2L
+    if (P->precision == LENS_MIXED && l > L - P->fine_levels)
+      P->mp32[l] = pool_get(n * sizeof(float), st);
+  }
+}
+
+// Plan phase 3: kernels only (no allocation, no copy, no memset) -- sort the
+// sources by leaf box, then P2M / M2M.
+void plan_enqueue(lens_plan *P, const double *xy, const double *q, hipStream_t st) {
+  const int L = P->g.L;
+  const int64_t nbox = int64_t(1) << (2 * L);
+  const int64_t N = P->n_stars;
+  auto *leaf_start = static_cast<int32_t *>(P->leaf_start.ptr);
+  auto *sxy = static_cast<double *>(P->sxy.ptr);
+  auto *sm = static_cast<double *>(P->sm.ptr);
+  {
+    StageTimer tm("tree", st);
+    auto *k = static_cast<uint32_t *>(P->keys.ptr), *v = static_cast<uint32_t *>(P->vals.ptr);
+    auto *kt = static_cast<uint32_t *>(P->keys_tmp.ptr), *vt = static_cast<uint32_t *>(P->vals_tmp.ptr);
+    launch_leaf_keys(xy, N, P->g, k, v, st);
+    const bool in_tmp = radix_sort_pairs(k, v, kt, vt, N, 2 * L, static_cast<uint32_t *>(P->cnt.ptr),
+                                         static_cast<uint32_t *>(P->scan_tmp.ptr), st);
+    const uint32_t *ks = in_tmp ? kt : k, *vs = in_tmp ? vt : v;
+    launch_gather_stars(vs, xy, q, P->qdim, N, sxy, sm, st);
+    launch_box_starts(ks, N, nbox, leaf_start, st);  // all zero when N = 0
+  }
+  const OpTables &T = op_tables(P->p, st);
+  {
+    StageTimer tm("upward", st);
+    const int direct_levels = 3;  // levels L, L-1, L-2 from the stars
+    for (int l = L; l >= 2; --l) {
+      double *out = static_cast<double *>(P->mp[l].ptr);
+      float *out32 = static_cast<float *>(P->mp32[l].ptr);
+      if (l > L - direct_levels)
+        launch_p2m(P->g, l, sxy, sm, P->qdim, leaf_start, P->p, out, out32, st);
+      else
+        launch_m2m(l, P->p, P->mp_at(l + 1), out, out32, T.m2m, st);
+    }
+  }
+  P->last_stream = st;
+}
+
 // Sources are f.xy with charges f.m (real), or, if qc is given, the complex
-// charges qc[n][2] (the adjoint's rays).
+// charges qc[n][2] (the adjoint's rays).  sb_known: the sources' bounding box
+// if already known (else it is read back from the device).
 lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_grid *align,
                       double rays_density, const lens_opts &o, hipStream_t st,
-                      const double *qc = nullptr) {
+                      const double *qc = nullptr, const double *sb_known = nullptr) {
   auto *P = new lens_plan();
   P->qdim = qc ? 2 : 1;
   try {
     LENS_HIP(hipGetDevice(&P->device));
-    P->p = o.order_p;
-    P->precision = o.precision;
-    P->n_stars = f.n_stars;
     P->kappa_s = f.kappa_s;
     P->gamma = f.gamma;
-    double sb[4] = {0, 0, 0, 0};
-    bool have = false;
+    double sb[4];
+    const double *sbp = nullptr;
     if (f.n_stars > 0) {
-      device_bbox(f.xy, f.n_stars, st, sb);
-      have = true;
+      if (sb_known)
+        std::copy(sb_known, sb_known + 4, sb);
+      else
+        device_bbox(f.xy, f.n_stars, st, sb);
+      sbp = sb;
     }
-    double dom[4];
-    if (have) std::copy(sb, sb + 4, dom);
-    if (ray_box) {
-      if (!have) std::copy(ray_box, ray_box + 4, dom);
-      dom[0] = std::min(dom[0], ray_box[0]);
-      dom[1] = std::min(dom[1], ray_box[1]);
-      dom[2] = std::max(dom[2], ray_box[2]);
-      dom[3] = std::max(dom[3], ray_box[3]);
-      have = true;
-    }
-    if (!have) dom[0] = dom[1] = 0, dom[2] = dom[3] = 1;
-    std::copy(dom, dom + 4, P->domain);
-    double side = std::max(dom[2] - dom[0], dom[3] - dom[1]);
-    if (!(side > 0)) side = 1.0;
-    side *= 1.0 + 1.0 / 1024;
-    const double rho = star_density(f.n_stars, have ? sb : dom);
-    bool aligned = false;
-    if (align && align->nx > 0 && align->ny > 0 && f.n_stars > 0)
-      aligned = aligned_geometry(*align, dom, o.leaf_level, rho, P->p, &P->g);
-    if (!aligned) {
-      const double cxm = 0.5 * (dom[0] + dom[2]), cym = 0.5 * (dom[1] + dom[3]);
-      P->g.side = side;
-      P->g.x0 = cxm - 0.5 * side;
-      P->g.y0 = cym - 0.5 * side;
-      P->g.L = o.leaf_level > 0
-                   ? o.leaf_level
-                   : level_for_side(side, preferred_leaf_side(rho, rays_density, side, P->p), P->p);
-    }
-    const int L = P->g.L;
-    const int64_t nL = int64_t(1) << L;
-    const int64_t nbox = nL * nL;
-    const int64_t N = f.n_stars;
-
-    P->mp.resize(L + 1);
-    P->leaf_start = pool_get((size_t)(nbox + 1) * sizeof(int32_t), st);
-    P->sxy = pool_get((size_t)std::max<int64_t>(N, 1) * 16, st);
-    P->sm = pool_get((size_t)std::max<int64_t>(N, 1) * 8 * P->qdim, st);
-    for (int l = 2; l <= L; ++l) {
-      const int64_t nb = int64_t(1) << (2 * l);
-      P->mp[l] = pool_get((size_t)nb * P->p * 16, st);
-    }
-
-    Scratch sc(st);
-    auto *leaf_start = static_cast<int32_t *>(P->leaf_start.ptr);
-    auto *sxy = static_cast<double *>(P->sxy.ptr);
-    auto *sm = static_cast<double *>(P->sm.ptr);
-    {
-      StageTimer tm("tree", st);
-      if (N > 0) {
-        uint32_t *k = sc.get<uint32_t>(N), *v = sc.get<uint32_t>(N);
-        uint32_t *kt = sc.get<uint32_t>(N), *vt = sc.get<uint32_t>(N);
-        const size_t ncnt = radix_counts_len(N);
-        uint32_t *cnt = sc.get<uint32_t>(ncnt);
-        uint32_t *stmp = sc.get<uint32_t>(scan_tmp_len(ncnt));
-        launch_leaf_keys(f.xy, N, P->g, k, v, st);
-        const bool in_tmp = radix_sort_pairs(k, v, kt, vt, N, 2 * L, cnt, stmp, st);
-        const uint32_t *ks = in_tmp ? kt : k, *vs = in_tmp ? vt : v;
-        launch_gather_stars(vs, f.xy, qc ? qc : f.m, P->qdim, N, sxy, sm, st);
-        launch_box_starts(ks, N, nbox, leaf_start, st);
-      } else {
-        LENS_HIP(hipMemsetAsync(leaf_start, 0, (size_t)(nbox + 1) * sizeof(int32_t), st));
-      }
-    }
-    const OpTables &T = op_tables(P->p, st);
-    {
-      StageTimer tm("upward", st);
-      // LENS_MIXED: the fine levels also get FP32 copies for their M2L
-      P->mp32.resize(L + 1);
-      auto f32_at = [&](int l) -> float * {
-        if (P->precision != LENS_MIXED || l <= L - P->fine_levels) return nullptr;
-        const size_t n = (size_t)(int64_t(1) << (2 * l)) * P->p * 2;
-        P->mp32[l] = pool_get(n * sizeof(float), st);
-        return static_cast<float *>(P->mp32[l].ptr);
-      };
-      const int direct_levels = 3;  // levels L, L-1, L-2 from the stars
-      for (int l = L; l >= 2; --l) {
-        double *out = static_cast<double *>(P->mp[l].ptr);
-        if (l > L - direct_levels)
-          launch_p2m(P->g, l, sxy, sm, P->qdim, leaf_start, P->p, out, f32_at(l), st);
-        else
-          launch_m2m(l, P->p, P->mp_at(l + 1), out, f32_at(l), T.m2m, st);
-      }
-    }
-    P->last_stream = st;
+    plan_geometry(P, f.n_stars, sbp, ray_box, align, rays_density, o);
+    (void)op_tables(o.order_p, st);
+    plan_alloc(P, st);
+    plan_enqueue(P, f.xy, qc ? qc : f.m, st);
   } catch (...) {
     P->release();
     delete P;
@@ -334,31 +359,44 @@ void check_inside(const lens_plan &P, const double bb[4]) {
     fail(LENS_EINVAL, "rays lie outside the region the plan was built for (pass ray_box to lens_plan_create)");
 }
 
-// Downward pass over the windows of `bb`: locals of every level 2..L.
-// Returns the leaf window; *leaf_loc receives its local expansions.
-// Levels >= 3 among the two finest run M2L and L2L in one fused kernel,
-// in order; the coarser ones run M2L batched, then the L2L sweep.
-Window downward(lens_plan &P, const double bb[4], Scratch &sc, hipStream_t st, double **leaf_loc) {
+// Windows and local-expansion buffers of every level for rays in `bb`.
+struct LocalSet {
+  std::vector<Window> win;
+  std::vector<DevBuf> loc;
+  double *at(int l) const { return static_cast<double *>(loc[l].ptr); }
+  void put_all(hipStream_t st) {
+    for (auto &b : loc) pool_put(b, st);
+  }
+};
+
+void locals_alloc(const lens_plan &P, const double bb[4], LocalSet &ls, hipStream_t st) {
+  const int L = P.g.L;
+  ls.win.assign(L + 1, Window{0, 0, 0, 0});
+  ls.loc.assign(L + 1, DevBuf{});
+  for (int l = 2; l <= L; ++l) {
+    ls.win[l] = window_for(P, l, bb);
+    ls.loc[l] = pool_get((size_t)ls.win[l].count() * P.p * 16, st);
+  }
+}
+
+// Downward pass (kernels only): locals of every level 2..L.  Levels >= 3
+// among the two finest run M2L and L2L in one fused kernel, in order; the
+// coarser ones run M2L batched, then the L2L sweep.
+void downward_enqueue(const lens_plan &P, const LocalSet &ls, hipStream_t st) {
   const int L = P.g.L;
   const OpTables &T = op_tables(P.p, st);
   StageTimer tm("downward", st);
-  std::vector<Window> win(L + 1);
-  std::vector<double *> loc(L + 1, nullptr);
   auto is_f32 = [&](int l) {
     return P.precision == LENS_MIXED && l > L - P.fine_levels && P.mp32_at(l) != nullptr;
   };
   auto level_of = [&](int l) {
-    return M2LLevel{l, std::ldexp(P.g.side, -l), win[l],
-                    is_f32(l) ? (const void *)P.mp32_at(l) : (const void *)P.mp_at(l), loc[l],
+    return M2LLevel{l, std::ldexp(P.g.side, -l), ls.win[l],
+                    is_f32(l) ? (const void *)P.mp32_at(l) : (const void *)P.mp_at(l), ls.at(l),
                     nullptr, Window{0, 0, 0, 0}};
   };
   const int first_fused = std::max(3, L - 1);
   M2LBatch coarse, fine;
   coarse.p = fine.p = P.p;
-  for (int l = 2; l <= L; ++l) {
-    win[l] = window_for(P, l, bb);
-    loc[l] = sc.get<double>((size_t)win[l].count() * P.p * 2);
-  }
   for (int l = 2; l < first_fused && l <= L; ++l) {
     M2LBatch &b = is_f32(l) ? fine : coarse;
     b.lv[b.count++] = level_of(l);
@@ -370,10 +408,10 @@ Window downward(lens_plan &P, const double bb[4], Scratch &sc, hipStream_t st, d
     d.level = l;
     d.p = P.p;
     d.s = std::ldexp(P.g.side, -l);
-    d.win = win[l];
-    d.pwin = win[l - 1];
-    d.ploc = loc[l - 1];
-    d.loc = loc[l];
+    d.win = ls.win[l];
+    d.pwin = ls.win[l - 1];
+    d.ploc = ls.at(l - 1);
+    d.loc = ls.at(l);
     launch_l2l(d, T, st);
   };
   for (int l = 3; l < first_fused && l <= L; ++l) l2l(l);
@@ -382,16 +420,25 @@ Window downward(lens_plan &P, const double bb[4], Scratch &sc, hipStream_t st, d
     one.p = P.p;
     one.count = 1;
     one.lv[0] = level_of(l);
-    one.lv[0].ploc = loc[l - 1];
-    one.lv[0].pwin = win[l - 1];
+    one.lv[0].ploc = ls.at(l - 1);
+    one.lv[0].pwin = ls.win[l - 1];
     if (!launch_m2l_l2l(one, T, is_f32(l), st)) {
       one.lv[0].ploc = nullptr;
       launch_m2l_batch(one, T, is_f32(l), st);
       l2l(l);
     }
   }
-  *leaf_loc = loc[L];
-  return win[L];
+}
+
+// Convenience: allocate (released behind the stream's work by `sc`) and run.
+Window downward(lens_plan &P, const double bb[4], Scratch &sc, hipStream_t st, double **leaf_loc) {
+  LocalSet ls;
+  locals_alloc(P, bb, ls, st);
+  downward_enqueue(P, ls, st);
+  for (auto &b : ls.loc)
+    if (b.ptr) sc.bufs.push_back(b);
+  *leaf_loc = ls.at(P.g.L);
+  return ls.win[P.g.L];
 }
 
 void fill_star_side(const lens_plan &P, Window wl, double *loc, EvalArgs &ea) {
@@ -436,33 +483,36 @@ void grid_bbox(const lens_grid &g, int64_t j0, int64_t j1, double bb[4]) {
   bb[3] = grid_y(g, j1 - 1);
 }
 
-// Grid rows [j0, j1) through the FMM path (deflect: y_out; map: binning).
-void fmm_grid_rows(lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, double c1, double c2,
-                   double *y_out, const lens_map_desc *map, double S, hipStream_t st) {
-  Scratch sc(st);
+// Evaluation of grid rows [j0, j1): its locals, ray ranges and launch shape.
+struct GridExec {
+  int64_t j0 = 0, j1 = 0;
   double bb[4];
-  grid_bbox(grid, j0, j1, bb);
-  check_inside(P, bb);
-  double *loc = nullptr;
-  const Window wl = downward(P, bb, sc, st, &loc);
+  LocalSet ls;
+  DevBuf col_start, row_start;
   EvalArgs ea{};
-  fill_star_side(P, wl, loc, ea);
+  void put_all(hipStream_t st) {
+    ls.put_all(st);
+    pool_put(col_start, st);
+    pool_put(row_start, st);
+  }
+};
+
+void gridexec_alloc(const lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, GridExec &ge,
+                    hipStream_t st) {
+  ge.j0 = j0;
+  ge.j1 = j1;
+  grid_bbox(grid, j0, j1, ge.bb);
+  check_inside(P, ge.bb);
+  locals_alloc(P, ge.bb, ge.ls, st);
+  const Window wl = ge.ls.win[P.g.L];
+  ge.col_start = pool_get((size_t)(wl.nbx + 1) * sizeof(int32_t), st);
+  ge.row_start = pool_get((size_t)(wl.nby + 1) * sizeof(int32_t), st);
+  EvalArgs &ea = ge.ea;
+  fill_star_side(P, wl, ge.ls.at(P.g.L), ea);
   ea.grid_mode = 1;
   ea.grid = grid;
-  ea.c1 = c1;
-  ea.c2 = c2;
-  ea.y_out = y_out;
-  if (map) {
-    ea.counts = map->counts;
-    ea.y1min = map->y1min;
-    ea.y2min = map->y2min;
-    ea.S = S;
-    ea.npix = map->npix;
-  }
-  int32_t *cs = sc.get<int32_t>(wl.nbx + 1), *rs = sc.get<int32_t>(wl.nby + 1);
-  launch_grid_ranges(grid, P.g, wl, j0, j1, cs, rs, st);
-  ea.col_start = cs;
-  ea.row_start = rs;
+  ea.col_start = static_cast<int32_t *>(ge.col_start.ptr);
+  ea.row_start = static_cast<int32_t *>(ge.row_start.ptr);
   // a leaf box of side s holds k grid columns when s = k dx, else at most
   // floor(s/dx) + 1 (rows likewise); a longer box chunk is still processed
   // whole by the kernel, only less efficiently
@@ -475,7 +525,45 @@ void fmm_grid_rows(lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, 
   };
   eval_shape(per_box(grid.dx, grid.nx) * per_box(grid.dy, j1 - j0), &ea.rays_per_lane,
              &ea.chunks_per_box);
-  launch_eval_checked(ea, P.precision, st);
+  while (wl.count() * ea.chunks_per_box > (int64_t)0x7fffffff && ea.chunks_per_box > 1)
+    ea.chunks_per_box = (ea.chunks_per_box + 1) / 2;
+  if (wl.count() > (int64_t)0x7fffffff) fail(LENS_EUNSUPPORTED, "leaf window too large");
+}
+
+// Kernels only: downward pass, ray ranges, evaluation (y_out or map).
+void gridexec_enqueue(const lens_plan &P, GridExec &ge, double c1, double c2, double *y_out,
+                      const lens_map_desc *map, hipStream_t st) {
+  downward_enqueue(P, ge.ls, st);
+  EvalArgs ea = ge.ea;
+  ea.c1 = c1;
+  ea.c2 = c2;
+  ea.y_out = y_out;
+  if (map) {
+    ea.counts = map->counts;
+    ea.y1min = map->y1min;
+    ea.y2min = map->y2min;
+    ea.S = (double)map->npix / map->side;
+    ea.npix = map->npix;
+  }
+  launch_grid_ranges(ea.grid, P.g, ea.win, ge.j0, ge.j1, const_cast<int32_t *>(ea.col_start),
+                     const_cast<int32_t *>(ea.row_start), st);
+  StageTimer tm(ea.counts ? "eval_map" : "eval", st);
+  launch_eval(ea, P.precision, st);
+}
+
+// Grid rows [j0, j1) through the FMM path (deflect: y_out; map: binning).
+void fmm_grid_rows(lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, double c1, double c2,
+                   double *y_out, const lens_map_desc *map, double S, hipStream_t st) {
+  (void)S;
+  GridExec ge;
+  try {
+    gridexec_alloc(P, grid, j0, j1, ge, st);
+    gridexec_enqueue(P, ge, c1, c2, y_out, map, st);
+  } catch (...) {
+    ge.put_all(st);
+    throw;
+  }
+  ge.put_all(st);
   P.last_stream = st;
 }
 
@@ -519,11 +607,7 @@ void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4
 
 void release_owned(lens_plan *owned, hipStream_t st) {
   // stream-ordered release: the buffers go back to the pool behind the work
-  pool_put(owned->sxy, st);
-  pool_put(owned->sm, st);
-  pool_put(owned->leaf_start, st);
-  for (auto &b : owned->mp) pool_put(b, st);
-  for (auto &b : owned->mp32) pool_put(b, st);
+  owned->put_all(st);
   delete owned;
 }
 
@@ -553,6 +637,178 @@ void check_plan_device(const lens_plan *plan) {
   int dev = 0;
   LENS_HIP(hipGetDevice(&dev));
   if (dev != plan->device) fail(LENS_EINVAL, "plan was created on another device");
+}
+
+}  // namespace
+
+namespace {
+
+// ------------------------------------------------------- batched fields
+// lens_map_batched: every field's tree build, upward pass, downward pass and
+// binned evaluation, allocated up front and captured as one HIP graph whose
+// branches (fields spread over kSideStreams forked streams) run
+// concurrently; the graph is cached by the batch's arrays and parameters and
+// replayed while every field's stars stay inside its captured tree.
+
+constexpr int kSideStreams = 4;
+constexpr size_t kBatchCache = 4;
+
+struct BatchExec {
+  std::vector<uint64_t> key;
+  int device = 0;
+  std::vector<lens_plan *> plans;  // nullptr for fields without stars
+  std::vector<std::unique_ptr<GridExec>> ge;
+  hipStream_t origin = nullptr;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last = nullptr;
+
+  ~BatchExec() {
+    if (last) (void)hipStreamSynchronize(last);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto *P : plans)
+      if (P) {
+        P->put_all(nullptr);
+        delete P;
+      }
+    for (auto &g : ge)
+      if (g) g->put_all(nullptr);
+    for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto s : side) (void)hipStreamDestroy(s);
+    if (origin) (void)hipStreamDestroy(origin);
+  }
+};
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<BatchExec>> g_batches;
+
+void key_push(std::vector<uint64_t> &k, double v) {
+  uint64_t w;
+  std::memcpy(&w, &v, 8);
+  k.push_back(w);
+}
+void key_push(std::vector<uint64_t> &k, int64_t v) { k.push_back((uint64_t)v); }
+void key_push(std::vector<uint64_t> &k, const void *p) { k.push_back((uint64_t)(uintptr_t)p); }
+
+std::vector<uint64_t> batch_key(int dev, int n, const lens_field *f, const lens_grid *g,
+                                const lens_map_desc *m, const lens_opts &o) {
+  std::vector<uint64_t> k;
+  key_push(k, (int64_t)dev);
+  key_push(k, (int64_t)n);
+  key_push(k, (int64_t)o.method);
+  key_push(k, (int64_t)o.precision);
+  key_push(k, (int64_t)o.order_p);
+  key_push(k, (int64_t)o.leaf_level);
+  for (int i = 0; i < n; ++i) {
+    key_push(k, f[i].n_stars);
+    key_push(k, (const void *)f[i].xy);
+    key_push(k, (const void *)f[i].m);
+    key_push(k, f[i].kappa_s);
+    key_push(k, f[i].gamma);
+    key_push(k, g[i].x0);
+    key_push(k, g[i].y0);
+    key_push(k, g[i].dx);
+    key_push(k, g[i].dy);
+    key_push(k, g[i].nx);
+    key_push(k, g[i].ny);
+    key_push(k, m[i].y1min);
+    key_push(k, m[i].y2min);
+    key_push(k, m[i].side);
+    key_push(k, (int64_t)m[i].npix);
+    key_push(k, (const void *)m[i].counts);
+  }
+  return k;
+}
+
+bool inside(const double dom[4], const double bb[4]) {
+  return bb[0] >= dom[0] && bb[1] >= dom[1] && bb[2] <= dom[2] && bb[3] <= dom[3];
+}
+
+std::unique_ptr<BatchExec> batch_build(int n, const lens_field *f, const lens_grid *g,
+                                       const lens_map_desc *m, const lens_opts &o,
+                                       const std::vector<double> &bbox, hipStream_t st) {
+  auto B = std::make_unique<BatchExec>();
+  LENS_HIP(hipGetDevice(&B->device));
+  (void)op_tables(o.order_p, st);
+  B->plans.assign(n, nullptr);
+  B->ge.resize(n);
+  for (int i = 0; i < n; ++i) {
+    if (f[i].n_stars == 0 || o.method == LENS_DIRECT) continue;
+    auto *P = new lens_plan();
+    B->plans[i] = P;
+    P->device = B->device;
+    P->kappa_s = f[i].kappa_s;
+    P->gamma = f[i].gamma;
+    double gb[4];
+    grid_bbox(g[i], 0, g[i].ny, gb);
+    const double area = std::max((gb[2] - gb[0]) * (gb[3] - gb[1]), 1e-300);
+    plan_geometry(P, f[i].n_stars, &bbox[4 * i], gb, &g[i], (double)(g[i].nx * g[i].ny) / area, o);
+    plan_alloc(P, st);
+    B->ge[i] = std::make_unique<GridExec>();
+    gridexec_alloc(*P, g[i], 0, g[i].ny, *B->ge[i], st);
+  }
+  LENS_HIP(hipStreamCreateWithFlags(&B->origin, hipStreamNonBlocking));
+  B->side.assign(kSideStreams, nullptr);
+  for (auto &s : B->side) LENS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  B->ev.assign(kSideStreams + 1, nullptr);
+  for (auto &e : B->ev) LENS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // the buffers above were handed out on `st`; the graph runs after it
+  LENS_HIP(hipStreamSynchronize(st));
+
+  set_capturing(true);
+  hipError_t began = hipStreamBeginCapture(B->origin, hipStreamCaptureModeThreadLocal);
+  if (began != hipSuccess) {
+    set_capturing(false);
+    LENS_HIP(began);
+  }
+  try {
+    LENS_HIP(hipEventRecord(B->ev[0], B->origin));
+    for (auto s : B->side) LENS_HIP(hipStreamWaitEvent(s, B->ev[0], 0));
+    for (int i = 0; i < n; ++i) {
+      hipStream_t s = B->side[i % kSideStreams];
+      const double c1 = (1.0 - f[i].kappa_s) - f[i].gamma;
+      const double c2 = (1.0 - f[i].kappa_s) + f[i].gamma;
+      if (!B->plans[i]) {
+        DirectArgs d{};
+        d.n_stars = f[i].n_stars;
+        d.sxy = f[i].xy;
+        d.sm = f[i].m;
+        d.grid_mode = 1;
+        d.grid = g[i];
+        d.n_rays = g[i].nx * g[i].ny;
+        d.c1 = c1;
+        d.c2 = c2;
+        d.counts = m[i].counts;
+        d.y1min = m[i].y1min;
+        d.y2min = m[i].y2min;
+        d.S = (double)m[i].npix / m[i].side;
+        d.npix = m[i].npix;
+        launch_direct(d, s);
+        continue;
+      }
+      plan_enqueue(B->plans[i], f[i].xy, f[i].m, s);
+      gridexec_enqueue(*B->plans[i], *B->ge[i], c1, c2, nullptr, &m[i], s);
+    }
+    for (int j = 0; j < kSideStreams; ++j) {
+      LENS_HIP(hipEventRecord(B->ev[j + 1], B->side[j]));
+      LENS_HIP(hipStreamWaitEvent(B->origin, B->ev[j + 1], 0));
+    }
+  } catch (...) {
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(B->origin, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    set_capturing(false);
+    (void)hipGetLastError();
+    throw;
+  }
+  const hipError_t ended = hipStreamEndCapture(B->origin, &B->graph);
+  set_capturing(false);
+  LENS_HIP(ended);
+  LENS_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+  return B;
 }
 
 }  // namespace
@@ -834,6 +1090,92 @@ lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid
     }
     release_owned(P, st);
   });
+}
+
+lens_status lens_map_batched(int32_t n_fields, const lens_field *fields, const lens_grid *grids,
+                             const lens_map_desc *maps, const lens_opts *opts, void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    const lens_opts o = resolve_opts(opts);
+    if (n_fields < 0) fail(LENS_EINVAL, "n_fields < 0");
+    if (n_fields == 0) return;
+    if (!fields || !grids || !maps) fail(LENS_EINVAL, "fields / grids / maps is NULL");
+    for (int i = 0; i < n_fields; ++i) {
+      const std::string at = " (field " + std::to_string(i) + ")";
+      try {
+        check_field(&fields[i]);
+        check_grid(&grids[i]);
+      } catch (const LensError &e) {
+        fail(e.status, e.msg + at);
+      }
+      const lens_map_desc &m = maps[i];
+      if (m.npix <= 0 || (int64_t)m.npix * m.npix > (int64_t)std::numeric_limits<int32_t>::max())
+        fail(LENS_EINVAL, "map.npix out of range" + at);
+      if (!is_finite(m.y1min) || !is_finite(m.y2min) || !is_finite(m.side) || !(m.side > 0))
+        fail(LENS_EINVAL, "map placement must be finite with side > 0" + at);
+      if (!m.counts) fail(LENS_EINVAL, "map.counts is NULL" + at);
+      if (grids[i].nx * grids[i].ny > (int64_t)std::numeric_limits<int32_t>::max())
+        fail(LENS_EINVAL, "a field may shoot at most 2^31-1 rays" + at);
+    }
+    int dev = 0;
+    LENS_HIP(hipGetDevice(&dev));
+    // bounding boxes of every field's stars: one pass, one read-back
+    std::vector<double> bbox((size_t)4 * n_fields, 0.0);
+    {
+      Scratch sc(st);
+      std::vector<BBoxSet> sets(n_fields);
+      int64_t nmax = 1;
+      for (int i = 0; i < n_fields; ++i) {
+        sets[i] = BBoxSet{fields[i].xy, fields[i].n_stars};
+        nmax = std::max(nmax, fields[i].n_stars);
+      }
+      const int parts = bbox_parts(nmax);
+      auto *sets_d = sc.get<BBoxSet>(n_fields);
+      double *partial = sc.get<double>((size_t)n_fields * parts * 4);
+      double *out = sc.get<double>((size_t)n_fields * 4);
+      LENS_HIP(hipMemcpyAsync(sets_d, sets.data(), sizeof(BBoxSet) * n_fields,
+                              hipMemcpyHostToDevice, st));
+      launch_bbox_multi(sets_d, n_fields, parts, partial, out, st);
+      LENS_HIP(hipMemcpyAsync(bbox.data(), out, sizeof(double) * 4 * n_fields,
+                              hipMemcpyDeviceToHost, st));
+      LENS_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < n_fields; ++i)
+        if (fields[i].n_stars > 0)
+          for (int c = 0; c < 4; ++c)
+            if (!is_finite(bbox[4 * i + c]))
+              fail(LENS_EINVAL, "non-finite star coordinates (field " + std::to_string(i) + ")");
+    }
+    const auto key = batch_key(dev, n_fields, fields, grids, maps, o);
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchExec *B = nullptr;
+    for (auto it = g_batches.begin(); it != g_batches.end(); ++it) {
+      if ((*it)->key != key) continue;
+      bool ok = true;
+      for (int i = 0; i < n_fields && ok; ++i)
+        if ((*it)->plans[i]) ok = inside((*it)->plans[i]->domain, &bbox[4 * i]);
+      if (ok) {
+        B = it->get();
+      } else {
+        g_batches.erase(it);  // stars moved outside the captured trees
+      }
+      break;
+    }
+    if (!B) {
+      auto nb = batch_build(n_fields, fields, grids, maps, o, bbox, st);
+      nb->key = key;
+      if (g_batches.size() >= kBatchCache) g_batches.erase(g_batches.begin());
+      g_batches.push_back(std::move(nb));
+      B = g_batches.back().get();
+    }
+    StageTimer tm("batched_graph", st);
+    LENS_HIP(hipGraphLaunch(B->exec, st));
+    B->last = st;
+  });
+}
+
+void lens_release_cached(void) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batches.clear();
 }
 
 }  // extern "C"

@@ -81,6 +81,13 @@ struct Window {
 void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, double *out4,
                  hipStream_t stream);
 int bbox_parts(int64_t n);
+struct BBoxSet {
+  const double *xy;
+  int64_t n;
+};
+// out[s][4] = bounding box of set s (sets_dev: device array of nsets sets)
+void launch_bbox_multi(const BBoxSet *sets_dev, int nsets, int nparts, double *partial,
+                       double *out, hipStream_t stream);
 void launch_leaf_keys(const double *xy, int64_t n, Geometry g, uint32_t *keys, uint32_t *vals,
                       hipStream_t stream);
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.
@@ -246,6 +253,8 @@ namespace lensfmm {
 // Per-stage timing with HIP events on the launching stream, enabled by
 // lens_profile_enable().  A StageTimer brackets one stage of one call.
 bool profiling_enabled();
+// While a thread captures a HIP graph, StageTimer records nothing.
+void set_capturing(bool on);
 struct StageTimer {
   const char *name;
   hipStream_t stream;

@@ -38,7 +38,9 @@ void resolve_locked() {
 }
 }  // namespace
 
-bool profiling_enabled() { return g_on.load(std::memory_order_relaxed); }
+thread_local bool t_capturing = false;
+void set_capturing(bool on) { t_capturing = on; }
+bool profiling_enabled() { return !t_capturing && g_on.load(std::memory_order_relaxed); }
 
 StageTimer::StageTimer(const char *n, hipStream_t s) : name(n), stream(s) {
   if (!profiling_enabled()) return;

@@ -72,6 +72,65 @@ __global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restric
   if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Bounding boxes of several point sets at once: blockIdx.y = set; partial
+// results [set][part][4], then one workgroup per set reduces its parts.
+__global__ __launch_bounds__(kThreads) void k_bbox_multi_partial(const BBoxSet *__restrict__ sets,
+                                                                 int nparts,
+                                                                 double *__restrict__ partial) {
+  const BBoxSet S = sets[blockIdx.y];
+  double mn0 = DBL_MAX, mn1 = DBL_MAX, mx0 = -DBL_MAX, mx1 = -DBL_MAX;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < S.n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double a = S.xy[2 * i], b = S.xy[2 * i + 1];
+    mn0 = fmin(mn0, a);
+    mx0 = fmax(mx0, a);
+    mn1 = fmin(mn1, b);
+    mx1 = fmax(mx1, b);
+  }
+  __shared__ double red[4][kThreads];
+  red[0][threadIdx.x] = mn0;
+  red[1][threadIdx.x] = mn1;
+  red[2][threadIdx.x] = mx0;
+  red[3][threadIdx.x] = mx1;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4)
+    partial[((size_t)blockIdx.y * nparts + blockIdx.x) * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_bbox_multi_final(const double *__restrict__ partial,
+                                                               int nparts, double *__restrict__ out) {
+  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
+  const double *pp = partial + (size_t)blockIdx.x * nparts * 4;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) {
+    v[0] = fmin(v[0], pp[4 * i + 0]);
+    v[1] = fmin(v[1], pp[4 * i + 1]);
+    v[2] = fmax(v[2], pp[4 * i + 2]);
+    v[3] = fmax(v[3], pp[4 * i + 3]);
+  }
+  __shared__ double red[4][kThreads];
+  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + o]);
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
 // --------------------------------------------------------------- leaf keys
 
 __global__ __launch_bounds__(kThreads) void k_leaf_keys(const double *__restrict__ xy, int64_t n,
@@ -314,6 +373,16 @@ void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, doubl
                  hipStream_t stream) {
   hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(kThreads), 0, stream, xy, n, partial);
   hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kThreads), 0, stream, partial, nparts, out4);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_bbox_multi(const BBoxSet *sets_dev, int nsets, int nparts, double *partial,
+                       double *out, hipStream_t stream) {
+  if (nsets == 0) return;
+  hipLaunchKernelGGL(k_bbox_multi_partial, dim3(nparts, nsets), dim3(kThreads), 0, stream, sets_dev,
+                     nparts, partial);
+  hipLaunchKernelGGL(k_bbox_multi_final, dim3(nsets), dim3(kThreads), 0, stream, partial, nparts,
+                     out);
   LENS_HIP(hipGetLastError());
 }
 
