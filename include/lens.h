@@ -106,6 +106,10 @@ typedef struct {
   int32_t leaf_level;   /* quadtree leaf level in [2, LENS_MAX_LEVEL]; 0 = chosen
                            by the library's cost model */
   int64_t max_rays_per_chunk;  /* lens_map: rays per chunk; 0 = 1.6e7 */
+  int32_t fp32_levels;  /* LENS_MIXED: M2L of the finest fp32_levels quadtree
+                           levels runs on FP32 MFMA, coarser levels on FP64;
+                           0 = 2 levels, -1 = none (all M2L in FP64), at most
+                           LENS_MAX_LEVEL.  Ignored for LENS_FP64. */
 } lens_opts;
 
 /* Fill *o with the defaults (FMM, mixed, p = 12, automatic leaf level). */

@@ -74,7 +74,8 @@ def _stream():
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
 
-def _opts(method="fmm", precision="mixed", p=12, leaf_level=0, max_rays_per_chunk=0) -> LensOpts:
+def _opts(method="fmm", precision="mixed", p=12, leaf_level=0, max_rays_per_chunk=0,
+          fp32_levels=0) -> LensOpts:
     o = LensOpts()
     _lib.load().lens_opts_default(ctypes.byref(o))
     o.method = {"fmm": LENS_FMM, "direct": LENS_DIRECT}[method]
@@ -82,6 +83,7 @@ def _opts(method="fmm", precision="mixed", p=12, leaf_level=0, max_rays_per_chun
     o.order_p = int(p)
     o.leaf_level = int(leaf_level)
     o.max_rays_per_chunk = int(max_rays_per_chunk)
+    o.fp32_levels = int(fp32_levels)
     return o
 
 
@@ -105,12 +107,12 @@ class Plan:
     """
 
     def __init__(self, star_xy, star_m, kappa_s=0.0, gamma=0.0, ray_box=None, grid=None,
-                 precision="mixed", p=12, leaf_level=0):
+                 precision="mixed", p=12, leaf_level=0, fp32_levels=0):
         lib = _lib.load()
         self._f = _field(star_xy, star_m, kappa_s, gamma)
         self.precision = precision
         self.kappa_s, self.gamma = float(kappa_s), float(gamma)
-        o = _opts("fmm", precision, p, leaf_level)
+        o = _opts("fmm", precision, p, leaf_level, fp32_levels=fp32_levels)
         box = (ctypes.c_double * 4)(*ray_box) if ray_box is not None else None
         g = ctypes.byref(grid.c()) if grid is not None else None
         h = ctypes.c_void_p()
@@ -144,7 +146,7 @@ class Plan:
 
 def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, kappa_s=0.0,
             gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0,
-            plan: Optional[Plan] = None, out=None):
+            plan: Optional[Plan] = None, out=None, fp32_levels=0):
     """Lens-map rays: returns y [n, 2] float64 on the GPU (eq. 1 + smooth term).
 
     Rays come from ``grid`` or from the explicit tensor ``rays`` [n, 2].  With
@@ -173,7 +175,7 @@ def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, k
         _check_tensor(out, "out", 2)
         if out.numel() != 2 * n:
             raise ValueError("out must be [n, 2]")
-    o = _opts(method, precision, p, leaf_level)
+    o = _opts(method, precision, p, leaf_level, fp32_levels=fp32_levels)
     _lib.check(lib.lens_deflect(plan.handle if plan else None, ctypes.byref(f), gp, rp, n,
                                 out.data_ptr() if n else None, ctypes.byref(o), _stream()))
     return out
@@ -181,7 +183,7 @@ def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, k
 
 def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, kappa_s=0.0,
             gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0,
-            max_rays_per_chunk=0, plan: Optional[Plan] = None, counts=None):
+            max_rays_per_chunk=0, plan: Optional[Plan] = None, counts=None, fp32_levels=0):
     """Inverse ray shooting into an int32 [npix, npix] count map (accumulated
     into ``counts`` if given, indexed [v, u])."""
     torch = _torch()
@@ -198,14 +200,14 @@ def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
         raise ValueError("counts must be a contiguous int32 [npix, npix] GPU tensor")
     md = LensMapDesc(map.y1min, map.y2min, map.side, map.npix, counts.data_ptr())
     g = grid.c()
-    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk)
+    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk, fp32_levels)
     _lib.check(lib.lens_map(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
                             ctypes.byref(md), ctypes.byref(o), _stream()))
     return counts
 
 
 def irs_map_batched(fields, grids, maps, counts=None, method="fmm", precision="mixed", p=12,
-                    leaf_level=0):
+                    leaf_level=0, fp32_levels=0):
     """Inverse ray shooting for many independent fields in one captured HIP
     graph.  ``fields`` is a list of (star_xy, star_m, kappa_s, gamma);
     ``grids``/``maps`` lists of Grid/MapDesc; returns the list of int32 count
@@ -228,7 +230,7 @@ def irs_map_batched(fields, grids, maps, counts=None, method="fmm", precision="m
                 or c.shape != (mp.npix, mp.npix):
             raise ValueError("counts must be contiguous int32 [npix, npix] GPU tensors")
         ma[k] = LensMapDesc(mp.y1min, mp.y2min, mp.side, mp.npix, c.data_ptr())
-    o = _opts(method, precision, p, leaf_level)
+    o = _opts(method, precision, p, leaf_level, fp32_levels=fp32_levels)
     _lib.check(lib.lens_map_batched(n, fa, ga, ma, ctypes.byref(o), _stream()))
     return counts
 

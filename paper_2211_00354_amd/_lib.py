@@ -44,7 +44,7 @@ class LensMapDesc(ctypes.Structure):
 class LensOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("order_p", ctypes.c_int32), ("leaf_level", ctypes.c_int32),
-                ("max_rays_per_chunk", ctypes.c_int64)]
+                ("max_rays_per_chunk", ctypes.c_int64), ("fp32_levels", ctypes.c_int32)]
 
 
 _lib = None

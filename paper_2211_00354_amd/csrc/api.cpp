@@ -25,7 +25,7 @@ struct lens_plan {
   int device = 0;
   int p = 12;
   int precision = LENS_MIXED;
-  int fine_levels = 2;  // LENS_MIXED: levels L-fine_levels+1 .. L run M2L in FP32
+  int fine_levels = 0;  // LENS_MIXED: levels L-fine_levels+1 .. L run M2L in FP32
   int qdim = 1;         // charge components per source: 1 (masses) or 2 (complex)
   Geometry g{};
   int64_t n_stars = 0;
@@ -57,6 +57,7 @@ struct lens_plan {
 namespace {
 
 constexpr int64_t kDefaultChunk = 16000000;  // nmaxarg of Section 2.4
+constexpr int kDefaultFp32Levels = 2;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -69,6 +70,8 @@ void check_opts(const lens_opts &o) {
   if (o.leaf_level != 0 && (o.leaf_level < 2 || o.leaf_level > LENS_MAX_LEVEL))
     fail(LENS_EINVAL, "opts.leaf_level must be in [2, " + std::to_string(LENS_MAX_LEVEL) + "] or 0");
   if (o.max_rays_per_chunk < 0) fail(LENS_EINVAL, "opts.max_rays_per_chunk must be >= 0");
+  if (o.fp32_levels < -1 || o.fp32_levels > LENS_MAX_LEVEL)
+    fail(LENS_EINVAL, "opts.fp32_levels must be in [-1, " + std::to_string(LENS_MAX_LEVEL) + "]");
 }
 
 lens_opts resolve_opts(const lens_opts *o) {
@@ -78,6 +81,7 @@ lens_opts resolve_opts(const lens_opts *o) {
   check_opts(r);
   if (r.order_p == 0) r.order_p = 12;
   if (r.max_rays_per_chunk == 0) r.max_rays_per_chunk = kDefaultChunk;
+  r.fp32_levels = r.fp32_levels == 0 ? kDefaultFp32Levels : (r.fp32_levels < 0 ? 0 : r.fp32_levels);
   return r;
 }
 
@@ -227,6 +231,7 @@ void plan_geometry(lens_plan *P, int64_t n_sources, const double *sb, const doub
                    const lens_grid *align, double rays_density, const lens_opts &o) {
   P->p = o.order_p;
   P->precision = o.precision;
+  P->fine_levels = o.fp32_levels;
   P->n_stars = n_sources;
   bool have = sb != nullptr;
   double dom[4];
@@ -701,6 +706,7 @@ std::vector<uint64_t> batch_key(int dev, int n, const lens_field *f, const lens_
   key_push(k, (int64_t)o.method);
   key_push(k, (int64_t)o.precision);
   key_push(k, (int64_t)o.order_p);
+  key_push(k, (int64_t)o.fp32_levels);
   key_push(k, (int64_t)o.leaf_level);
   for (int i = 0; i < n; ++i) {
     key_push(k, f[i].n_stars);

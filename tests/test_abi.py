@@ -32,6 +32,7 @@ def _opts(**kw):
 def test_opts_defaults():
     o = _opts()
     assert (o.method, o.precision, o.order_p, o.leaf_level) == (_lib.LENS_FMM, _lib.LENS_MIXED, 12, 0)
+    assert o.fp32_levels == 0
 
 
 @pytest.mark.parametrize("field,opts,msg", [
@@ -42,6 +43,8 @@ def test_opts_defaults():
     (dict(n_stars=0), dict(order_p=-2), "order_p"),
     (dict(n_stars=0), dict(leaf_level=1), "leaf_level"),
     (dict(n_stars=0), dict(leaf_level=16), "leaf_level"),
+    (dict(n_stars=0), dict(fp32_levels=-2), "fp32_levels"),
+    (dict(n_stars=0), dict(fp32_levels=16), "fp32_levels"),
     (dict(n_stars=0), dict(method=7), "method"),
     (dict(n_stars=0), dict(precision=3), "precision"),
 ])

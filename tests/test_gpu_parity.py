@@ -450,3 +450,99 @@ def test_batched_config4_full_size(lf):
         single = host(lf.irs_map(xy, m, grid=grids[k], map=maps[k], kappa_s=ks, gamma=gm))
         np.testing.assert_array_equal(host(counts[k]), single)
     lf.release_cached()
+
+
+# ------------------------------------------------------- full-size workloads
+
+@pytest.mark.parametrize("prec,p,fl", [("mixed", 20, -1), ("fp64", 24, 0)])
+def test_config3_full_map(lf, prec, p, fl):
+    """High magnification: 5e6 stars, 16384^2 rays over [-120,120]x[-60,60],
+    2000^2 map over [-10,10]^2, kappa_s=0.75, gamma=0.05 (mu = 50).  At mu = 50
+    y is a small difference of large terms: a 1e-4 bin-reassignment rate
+    needs |dy| ~ 1e-6, hence p = 20 and every M2L level in FP64 (the near
+    field stays FP32) for the mixed path."""
+    import time
+    import torch
+    f, g, mp = wl.config3()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
+    kw = dict(kappa_s=f.kappa_s, gamma=f.gamma, precision=prec, p=p, fp32_levels=fl)
+    _say("config3 map", prec, p, fl)
+    counts = lf.irs_map(xy, m, grid=lfgrid(g), map=md, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    counts2 = lf.irs_map(xy, m, grid=lfgrid(g), map=md, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"config3 {prec} p={p}: {dt * 1e3:.1f} ms for {g.n:.3e} rays -> {g.n / dt:.3e} rays/s")
+    c = host(counts)
+    np.testing.assert_array_equal(c, host(counts2))          # deterministic
+    # the map is the oracle's binning of the GPU's own y (same decisions)
+    y = lf.deflect(xy, m, grid=lfgrid(g), **kw)
+    yh = host(y)
+    del y
+    mine, landed = oracle.bin_rays(yh, mp.y1min, mp.y2min, mp.side, mp.npix)
+    np.testing.assert_array_equal(c, mine)
+    # mean counts ~ mu * pixel area / ray cell area; at mu = 50 the mean
+    # magnification of one 20x20 map fluctuates by several per cent
+    expect = 50.0 * (mp.side / mp.npix) ** 2 / (g.dx * g.dy)
+    assert abs(c.mean() / expect - 1) < 0.15, (c.mean(), expect)
+    # bin reassignment against the oracle on sampled rays: counted, and
+    # estimated from the per-ray error (a coordinate error d moves a ray with
+    # probability d / pixel)
+    idx = g.strided(256, 128)
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), f.kappa_s, f.gamma)
+    ys = yh[idx]
+    S = mp.npix / mp.side
+    moved = np.count_nonzero(np.any(np.floor((ys - [mp.y1min, mp.y2min]) * S)
+                                    != np.floor((yo - [mp.y1min, mp.y2min]) * S), axis=1))
+    est = float(np.mean(np.abs(ys - yo).sum(1)) * S)
+    print(f"config3 {prec}: rel l2 {rel_l2(ys, yo, ao):.2e}, moved {moved}/{len(idx)}, "
+          f"estimated reassignment {est:.2e}")
+    assert est <= 1e-4
+    assert moved <= max(2, 2e-4 * len(idx))
+
+
+def test_config5_full_gradient(lf):
+    """Clustered lenses (2000 clusters x 100 stars), 1e6 random rays: the mixed
+    adjoint FMM against the FP64 direct gradient on the GPU (all stars), the
+    oracle (64 stars) and central differences of the loss (64 stars x 3)."""
+    import torch
+    f, rays, tn = wl.config5()
+    xy, m, r = dev_tensor(f.xy), dev_tensor(f.m), dev_tensor(rays)
+    _say("config5 forward")
+    y0 = lf.deflect(xy, m, rays=r, method="direct")
+    t = y0 + dev_tensor(tn)
+    G = 2 * (y0 - t)
+    _say("config5 adjoint")
+    gd_xy, gd_m = lf.deflect_backward(xy, m, G, rays=r, method="direct")
+    gf_xy, gf_m = lf.deflect_backward(xy, m, G, rays=r, precision="mixed", p=12)
+    e_xy = _grad_err(host(gf_xy), host(gd_xy))
+    e_m = _grad_err(host(gf_m), host(gd_m))
+    print(f"config5 mixed adjoint vs FP64 direct: grad_xy {e_xy:.2e}, grad_m {e_m:.2e}")
+    assert e_xy <= 1e-5 and e_m <= 1e-5
+    # oracle on 64 seeded stars
+    sel = np.random.default_rng(5).choice(f.n, 64, replace=False)
+    Gh = host(G)
+    o_xy = np.empty((64, 2))
+    o_m = np.empty(64)
+    for j, i in enumerate(sel):
+        a, b = oracle.grad(f.xy[i:i + 1], f.m[i:i + 1], rays, Gh)
+        o_xy[j], o_m[j] = a[0], b[0]
+    assert _grad_err(host(gd_xy)[sel], o_xy) <= 1e-12
+    assert _grad_err(host(gd_m)[sel], o_m) <= 1e-12
+    # complex-step derivatives of the loss (no subtractive cancellation, so
+    # exact to rounding): moving star i changes every y_k by its own term only
+    y0h, th = host(y0), host(t)
+    h = 1e-30
+    for j, i in enumerate(sel[:16]):
+        def term(sx, sy, mm):
+            d = rays - np.array([sx, sy])
+            return mm * d / (d * d).sum(1, keepdims=True)
+        base = term(f.xy[i, 0], f.xy[i, 1], f.m[i])
+        for c, (dx, dy, dm) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+            yk = y0h + base - term(f.xy[i, 0] + 1j * h * dx, f.xy[i, 1] + 1j * h * dy,
+                                   f.m[i] + 1j * h * dm)
+            cs = float(((yk - th) ** 2).sum().imag) / h
+            ref = o_xy[j, c] if c < 2 else o_m[j]
+            assert abs(cs - ref) <= 1e-9 * max(1.0, abs(ref)), (i, c, cs, ref)
