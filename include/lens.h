@@ -105,7 +105,8 @@ typedef struct {
   int32_t order_p;      /* expansion terms p in [1, LENS_MAX_ORDER]; 0 = 12 */
   int32_t leaf_level;   /* quadtree leaf level in [2, LENS_MAX_LEVEL]; 0 = chosen
                            by the library's cost model */
-  int64_t max_rays_per_chunk;  /* lens_map: rays per chunk; 0 = 1.6e7 */
+  int64_t max_rays_per_chunk;  /* lens_map: rays per chunk; 0 = the whole grid
+                                  in one pass (a map needs no per-ray memory) */
   int32_t fp32_levels;  /* LENS_MIXED: M2L of the finest fp32_levels quadtree
                            levels runs on FP32 MFMA, coarser levels on FP64;
                            0 = 2 levels, -1 = none (all M2L in FP64), at most
@@ -160,7 +161,8 @@ LENS_API lens_status lens_deflect(lens_plan *plan, const lens_field *field, cons
 /*
  * Inverse ray shooting: deflect every ray of `grid` and add it to the map
  * (see lens_map_desc).  Rays are processed in chunks of whole grid rows of at
- * most opts->max_rays_per_chunk rays (Section 2.4); the result does not
+ * most opts->max_rays_per_chunk rays (the bounded passes of Section 2.4; by
+ * default one pass, as the map needs no per-ray memory); the result does not
  * depend on the chunking.  `plan` may be NULL as in lens_deflect.
  */
 LENS_API lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *grid,

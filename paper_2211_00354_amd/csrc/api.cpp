@@ -31,6 +31,12 @@ struct lens_plan {
   int64_t n_stars = 0;
   double kappa_s = 0, gamma = 0;
   double domain[4] = {0, 0, 0, 0};
+  double target[4] = {0, 0, 0, 0};  // every ray evaluated with the plan lies in this box
+  // Levels 2..dense_top hold the multipoles of every box; a finer level only
+  // those of its source window swin[l] (the boxes that can be M2L sources
+  // for targets in the box above), each formed straight from the stars.
+  int dense_top = 0;
+  std::vector<Window> swin;  // index = level
   DevBuf sxy, sm, leaf_start;
   std::vector<DevBuf> mp;    // index = level, FP64 multipoles
   std::vector<DevBuf> mp32;  // index = level, FP32 copies (fine levels, mixed)
@@ -56,7 +62,9 @@ struct lens_plan {
 
 namespace {
 
-constexpr int64_t kDefaultChunk = 16000000;  // nmaxarg of Section 2.4
+// lens_map rays per pass by default: all of them (the paper's bounded passes,
+// Section 2.4, are kept as an option; a map needs no per-ray memory)
+constexpr int64_t kDefaultChunk = std::numeric_limits<int64_t>::max();
 constexpr int kDefaultFp32Levels = 2;
 
 bool is_finite(double v) { return std::isfinite(v); }
@@ -225,6 +233,37 @@ Window window_for(const lens_plan &P, int level, const double bb[4]) {
   return Window{x0, y0, x1 - x0 + 1, y1 - y0 + 1};
 }
 
+// Multipole storage per level.  M2L sources of a target box lie within 3
+// boxes of it, so level l needs the multipoles of the target window (rays'
+// boxes plus one) grown by 3 boxes.  Where that covers under a quarter of the
+// level, and at every finer level, only that window is stored and formed
+// from the stars; the coarser levels hold every box, down to a level where
+// boxes hold ~512 sources or fewer so that forming them from the stars stays
+// short.  When the rays cover the sources (the common case) every level is
+// dense.
+void source_windows(lens_plan *P) {
+  const int L = P->g.L;
+  P->swin.assign(L + 1, Window{0, 0, 0, 0});
+  int lw = L + 1;
+  for (int l = L; l >= 2; --l) {
+    const int64_t n = int64_t(1) << l;
+    Window w = window_for(*P, l, P->target);
+    const int64_t x0 = std::max<int64_t>(w.bx0 - 3, 0), y0 = std::max<int64_t>(w.by0 - 3, 0);
+    const int64_t x1 = std::min<int64_t>(w.bx0 + w.nbx + 3, n), y1 = std::min<int64_t>(w.by0 + w.nby + 3, n);
+    P->swin[l] = Window{x0, y0, x1 - x0, y1 - y0};
+    if (P->swin[l].count() * 4 <= n * n && lw == l + 1) lw = l;
+  }
+  int dmin = 2;
+  while (dmin < L && (double)P->n_stars / (double)(int64_t(1) << (2 * dmin)) > 512.0) ++dmin;
+  int D = std::max(lw - 1, dmin);
+  if (D >= L) D = L;
+  P->dense_top = std::max(D, 2);
+  for (int l = 2; l <= P->dense_top; ++l) {
+    const int64_t n = int64_t(1) << l;
+    P->swin[l] = Window{0, 0, n, n};
+  }
+}
+
 // Plan phase 1 (host): domain = star bounding box sb (if any) united with
 // ray_box, root square and leaf level (aligned with `align` if possible).
 void plan_geometry(lens_plan *P, int64_t n_sources, const double *sb, const double *ray_box,
@@ -262,6 +301,11 @@ void plan_geometry(lens_plan *P, int64_t n_sources, const double *sb, const doub
                  ? o.leaf_level
                  : level_for_side(side, preferred_leaf_side(rho, rays_density, side, P->p), P->p);
   }
+  if (ray_box)
+    std::copy(ray_box, ray_box + 4, P->target);
+  else
+    std::copy(dom, dom + 4, P->target);
+  source_windows(P);
 }
 
 // Plan phase 2: every device buffer the tree build and the upward pass use.
@@ -280,7 +324,7 @@ void plan_alloc(lens_plan *P, hipStream_t st) {
   P->cnt = pool_get(ncnt * sizeof(uint32_t), st);
   P->scan_tmp = pool_get(scan_tmp_len(ncnt) * sizeof(uint32_t), st);
   for (int l = 2; l <= L; ++l) {
-    const size_t n = (size_t)(int64_t(1) << (2 * l)) * P->p * 2;
+    const size_t n = (size_t)P->swin[l].count() * P->p * 2;
     P->mp[l] = pool_get(n * sizeof(double), st);
     // LENS_MIXED: the fine levels also get FP32 copies for their M2L
     if (P->precision == LENS_MIXED && l > L - P->fine_levels)
@@ -311,12 +355,20 @@ void plan_enqueue(lens_plan *P, const double *xy, const double *q, hipStream_t s
   const OpTables &T = op_tables(P->p, st);
   {
     StageTimer tm("upward", st);
-    const int direct_levels = 3;  // levels L, L-1, L-2 from the stars
+    // windowed levels, and up to three of the finest dense ones (while boxes
+    // hold ~2048 sources or fewer on average), from the stars; the coarser
+    // dense levels by M2M
+    const int D = P->dense_top, direct_levels = 3;
+    auto from_stars = [&](int l) {
+      if (l > D) return true;
+      return l > D - direct_levels &&
+             (l == D || (double)N <= 2048.0 * (double)(int64_t(1) << (2 * l)));
+    };
     for (int l = L; l >= 2; --l) {
       double *out = static_cast<double *>(P->mp[l].ptr);
       float *out32 = static_cast<float *>(P->mp32[l].ptr);
-      if (l > L - direct_levels)
-        launch_p2m(P->g, l, sxy, sm, P->qdim, leaf_start, P->p, out, out32, st);
+      if (from_stars(l))
+        launch_p2m(P->g, l, P->swin[l], sxy, sm, P->qdim, leaf_start, P->p, out, out32, N, st);
       else
         launch_m2m(l, P->p, P->mp_at(l + 1), out, out32, T.m2m, st);
     }
@@ -359,8 +411,8 @@ lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_gri
 
 void check_inside(const lens_plan &P, const double bb[4]) {
   const double tol = 1e-12 * P.g.side;
-  if (bb[0] < P.domain[0] - tol || bb[1] < P.domain[1] - tol || bb[2] > P.domain[2] + tol ||
-      bb[3] > P.domain[3] + tol)
+  if (bb[0] < P.target[0] - tol || bb[1] < P.target[1] - tol || bb[2] > P.target[2] + tol ||
+      bb[3] > P.target[3] + tol)
     fail(LENS_EINVAL, "rays lie outside the region the plan was built for (pass ray_box to lens_plan_create)");
 }
 
@@ -397,7 +449,7 @@ void downward_enqueue(const lens_plan &P, const LocalSet &ls, hipStream_t st) {
   auto level_of = [&](int l) {
     return M2LLevel{l, std::ldexp(P.g.side, -l), ls.win[l],
                     is_f32(l) ? (const void *)P.mp32_at(l) : (const void *)P.mp_at(l), ls.at(l),
-                    nullptr, Window{0, 0, 0, 0}};
+                    nullptr, Window{0, 0, 0, 0}, P.swin[l]};
   };
   const int first_fused = std::max(3, L - 1);
   M2LBatch coarse, fine;
@@ -528,8 +580,9 @@ void gridexec_alloc(const lens_plan &P, const lens_grid &grid, int64_t j0, int64
     const int64_t n = std::fabs(r - k) < 1e-9 * r ? (int64_t)k : (int64_t)std::floor(r) + 1;
     return std::max<int64_t>(1, std::min(n, cap));
   };
-  eval_shape(per_box(grid.dx, grid.nx) * per_box(grid.dy, j1 - j0), &ea.rays_per_lane,
-             &ea.chunks_per_box);
+  int64_t tiles = 0;
+  grid_tile_shape(per_box(grid.dx, grid.nx), per_box(grid.dy, j1 - j0), &ea.tile_shift, &tiles);
+  eval_shape(tiles * 64, &ea.rays_per_lane, &ea.chunks_per_box);
   while (wl.count() * ea.chunks_per_box > (int64_t)0x7fffffff && ea.chunks_per_box > 1)
     ea.chunks_per_box = (ea.chunks_per_box + 1) / 2;
   if (wl.count() > (int64_t)0x7fffffff) fail(LENS_EUNSUPPORTED, "leaf window too large");
@@ -860,7 +913,14 @@ lens_status lens_plan_create(const lens_field *field, const double *ray_box, con
         if (!is_finite(ray_box[c])) fail(LENS_EINVAL, "ray_box must be finite");
       if (ray_box[2] < ray_box[0] || ray_box[3] < ray_box[1]) fail(LENS_EINVAL, "ray_box is empty");
     }
-    *out = build_plan(*field, ray_box, grid, 0.0, o, (hipStream_t)stream);
+    // with a grid, the leaf level is chosen for its ray density, as for the
+    // plans lens_deflect and lens_map build themselves
+    double density = 0.0;
+    if (grid && grid->nx > 0 && grid->ny > 0) {
+      const double area = std::max((gbox[2] - gbox[0]) * (gbox[3] - gbox[1]), 1e-300);
+      density = (double)(grid->nx * grid->ny) / area;
+    }
+    *out = build_plan(*field, ray_box, grid, density, o, (hipStream_t)stream);
   });
 }
 

@@ -131,15 +131,15 @@ __global__ __launch_bounds__(kThreads) void k_m2l_mfma(M2LBatch bt, const T *__r
   const M2LLevel &a = bt.lv[li];
   const T *__restrict__ mp = static_cast<const T *>(a.mp);
   const int p = bt.p, twop = 2 * p;
-  const int64_t nb = int64_t(1) << a.level;
   const int64_t ex0 = a.win.bx0 & ~int64_t(1), ey0 = a.win.by0 & ~int64_t(1);
   const int64_t ntx = (a.win.bx0 + a.win.nbx - ex0 + TILE - 1) / TILE;
   const int64_t tile = (int64_t)blockIdx.x - bt.tile_begin[li];
   const int64_t tx0 = ex0 + TILE * (tile % ntx);
   const int64_t ty0 = ey0 + TILE * (tile / ntx);
 
-  // stage the source multipoles of boxes [tx0-2, tx0+TILE+2) x [ty0-2, ...):
-  // all of a thread's loads are issued before its LDS stores
+  // stage the source multipoles of boxes [tx0-2, tx0+TILE+2) x [ty0-2, ...)
+  // (zero outside the stored window swin, which holds every source of the
+  // level's targets): all of a thread's loads are issued before its LDS stores
   constexpr int KP = 4 * KS;
   constexpr int NE = S * S * KP, NIT = (NE + kThreads - 1) / kThreads;
   {
@@ -149,10 +149,10 @@ __global__ __launch_bounds__(kThreads) void k_m2l_mfma(M2LBatch bt, const T *__r
       const int e = it * kThreads + threadIdx.x;
       const int k = e % KP, bl = e / KP;
       const int bx = bl % S, by = bl / S;
-      const int64_t gx = tx0 - 2 + bx, gy = ty0 - 2 + by;
+      const int64_t gx = tx0 - 2 + bx - a.swin.bx0, gy = ty0 - 2 + by - a.swin.by0;
       v[it] = 0;
-      if (e < NE && k < twop && gx >= 0 && gy >= 0 && gx < nb && gy < nb)
-        v[it] = mp[(gy * nb + gx) * twop + k];
+      if (e < NE && k < twop && gx >= 0 && gy >= 0 && gx < a.swin.nbx && gy < a.swin.nby)
+        v[it] = mp[(gy * a.swin.nbx + gx) * twop + k];
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -341,13 +341,12 @@ __global__ __launch_bounds__(kThreads) void k_m2l_valu(DownArgs a, const T *__re
   T ar[PMAX], ai[PMAX];
 #pragma unroll
   for (int l = 0; l < PMAX; ++l) ar[l] = ai[l] = 0;
-  const int64_t nb = int64_t(1) << a.level;
   for (int ty = -2 - qy; ty <= 3 - qy; ++ty) {
     for (int tx = -2 - qx; tx <= 3 - qx; ++tx) {
       if (tx >= -1 && tx <= 1 && ty >= -1 && ty <= 1) continue;
-      const int64_t sx = tg.tx + tx, sy = tg.ty + ty;
-      if (sx < 0 || sy < 0 || sx >= nb || sy >= nb) continue;
-      const T *src = mp + 2 * (sy * nb + sx) * p;
+      const int64_t sx = tg.tx + tx - a.swin.bx0, sy = tg.ty + ty - a.swin.by0;
+      if (sx < 0 || sy < 0 || sx >= a.swin.nbx || sy >= a.swin.nby) continue;
+      const T *src = mp + 2 * (sy * a.swin.nbx + sx) * p;
       const T *t = m2l + (size_t)((ty + 3) * 7 + (tx + 3)) * p * p * 2;
 #pragma unroll
       for (int k = 0; k < PMAX; ++k) {
@@ -462,6 +461,7 @@ void launch_m2l_batch(M2LBatch &b, const OpTables &t, bool fp32, hipStream_t str
       a.p = b.p;
       a.s = b.lv[i].s;
       a.win = b.lv[i].win;
+      a.swin = b.lv[i].swin;
       a.loc = b.lv[i].loc;
       if (a.win.count() == 0) continue;
       if (fp32) {

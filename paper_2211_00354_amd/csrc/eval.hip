@@ -63,6 +63,22 @@ __device__ __forceinline__ void pair_update(const double (&rx)[R], const double 
   }
 }
 
+// Add one count per lane whose key is >= 0 to counts[key], one atomic per
+// distinct key of the wave: the lanes holding the first pending key are
+// found with a ballot and their count added by one lane.  Neighbouring rays
+// mostly land in one pixel, so a wave of rays issues a few atomics, not 64.
+__device__ __forceinline__ void wave_add_counts(int32_t key, int32_t *__restrict__ counts) {
+  const int lane = threadIdx.x;
+  uint64_t pending = __ballot(key >= 0);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int32_t k = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t same = __ballot(key == k);
+    if (lane == leader) atomicAdd(&counts[k], (int32_t)__popcll(same));
+    pending &= ~same;
+  }
+}
+
 template <int PMAX, bool MIXED, bool MAP, bool GRID, int R>
 __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__restrict__ loc,
                                                 const double *__restrict__ sxy,
@@ -75,6 +91,8 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
                                                 const int32_t *__restrict__ ray_start,
                                                 double *__restrict__ y_out,
                                                 int32_t *__restrict__ counts) {
+  // the box's local expansion, read by every lane (LDS broadcast)
+  __shared__ double2 lds_loc[PMAX];
   const int lane = threadIdx.x;
   // unit counts fit in 31 bits (checked at launch)
   const uint32_t CH = (uint32_t)a.chunks_per_box;
@@ -90,6 +108,10 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
   const double inv_s = 1.0 / s;
   const int p = a.p;
   constexpr int RPC = kWave * R;
+  // grid rays: a wave's R slots are R tiles of TX x TY rays (TX * TY = 64)
+  const int tsh = a.tile_shift;
+  const int TX = 1 << tsh, TY = kWave >> tsh;
+  const int lx = lane & (TX - 1), ly = lane >> tsh;
 
   for (uint32_t u = vb; u < nunits; u += G) {
     const uint32_t b = CH == 1 ? u : u / CH;
@@ -97,18 +119,24 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
     const uint32_t byw = b / nbx, bxw = b - byw * nbx;
     const int64_t gx = a.win.bx0 + bxw, gy = a.win.by0 + byw;
 
-    int32_t nr, i0 = 0, j0 = 0, W = 1, r0 = 0;
+    // grid: the box's rays are columns [i0, i0+W) x rows [j0, j0+H), cut into
+    // nt = TW x TH tiles, tpc consecutive tiles per unit; explicit: rays
+    // [r0, r0+nr) of the sorted array in chunks of RPC
+    int32_t nr = 0, r0 = 0, i0 = 0, j0 = 0, W = 0, H = 0, TW = 1, nt = 0, tpc = 0;
     if (GRID) {
       i0 = col_start[bxw];
       W = col_start[bxw + 1] - i0;
       j0 = row_start[byw];
-      nr = W * (row_start[byw + 1] - j0);
+      H = row_start[byw + 1] - j0;
+      TW = (W + TX - 1) >> tsh;
+      nt = TW * ((H + TY - 1) / TY);
+      tpc = (nt + (int32_t)CH - 1) / (int32_t)CH;
+      if (nt == 0 || (int64_t)c0 * tpc >= nt) continue;  // uniform
     } else {
       r0 = ray_start[b];
       nr = ray_start[b + 1] - r0;
+      if (nr == 0 || (int64_t)c0 * RPC >= nr) continue;  // uniform
     }
-    if (nr == 0 || (int64_t)c0 * (GRID ? (nr + (int64_t)CH - 1) / (int64_t)CH : RPC) >= nr)
-      continue;  // uniform
 
     int32_t rs[3], re[3];
 #pragma unroll
@@ -125,17 +153,23 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
     }
     const double cx = a.g.x0 + ((double)gx + 0.5) * s;
     const double cy = a.g.y0 + ((double)gy + 0.5) * s;
-    cplx lc[PMAX];
-    const double *lb = loc + 2 * (int64_t)b * p;
-#pragma unroll
-    for (int l = 0; l < PMAX; ++l) lc[l] = (l < p) ? cplx{lb[2 * l], lb[2 * l + 1]} : cplx{0.0, 0.0};
+    __syncthreads();  // the previous unit's reads of lds_loc are done
+    if (lane < p) lds_loc[lane] = reinterpret_cast<const double2 *>(loc + 2 * (int64_t)b * p)[lane];
+    __syncthreads();
 
-    // grid rays: the box's rays split evenly over its CH units; explicit rays:
-    // chunks of RPC rays, a box's extra chunks looped over by its units.  A
-    // chunk longer than RPC is processed RPC rays at a time.
-    const int32_t csz = GRID ? (int32_t)((nr + (int32_t)CH - 1) / (int32_t)CH) : RPC;
-    for (uint32_t c = c0; (int64_t)c * csz < nr; c += CH)
-    for (int32_t base = (int32_t)c * csz, cend = min(nr, base + csz); base < cend; base += RPC) {
+    // passes of R tiles (grid) or RPC rays (explicit); explicit rays beyond
+    // CH chunks are looped over by the box's units
+    int32_t pos, pend, pstep;
+    if (GRID) {
+      pos = (int32_t)c0 * tpc;
+      pend = min(nt, pos + tpc);
+      pstep = R;
+    } else {
+      pos = (int32_t)c0 * RPC;
+      pend = nr;
+      pstep = (int32_t)CH * RPC;
+    }
+    for (; pos < pend; pos += pstep) {
       double rx[R], ry[R];
       using acc_t = typename std::conditional<MIXED, float, double>::type;
       acc_t ax[R], ay[R];
@@ -143,16 +177,19 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
       bool act[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int32_t idx = base + r * kWave + lane;
-        act[r] = idx < cend;
-        const int32_t id = act[r] ? idx : 0;
         if (GRID) {
-          const int32_t q = id / W;
-          const int64_t i = i0 + (id - q * W), j = j0 + q;
+          const int32_t t = pos + r;  // wave-uniform tile index
+          const int32_t ty = t / TW, tx = t - ty * TW;
+          const int32_t ci = tx * TX + lx, cj = ty * TY + ly;
+          act[r] = t < pend && ci < W && cj < H;
+          const int64_t i = i0 + (act[r] ? ci : 0), j = j0 + (act[r] ? cj : 0);
           rx[r] = grid_coord(a.grid.x0, a.grid.dx, i);
           ry[r] = grid_coord(a.grid.y0, a.grid.dy, j);
           oidx[r] = j * a.grid.nx + i;
         } else {
+          const int32_t idx = pos + r * kWave + lane;
+          act[r] = idx < min(nr, pos + RPC);
+          const int32_t id = act[r] ? idx : 0;
           rx[r] = rxy[2 * ((int64_t)r0 + id)];
           ry[r] = rxy[2 * ((int64_t)r0 + id) + 1];
           oidx[r] = rperm ? (int64_t)rperm[r0 + id] : (int64_t)r0 + id;
@@ -180,27 +217,38 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
           pair_update<MIXED, R>(rx, ry, sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i], ax, ay);
       }
 
+      // far field: Horner over the R rays, one LDS read per coefficient
+      cplx w[R], f[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const cplx w = {(rx[r] - cx) * inv_s, (ry[r] - cy) * inv_s};
-        cplx f = {0.0, 0.0};
+        w[r] = cplx{(rx[r] - cx) * inv_s, (ry[r] - cy) * inv_s};
+        f[r] = cplx{0.0, 0.0};
+      }
 #pragma unroll
-        for (int l = PMAX - 1; l >= 0; --l)
-          if (l < p) f = cmad(f, w, lc[l]);
-        const double al1 = f.re + (double)ax[r];
-        const double al2 = (double)ay[r] - f.im;
+      for (int l = PMAX - 1; l >= 0; --l)
+        if (l < p) {
+          const double2 c = lds_loc[l];
+#pragma unroll
+          for (int r = 0; r < R; ++r) f[r] = cmad(f[r], w[r], cplx{c.x, c.y});
+        }
+
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double al1 = f[r].re + (double)ax[r];
+        const double al2 = (double)ay[r] - f[r].im;
         const double y1 = a.c1 * rx[r] - al1;
         const double y2 = a.c2 * ry[r] - al2;
-        if (!act[r]) continue;
         if (MAP) {
+          int32_t key = -1;
           const double t1 = (y1 - a.y1min) * a.S;
           const double t2 = (y2 - a.y2min) * a.S;
-          if (t1 >= 0.0 && t2 >= 0.0) {
+          if (act[r] && t1 >= 0.0 && t2 >= 0.0) {
             const double f1 = floor(t1), f2 = floor(t2);
             if (f1 < (double)a.npix && f2 < (double)a.npix)
-              atomicAdd(&counts[(int64_t)f2 * a.npix + (int64_t)f1], 1);
+              key = (int32_t)f2 * a.npix + (int32_t)f1;
           }
-        } else {
+          wave_add_counts(key, counts);
+        } else if (act[r]) {
           *reinterpret_cast<double2 *>(y_out + 2 * oidx[r]) = make_double2(y1, y2);
         }
       }
@@ -300,6 +348,24 @@ void eval_shape(int64_t max_rays, int *R, int64_t *CH) {
   }
   *R = best_r;
   *CH = best_ch;
+}
+
+// Tile shape for grid rays in boxes of at most W x H rays: TX = 2^shift
+// columns by 64/TX rows, the fewest tiles per box, ties going to the
+// squarest tile (rays of a square tile land close together in a map).
+void grid_tile_shape(int64_t W, int64_t H, int *shift, int64_t *tiles) {
+  int best = 3;
+  int64_t best_t = -1;
+  for (int sh : {3, 2, 4, 1, 5, 0, 6}) {
+    const int64_t tx = int64_t(1) << sh, ty = kWave / tx;
+    const int64_t t = ((W + tx - 1) / tx) * ((H + ty - 1) / ty);
+    if (best_t < 0 || t < best_t) {
+      best_t = t;
+      best = sh;
+    }
+  }
+  *shift = best;
+  *tiles = best_t;
 }
 
 void launch_eval(const EvalArgs &a, int precision, hipStream_t stream) {

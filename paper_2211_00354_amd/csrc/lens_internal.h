@@ -133,8 +133,10 @@ void build_l2l_bfrag(int p, int ks_count, int nt_count, std::vector<double> &out
 
 // Upward pass (upward.hip)
 // (mp32 outputs are optional FP32 copies of the same coefficients)
-void launch_p2m(Geometry g, int level, const double *sxy, const double *sq, int qdim,
-                const int32_t *leaf_start, int p, double *mp, float *mp32, hipStream_t stream);
+// n_sources (all levels) picks a wave per box when boxes hold many sources.
+void launch_p2m(Geometry g, int level, Window win, const double *sxy, const double *sq, int qdim,
+                const int32_t *leaf_start, int p, double *mp, float *mp32, int64_t n_sources,
+                hipStream_t stream);
 void launch_m2m(int level, int p, const double *child, double *parent, float *parent32,
                 const double *m2m, hipStream_t stream);
 
@@ -144,8 +146,9 @@ struct DownArgs {
   int level, p;
   double s;              // box side at this level
   Window win, pwin;      // target window and parent window
-  const double *mp;      // multipoles at this level, [4^level][p] complex FP64
+  const double *mp;      // multipoles at this level, [swin][p] complex FP64
   const float *mp32;     // same in FP32 (mixed fine levels) or nullptr
+  Window swin;           // boxes held in mp / mp32
   const double *ploc;    // parent locals [pwin][p] or nullptr (level 2)
   double *loc;           // output locals [win][p]
 };
@@ -164,6 +167,7 @@ struct M2LLevel {
   double *loc;
   const double *ploc;   // fused L2L: parent locals (window pwin), or nullptr
   Window pwin;
+  Window swin;          // boxes held in mp ([swin][p], row-major in the window)
 };
 struct M2LBatch {
   int count = 0, p = 0;
@@ -196,6 +200,7 @@ struct EvalArgs {
   const int32_t *ray_start;   // explicit: [win.count() + 1]
   int64_t chunks_per_box;     // units (waves) per leaf box
   int rays_per_lane;          // R: rays held per lane (1..4), 64*R rays per unit
+  int tile_shift;             // grid: a wave's 64 rays are a 2^tile_shift-wide tile
   double c1, c2;              // (1 - kappa_s - gamma), (1 - kappa_s + gamma)
   double *y_out;              // [n][2] or nullptr
   // map
@@ -209,6 +214,7 @@ void launch_eval(const EvalArgs &a, int precision, hipStream_t stream);
 void launch_grid_ranges(const lens_grid &grid, Geometry g, Window win, int64_t j_begin,
                         int64_t j_end, int32_t *col_start, int32_t *row_start, hipStream_t stream);
 void eval_shape(int64_t max_rays, int *R, int64_t *CH);
+void grid_tile_shape(int64_t W, int64_t H, int *shift, int64_t *tiles);
 void launch_ray_keys(const double *rxy, int64_t n, Geometry g, Window win, uint32_t *keys,
                      uint32_t *vals, hipStream_t stream);
 
