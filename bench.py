@@ -13,8 +13,8 @@ are resident in HBM before the timed region; grid rays need no input bytes.
 --workload map runs the high-magnification map instead: 5e6 equal-mass
 stars (kappa_* = 0.1, kappa_s = 0.75, gamma = 0.05, mu = 50), a 16384^2 ray
 grid over [-120,120] x [-60,60] shot into a 2000^2 int32 map over [-10,10]^2
-(one lens_map call per step, mixed precision at p = 20 with every M2L level
-in FP64, the setting that keeps the bin-reassignment rate under 1e-4).
+(one lens_map call per step, mixed precision with p, leaf level and FP32 M2L
+levels from the autotuner for a 1e-4 expected bin-reassignment rate).
 """
 from __future__ import annotations
 
@@ -263,14 +263,20 @@ def bench_map(args):
     from paper_2211_00354_amd import _lib
     import workloads as wl
 
-    p = 20 if args.p == 12 else args.p  # the map's accuracy needs p = 20
-    fl = -1
     log("generating workload")
     f, g, mp = wl.config3()
     xy = torch.from_numpy(f.xy).cuda()
     m = torch.from_numpy(f.m).cuda()
     grid = lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny)
     md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
+    # p, leaf level and FP32 levels from the autotuner for a 1e-4 expected
+    # bin-reassignment rate (outside the timed region)
+    t0 = time.perf_counter()
+    tuned = lf.autotune(xy, m, grid, map=md, tol=1e-4, kappa_s=f.kappa_s, gamma=f.gamma,
+                        leaf_level=args.leaf)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune: {tuned} in {tune_s:.2f} s")
+    p, fl, args.leaf = tuned["p"], tuned["fp32_levels"], tuned["leaf_level"]
     counts = torch.zeros((mp.npix, mp.npix), dtype=torch.int32, device="cuda")
     kw = dict(kappa_s=f.kappa_s, gamma=f.gamma, precision="mixed", p=p, fp32_levels=fl,
               leaf_level=args.leaf)
@@ -305,7 +311,8 @@ def bench_map(args):
     ev_ms, ev_n = prof.get("eval_map", (float("nan"), 1))
     ev_avg = ev_ms / max(ev_n, 1)
     achieved = flops / (ev_avg * 1e-3)
-    extra = {"leaf_level": leaf, "p": p, "fp32_levels": "none", "near_pairs_per_ray": pairs / g.n,
+    extra = {"leaf_level": leaf, "p": p, "fp32_levels": fl, "autotune": tuned, "autotune_s": tune_s,
+             "near_pairs_per_ray": pairs / g.n,
              "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
              "eval_flops_per_launch": flops, "mean_count": float(counts.double().mean())}
     cpu = None

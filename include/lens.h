@@ -111,6 +111,10 @@ typedef struct {
                            levels runs on FP32 MFMA, coarser levels on FP64;
                            0 = 2 levels, -1 = none (all M2L in FP64), at most
                            LENS_MAX_LEVEL.  Ignored for LENS_FP64. */
+  double tol;           /* lens_map_batched with order_p = 0 and tol > 0: each
+                           field's p, leaf level and fp32_levels are chosen by
+                           lens_autotune for this expected bin-reassignment
+                           fraction; otherwise unused */
 } lens_opts;
 
 /* Fill *o with the defaults (FMM, mixed, p = 12, automatic leaf level). */
@@ -167,6 +171,28 @@ LENS_API lens_status lens_deflect(lens_plan *plan, const lens_field *field, cons
  */
 LENS_API lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *grid,
                      const lens_map_desc *map, const lens_opts *opts, void *stream);
+
+/*
+ * Empirical autotuner for one field and ray grid: the expansion order p, the
+ * leaf level and, for LENS_MIXED, fp32_levels (Appendix A leaves p and the
+ * tree depth to the user; here they are measured).  A strided sample of at
+ * most 128 x 128 rays of `grid` is deflected by the FP64 direct sum and by
+ * the FMM at p = 6, 7, ... (a plan over the whole grid, as lens_deflect and
+ * lens_map build it).  The error is the relative l2 norm of the deflection
+ * error over that of alpha when map is NULL, else the expected fraction of
+ * rays binned into another pixel of `map`, mean(|dy1| + |dy2|) npix / side
+ * (map->counts is not touched).  Of the settings that reach `tol` the one
+ * with the fastest whole lens_deflect (or lens_map) call is kept, and the
+ * leaf level one either side of the library's choice is timed too (unless
+ * base->leaf_level is set).  base: method and precision.  Runs full calls on
+ * scratch memory and synchronises `stream`.  *out receives the chosen
+ * options; err_out and ms_out (may be NULL) the sampled error and the time
+ * of one call in ms.  LENS_EUNSUPPORTED if no p up to LENS_MAX_ORDER reaches
+ * tol; *out then holds the most accurate setting tried.
+ */
+LENS_API lens_status lens_autotune(const lens_field *field, const lens_grid *grid,
+                                   const lens_map_desc *map, double tol, const lens_opts *base,
+                                   void *stream, lens_opts *out, double *err_out, double *ms_out);
 
 /*
  * Stage profiler.  lens_profile_enable(1) clears the totals and starts

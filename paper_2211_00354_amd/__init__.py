@@ -19,8 +19,8 @@ from . import _lib
 from ._lib import (LENS_DIRECT, LENS_FMM, LENS_FP64, LENS_MIXED, LensError, LensField, LensGrid,
                    LensMapDesc, LensOpts)
 
-__all__ = ["Grid", "MapDesc", "Plan", "deflect", "deflect_backward", "irs_map", "irs_map_batched",
-           "LensDeflect", "LensError", "release_cached", "version"]
+__all__ = ["Grid", "MapDesc", "Plan", "autotune", "deflect", "deflect_backward", "irs_map",
+           "irs_map_batched", "LensDeflect", "LensError", "release_cached", "version"]
 
 
 @dataclass
@@ -207,11 +207,13 @@ def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
 
 
 def irs_map_batched(fields, grids, maps, counts=None, method="fmm", precision="mixed", p=12,
-                    leaf_level=0, fp32_levels=0):
+                    leaf_level=0, fp32_levels=0, tol=0.0):
     """Inverse ray shooting for many independent fields in one captured HIP
     graph.  ``fields`` is a list of (star_xy, star_m, kappa_s, gamma);
     ``grids``/``maps`` lists of Grid/MapDesc; returns the list of int32 count
-    maps (accumulated into ``counts`` if given)."""
+    maps (accumulated into ``counts`` if given).  With ``p=0`` and ``tol > 0``
+    each field's p, leaf level and FP32 levels come from the autotuner (bin
+    reassignment target ``tol``) when the batch is first built."""
     torch = _torch()
     lib = _lib.load()
     n = len(fields)
@@ -231,8 +233,31 @@ def irs_map_batched(fields, grids, maps, counts=None, method="fmm", precision="m
             raise ValueError("counts must be contiguous int32 [npix, npix] GPU tensors")
         ma[k] = LensMapDesc(mp.y1min, mp.y2min, mp.side, mp.npix, c.data_ptr())
     o = _opts(method, precision, p, leaf_level, fp32_levels=fp32_levels)
+    o.tol = float(tol)
     _lib.check(lib.lens_map_batched(n, fa, ga, ma, ctypes.byref(o), _stream()))
     return counts
+
+
+def autotune(star_xy, star_m, grid: Grid, map: Optional[MapDesc] = None, tol=1e-5, kappa_s=0.0,
+             gamma=0.0, precision="mixed", leaf_level=0) -> dict:
+    """Choose p, leaf level and FP32 levels by measurement: the sampled error
+    against the FP64 direct sum (relative l2 of alpha, or with ``map`` the
+    expected bin-reassignment fraction) must reach ``tol``, and the fastest
+    such whole call wins.  Returns {"p", "leaf_level", "fp32_levels",
+    "error", "ms"}; raises LensError if no p up to 40 reaches tol."""
+    lib = _lib.load()
+    f = _field(star_xy, star_m, kappa_s, gamma)
+    g = grid.c()
+    base = _opts("fmm", precision, 0, leaf_level)
+    out = LensOpts()
+    err, ms = ctypes.c_double(), ctypes.c_double()
+    md = None
+    if map is not None:
+        md = ctypes.byref(LensMapDesc(map.y1min, map.y2min, map.side, map.npix, None))
+    _lib.check(lib.lens_autotune(ctypes.byref(f), ctypes.byref(g), md, float(tol), ctypes.byref(base),
+                                 _stream(), ctypes.byref(out), ctypes.byref(err), ctypes.byref(ms)))
+    return {"p": out.order_p, "leaf_level": out.leaf_level, "fp32_levels": out.fp32_levels,
+            "error": err.value, "ms": ms.value}
 
 
 def release_cached():

@@ -44,7 +44,8 @@ class LensMapDesc(ctypes.Structure):
 class LensOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("order_p", ctypes.c_int32), ("leaf_level", ctypes.c_int32),
-                ("max_rays_per_chunk", ctypes.c_int64), ("fp32_levels", ctypes.c_int32)]
+                ("max_rays_per_chunk", ctypes.c_int64), ("fp32_levels", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
 
 
 _lib = None
@@ -86,6 +87,9 @@ def load(path: str = LIB_PATH):
     lib.lens_deflect_backward.restype = ctypes.c_int
     lib.lens_map_batched.argtypes = [I32, P(LensField), P(LensGrid), P(LensMapDesc), P(LensOpts), V]
     lib.lens_map_batched.restype = ctypes.c_int
+    lib.lens_autotune.argtypes = [P(LensField), P(LensGrid), P(LensMapDesc), D, P(LensOpts), V,
+                                  P(LensOpts), P(D), P(D)]
+    lib.lens_autotune.restype = ctypes.c_int
     lib.lens_release_cached.argtypes = []
     lib.lens_release_cached.restype = None
     lib.lens_profile_enable.argtypes = [I32]

@@ -701,6 +701,212 @@ void check_plan_device(const lens_plan *plan) {
 
 namespace {
 
+// ------------------------------------------------------------- autotuner
+// Accuracy is measured, not modelled: a strided sample of at most 128 x 128
+// rays of the grid is deflected by the FP64 direct sum and by the FMM (a
+// plan over the whole grid, as a real call builds it) at increasing p.  The
+// error is the relative l2 of alpha, or for a map the expected fraction of
+// rays binned into another pixel, mean(|dy1| + |dy2|) * npix / side.  Among
+// the settings that reach the target the fastest whole call is kept.
+
+struct TuneOut {
+  lens_opts o;
+  double err = 0, ms = 0;
+  bool met = false;
+};
+
+struct TuneSample {
+  int64_t n = 0;
+  std::vector<double> rays, yref;
+  double *d_rays = nullptr, *d_y = nullptr;
+  double bb[4];
+};
+
+double tune_error(const TuneSample &ts, const std::vector<double> &y, double c1, double c2,
+                  const lens_map_desc *map) {
+  if (map) {
+    double acc = 0;
+    for (int64_t k = 0; k < ts.n; ++k)
+      acc += std::fabs(y[2 * k] - ts.yref[2 * k]) + std::fabs(y[2 * k + 1] - ts.yref[2 * k + 1]);
+    return acc / (double)std::max<int64_t>(ts.n, 1) * (double)map->npix / map->side;
+  }
+  double num = 0, den = 0;
+  for (int64_t k = 0; k < ts.n; ++k) {
+    const double d1 = y[2 * k] - ts.yref[2 * k], d2 = y[2 * k + 1] - ts.yref[2 * k + 1];
+    const double a1 = c1 * ts.rays[2 * k] - ts.yref[2 * k];
+    const double a2 = c2 * ts.rays[2 * k + 1] - ts.yref[2 * k + 1];
+    num += d1 * d1 + d2 * d2;
+    den += a1 * a1 + a2 * a2;
+  }
+  return den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+}
+
+// Time of one whole call (lens_map into a scratch map, or lens_deflect into
+// a scratch output), after one untimed call.
+double tune_time(const lens_field &f, const lens_grid &g, const lens_map_desc *map,
+                 const lens_opts &o, void *scratch, hipStream_t st) {
+  lens_map_desc md{};
+  if (map) {
+    md = *map;
+    md.counts = static_cast<int32_t *>(scratch);
+  }
+  auto call = [&] {
+    const lens_status r = map ? lens_map(nullptr, &f, &g, &md, &o, st)
+                              : lens_deflect(nullptr, &f, &g, nullptr, g.nx * g.ny,
+                                             static_cast<double *>(scratch), &o, st);
+    if (r != LENS_OK) fail(r, last_error());
+  };
+  call();
+  hipEvent_t e0, e1;
+  LENS_HIP(hipEventCreate(&e0));
+  LENS_HIP(hipEventCreate(&e1));
+  float ms = 0;
+  try {
+    LENS_HIP(hipEventRecord(e0, st));
+    call();
+    LENS_HIP(hipEventRecord(e1, st));
+    LENS_HIP(hipEventSynchronize(e1));
+    LENS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+TuneOut autotune_field(const lens_field &f, const lens_grid &g, const lens_map_desc *map,
+                       double tol, const lens_opts &base, hipStream_t st) {
+  TuneOut best;
+  best.o = base;
+  if (base.method == LENS_DIRECT || f.n_stars == 0 || g.nx == 0 || g.ny == 0) {
+    best.met = true;
+    return best;
+  }
+  Scratch sc(st);
+  TuneSample ts;
+  const int64_t sx = std::max<int64_t>(1, g.nx / 128), sy = std::max<int64_t>(1, g.ny / 128);
+  for (int64_t j = sy / 2; j < g.ny; j += sy)
+    for (int64_t i = sx / 2; i < g.nx; i += sx) {
+      ts.rays.push_back(grid_x(g, i));
+      ts.rays.push_back(g.y0 + ((double)j + 0.5) * g.dy);
+    }
+  ts.n = (int64_t)ts.rays.size() / 2;
+  ts.d_rays = sc.get<double>(ts.rays.size());
+  ts.d_y = sc.get<double>(ts.rays.size());
+  LENS_HIP(hipMemcpyAsync(ts.d_rays, ts.rays.data(), ts.rays.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+  const double c1 = (1.0 - f.kappa_s) - f.gamma, c2 = (1.0 - f.kappa_s) + f.gamma;
+  {
+    DirectArgs d{};
+    d.n_stars = f.n_stars;
+    d.sxy = f.xy;
+    d.sm = f.m;
+    d.rxy = ts.d_rays;
+    d.n_rays = ts.n;
+    d.c1 = c1;
+    d.c2 = c2;
+    d.y_out = ts.d_y;
+    launch_direct(d, st);
+  }
+  ts.yref.resize(ts.rays.size());
+  LENS_HIP(hipMemcpyAsync(ts.yref.data(), ts.d_y, ts.rays.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+  LENS_HIP(hipStreamSynchronize(st));
+  double gb[4];
+  grid_bbox(g, 0, g.ny, gb);
+  const double area = std::max((gb[2] - gb[0]) * (gb[3] - gb[1]), 1e-300);
+  const double density = (double)(g.nx * g.ny) / area;
+  // sampled error of one setting
+  auto measure = [&](lens_opts o) {
+    const lens_opts r = resolve_opts(&o);
+    lens_plan *P = build_plan(f, gb, &g, density, r, st);
+    std::vector<double> y(ts.rays.size());
+    try {
+      fmm_explicit(*P, ts.d_rays, ts.n, gb, c1, c2, ts.d_y, st);
+      LENS_HIP(hipMemcpyAsync(y.data(), ts.d_y, y.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      LENS_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      lens_plan_destroy(P);
+      throw;
+    }
+    lens_plan_destroy(P);
+    return tune_error(ts, y, c1, c2, map);
+  };
+  // per FP32-level family, the smallest p that reaches tol.  The error falls
+  // in steps rather than smoothly (for near-uniform boxes the moments a_k
+  // with k a multiple of 4 dominate, so p = 14 and p = 16 can tie), so every
+  // p is tried; a family stops after six orders without a 30% gain (its
+  // rounding floor).
+  std::vector<int> families = {0};
+  if (base.precision == LENS_MIXED) families = {2, -1};
+  std::vector<TuneOut> met;
+  TuneOut most{};
+  most.err = std::numeric_limits<double>::infinity();
+  for (int fl : families) {
+    double best_e = std::numeric_limits<double>::infinity();
+    int stall = 0;
+    for (int p = 6; p <= LENS_MAX_ORDER; ++p) {
+      lens_opts o = base;
+      o.order_p = p;
+      o.fp32_levels = fl;
+      const double e = measure(o);
+      if (e < most.err) {
+        most.o = o;
+        most.err = e;
+      }
+      if (e <= tol) {
+        TuneOut t;
+        t.o = o;
+        t.err = e;
+        t.met = true;
+        met.push_back(t);
+        break;
+      }
+      if (e < 0.7 * best_e) {
+        best_e = e;
+        stall = 0;
+      } else if (++stall >= 6) {
+        break;
+      }
+    }
+  }
+  if (met.empty()) {
+    most.met = false;
+    return most;
+  }
+  // the fastest of the families' settings, then the leaf level around the
+  // library's choice
+  void *scratch = map ? (void *)sc.get<int32_t>((size_t)map->npix * map->npix)
+                      : (void *)sc.get<double>((size_t)g.nx * g.ny * 2);
+  for (auto &t : met) t.ms = tune_time(f, g, map, t.o, scratch, st);
+  best = *std::min_element(met.begin(), met.end(),
+                           [](const TuneOut &a, const TuneOut &b) { return a.ms < b.ms; });
+  if (base.leaf_level == 0) {
+    lens_plan *P = build_plan(f, gb, &g, density, resolve_opts(&best.o), st);
+    const int L0 = P->g.L;
+    lens_plan_destroy(P);
+    best.o.leaf_level = L0;
+    for (int L : {L0 - 1, L0 + 1}) {
+      if (L < 2 || L > 13) continue;
+      lens_opts o = best.o;
+      o.leaf_level = L;
+      const double ms = tune_time(f, g, map, o, scratch, st);
+      if (ms < best.ms) {
+        const double e = measure(o);
+        if (e <= tol) {
+          best.o = o;
+          best.ms = ms;
+          best.err = e;
+        }
+      }
+    }
+  }
+  return best;
+}
+
 // ------------------------------------------------------- batched fields
 // lens_map_batched: every field's tree build, upward pass, downward pass and
 // binned evaluation, allocated up front and captured as one HIP graph whose
@@ -760,6 +966,7 @@ std::vector<uint64_t> batch_key(int dev, int n, const lens_field *f, const lens_
   key_push(k, (int64_t)o.precision);
   key_push(k, (int64_t)o.order_p);
   key_push(k, (int64_t)o.fp32_levels);
+  key_push(k, o.tol);
   key_push(k, (int64_t)o.leaf_level);
   for (int i = 0; i < n; ++i) {
     key_push(k, f[i].n_stars);
@@ -786,9 +993,12 @@ bool inside(const double dom[4], const double bb[4]) {
   return bb[0] >= dom[0] && bb[1] >= dom[1] && bb[2] <= dom[2] && bb[3] <= dom[3];
 }
 
+// tune: each field's options come from the autotuner (target tune_base.tol,
+// method and precision of tune_base); otherwise every field uses o.
 std::unique_ptr<BatchExec> batch_build(int n, const lens_field *f, const lens_grid *g,
                                        const lens_map_desc *m, const lens_opts &o,
-                                       const std::vector<double> &bbox, hipStream_t st) {
+                                       const std::vector<double> &bbox, bool tune,
+                                       const lens_opts &tune_base, hipStream_t st) {
   auto B = std::make_unique<BatchExec>();
   LENS_HIP(hipGetDevice(&B->device));
   (void)op_tables(o.order_p, st);
@@ -796,6 +1006,12 @@ std::unique_ptr<BatchExec> batch_build(int n, const lens_field *f, const lens_gr
   B->ge.resize(n);
   for (int i = 0; i < n; ++i) {
     if (f[i].n_stars == 0 || o.method == LENS_DIRECT) continue;
+    lens_opts oi = o;
+    if (tune) {
+      const TuneOut t = autotune_field(f[i], g[i], &m[i], tune_base.tol, tune_base, st);
+      oi = resolve_opts(&t.o);  // the most accurate setting if none reached tol
+      (void)op_tables(oi.order_p, st);
+    }
     auto *P = new lens_plan();
     B->plans[i] = P;
     P->device = B->device;
@@ -804,7 +1020,7 @@ std::unique_ptr<BatchExec> batch_build(int n, const lens_field *f, const lens_gr
     double gb[4];
     grid_bbox(g[i], 0, g[i].ny, gb);
     const double area = std::max((gb[2] - gb[0]) * (gb[3] - gb[1]), 1e-300);
-    plan_geometry(P, f[i].n_stars, &bbox[4 * i], gb, &g[i], (double)(g[i].nx * g[i].ny) / area, o);
+    plan_geometry(P, f[i].n_stars, &bbox[4 * i], gb, &g[i], (double)(g[i].nx * g[i].ny) / area, oi);
     plan_alloc(P, st);
     B->ge[i] = std::make_unique<GridExec>();
     gridexec_alloc(*P, g[i], 0, g[i].ny, *B->ge[i], st);
@@ -1163,6 +1379,8 @@ lens_status lens_map_batched(int32_t n_fields, const lens_field *fields, const l
   return guarded([&] {
     hipStream_t st = (hipStream_t)stream;
     const lens_opts o = resolve_opts(opts);
+    if (opts && opts->order_p == 0 && !(opts->tol >= 0 && is_finite(opts->tol)))
+      fail(LENS_EINVAL, "opts.tol must be finite and >= 0");
     if (n_fields < 0) fail(LENS_EINVAL, "n_fields < 0");
     if (n_fields == 0) return;
     if (!fields || !grids || !maps) fail(LENS_EINVAL, "fields / grids / maps is NULL");
@@ -1211,7 +1429,9 @@ lens_status lens_map_batched(int32_t n_fields, const lens_field *fields, const l
             if (!is_finite(bbox[4 * i + c]))
               fail(LENS_EINVAL, "non-finite star coordinates (field " + std::to_string(i) + ")");
     }
-    const auto key = batch_key(dev, n_fields, fields, grids, maps, o);
+    const bool tune = opts && opts->order_p == 0 && opts->tol > 0 && o.method == LENS_FMM;
+    auto key = batch_key(dev, n_fields, fields, grids, maps, o);
+    key_push(key, (int64_t)tune);
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchExec *B = nullptr;
     for (auto it = g_batches.begin(); it != g_batches.end(); ++it) {
@@ -1227,7 +1447,7 @@ lens_status lens_map_batched(int32_t n_fields, const lens_field *fields, const l
       break;
     }
     if (!B) {
-      auto nb = batch_build(n_fields, fields, grids, maps, o, bbox, st);
+      auto nb = batch_build(n_fields, fields, grids, maps, o, bbox, tune, tune ? *opts : o, st);
       nb->key = key;
       if (g_batches.size() >= kBatchCache) g_batches.erase(g_batches.begin());
       g_batches.push_back(std::move(nb));
@@ -1236,6 +1456,35 @@ lens_status lens_map_batched(int32_t n_fields, const lens_field *fields, const l
     StageTimer tm("batched_graph", st);
     LENS_HIP(hipGraphLaunch(B->exec, st));
     B->last = st;
+  });
+}
+
+lens_status lens_autotune(const lens_field *field, const lens_grid *grid, const lens_map_desc *map,
+                          double tol, const lens_opts *base, void *stream, lens_opts *out,
+                          double *err_out, double *ms_out) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    const lens_opts b = resolve_opts(base);
+    check_field(field);
+    if (!grid) fail(LENS_EINVAL, "grid is NULL");
+    check_grid(grid);
+    if (!out) fail(LENS_EINVAL, "out is NULL");
+    if (!is_finite(tol) || !(tol > 0)) fail(LENS_EINVAL, "tol must be finite and > 0");
+    if (map && (map->npix <= 0 || (int64_t)map->npix * map->npix > (int64_t)std::numeric_limits<int32_t>::max() ||
+                !is_finite(map->y1min) || !is_finite(map->y2min) || !is_finite(map->side) ||
+                !(map->side > 0)))
+      fail(LENS_EINVAL, "map placement must be finite with side > 0 and 0 < npix^2 <= 2^31-1");
+    lens_opts ub = base ? *base : b;  // keep the caller's encodings
+    if (!base) lens_opts_default(&ub);
+    ub.method = b.method;
+    ub.precision = b.precision;
+    const TuneOut t = autotune_field(*field, *grid, map, tol, ub, st);
+    *out = t.o;
+    if (err_out) *err_out = t.err;
+    if (ms_out) *ms_out = t.ms;
+    if (!t.met)
+      fail(LENS_EUNSUPPORTED, "no expansion order up to " + std::to_string(LENS_MAX_ORDER) +
+                                  " reaches tol (best sampled error " + std::to_string(t.err) + ")");
   });
 }
 

@@ -69,6 +69,67 @@ __global__ __launch_bounds__(kThreads) void k_p2m(Geometry g, int level, Window 
   }
 }
 
+// P2M for boxes holding few sources: one thread per box of `win` with all p
+// coefficients in registers (running powers m w^k); the wave's 64 boxes are
+// staged in LDS so that the [64][p] block is written with coalesced stores.
+template <int PMAX, int QDIM>
+__global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window win,
+                                                   const double *__restrict__ sxy,
+                                                   const double *__restrict__ sq,
+                                                   const int32_t *__restrict__ leaf_start, int p,
+                                                   double *__restrict__ mp, float *__restrict__ mp32) {
+  constexpr int STR = 2 * PMAX + 1;
+  __shared__ double stage[kWave * STR];
+  const int lane = threadIdx.x;
+  const int64_t nbox = win.count();
+  const int64_t b0 = (int64_t)blockIdx.x * kWave;
+  const int64_t b = b0 + lane;
+  cplx acc[PMAX];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) acc[k] = cplx{0.0, 0.0};
+  if (b < nbox) {
+    const int64_t ix = win.bx0 + b % win.nbx, iy = win.by0 + b / win.nbx;
+    const double s = ldexp(g.side, -level);
+    const double inv_s = 1.0 / s;
+    const double cx = g.x0 + ((double)ix + 0.5) * s;
+    const double cy = g.y0 + ((double)iy + 0.5) * s;
+    const int sh = g.L - level;
+    const int64_t nL = int64_t(1) << g.L;
+    const int64_t span = int64_t(1) << sh;
+    for (int64_t r = 0; r < span; ++r) {
+      const int64_t row = (iy << sh) + r;
+      const int32_t i0 = leaf_start[row * nL + (ix << sh)];
+      const int32_t i1 = leaf_start[row * nL + (ix << sh) + span];
+      for (int32_t i = i0; i < i1; ++i) {
+        const cplx w = {(sxy[2 * (int64_t)i] - cx) * inv_s, (sxy[2 * (int64_t)i + 1] - cy) * inv_s};
+        cplx pw = QDIM == 1 ? cplx{sq[i], 0.0} : cplx{sq[2 * (int64_t)i], sq[2 * (int64_t)i + 1]};
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k)
+          if (k < p) {
+            acc[k].re += pw.re;
+            acc[k].im += pw.im;
+            pw = cmul(pw, w);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k)
+    if (k < p) {
+      stage[lane * STR + 2 * k] = acc[k].re;
+      stage[lane * STR + 2 * k + 1] = acc[k].im;
+    }
+  __syncthreads();
+  const int twop = 2 * p;
+  const int64_t nb = nbox - b0 < kWave ? nbox - b0 : kWave;
+  for (int e = lane; e < nb * twop; e += kWave) {
+    const int bl = e / twop, c = e - bl * twop;
+    const double v = stage[bl * STR + c];
+    mp[b0 * twop + e] = v;
+    if (mp32) mp32[b0 * twop + e] = (float)v;
+  }
+}
+
 // P2M for boxes holding many sources: one wave per box of `win`.  The box's
 // leaf rows are taken 64 at a time; their source counts are scanned across
 // the wave so that the lanes share the rows' sources evenly (lane t takes
@@ -205,6 +266,19 @@ void launch_p2m(Geometry g, int level, Window win, const double *sxy, const doub
                                                g, level, win, sxy, sq, leaf_start, p, mp, mp32));
     else
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_wave<PM, 1>), dim3(nb), dim3(kWave), 0, stream,
+                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32));
+    LENS_HIP(hipGetLastError());
+    return;
+  }
+  // otherwise a thread per box (all coefficients), unless p exceeds the
+  // register budget of that kernel's largest instance
+  if (p <= 24) {
+    const unsigned nb = (unsigned)((win.count() + kWave - 1) / kWave);
+    if (qdim == 2)
+      LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_box<PM, 2>), dim3(nb), dim3(kWave), 0, stream,
+                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32));
+    else
+      LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_box<PM, 1>), dim3(nb), dim3(kWave), 0, stream,
                                                g, level, win, sxy, sq, leaf_start, p, mp, mp32));
     LENS_HIP(hipGetLastError());
     return;

@@ -129,3 +129,30 @@ def test_plan_create_rejects_bad_ray_box():
     g = _lib.LensGrid(0.0, 0.0, -1.0, 1.0, 2, 2)
     assert lib.lens_plan_create(ctypes.byref(f), None, ctypes.byref(g), None, None,
                                 ctypes.byref(h)) == _lib.LENS_EINVAL
+
+
+@pytest.mark.parametrize("tol,grid,out,msg", [
+    (0.0, True, True, "tol"),
+    (float("nan"), True, True, "tol"),
+    (1e-5, False, True, "grid"),
+    (1e-5, True, False, "out"),
+])
+def test_autotune_rejects_bad_arguments(tol, grid, out, msg):
+    lib = _lib.load()
+    f = _lib.LensField(0, None, None, 0.0, 0.0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2)
+    o = _lib.LensOpts()
+    st = lib.lens_autotune(ctypes.byref(f), ctypes.byref(g) if grid else None, None, tol, None, None,
+                           ctypes.byref(o) if out else None, None, None)
+    assert st == _lib.LENS_EINVAL
+    assert msg in lib.lens_last_error().decode()
+
+
+def test_batched_rejects_bad_tol():
+    lib = _lib.load()
+    f = (_lib.LensField * 1)(_lib.LensField(0, None, None, 0.0, 0.0))
+    g = (_lib.LensGrid * 1)(_lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2))
+    m = (_lib.LensMapDesc * 1)(_lib.LensMapDesc(0.0, 0.0, 1.0, 4, ctypes.c_void_p(8)))
+    o = _opts(order_p=0, tol=float("inf"))
+    assert lib.lens_map_batched(1, f, g, m, ctypes.byref(o), None) == _lib.LENS_EINVAL
+    assert "tol" in lib.lens_last_error().decode()

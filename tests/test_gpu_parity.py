@@ -584,3 +584,63 @@ def test_config5_full_gradient(lf):
             cs = float(((yk - th) ** 2).sum().imag) / h
             ref = o_xy[j, c] if c < 2 else o_m[j]
             assert abs(cs - ref) <= 1e-9 * max(1.0, abs(ref)), (i, c, cs, ref)
+
+
+# ------------------------------------------------------------------ autotuner
+
+def test_autotune_deflect_reaches_tol(lf):
+    """The tuned setting meets the target on rays the tuner did not sample."""
+    f = wl.random_field(50_000, 150.0, seed=61, masses="powerlaw", kappa_s=0.2, gamma=0.3)
+    g = wl.centred_grid(200.0, 200.0, 1024, 1024)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    kw = dict(kappa_s=f.kappa_s, gamma=f.gamma)
+    for prec, tol in (("mixed", 1e-6), ("fp64", 1e-11)):
+        _say("autotune deflect", prec, tol)
+        t = lf.autotune(xy, m, lfgrid(g), tol=tol, precision=prec, **kw)
+        print("autotune", prec, tol, t)
+        assert t["error"] <= tol and t["ms"] > 0 and 2 <= t["leaf_level"] <= 15
+        y = host(lf.deflect(xy, m, grid=lfgrid(g), precision=prec, p=t["p"],
+                            leaf_level=t["leaf_level"], fp32_levels=t["fp32_levels"], **kw))
+        idx = g.strided(41, 7)
+        yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), **kw)
+        assert rel_l2(y[idx], yo, ao) <= 3 * tol
+
+
+def test_autotune_high_magnification_map(lf):
+    """The 5e6-star, mu = 50 map: the tuner's setting keeps the expected bin
+    reassignment under 1e-4 on rays it did not sample (oracle)."""
+    f, g, mp = wl.config3()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
+    _say("autotune config3 map")
+    t = lf.autotune(xy, m, lfgrid(g), map=md, tol=1e-4, kappa_s=f.kappa_s, gamma=f.gamma)
+    print("autotune config3", t)
+    assert t["error"] <= 1e-4
+    plan = lf.Plan(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma, p=t["p"],
+                   leaf_level=t["leaf_level"], fp32_levels=t["fp32_levels"])
+    idx = g.strided(331, 101)
+    rays = g.rays(idx)
+    ys = host(lf.deflect(rays=dev_tensor(rays), plan=plan, kappa_s=f.kappa_s, gamma=f.gamma))
+    plan.close()
+    yo, _, _ = oracle.deflect(f.xy, f.m, rays, f.kappa_s, f.gamma)
+    est = float(np.abs(ys - yo).sum(1).mean() * mp.npix / mp.side)
+    print(f"config3 tuned: reassignment estimate {est:.2e} on {len(idx)} rays")
+    assert est <= 2e-4
+
+
+def test_batched_autotuned_maps_against_direct(lf):
+    cases = _batch_fields(4, 512, 128, 41, (2000, 20000))
+    fields, grids, maps = [], [], []
+    for f, g, mp in cases:
+        fields.append((dev_tensor(f.xy), dev_tensor(f.m), f.kappa_s, f.gamma))
+        grids.append(lfgrid(g))
+        maps.append(lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix))
+    _say("batched autotuned")
+    got = [host(c) for c in lf.irs_map_batched(fields, grids, maps, p=0, tol=1e-4)]
+    for k, ((xy, m, ks, gm), g, mp) in enumerate(zip(fields, grids, maps)):
+        d = host(lf.irs_map(xy, m, grid=g, map=mp, kappa_s=ks, gamma=gm, method="direct"))
+        moved = np.abs(got[k].astype(np.int64) - d).sum() / 2
+        n = g.nx * g.ny
+        print(f"field {k}: {moved} of {n} rays binned differently from the FP64 direct sum")
+        assert moved <= 3e-4 * n + 2
+    lf.release_cached()
