@@ -145,13 +145,20 @@ def main():
     for _ in range(args.warmup):
         run(leaf=leaf)
     torch.cuda.synchronize()
-    _lib.profile_enable(True)
+    # timed region: repeated identical calls replay the library's captured
+    # graph of the call (built during the warmup)
     t0 = time.perf_counter()
     ms = timed(lambda: run(leaf=leaf), args.steps)
     wall = time.perf_counter() - t0
+    # the same steps once more with the stage profiler on (HIP events around
+    # every stage on its stream; the profiler runs the calls eagerly), for the
+    # evaluation kernel's duration
+    _lib.profile_enable(True)
+    ms_prof = timed(lambda: run(leaf=leaf), args.steps)
     prof = _lib.profile_read()
     _lib.profile_enable(False)
-    log(f"mixed FMM: {ms:.3f} ms/step ({wall:.2f} s wall for {args.steps} steps); stages {prof}")
+    log(f"mixed FMM: {ms:.3f} ms/step ({wall:.2f} s wall for {args.steps} steps); "
+        f"profiled eager steps {ms_prof:.3f} ms; stages {prof}")
     if args.profile_only:
         if args.calib_copy_mib:
             # known-size reference kernels for the FETCH_SIZE / WRITE_SIZE
@@ -195,7 +202,7 @@ def main():
     extra = {"leaf_level": leaf, "p": args.p, "near_pairs_per_ray": pairs / n_rays,
              "leaf_box_side": math.ldexp(info["root_side"], -leaf),
              "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
-             "eval_flops_per_launch": flops}
+             "eval_flops_per_launch": flops, "profiled_eager_ms_per_step": ms_prof}
 
     # FP64 direct sum on the same GPU, on 128 full rows of the grid (rays/s is
     # exactly linear in the ray count for a direct sum)
@@ -285,20 +292,24 @@ def bench_map(args):
         counts.zero_()
         lf.irs_map(xy, m, grid=grid, map=md, counts=counts, **kw)
 
+    def timed_steps():
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
+    ms = timed_steps()   # graph replays of the call
     _lib.profile_enable(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms_prof = timed_steps()   # eager, with HIP events around every stage
     prof = _lib.profile_read()
     _lib.profile_enable(False)
-    log(f"map: {ms:.3f} ms/step; stages {prof}")
+    log(f"map: {ms:.3f} ms/step; profiled eager steps {ms_prof:.3f} ms; stages {prof}")
     if args.profile_only:
         return
     value = g.n / (ms * 1e-3)
@@ -314,7 +325,8 @@ def bench_map(args):
     extra = {"leaf_level": leaf, "p": p, "fp32_levels": fl, "autotune": tuned, "autotune_s": tune_s,
              "near_pairs_per_ray": pairs / g.n,
              "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
-             "eval_flops_per_launch": flops, "mean_count": float(counts.double().mean())}
+             "eval_flops_per_launch": flops, "mean_count": float(counts.double().mean()),
+             "profiled_eager_ms_per_step": ms_prof}
     cpu = None
     if not args.no_cpu:
         import oracle

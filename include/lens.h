@@ -151,8 +151,13 @@ LENS_API lens_status lens_plan_info(const lens_plan *plan, int32_t *order_p, int
  * Deflect rays: y_out[k][2] = y(x_k) (FP64, device).  Rays come from `grid`
  * (then rays_xy must be NULL and n_rays = grid->nx * grid->ny) or from the
  * explicit device array rays_xy[n_rays][2] (then grid must be NULL).
- * `plan` may be NULL: the library then builds the star tree for this call
- * (explicit rays: waits on the stream once to read back their bounding box).
+ * `plan` may be NULL: the library then builds the star tree for this call,
+ * waiting on the stream once to read back the stars' (and, for explicit
+ * rays, the rays') bounding box.  Grid calls without a plan are cached: from
+ * the second call with the same stream, input addresses and sizes, options,
+ * smooth terms and resulting tree geometry on, the call's kernels run as one
+ * captured HIP graph (its buffers stay allocated until lens_release_cached;
+ * calls made while the stage profiler is on run uncached).
  * With a plan, the plan's (sorted) stars, expansion order, leaf level and
  * precision are used and opts->method still selects FMM or direct; `field`
  * may then be NULL (the plan's kappa_s and gamma apply) or supply only
@@ -244,7 +249,8 @@ LENS_API lens_status lens_map_batched(int32_t n_fields, const lens_field *fields
                                       const lens_grid *grids, const lens_map_desc *maps,
                                       const lens_opts *opts, void *stream);
 
-/* Release the cached batch graphs and their device buffers (waits for them). */
+/* Release the cached graphs (lens_map_batched, and plan-less grid calls of
+ * lens_deflect / lens_map) and their device buffers (waits for them). */
 LENS_API void lens_release_cached(void);
 
 /* Thread-local text for the last status other than LENS_OK (host string). */

@@ -261,7 +261,8 @@ def autotune(star_xy, star_m, grid: Grid, map: Optional[MapDesc] = None, tol=1e-
 
 
 def release_cached():
-    """Free the cached batch graphs and their buffers."""
+    """Free the cached graphs (batched maps, plan-less grid calls) and their
+    buffers."""
     _lib.load().lens_release_cached()
 
 

@@ -40,7 +40,7 @@ struct lens_plan {
   DevBuf sxy, sm, leaf_start;
   std::vector<DevBuf> mp;    // index = level, FP64 multipoles
   std::vector<DevBuf> mp32;  // index = level, FP32 copies (fine levels, mixed)
-  DevBuf keys, vals, keys_tmp, vals_tmp, cnt, scan_tmp;  // tree-build scratch
+  DevBuf keys, vals, keys_tmp, vals_tmp, cnt, scan_tmp, box_coarse;  // tree-build scratch
   hipStream_t last_stream = nullptr;
 
   const double *mp_at(int l) const { return static_cast<const double *>(mp[l].ptr); }
@@ -49,10 +49,11 @@ struct lens_plan {
   }
   // return every buffer to the pool, ordered after the work on `st`
   void put_all(hipStream_t st) {
-    for (DevBuf *b : {&sxy, &sm, &leaf_start, &keys, &vals, &keys_tmp, &vals_tmp, &cnt, &scan_tmp})
-      pool_put(*b, st);
-    for (auto &b : mp) pool_put(b, st);
-    for (auto &b : mp32) pool_put(b, st);
+    std::vector<DevBuf *> ps = {&sxy, &sm, &leaf_start, &keys, &vals, &keys_tmp, &vals_tmp, &cnt,
+                                &scan_tmp, &box_coarse};
+    for (auto &b : mp) ps.push_back(&b);
+    for (auto &b : mp32) ps.push_back(&b);
+    pool_put_batch(ps.data(), ps.size(), st);
   }
   void release() {
     if (last_stream) (void)hipStreamSynchronize(last_stream);
@@ -323,6 +324,7 @@ void plan_alloc(lens_plan *P, hipStream_t st) {
   const size_t ncnt = radix_counts_len(N);
   P->cnt = pool_get(ncnt * sizeof(uint32_t), st);
   P->scan_tmp = pool_get(scan_tmp_len(ncnt) * sizeof(uint32_t), st);
+  P->box_coarse = pool_get((size_t)box_starts_coarse_len(nbox) * sizeof(int32_t), st);
   for (int l = 2; l <= L; ++l) {
     const size_t n = (size_t)P->swin[l].count() * P->p * 2;
     P->mp[l] = pool_get(n * sizeof(double), st);
@@ -345,12 +347,13 @@ void plan_enqueue(lens_plan *P, const double *xy, const double *q, hipStream_t s
     StageTimer tm("tree", st);
     auto *k = static_cast<uint32_t *>(P->keys.ptr), *v = static_cast<uint32_t *>(P->vals.ptr);
     auto *kt = static_cast<uint32_t *>(P->keys_tmp.ptr), *vt = static_cast<uint32_t *>(P->vals_tmp.ptr);
-    launch_leaf_keys(xy, N, P->g, k, v, st);
+    launch_leaf_keys(xy, N, P->g, k, v, nullptr, st);
     const bool in_tmp = radix_sort_pairs(k, v, kt, vt, N, 2 * L, static_cast<uint32_t *>(P->cnt.ptr),
                                          static_cast<uint32_t *>(P->scan_tmp.ptr), st);
     const uint32_t *ks = in_tmp ? kt : k, *vs = in_tmp ? vt : v;
     launch_gather_stars(vs, xy, q, P->qdim, N, sxy, sm, st);
-    launch_box_starts(ks, N, nbox, leaf_start, st);  // all zero when N = 0
+    // all zero when N = 0
+    launch_box_starts(ks, N, nbox, leaf_start, static_cast<int32_t *>(P->box_coarse.ptr), st);
   }
   const OpTables &T = op_tables(P->p, st);
   {
@@ -422,7 +425,9 @@ struct LocalSet {
   std::vector<DevBuf> loc;
   double *at(int l) const { return static_cast<double *>(loc[l].ptr); }
   void put_all(hipStream_t st) {
-    for (auto &b : loc) pool_put(b, st);
+    std::vector<DevBuf *> ps;
+    for (auto &b : loc) ps.push_back(&b);
+    pool_put_batch(ps.data(), ps.size(), st);
   }
 };
 
@@ -548,9 +553,9 @@ struct GridExec {
   DevBuf col_start, row_start;
   EvalArgs ea{};
   void put_all(hipStream_t st) {
-    ls.put_all(st);
-    pool_put(col_start, st);
-    pool_put(row_start, st);
+    std::vector<DevBuf *> ps = {&col_start, &row_start};
+    for (auto &b : ls.loc) ps.push_back(&b);
+    pool_put_batch(ps.data(), ps.size(), st);
   }
 };
 
@@ -646,7 +651,7 @@ void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4
   double *srays = sc.get<double>((size_t)n * 2);
   launch_gather_rays(vs, rays, n, srays, st);
   int32_t *rstart = sc.get<int32_t>(wl.count() + 1);
-  launch_box_starts(ks, n, wl.count(), rstart, st);
+  launch_box_starts(ks, n, wl.count(), rstart, sc.get<int32_t>(box_starts_coarse_len(wl.count())), st);
   EvalArgs ea{};
   fill_star_side(P, wl, loc, ea);
   ea.grid_mode = 0;
@@ -1088,6 +1093,164 @@ std::unique_ptr<BatchExec> batch_build(int n, const lens_field *f, const lens_gr
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------ call graphs
+// lens_deflect / lens_map over a ray grid without a caller's plan: once the
+// stars' bounding box is read back (the one wait), the rest of the call --
+// tree build, upward pass, downward pass, evaluation -- is the same kernel
+// sequence whenever the input addresses and sizes, the options, the smooth
+// terms and the tree geometry repeat.  The second time such a call is seen
+// that sequence is captured into a HIP graph (on a private stream, with the
+// buffers it uses kept alive) and from then on replayed with one launch.
+// The stage profiler needs eager launches, so calls made while it is on run
+// eagerly.
+struct CallExec {
+  std::vector<uint64_t> key;
+  lens_plan *P = nullptr;
+  GridExec ge;
+  hipStream_t origin = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last = nullptr;
+
+  ~CallExec() {
+    if (last) (void)hipStreamSynchronize(last);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (P) {
+      P->put_all(nullptr);
+      delete P;
+    }
+    ge.put_all(nullptr);
+    if (origin) (void)hipStreamDestroy(origin);
+  }
+};
+
+constexpr size_t kCallCache = 4;
+std::mutex g_call_mu;
+std::vector<std::unique_ptr<CallExec>> g_calls;        // most recently used last
+std::vector<std::vector<uint64_t>> g_call_seen;         // keys seen once
+
+std::vector<uint64_t> call_key(const lens_field &f, const lens_grid &g, const lens_opts &o,
+                               const double *y_out, const lens_map_desc *map, const lens_plan &P,
+                               hipStream_t st) {
+  std::vector<uint64_t> k;
+  key_push(k, (int64_t)P.device);
+  key_push(k, (const void *)st);  // replays on one stream are ordered; others get their own
+  key_push(k, (const void *)f.xy);
+  key_push(k, (const void *)f.m);
+  key_push(k, f.n_stars);
+  key_push(k, f.kappa_s);
+  key_push(k, f.gamma);
+  key_push(k, g.x0);
+  key_push(k, g.y0);
+  key_push(k, g.dx);
+  key_push(k, g.dy);
+  key_push(k, g.nx);
+  key_push(k, g.ny);
+  key_push(k, (int64_t)o.precision);
+  key_push(k, (int64_t)o.order_p);
+  key_push(k, (int64_t)o.fp32_levels);
+  key_push(k, (int64_t)o.leaf_level);
+  key_push(k, (const void *)y_out);
+  if (map) {
+    key_push(k, map->y1min);
+    key_push(k, map->y2min);
+    key_push(k, map->side);
+    key_push(k, (int64_t)map->npix);
+    key_push(k, (const void *)map->counts);
+  }
+  key_push(k, P.g.x0);
+  key_push(k, P.g.y0);
+  key_push(k, P.g.side);
+  key_push(k, (int64_t)P.g.L);
+  return k;
+}
+
+// The whole grid in one pass through the call-graph cache (see above).
+void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &o, double c1,
+                   double c2, double *y_out, const lens_map_desc *map, double S,
+                   hipStream_t st) {
+  double sb[4];
+  device_bbox(f.xy, f.n_stars, st, sb);
+  double bb[4];
+  grid_bbox(grid, 0, grid.ny, bb);
+  const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
+  const double density = (double)(grid.nx * grid.ny) / area;
+  auto eager = [&] {
+    lens_plan *P = build_plan(f, bb, &grid, density, o, st, nullptr, sb);
+    try {
+      fmm_grid_rows(*P, grid, 0, grid.ny, c1, c2, y_out, map, S, st);
+    } catch (...) {
+      lens_plan_destroy(P);
+      throw;
+    }
+    release_owned(P, st);
+  };
+  if (profiling_enabled()) return eager();
+  // host-side geometry only, to form the key
+  lens_plan probe;
+  LENS_HIP(hipGetDevice(&probe.device));
+  plan_geometry(&probe, f.n_stars, sb, bb, &grid, density, o);
+  auto key = call_key(f, grid, o, y_out, map, probe, st);
+  std::lock_guard<std::mutex> lk(g_call_mu);
+  for (size_t i = 0; i < g_calls.size(); ++i)
+    if (g_calls[i]->key == key) {
+      std::unique_ptr<CallExec> c = std::move(g_calls[i]);
+      g_calls.erase(g_calls.begin() + (long)i);
+      LENS_HIP(hipGraphLaunch(c->exec, st));
+      c->last = st;
+      g_calls.push_back(std::move(c));
+      return;
+    }
+  if (std::find(g_call_seen.begin(), g_call_seen.end(), key) == g_call_seen.end()) {
+    g_call_seen.push_back(key);
+    if (g_call_seen.size() > 16) g_call_seen.erase(g_call_seen.begin());
+    return eager();
+  }
+  auto c = std::make_unique<CallExec>();
+  c->key = key;
+  auto *P = new lens_plan();
+  c->P = P;
+  P->device = probe.device;
+  P->kappa_s = f.kappa_s;
+  P->gamma = f.gamma;
+  plan_geometry(P, f.n_stars, sb, bb, &grid, density, o);
+  (void)op_tables(o.order_p, st);
+  plan_alloc(P, st);
+  gridexec_alloc(*P, grid, 0, grid.ny, c->ge, st);
+  LENS_HIP(hipStreamCreateWithFlags(&c->origin, hipStreamNonBlocking));
+  LENS_HIP(hipStreamSynchronize(st));  // the buffers above were handed out on st
+  set_capturing(true);
+  hipError_t began = hipStreamBeginCapture(c->origin, hipStreamCaptureModeThreadLocal);
+  if (began != hipSuccess) {
+    set_capturing(false);
+    LENS_HIP(began);
+  }
+  try {
+    plan_enqueue(P, f.xy, f.m, c->origin);
+    gridexec_enqueue(*P, c->ge, c1, c2, y_out, map, c->origin);
+  } catch (...) {
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(c->origin, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    set_capturing(false);
+    (void)hipGetLastError();
+    throw;
+  }
+  const hipError_t ended = hipStreamEndCapture(c->origin, &c->graph);
+  set_capturing(false);
+  LENS_HIP(ended);
+  LENS_HIP(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+  LENS_HIP(hipGraphLaunch(c->exec, st));
+  c->last = st;
+  if (g_calls.size() >= kCallCache) g_calls.erase(g_calls.begin());
+  g_calls.push_back(std::move(c));
+}
+
+}  // namespace
+
 extern "C" {
 
 void lens_opts_default(lens_opts *o) {
@@ -1197,6 +1360,10 @@ lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_gr
       return;
     }
 
+    if (!plan && grid) {
+      fmm_grid_call(fv.f, *grid, o, c1, c2, y_out, nullptr, 0.0, st);
+      return;
+    }
     double bb[4];
     if (grid) {
       grid_bbox(*grid, 0, grid->ny, bb);
@@ -1268,6 +1435,10 @@ lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *
         StageTimer tm("direct_map", st);
         launch_direct(d, st);
       }
+      return;
+    }
+    if (!plan && rows >= grid->ny) {
+      fmm_grid_call(fv.f, *grid, o, c1, c2, nullptr, map, S, st);
       return;
     }
     double bb[4];
@@ -1354,7 +1525,8 @@ lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid
         const uint32_t *ks = in_tmp ? kt : k;
         v = in_tmp ? vt : v;
         launch_gather_stars(v, field->xy, field->m, 1, N, txy, tm, st);
-        launch_box_starts(ks, N, wl.count(), tstart, st);
+        launch_box_starts(ks, N, wl.count(), tstart,
+                          sc.get<int32_t>(box_starts_coarse_len(wl.count())), st);
       }
       EvalArgs ea{};
       fill_star_side(*P, wl, loc, ea);
@@ -1489,8 +1661,13 @@ lens_status lens_autotune(const lens_field *field, const lens_grid *grid, const 
 }
 
 void lens_release_cached(void) {
-  std::lock_guard<std::mutex> lk(g_batch_mu);
-  g_batches.clear();
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_batches.clear();
+  }
+  std::lock_guard<std::mutex> lk(g_call_mu);
+  g_calls.clear();
+  g_call_seen.clear();
 }
 
 }  // extern "C"

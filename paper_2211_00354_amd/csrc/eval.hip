@@ -63,18 +63,19 @@ __device__ __forceinline__ void pair_update(const double (&rx)[R], const double 
   }
 }
 
-// Add one count per lane whose key is >= 0 to counts[key], one atomic per
-// distinct key of the wave: the lanes holding the first pending key are
+// Add one count for every lane whose key is >= 0 to counts[key], one atomic
+// per distinct key of the wave: the lanes holding the first pending key are
 // found with a ballot and their count added by one lane.  Neighbouring rays
 // mostly land in one pixel, so a wave of rays issues a few atomics, not 64.
+// (Merging the R slots of a wave into one loop issues fewer atomics but
+// measured slower: each round then needs R ballots.)
 __device__ __forceinline__ void wave_add_counts(int32_t key, int32_t *__restrict__ counts) {
-  const int lane = threadIdx.x;
   uint64_t pending = __ballot(key >= 0);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
     const int32_t k = __builtin_amdgcn_readlane(key, leader);
     const uint64_t same = __ballot(key == k);
-    if (lane == leader) atomicAdd(&counts[k], (int32_t)__popcll(same));
+    if ((int)threadIdx.x == leader) atomicAdd(&counts[k], (int32_t)__popcll(same));
     pending &= ~same;
   }
 }
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
           for (int r = 0; r < R; ++r) f[r] = cmad(f[r], w[r], cplx{c.x, c.y});
         }
 
+      int32_t key[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const double al1 = f[r].re + (double)ax[r];
@@ -239,18 +241,21 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
         const double y1 = a.c1 * rx[r] - al1;
         const double y2 = a.c2 * ry[r] - al2;
         if (MAP) {
-          int32_t key = -1;
+          key[r] = -1;
           const double t1 = (y1 - a.y1min) * a.S;
           const double t2 = (y2 - a.y2min) * a.S;
           if (act[r] && t1 >= 0.0 && t2 >= 0.0) {
             const double f1 = floor(t1), f2 = floor(t2);
             if (f1 < (double)a.npix && f2 < (double)a.npix)
-              key = (int32_t)f2 * a.npix + (int32_t)f1;
+              key[r] = (int32_t)f2 * a.npix + (int32_t)f1;
           }
-          wave_add_counts(key, counts);
         } else if (act[r]) {
           *reinterpret_cast<double2 *>(y_out + 2 * oidx[r]) = make_double2(y1, y2);
         }
+      }
+      if (MAP) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) wave_add_counts(key[r], counts);
       }
     }
   }
@@ -333,13 +338,21 @@ void eval_dispatch(const EvalArgs &a, int precision, hipStream_t stream) {
 }  // namespace
 
 // Rays per lane R and units per box CH for boxes of at most max_rays rays:
-// the fewest lane slots 64*R*CH, ties going to the larger R (fewer units).
+// the fewest lane slots 64*R*passes*CH, ties going to the larger R, with up
+// to kPassesPerUnit passes of 64*R rays per unit.  A unit starts by loading
+// its box's local expansion with a vector load, which waits for every
+// earlier vector memory operation of the wave (the previous unit's stores or
+// map atomics); several passes per unit spread that wait.
+constexpr int64_t kPassesPerUnit = 8;
+
 void eval_shape(int64_t max_rays, int *R, int64_t *CH) {
   int best_r = 1;
   int64_t best_ch = 1, best_slots = -1;
   for (int r = 1; r <= 4; ++r) {
-    const int64_t ch = (max_rays + kWave * r - 1) / (kWave * r);
-    const int64_t slots = ch * kWave * r;
+    const int64_t passes = (max_rays + kWave * r - 1) / (kWave * r);
+    const int64_t ch = (passes + kPassesPerUnit - 1) / kPassesPerUnit;
+    const int64_t per = (passes + ch - 1) / ch;
+    const int64_t slots = ch * per * kWave * r;
     if (best_slots < 0 || slots <= best_slots) {
       best_slots = slots;
       best_r = r;

@@ -39,6 +39,8 @@ struct DevBuf {
 
 DevBuf pool_get(size_t bytes, hipStream_t stream);
 void pool_put(DevBuf &b, hipStream_t stream);
+// release several buffers behind one event
+void pool_put_batch(DevBuf *const *bufs, size_t n, hipStream_t stream);
 
 // RAII list of scratch buffers released at scope exit (stream-ordered).
 struct Scratch {
@@ -46,7 +48,9 @@ struct Scratch {
   std::vector<DevBuf> bufs;
   explicit Scratch(hipStream_t s) : stream(s) {}
   ~Scratch() {
-    for (auto &b : bufs) pool_put(b, stream);
+    std::vector<DevBuf *> ps;
+    for (auto &b : bufs) ps.push_back(&b);
+    pool_put_batch(ps.data(), ps.size(), stream);
   }
   template <typename T>
   T *get(size_t count) {
@@ -89,7 +93,9 @@ struct BBoxSet {
 void launch_bbox_multi(const BBoxSet *sets_dev, int nsets, int nparts, double *partial,
                        double *out, hipStream_t stream);
 void launch_leaf_keys(const double *xy, int64_t n, Geometry g, uint32_t *keys, uint32_t *vals,
-                      hipStream_t stream);
+                      uint32_t *box_count, hipStream_t stream);
+// p[0..n) = v (a kernel, so it may be captured in a graph)
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.
 // Uses (k_tmp, v_tmp) as ping-pong storage; returns true if the sorted result
 // ended up in the tmp buffers.
@@ -107,7 +113,9 @@ void launch_gather_rays(const uint32_t *perm, const double *xy, int64_t n, doubl
                         hipStream_t stream);
 // start[b] = first sorted index with key >= b, for b in [0, nbox]
 void launch_box_starts(const uint32_t *sorted_keys, int64_t n, int64_t nbox, int32_t *start,
-                       hipStream_t stream);
+                       int32_t *coarse, hipStream_t stream);
+// int32 entries of the scratch `coarse` that launch_box_starts needs
+int64_t box_starts_coarse_len(int64_t nbox);
 
 // Expansion operator tables (host-built, uploaded once per order).
 struct OpTables {

@@ -1,5 +1,6 @@
 // Error plumbing and the caching device allocator.
 #include <map>
+#include <memory>
 #include <mutex>
 
 #include "lens_internal.h"
@@ -22,11 +23,20 @@ void check_hip(hipError_t e, const char *what) {
 
 namespace {
 
+// One event per release batch, shared by the batch's blocks and destroyed
+// with the last of them.
+struct ReleaseEvent {
+  hipEvent_t ev = nullptr;
+  ~ReleaseEvent() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
 struct FreeBlock {
   void *ptr;
   size_t bytes;
-  hipStream_t stream;   // stream of the last use
-  hipEvent_t ev;        // recorded at release on `stream`
+  hipStream_t stream;                  // stream of the last use
+  std::shared_ptr<ReleaseEvent> ev;    // recorded at release on `stream`
 };
 
 struct DevicePool {
@@ -66,8 +76,7 @@ DevBuf pool_get(size_t bytes, hipStream_t stream) {
     if (it != pool.free_list.end() && it->first <= out.bytes * 2) {
       FreeBlock fb = it->second;
       pool.free_list.erase(it);
-      if (fb.stream != stream) LENS_HIP(hipStreamWaitEvent(stream, fb.ev, 0));
-      LENS_HIP(hipEventDestroy(fb.ev));
+      if (fb.stream != stream) LENS_HIP(hipStreamWaitEvent(stream, fb.ev->ev, 0));
       out.ptr = fb.ptr;
       out.bytes = fb.bytes;
       return out;
@@ -80,8 +89,7 @@ DevBuf pool_get(size_t bytes, hipStream_t stream) {
     (void)hipGetLastError();
     std::lock_guard<std::mutex> lk(pool.mu);
     for (auto &kv : pool.free_list) {
-      (void)hipEventSynchronize(kv.second.ev);
-      (void)hipEventDestroy(kv.second.ev);
+      (void)hipEventSynchronize(kv.second.ev->ev);
       (void)hipFree(kv.second.ptr);
     }
     pool.free_list.clear();
@@ -95,23 +103,35 @@ DevBuf pool_get(size_t bytes, hipStream_t stream) {
   return out;
 }
 
-void pool_put(DevBuf &b, hipStream_t stream) {
-  if (!b.ptr) return;
-  DevicePool &pool = pool_for(b.device);
-  FreeBlock fb{b.ptr, b.bytes, stream, nullptr};
-  if (hipEventCreateWithFlags(&fb.ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(fb.ev, stream) != hipSuccess) {
+void pool_put_batch(DevBuf *const *bufs, size_t n, hipStream_t stream) {
+  size_t live = 0;
+  for (size_t i = 0; i < n; ++i) live += bufs[i]->ptr != nullptr;
+  if (live == 0) return;
+  auto ev = std::make_shared<ReleaseEvent>();
+  if (hipEventCreateWithFlags(&ev->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev->ev, stream) != hipSuccess) {
     // cannot order the reuse: wait for the stream and free outright
     (void)hipGetLastError();
     (void)hipStreamSynchronize(stream);
-    if (fb.ev) (void)hipEventDestroy(fb.ev);
-    (void)hipFree(b.ptr);
-    b.ptr = nullptr;
+    for (size_t i = 0; i < n; ++i) {
+      if (bufs[i]->ptr) (void)hipFree(bufs[i]->ptr);
+      bufs[i]->ptr = nullptr;
+    }
     return;
   }
-  std::lock_guard<std::mutex> lk(pool.mu);
-  pool.free_list.emplace(fb.bytes, fb);
-  b.ptr = nullptr;
+  for (size_t i = 0; i < n; ++i) {
+    DevBuf &b = *bufs[i];
+    if (!b.ptr) continue;
+    DevicePool &pool = pool_for(b.device);
+    std::lock_guard<std::mutex> lk(pool.mu);
+    pool.free_list.emplace(b.bytes, FreeBlock{b.ptr, b.bytes, stream, ev});
+    b.ptr = nullptr;
+  }
+}
+
+void pool_put(DevBuf &b, hipStream_t stream) {
+  DevBuf *p = &b;
+  pool_put_batch(&p, 1, stream);
 }
 
 }  // namespace lensfmm

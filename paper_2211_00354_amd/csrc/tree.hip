@@ -133,17 +133,30 @@ __global__ __launch_bounds__(kThreads) void k_bbox_multi_final(const double *__r
 
 // --------------------------------------------------------------- leaf keys
 
+// Leaf key (row-major box index) and identity index of every source; with
+// box_count, also the number of sources per leaf box (integer atomics, so
+// the counts are exact whatever the order).
 __global__ __launch_bounds__(kThreads) void k_leaf_keys(const double *__restrict__ xy, int64_t n,
                                                         Geometry g, uint32_t *__restrict__ keys,
-                                                        uint32_t *__restrict__ vals) {
+                                                        uint32_t *__restrict__ vals,
+                                                        uint32_t *__restrict__ box_count) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   const int64_t nb = int64_t(1) << g.L;
   const double s = ldexp(g.side, -g.L);
   const int64_t ix = box_coord(xy[2 * i], g.x0, s, nb);
   const int64_t iy = box_coord(xy[2 * i + 1], g.y0, s, nb);
-  keys[i] = (uint32_t)(iy * nb + ix);
+  const uint32_t k = (uint32_t)(iy * nb + ix);
+  keys[i] = k;
   vals[i] = (uint32_t)i;
+  if (box_count) atomicAdd(&box_count[k], 1u);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_u32(uint32_t *__restrict__ p, int64_t n,
+                                                       uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    p[i] = v;
 }
 
 // ------------------------------------------------------------------ scans
@@ -261,28 +274,36 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(const uint32_t *__rest
 }
 
 // Stable scatter.  Items of a tile are taken in global order (round `it`,
-// then thread); a key's destination is the digit's global offset for this
-// tile + keys of that digit in earlier rounds + in lower waves of this round
-// + in lower lanes of its own wave (found with ballots on the digit bits).
+// then thread).  A key's destination is the digit's global offset for this
+// tile + the keys of that digit in earlier (round, wave) pairs of the tile +
+// those in lower lanes of its own wave (found with ballots on the digit
+// bits).  Every item of the tile is ranked first, the per-(round, wave,
+// digit) counts are turned into offsets by one thread per digit, and only
+// then are the items written: three barriers per tile.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offsets,
     int nblocks) {
   __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[kWaves][256];
+  // counts, then offsets within the tile (<= kSortTile, fits 16 bits)
+  __shared__ uint16_t cnt[kSortItems][kWaves][256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   run[t] = offsets[(size_t)t * nblocks + blockIdx.x];
-#pragma unroll
-  for (int q = 0; q < kWaves; ++q) wcnt[q][t] = 0;
+  {
+    uint32_t *c32 = reinterpret_cast<uint32_t *>(&cnt[0][0][0]);
+    for (int e = t; e < kSortItems * kWaves * 256 / 2; e += kThreads) c32[e] = 0u;
+  }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+#pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     const int64_t i = base + (int64_t)it * kThreads + t;
     const bool valid = i < n;
-    const uint32_t k = valid ? kin[i] : 0u;
-    const uint32_t v = valid ? vin[i] : 0u;
-    const uint32_t d = (k >> shift) & 255u;
+    key[it] = valid ? kin[i] : 0u;
+    val[it] = valid ? vin[i] : 0u;
+    const uint32_t d = (key[it] >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -290,24 +311,32 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
     }
-    const uint32_t rank = __popcll(peers & below);
-    if (valid && (peers >> lane) == 1ull) wcnt[w][d] = __popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
-      kout[pos] = k;
-      vout[pos] = v;
-    }
-    __syncthreads();
-    uint32_t add = 0;
+    rank[it] = (uint32_t)__popcll(peers & below);
+    // the highest lane of each digit group records the group's size
+    if (valid && (peers >> lane) == 1ull) cnt[it][w][d] = (uint16_t)__popcll(peers);
+  }
+  __syncthreads();
+  {
+    // thread t: exclusive prefix of digit t's counts over (round, wave)
+    uint32_t pre = 0;
+    for (int it = 0; it < kSortItems; ++it)
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) {
-      add += wcnt[q][t];
-      wcnt[q][t] = 0;
+      for (int q = 0; q < kWaves; ++q) {
+        const uint32_t c = cnt[it][q][t];
+        cnt[it][q][t] = (uint16_t)pre;
+        pre += c;
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t i = base + (int64_t)it * kThreads + t;
+    if (i < n) {
+      const uint32_t d = (key[it] >> shift) & 255u;
+      const uint32_t pos = run[d] + cnt[it][w][d] + rank[it];
+      kout[pos] = key[it];
+      vout[pos] = val[it];
     }
-    run[t] += add;
-    __syncthreads();
   }
 }
 
@@ -337,13 +366,38 @@ __global__ __launch_bounds__(kThreads) void k_gather_rays(const uint32_t *__rest
   sxy[2 * j + 1] = xy[2 * (int64_t)i + 1];
 }
 
+// start[b] = lower_bound of box b in the sorted keys, b = 0..nbox, in two
+// steps: every kBoxStride-th box searches the whole array, then each box
+// searches only between its two neighbouring coarse bounds.
+constexpr int64_t kBoxStride = 256;
+
+__global__ __launch_bounds__(kThreads) void k_box_starts_coarse(const uint32_t *__restrict__ keys,
+                                                                int64_t n, int64_t nbox,
+                                                                int32_t *__restrict__ coarse) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t nc = nbox / kBoxStride + 1;
+  if (c > nc) return;
+  const int64_t b = c * kBoxStride < nbox ? c * kBoxStride : nbox;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  coarse[c] = (int32_t)lo;
+}
+
 __global__ __launch_bounds__(kThreads) void k_box_starts(const uint32_t *__restrict__ keys,
-                                                         int64_t n, int64_t nbox,
+                                                         int64_t nbox,
+                                                         const int32_t *__restrict__ coarse,
                                                          int32_t *__restrict__ start) {
   const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (b > nbox) return;
-  // lower_bound of b in the sorted keys
-  int64_t lo = 0, hi = n;
+  const int64_t c = b / kBoxStride;
+  int64_t lo = coarse[c], hi = coarse[c + 1];
+  // the bound of box b lies between those of boxes c*stride and (c+1)*stride
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     if ((int64_t)keys[mid] < b)
@@ -387,10 +441,18 @@ void launch_bbox_multi(const BBoxSet *sets_dev, int nsets, int nparts, double *p
 }
 
 void launch_leaf_keys(const double *xy, int64_t n, Geometry g, uint32_t *keys, uint32_t *vals,
-                      hipStream_t stream) {
+                      uint32_t *box_count, hipStream_t stream) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_leaf_keys, dim3(blocks_for(n)), dim3(kThreads), 0, stream, xy, n, g, keys,
-                     vals);
+                     vals, box_count);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream) {
+  if (n == 0) return;
+  int64_t nb = blocks_for(n);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)nb), dim3(kThreads), 0, stream, p, n, v);
   LENS_HIP(hipGetLastError());
 }
 
@@ -446,10 +508,15 @@ void launch_gather_rays(const uint32_t *perm, const double *xy, int64_t n, doubl
 }
 
 void launch_box_starts(const uint32_t *sorted_keys, int64_t n, int64_t nbox, int32_t *start,
-                       hipStream_t stream) {
+                       int32_t *coarse, hipStream_t stream) {
+  const int64_t nc = nbox / kBoxStride + 2;
+  hipLaunchKernelGGL(k_box_starts_coarse, dim3(blocks_for(nc)), dim3(kThreads), 0, stream,
+                     sorted_keys, n, nbox, coarse);
   hipLaunchKernelGGL(k_box_starts, dim3(blocks_for(nbox + 1)), dim3(kThreads), 0, stream,
-                     sorted_keys, n, nbox, start);
+                     sorted_keys, nbox, coarse, start);
   LENS_HIP(hipGetLastError());
 }
+
+int64_t box_starts_coarse_len(int64_t nbox) { return nbox / kBoxStride + 2; }
 
 }  // namespace lensfmm

@@ -644,3 +644,57 @@ def test_batched_autotuned_maps_against_direct(lf):
         print(f"field {k}: {moved} of {n} rays binned differently from the FP64 direct sum")
         assert moved <= 3e-4 * n + 2
     lf.release_cached()
+
+
+# ---------------------------------------------------------------- call graphs
+
+def test_call_graph_replays_match_eager(lf):
+    """Plan-less grid calls are captured into a HIP graph from their second
+    occurrence on; every replay (with eager torch work and synchronisation in
+    between) must equal the eager result, also after the stars change in
+    place without changing the tree geometry."""
+    import torch
+    from paper_2211_00354_amd import _lib
+    f = wl.random_field(20000, 60.0, seed=91, masses="powerlaw")
+    g = wl.centred_grid(80.0, 80.0, 512, 512)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    y = torch.empty((g.n, 2), dtype=torch.float64, device="cuda")
+    kw = dict(kappa_s=0.2, gamma=0.1, precision="mixed", p=12)
+
+    def eager():
+        _lib.profile_enable(True)   # the profiler forces eager launches
+        r = host(lf.deflect(xy, m, grid=lfgrid(g), out=y, **kw))
+        _lib.profile_enable(False)
+        return r
+
+    lf.release_cached()
+    _say("call graph deflect")
+    ref = eager()
+    for rep in range(5):
+        y.fill_(float("nan"))
+        out = host(lf.deflect(xy, m, grid=lfgrid(g), out=y, **kw))
+        np.testing.assert_array_equal(out, ref, err_msg=f"call {rep}")
+        z = torch.randn(1 << 20, device="cuda")
+        assert math.isfinite(float(z.sum()))
+        torch.cuda.synchronize()
+    # swap two stars: same bounding box and geometry, different tree content
+    xy[[0, 1]] = xy[[1, 0]].clone()
+    m[[0, 1]] = m[[1, 0]].clone()
+    ref2 = eager()
+    y.fill_(float("nan"))
+    out = host(lf.deflect(xy, m, grid=lfgrid(g), out=y, **kw))
+    np.testing.assert_array_equal(out, ref2)
+    yo, ao, _ = oracle.deflect(host(xy), host(m), g.rays(g.strided(37, 3)), 0.2, 0.1)
+    assert rel_l2(out[g.strided(37, 3)], yo, ao) <= 1e-5
+    # maps accumulate through the replays
+    md = lf.MapDesc(-10.0, -10.0, 20.0, 128)
+    counts = torch.zeros((128, 128), dtype=torch.int32, device="cuda")
+    _say("call graph map")
+    for rep in range(4):
+        lf.irs_map(xy, m, grid=lfgrid(g), map=md, counts=counts, **kw)
+        torch.cuda.synchronize()
+    _lib.profile_enable(True)
+    one = host(lf.irs_map(xy, m, grid=lfgrid(g), map=md, **kw))
+    _lib.profile_enable(False)
+    np.testing.assert_array_equal(host(counts), 4 * one)
+    lf.release_cached()
