@@ -37,6 +37,7 @@ struct lens_plan {
   // for targets in the box above), each formed straight from the stars.
   int dense_top = 0;
   std::vector<Window> swin;  // index = level
+  std::vector<char> direct;  // index = level: multipoles formed from the stars (else M2M)
   DevBuf sxy, sm, leaf_start;
   std::vector<DevBuf> mp;    // index = level, FP64 multipoles
   std::vector<DevBuf> mp32;  // index = level, FP32 copies (fine levels, mixed)
@@ -238,10 +239,12 @@ Window window_for(const lens_plan &P, int level, const double bb[4]) {
 // boxes of it, so level l needs the multipoles of the target window (rays'
 // boxes plus one) grown by 3 boxes.  Where that covers under a quarter of the
 // level, and at every finer level, only that window is stored and formed
-// from the stars; the coarser levels hold every box, down to a level where
-// boxes hold ~512 sources or fewer so that forming them from the stars stays
-// short.  When the rays cover the sources (the common case) every level is
-// dense.
+// from the stars ("windowed" levels); the coarser ("dense") levels reach down
+// at least to where boxes hold ~512 sources, so that forming the finest of
+// them from the stars stays short, and are formed by M2M above that.  A
+// dense level formed from the stars whose parent level is too also stores
+// only its window.  When the rays cover the sources (the common case) every
+// level is dense.
 void source_windows(lens_plan *P) {
   const int L = P->g.L;
   P->swin.assign(L + 1, Window{0, 0, 0, 0});
@@ -259,9 +262,18 @@ void source_windows(lens_plan *P) {
   int D = std::max(lw - 1, dmin);
   if (D >= L) D = L;
   P->dense_top = std::max(D, 2);
+  // formed from the stars: the windowed levels, the finest dense level, and
+  // dense levels whose boxes hold ~8 sources or fewer on average (a thread
+  // per box then beats M2M from the children); the others by M2M
+  P->direct.assign(L + 1, 0);
+  for (int l = 2; l <= L; ++l)
+    P->direct[l] = l >= P->dense_top ||
+                   (double)P->n_stars <= 8.0 * (double)(int64_t(1) << (2 * l));
+  // a dense level keeps every box only if the level above is formed from it
   for (int l = 2; l <= P->dense_top; ++l) {
     const int64_t n = int64_t(1) << l;
-    P->swin[l] = Window{0, 0, n, n};
+    const bool m2m_child = l > 2 && !P->direct[l - 1];
+    if (m2m_child || !P->direct[l]) P->swin[l] = Window{0, 0, n, n};
   }
 }
 
@@ -358,19 +370,11 @@ void plan_enqueue(lens_plan *P, const double *xy, const double *q, hipStream_t s
   const OpTables &T = op_tables(P->p, st);
   {
     StageTimer tm("upward", st);
-    // windowed levels, and up to three of the finest dense ones (while boxes
-    // hold ~2048 sources or fewer on average), from the stars; the coarser
-    // dense levels by M2M
-    const int D = P->dense_top, direct_levels = 3;
-    auto from_stars = [&](int l) {
-      if (l > D) return true;
-      return l > D - direct_levels &&
-             (l == D || (double)N <= 2048.0 * (double)(int64_t(1) << (2 * l)));
-    };
+    // from the stars or by M2M, level by level as source_windows decided
     for (int l = L; l >= 2; --l) {
       double *out = static_cast<double *>(P->mp[l].ptr);
       float *out32 = static_cast<float *>(P->mp32[l].ptr);
-      if (from_stars(l))
+      if (P->direct[l])
         launch_p2m(P->g, l, P->swin[l], sxy, sm, P->qdim, leaf_start, P->p, out, out32, N, st);
       else
         launch_m2m(l, P->p, P->mp_at(l + 1), out, out32, T.m2m, st);

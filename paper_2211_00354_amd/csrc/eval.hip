@@ -9,9 +9,9 @@
 //     for every lane, so they are read with wave-uniform scalar loads into
 //     SGPRs and used directly as VALU operands -- every star is fetched once
 //     per wave and shared by all 64*R rays;
-//   * near field: alpha_near = sum m (x - x_i)/|x - x_i|^2 over those stars,
-//     pair differences formed in FP64, then (LENS_MIXED) rounded to FP32 for
-//     the square, reciprocal and accumulation;
+//   * near field: alpha_near = sum m (x - x_i)/|x - x_i|^2 over those stars;
+//     LENS_MIXED takes ray and star coordinates relative to the box centre
+//     (FP64, rounded to FP32) and does the pair arithmetic in FP32;
 //   * far field: f(z) = sum_l b~_l w^l, w = (z - c)/s, by Horner in FP64,
 //     alpha_far = conj(f);
 //   * y = (1-kappa_s-gamma, 1-kappa_s+gamma) * x - alpha in FP64, written as
@@ -29,21 +29,25 @@ constexpr int kXcd = 8;
 constexpr int kThreads = 256;  // helper kernels
 
 
-// One star against the R rays of a lane.  A coincident pair (dx = dy = 0)
-// contributes exactly zero: the tiny term keeps its weight finite (for any
-// |m| below ~1e18 in FP32, ~1e108 in FP64) and it multiplies dx = dy = 0,
-// so no branch or select is needed; the tiny term changes no other pair
-// unless the two points are closer than ~1e-7 (FP32) or ~1e-92 (FP64).
-template <bool MIXED, int R, typename A>
-__device__ __forceinline__ void pair_update(const double (&rx)[R], const double (&ry)[R], double sx,
-                                            double sy, double mm, A (&ax)[R], A (&ay)[R]) {
+// One star against the R rays of a lane.  LENS_MIXED: coordinates relative
+// to the evaluation box's centre, formed in FP64 and rounded to FP32 (a ray's
+// once per pass, a star's once per pass for all the lane's rays), so the
+// pair arithmetic is FP32 throughout; FP64: absolute coordinates.  A
+// coincident pair (dx = dy = 0) contributes exactly zero: the tiny term
+// keeps its weight finite (for any |m| below ~1e18 in FP32, ~1e108 in FP64)
+// and it multiplies dx = dy = 0, so no branch or select is needed.  In FP32 a
+// pair closer than about one ulp of the box size (~1e-7 of it) rounds to
+// coincident and is skipped the same way.
+template <bool MIXED, int R, typename C, typename A>
+__device__ __forceinline__ void pair_update(const C (&rx)[R], const C (&ry)[R], C sx, C sy,
+                                            double mm, A (&ax)[R], A (&ay)[R]) {
   if constexpr (MIXED) {
     const float m = (float)mm;
     constexpr float tiny = 0x1p-66f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const float dx = (float)(rx[r] - sx);
-      const float dy = (float)(ry[r] - sy);
+      const float dx = rx[r] - sx;
+      const float dy = ry[r] - sy;
       const float r2 = fmaf(dx, dx, fmaf(dy, dy, tiny));
       const float w = m * rcp_f32(r2);
       ax[r] = fmaf(w, dx, ax[r]);
@@ -199,6 +203,19 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
         ay[r] = 0;
       }
 
+      // pair coordinates (see pair_update)
+      using crd_t = typename std::conditional<MIXED, float, double>::type;
+      crd_t qx[R], qy[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        qx[r] = MIXED ? (crd_t)(rx[r] - cx) : (crd_t)rx[r];
+        qy[r] = MIXED ? (crd_t)(ry[r] - cy) : (crd_t)ry[r];
+      }
+      auto star = [&](double x, double y, double mass) {
+        const crd_t sx = MIXED ? (crd_t)(x - cx) : (crd_t)x;
+        const crd_t sy = MIXED ? (crd_t)(y - cy) : (crd_t)y;
+        pair_update<MIXED, R>(qx, qy, sx, sy, mass, ax, ay);
+      };
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         int32_t i = rs[d];
@@ -212,10 +229,9 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
             mm[q] = sm[i + q];
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) pair_update<MIXED, R>(rx, ry, sx[q], sy[q], mm[q], ax, ay);
+          for (int q = 0; q < 4; ++q) star(sx[q], sy[q], mm[q]);
         }
-        for (; i < re[d]; ++i)
-          pair_update<MIXED, R>(rx, ry, sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i], ax, ay);
+        for (; i < re[d]; ++i) star(sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i]);
       }
 
       // far field: Horner over the R rays, one LDS read per coefficient
