@@ -33,7 +33,7 @@ METRIC = "rays/s deflected at N_*=1e6 (mixed FMM vs FP64 direct) at stated rel. 
 PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak, FLOP/s
 PEAK_HBM = 8.0e12                # bytes/s
 PAIR_FLOPS = 12                  # per near pair: 2 sub, |d|^2 (3), rcp (1), m*rcp (1), 2 FMA (4), + cvt free
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_config2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_deflect_1e6_traffic.json")
 
 
 def log(*a):
@@ -107,7 +107,7 @@ def main():
     if args.workload == "map":
         return bench_map(args)
     log("generating workload")
-    f, g = wl.config2()
+    f, g = wl.powerlaw_disk()
     xy = torch.from_numpy(f.xy).cuda()
     m = torch.from_numpy(f.m).cuda()
     grid = lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny)
@@ -271,7 +271,7 @@ def bench_map(args):
     import workloads as wl
 
     log("generating workload")
-    f, g, mp = wl.config3()
+    f, g, mp = wl.high_magnification()
     xy = torch.from_numpy(f.xy).cuda()
     m = torch.from_numpy(f.m).cuda()
     grid = lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny)

@@ -45,9 +45,9 @@ def lfgrid(g: wl.Grid):
 
 # ------------------------------------------------------------ FP64 direct sum
 
-def test_direct_config1_matches_oracle(lf):
-    f, g, _ = wl.config1()
-    _say("direct config1", f.n, g.nx, g.ny)
+def test_direct_small_disk_matches_oracle(lf):
+    f, g, _ = wl.small_disk()
+    _say("direct small_disk", f.n, g.nx, g.ny)
     y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
                         gamma=f.gamma, method="direct"))
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
@@ -77,10 +77,10 @@ def test_direct_explicit_rays_edge_cases(lf, n):
         assert rel_l2(y, yo, ao) <= 1e-13
 
 
-def test_direct_map_config1(lf):
+def test_direct_map_small_disk(lf):
     import torch
-    f, g, mp = wl.config1()
-    _say("direct map config1")
+    f, g, mp = wl.small_disk()
+    _say("direct map small_disk")
     md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
     counts = host(lf.irs_map(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), map=md,
                              kappa_s=f.kappa_s, gamma=f.gamma, method="direct"))
@@ -100,9 +100,9 @@ def test_direct_map_config1(lf):
 @pytest.mark.parametrize("precision,p,tol", [
     ("fp64", 12, 1e-6), ("fp64", 20, 1e-8), ("fp64", 30, 1e-10), ("mixed", 12, 1e-5),
 ])
-def test_fmm_config1(lf, precision, p, tol):
-    f, g, _ = wl.config1()
-    _say("fmm config1", precision, p)
+def test_fmm_small_disk(lf, precision, p, tol):
+    f, g, _ = wl.small_disk()
+    _say("fmm small_disk", precision, p)
     y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
                         gamma=f.gamma, precision=precision, p=p))
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
@@ -113,7 +113,7 @@ def test_fmm_config1(lf, precision, p, tol):
 
 @pytest.mark.parametrize("leaf", [2, 3, 4, 6, 8])
 def test_fmm_leaf_levels(lf, leaf):
-    f, g, _ = wl.config1()
+    f, g, _ = wl.small_disk()
     _say("fmm leaf level", leaf)
     y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
                         gamma=f.gamma, precision="fp64", p=24, leaf_level=leaf))
@@ -272,7 +272,7 @@ def test_plan_rejects_rays_outside_its_ray_box(lf):
 
 @pytest.mark.parametrize("prec,p", [("fp64", 20), ("mixed", 16)])
 def test_fmm_map_equals_binned_deflect(lf, prec, p):
-    f, g, mp = wl.config1()
+    f, g, mp = wl.small_disk()
     md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
     _say("fmm map", prec, p)
@@ -295,13 +295,13 @@ def test_fmm_map_equals_binned_deflect(lf, prec, p):
 
 # -------------------------------------------------------- the N_*=1e6 field
 
-def test_config2_reduced(lf):
-    f, g = wl.config2(n_stars=50000, n_side=1024)
+def test_powerlaw_disk_reduced(lf):
+    f, g = wl.powerlaw_disk(n_stars=50000, n_side=1024)
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
     idx = g.strided(8, 3)
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), f.kappa_s, f.gamma)
     for prec, p, tol in (("mixed", 12, 1e-5), ("fp64", 12, 1e-6), ("fp64", 30, 1e-10)):
-        _say("config2 reduced", prec, p)
+        _say("powerlaw_disk reduced", prec, p)
         y = host(lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma,
                             precision=prec, p=p))
         err = rel_l2(y[idx], yo, ao)
@@ -309,27 +309,27 @@ def test_config2_reduced(lf):
         assert err <= tol
 
 
-def test_config2_full_size_sampled(lf):
+def test_powerlaw_disk_full_size_sampled(lf):
     """The benchmark workload itself (1e6 stars, 8192^2 rays, mixed, p=12) in
     the launch configuration the benchmark times, checked on a strided sample."""
     import torch
-    f, g = wl.config2()
+    f, g = wl.powerlaw_disk()
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
-    _say("config2 full mixed")
+    _say("powerlaw_disk full mixed")
     y = lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma, precision="mixed", p=12)
     idx = torch.from_numpy(g.strided(128, 64)).cuda()
     ys = host(y[idx])
     assert bool(torch.isfinite(y).all())
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx.cpu().numpy()), f.kappa_s, f.gamma)
     err = rel_l2(ys, yo, ao)
-    print("config2 full mixed rel l2", err)
+    print("powerlaw_disk full mixed rel l2", err)
     assert err <= 1e-5
 
 
 # ------------------------------------------------------------------- adjoint
 
 def _adjoint_case(n_clusters=40, per=25, n_rays=20000, seed=55):
-    f, rays, tn = wl.config5(n_clusters=n_clusters, per_cluster=per, n_rays=n_rays, seed=seed)
+    f, rays, tn = wl.clustered_lenses(n_clusters=n_clusters, per_cluster=per, n_rays=n_rays, seed=seed)
     f.m[:] = np.random.default_rng(seed + 1).uniform(0.5, 1.5, f.n)
     yo, ao, _ = oracle.deflect(f.xy, f.m, rays)
     t = yo + tn
@@ -420,7 +420,7 @@ def test_adjoint_invariants_and_autograd(lf):
 # ------------------------------------------------------------------ batching
 
 def _batch_fields(n_fields, n_side, npix, seed, n_range):
-    return wl.config4(n_fields=n_fields, n_side=n_side, npix=npix, seed=seed, n_range=n_range)
+    return wl.field_batch(n_fields=n_fields, n_side=n_side, npix=npix, seed=seed, n_range=n_range)
 
 
 def test_batched_maps_equal_single_maps_and_replay(lf):
@@ -462,18 +462,18 @@ def test_batched_maps_equal_single_maps_and_replay(lf):
     lf.release_cached()
 
 
-def test_batched_config4_full_size(lf):
+def test_batched_field_batch_full_size(lf):
     """64 fields with N_* log-uniform in [1e4, 2e5], 2048^2 rays each, 512^2
     maps, one captured graph; checked field by field against single maps."""
     import time
     import torch
-    cases = wl.config4()
+    cases = wl.field_batch()
     fields, grids, maps = [], [], []
     for f, g, mp in cases:
         fields.append((dev_tensor(f.xy), dev_tensor(f.m), f.kappa_s, f.gamma))
         grids.append(lfgrid(g))
         maps.append(lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix))
-    _say("batched config4 full")
+    _say("batched field_batch full")
     got = lf.irs_map_batched(fields, grids, maps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -482,7 +482,7 @@ def test_batched_config4_full_size(lf):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rays = sum(g.nx * g.ny for g in grids)
-    print(f"batched config4: {dt * 1e3:.2f} ms for {rays:.3e} rays -> {rays / dt:.3e} rays/s")
+    print(f"batched field_batch: {dt * 1e3:.2f} ms for {rays:.3e} rays -> {rays / dt:.3e} rays/s")
     for k in (0, 17, 63):
         xy, m, ks, gm = fields[k]
         single = host(lf.irs_map(xy, m, grid=grids[k], map=maps[k], kappa_s=ks, gamma=gm))
@@ -493,7 +493,7 @@ def test_batched_config4_full_size(lf):
 # ------------------------------------------------------- full-size workloads
 
 @pytest.mark.parametrize("prec,p,fl", [("mixed", 20, -1), ("fp64", 24, 0)])
-def test_config3_full_map(lf, prec, p, fl):
+def test_high_magnification_full_map(lf, prec, p, fl):
     """High magnification: 5e6 stars, 16384^2 rays over [-120,120]x[-60,60],
     2000^2 map over [-10,10]^2, kappa_s=0.75, gamma=0.05 (mu = 50).  At mu = 50
     y is a small difference of large terms: a 1e-4 bin-reassignment rate
@@ -501,18 +501,18 @@ def test_config3_full_map(lf, prec, p, fl):
     field stays FP32) for the mixed path."""
     import time
     import torch
-    f, g, mp = wl.config3()
+    f, g, mp = wl.high_magnification()
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
     md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
     kw = dict(kappa_s=f.kappa_s, gamma=f.gamma, precision=prec, p=p, fp32_levels=fl)
-    _say("config3 map", prec, p, fl)
+    _say("high_magnification map", prec, p, fl)
     counts = lf.irs_map(xy, m, grid=lfgrid(g), map=md, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     counts2 = lf.irs_map(xy, m, grid=lfgrid(g), map=md, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    print(f"config3 {prec} p={p}: {dt * 1e3:.1f} ms for {g.n:.3e} rays -> {g.n / dt:.3e} rays/s")
+    print(f"high_magnification {prec} p={p}: {dt * 1e3:.1f} ms for {g.n:.3e} rays -> {g.n / dt:.3e} rays/s")
     c = host(counts)
     np.testing.assert_array_equal(c, host(counts2))          # deterministic
     # the map is the oracle's binning of the GPU's own y (same decisions)
@@ -535,29 +535,29 @@ def test_config3_full_map(lf, prec, p, fl):
     moved = np.count_nonzero(np.any(np.floor((ys - [mp.y1min, mp.y2min]) * S)
                                     != np.floor((yo - [mp.y1min, mp.y2min]) * S), axis=1))
     est = float(np.mean(np.abs(ys - yo).sum(1)) * S)
-    print(f"config3 {prec}: rel l2 {rel_l2(ys, yo, ao):.2e}, moved {moved}/{len(idx)}, "
+    print(f"high_magnification {prec}: rel l2 {rel_l2(ys, yo, ao):.2e}, moved {moved}/{len(idx)}, "
           f"estimated reassignment {est:.2e}")
     assert est <= 1e-4
     assert moved <= max(2, 2e-4 * len(idx))
 
 
-def test_config5_full_gradient(lf):
+def test_clustered_lenses_full_gradient(lf):
     """Clustered lenses (2000 clusters x 100 stars), 1e6 random rays: the mixed
     adjoint FMM against the FP64 direct gradient on the GPU (all stars), the
     oracle (64 stars) and central differences of the loss (64 stars x 3)."""
     import torch
-    f, rays, tn = wl.config5()
+    f, rays, tn = wl.clustered_lenses()
     xy, m, r = dev_tensor(f.xy), dev_tensor(f.m), dev_tensor(rays)
-    _say("config5 forward")
+    _say("clustered_lenses forward")
     y0 = lf.deflect(xy, m, rays=r, method="direct")
     t = y0 + dev_tensor(tn)
     G = 2 * (y0 - t)
-    _say("config5 adjoint")
+    _say("clustered_lenses adjoint")
     gd_xy, gd_m = lf.deflect_backward(xy, m, G, rays=r, method="direct")
     gf_xy, gf_m = lf.deflect_backward(xy, m, G, rays=r, precision="mixed", p=12)
     e_xy = _grad_err(host(gf_xy), host(gd_xy))
     e_m = _grad_err(host(gf_m), host(gd_m))
-    print(f"config5 mixed adjoint vs FP64 direct: grad_xy {e_xy:.2e}, grad_m {e_m:.2e}")
+    print(f"clustered_lenses mixed adjoint vs FP64 direct: grad_xy {e_xy:.2e}, grad_m {e_m:.2e}")
     assert e_xy <= 1e-5 and e_m <= 1e-5
     # oracle on 64 seeded stars
     sel = np.random.default_rng(5).choice(f.n, 64, replace=False)
@@ -609,12 +609,12 @@ def test_autotune_deflect_reaches_tol(lf):
 def test_autotune_high_magnification_map(lf):
     """The 5e6-star, mu = 50 map: the tuner's setting keeps the expected bin
     reassignment under 1e-4 on rays it did not sample (oracle)."""
-    f, g, mp = wl.config3()
+    f, g, mp = wl.high_magnification()
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
     md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
-    _say("autotune config3 map")
+    _say("autotune high_magnification map")
     t = lf.autotune(xy, m, lfgrid(g), map=md, tol=1e-4, kappa_s=f.kappa_s, gamma=f.gamma)
-    print("autotune config3", t)
+    print("autotune high_magnification", t)
     assert t["error"] <= 1e-4
     plan = lf.Plan(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma, p=t["p"],
                    leaf_level=t["leaf_level"], fp32_levels=t["fp32_levels"])
@@ -624,7 +624,7 @@ def test_autotune_high_magnification_map(lf):
     plan.close()
     yo, _, _ = oracle.deflect(f.xy, f.m, rays, f.kappa_s, f.gamma)
     est = float(np.abs(ys - yo).sum(1).mean() * mp.npix / mp.side)
-    print(f"config3 tuned: reassignment estimate {est:.2e} on {len(idx)} rays")
+    print(f"high_magnification tuned: reassignment estimate {est:.2e} on {len(idx)} rays")
     assert est <= 2e-4
 
 

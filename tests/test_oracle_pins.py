@@ -354,10 +354,10 @@ def test_gradient_invariants():
 # ------------------------------------------------------------------ workloads
 
 def test_workload_readings():
-    f, g, mp = wl.config1()
+    f, g, mp = wl.small_disk()
     assert f.n == 1000 and abs(f.kappa_star - 1000 / 26.6 ** 2) < 1e-12
     assert g.dx == 10 / 512 and g.rays()[0, 0] == -5 + 0.5 * 10 / 512
-    f2, g2 = wl.config2(n_stars=20000, n_side=256)
+    f2, g2 = wl.powerlaw_disk(n_stars=20000, n_side=256)
     assert abs(f2.m.mean() - 1.0) < 1e-12
     assert 0.44 < f2.m.min() and f2.m.max() < 4.5
     assert abs(f2.kappa_star - 0.4) < 1e-12

@@ -124,7 +124,7 @@ def powerlaw_masses(rng: np.random.Generator, n: int, lo=0.1, hi=1.0, slope=2.35
 # ---------------------------------------------------------------- workloads
 
 
-def config1():
+def small_disk():
     """1000 unit-mass lenses in a disk of radius 26.6, gamma=0.3; 512^2 rays
     over [-5,5]^2; 256^2 map over [-2,2]^2.  The literal radius is kept, so the
     effective convergence is sum(m)/R^2 = 1.413."""
@@ -138,7 +138,7 @@ def config1():
     return f, g, mp
 
 
-def config2(n_stars: int = 1_000_000, n_side: int = 8192, seed: int = 2):
+def powerlaw_disk(n_stars: int = 1_000_000, n_side: int = 8192, seed: int = 2):
     """N_*=1e6 power-law masses in a disk with kappa_*=0.4, kappa_s=0.2,
     gamma=0.35; an 8192^2 ray grid over the square inscribed in the disk."""
     rng = np.random.default_rng(seed)
@@ -151,7 +151,7 @@ def config2(n_stars: int = 1_000_000, n_side: int = 8192, seed: int = 2):
     return f, g
 
 
-def config3(n_stars: int = 5_000_000, nx: int = 16384, ny: int = 16384, kappa_s: float = 0.75,
+def high_magnification(n_stars: int = 5_000_000, nx: int = 16384, ny: int = 16384, kappa_s: float = 0.75,
             seed: int = 3):
     """High-magnification field: kappa_*=0.1, kappa_s=0.75, gamma=0.05
     (macro magnification 50); rays over [-120,120]x[-60,60]; 2000^2 map over
@@ -165,7 +165,7 @@ def config3(n_stars: int = 5_000_000, nx: int = 16384, ny: int = 16384, kappa_s:
     return f, g, mp
 
 
-def config4(n_fields: int = 64, n_side: int = 2048, npix: int = 512, seed: int = 4,
+def field_batch(n_fields: int = 64, n_side: int = 2048, npix: int = 512, seed: int = 4,
             n_range=(1e4, 2e5)):
     """Batch of independent star fields with uneven N_*, kappa_* and gamma."""
     master = np.random.default_rng(seed)
@@ -187,7 +187,7 @@ def config4(n_fields: int = 64, n_side: int = 2048, npix: int = 512, seed: int =
     return out
 
 
-def config5(n_clusters: int = 2000, per_cluster: int = 100, n_rays: int = 1_000_000,
+def clustered_lenses(n_clusters: int = 2000, per_cluster: int = 100, n_rays: int = 1_000_000,
             radius: float = 60.0, sigma: float = 0.5, noise: float = 0.01, seed: int = 5):
     """Clustered lenses for the gradient workload: Gaussian clusters around
     centres uniform in a disk, rays uniform in the same disk.  Returns the
