@@ -35,6 +35,20 @@
  *    S = npix/side, decided as u = floor((y1 - y1min) * S) with one rounding
  *    per operation.  Rays outside the map are dropped.
  *
+ *  - oracle_ipm: inverse polygon mapping (Section 2.3, first order as used in
+ *    Section 2.4).  Adjacent grid rays are the corners of image-plane cells
+ *    of area dx dy; cell (i, j) with corners y(i,j), y(i+1,j), y(i+1,j+1),
+ *    y(i,j+1) maps to a quadrilateral Q in the source plane and its area is
+ *    shared among the pixels Q overlaps in proportion to the overlap areas:
+ *    pixel P receives dx dy |Q n P| / |Q|, and mu[P] accumulates that over
+ *    the pixel area, so mu is the magnification sum S_i / S_pixel of the
+ *    paper.  A quadrilateral whose edges cross (the cell straddles a critical
+ *    curve) or whose area is zero is treated at zeroth order: each corner
+ *    carries a quarter of the cell's area to the pixel it falls in (the IRS
+ *    rule).  Overlaps are found by clipping Q against each pixel square of
+ *    its bounding box (Sutherland-Hodgman) and measuring the clipped polygon
+ *    by the shoelace formula, in pixel units (p = (y - ymin) S).
+ *
  *  - oracle_grad: the gradient of a scalar loss L(y) with respect to the star
  *    positions and masses, given G_k = dL/dy_k, from differentiating eq. (1):
  *        dL/dx_i = m_i sum_k ( G_k / r^2 - 2 d (d . G_k) / r^4 )
@@ -220,5 +234,122 @@ int oracle_grad(int64_t n_stars, const double *sxy, const double *sm,
     grad_xy[2 * i + 1] = sm[i] * nval(&gy);
     grad_m[i] = nval(&gm);
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ IPM */
+
+/* signed area (twice) of the triangle a, b, c */
+static double orient2(const double *a, const double *b, const double *c) {
+  return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
+}
+
+/* proper crossing of segments ab and cd (touching does not count) */
+static int segments_cross(const double *a, const double *b, const double *c, const double *d) {
+  const double o1 = orient2(a, b, c), o2 = orient2(a, b, d);
+  const double o3 = orient2(c, d, a), o4 = orient2(c, d, b);
+  return ((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) && ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0));
+}
+
+/* shoelace area (signed) of an n-gon */
+static double poly_area(int n, const double (*p)[2]) {
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const int k1 = (k + 1) % n;
+    s += p[k][0] * p[k1][1] - p[k1][0] * p[k][1];
+  }
+  return 0.5 * s;
+}
+
+/* clip polygon in[n] against the half-plane coordinate c (0: x, 1: y)
+ * >= lo (sign = +1) or <= hi (sign = -1); returns the new vertex count */
+static int clip_half(int n, const double (*in)[2], double (*out)[2], int c, double bound, int keep_ge) {
+  int m = 0;
+  for (int k = 0; k < n; ++k) {
+    const double *S = in[(k + n - 1) % n], *E = in[k];
+    const int sin_ = keep_ge ? S[c] >= bound : S[c] <= bound;
+    const int ein = keep_ge ? E[c] >= bound : E[c] <= bound;
+    if (ein != sin_) {
+      const double t = (bound - S[c]) / (E[c] - S[c]);
+      out[m][c] = bound;
+      out[m][1 - c] = S[1 - c] + t * (E[1 - c] - S[1 - c]);
+      ++m;
+    }
+    if (ein) {
+      out[m][0] = E[0];
+      out[m][1] = E[1];
+      ++m;
+    }
+  }
+  return m;
+}
+
+/* area of polygon q[4] (pixel units) inside the unit square [u,u+1]x[v,v+1] */
+static double quad_pixel_overlap(const double (*q)[2], double u, double v) {
+  double a[16][2], b[16][2];
+  int n = 4;
+  for (int k = 0; k < 4; ++k) {
+    a[k][0] = q[k][0] - u;
+    a[k][1] = q[k][1] - v;
+  }
+  n = clip_half(n, (const double (*)[2])a, b, 0, 0.0, 1);
+  n = clip_half(n, (const double (*)[2])b, a, 0, 1.0, 0);
+  n = clip_half(n, (const double (*)[2])a, b, 1, 0.0, 1);
+  n = clip_half(n, (const double (*)[2])b, a, 1, 1.0, 0);
+  return n >= 3 ? fabs(poly_area(n, (const double (*)[2])a)) : 0.0;
+}
+
+static void add_corner(double *mu, int32_t npix, const double *p, double w) {
+  if (!(p[0] >= 0.0) || !(p[1] >= 0.0)) return;
+  const double f1 = floor(p[0]), f2 = floor(p[1]);
+  if (f1 >= (double)npix || f2 >= (double)npix) return;
+  mu[(int64_t)f2 * npix + (int64_t)f1] += w;
+}
+
+/*
+ * IPM magnification of the (nx-1) x (ny-1) cells spanned by the mapped grid
+ * y[ny][nx][2] (row-major, y[(j*nx + i)*2 + c]), accumulated into
+ * mu[v*npix + u] (+=).  cell_area = dx * dy.  Returns 0 or -1.
+ */
+int oracle_ipm(int64_t nx, int64_t ny, const double *y, double cell_area, double y1min,
+               double y2min, double side, int32_t npix, double *mu) {
+  if (nx < 0 || ny < 0 || npix <= 0 || !(side > 0.0) || !(cell_area >= 0.0)) return -1;
+  const double S = (double)npix / side;
+  const double cell_px = cell_area * S * S; /* cell area in pixel units */
+  for (int64_t j = 0; j + 1 < ny; ++j)
+    for (int64_t i = 0; i + 1 < nx; ++i) {
+      const int64_t id[4] = {j * nx + i, j * nx + i + 1, (j + 1) * nx + i + 1, (j + 1) * nx + i};
+      double q[4][2];
+      int finite = 1;
+      for (int k = 0; k < 4; ++k) {
+        q[k][0] = (y[2 * id[k]] - y1min) * S;
+        q[k][1] = (y[2 * id[k] + 1] - y2min) * S;
+        finite &= isfinite(q[k][0]) && isfinite(q[k][1]);
+      }
+      if (!finite) continue;
+      const double area = fabs(poly_area(4, (const double (*)[2])q));
+      const int folded = segments_cross(q[0], q[1], q[2], q[3]) || segments_cross(q[1], q[2], q[3], q[0]);
+      if (folded || !(area > 0.0)) {
+        for (int k = 0; k < 4; ++k) add_corner(mu, npix, q[k], 0.25 * cell_px);
+        continue;
+      }
+      double lo0 = q[0][0], hi0 = q[0][0], lo1 = q[0][1], hi1 = q[0][1];
+      for (int k = 1; k < 4; ++k) {
+        lo0 = fmin(lo0, q[k][0]);
+        hi0 = fmax(hi0, q[k][0]);
+        lo1 = fmin(lo1, q[k][1]);
+        hi1 = fmax(hi1, q[k][1]);
+      }
+      if (hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix) continue;
+      const int64_t u0 = lo0 < 0.0 ? 0 : (int64_t)floor(lo0);
+      const int64_t v0 = lo1 < 0.0 ? 0 : (int64_t)floor(lo1);
+      const int64_t u1 = hi0 >= (double)npix ? npix - 1 : (int64_t)floor(hi0);
+      const int64_t v1 = hi1 >= (double)npix ? npix - 1 : (int64_t)floor(hi1);
+      for (int64_t v = v0; v <= v1; ++v)
+        for (int64_t u = u0; u <= u1; ++u) {
+          const double ov = quad_pixel_overlap((const double (*)[2])q, (double)u, (double)v);
+          if (ov > 0.0) mu[v * npix + u] += cell_px * (ov / area);
+        }
+    }
   return 0;
 }

@@ -366,3 +366,160 @@ def test_workload_readings():
     i = np.arange(g2.n) % g2.nx
     assert np.all(r[:, 0] == g2.x0 + (i + 0.5) * g2.dx)
     assert (g2.dx * 2 ** 20) == round(g2.dx * 2 ** 20)
+
+
+# ----------------------------------------------------------------------- IPM
+# Inverse polygon mapping (Section 2.3, first order): each image-plane cell's
+# area is shared among the source pixels its mapped quadrilateral overlaps.
+
+def _convex_overlap_exact(poly, u, v):
+    """Area of convex polygon `poly` (Fractions) inside [u,u+1]x[v,v+1], by a
+    different route than clipping: the intersection of two convex polygons is
+    the hull of the vertices of each inside the other and the crossings of
+    their edges."""
+    F = Fraction
+    sq = [(F(u), F(v)), (F(u + 1), F(v)), (F(u + 1), F(v + 1)), (F(u), F(v + 1))]
+
+    def inside(pt, pg):
+        sgn = 0
+        for k in range(len(pg)):
+            a, b = pg[k], pg[(k + 1) % len(pg)]
+            c = (b[0] - a[0]) * (pt[1] - a[1]) - (b[1] - a[1]) * (pt[0] - a[0])
+            if c != 0:
+                if sgn == 0:
+                    sgn = 1 if c > 0 else -1
+                elif (c > 0) != (sgn > 0):
+                    return False
+        return True
+
+    pts = [p for p in poly if inside(p, sq)] + [p for p in sq if inside(p, poly)]
+    for k in range(len(poly)):
+        a, b = poly[k], poly[(k + 1) % len(poly)]
+        for q in range(4):
+            c, d = sq[q], sq[(q + 1) % 4]
+            den = (b[0] - a[0]) * (d[1] - c[1]) - (b[1] - a[1]) * (d[0] - c[0])
+            if den == 0:
+                continue
+            t = ((c[0] - a[0]) * (d[1] - c[1]) - (c[1] - a[1]) * (d[0] - c[0])) / den
+            s = ((c[0] - a[0]) * (b[1] - a[1]) - (c[1] - a[1]) * (b[0] - a[0])) / den
+            if 0 <= t <= 1 and 0 <= s <= 1:
+                pts.append((a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1])))
+    pts = list(set(pts))
+    if len(pts) < 3:
+        return Fraction(0)
+    # convex hull (monotone chain) and its area
+    pts.sort()
+
+    def cross(o, a, b):
+        return (a[0] - o[0]) * (b[1] - o[1]) - (a[1] - o[1]) * (b[0] - o[0])
+    lo, hi = [], []
+    for p in pts:
+        while len(lo) >= 2 and cross(lo[-2], lo[-1], p) <= 0:
+            lo.pop()
+        lo.append(p)
+    for p in reversed(pts):
+        while len(hi) >= 2 and cross(hi[-2], hi[-1], p) <= 0:
+            hi.pop()
+        hi.append(p)
+    hull = lo[:-1] + hi[:-1]
+    return abs(sum(hull[k][0] * hull[(k + 1) % len(hull)][1] - hull[(k + 1) % len(hull)][0] * hull[k][1]
+                   for k in range(len(hull)))) / 2
+
+
+def _one_cell(corners, dx=0.5, dy=0.25, npix=8, side=8.0):
+    """A 2x2 grid (one cell) whose corners map to `corners` (source plane,
+    map [0, side)^2 so pixel units equal source units)."""
+    y = np.array([[corners[0], corners[1]], [corners[3], corners[2]]], dtype=np.float64)
+    return oracle.ipm(y, dx * dy, 0.0, 0.0, side, npix)
+
+
+@pytest.mark.parametrize("corners", [
+    [(1.25, 1.5), (5.75, 2.0), (4.5, 6.625), (0.5, 3.25)],        # convex, counter-clockwise
+    [(0.5, 3.25), (4.5, 6.625), (5.75, 2.0), (1.25, 1.5)],        # same, clockwise (parity flip)
+    [(2.0, 2.0), (2.75, 2.125), (2.5, 2.875), (2.125, 2.5)],      # inside one pixel... and two
+])
+def test_ipm_convex_cell_matches_exact_overlaps(corners):
+    mu = _one_cell(corners)
+    F = Fraction
+    poly = [(F(x), F(y)) for x, y in corners]
+    area = abs(sum(poly[k][0] * poly[(k + 1) % 4][1] - poly[(k + 1) % 4][0] * poly[k][1]
+                   for k in range(4))) / 2
+    cell = F(1, 8)   # dx dy in pixel units (pixel side 1)
+    for v in range(8):
+        for u in range(8):
+            want = float(cell * _convex_overlap_exact(poly, u, v) / area)
+            assert abs(mu[v, u] - want) <= 1e-15 + 1e-13 * want, (u, v, mu[v, u], want)
+    assert abs(mu.sum() - 0.125) <= 1e-14
+
+
+def test_ipm_concave_cell_splits_into_triangles():
+    # reflex vertex at index 3: the quad is the union of triangles (0,1,3), (1,2,3)
+    corners = [(1.0, 1.0), (6.5, 1.5), (5.5, 6.0), (3.25, 2.75)]
+    mu = _one_cell(corners)
+    F = Fraction
+    P = [(F(x), F(y)) for x, y in corners]
+    t1, t2 = [P[0], P[1], P[3]], [P[1], P[2], P[3]]
+
+    def tri_area(t):
+        return abs((t[1][0] - t[0][0]) * (t[2][1] - t[0][1]) - (t[1][1] - t[0][1]) * (t[2][0] - t[0][0])) / 2
+    area = tri_area(t1) + tri_area(t2)
+    for v in range(8):
+        for u in range(8):
+            ov = _convex_overlap_exact(t1, u, v) + _convex_overlap_exact(t2, u, v)
+            want = float(F(1, 8) * ov / area)
+            assert abs(mu[v, u] - want) <= 1e-15 + 1e-13 * want
+
+
+def test_ipm_folded_cell_goes_to_its_corners():
+    corners = [(1.5, 1.5), (5.5, 5.5), (5.5, 1.5), (1.5, 5.5)]   # a bow tie
+    mu = _one_cell(corners)
+    want = np.zeros((8, 8))
+    for x, y in corners:
+        want[int(y), int(x)] += 0.125 / 4
+    np.testing.assert_allclose(mu, want, rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("M", [((0.7, 0.0), (0.0, 1.3)), ((0.45, -0.62), (0.81, 0.2)),
+                               ((-0.5, 0.3), (0.4, 0.9))])
+def test_ipm_linear_map_gives_inverse_determinant(M):
+    """Under y = M x every cell is a parallelogram of area |det M| dx dy, so
+    every pixel the grid's image covers has mu = 1/|det M| exactly."""
+    M = np.array(M)
+    n = 241
+    xs = np.linspace(-12.0, 12.0, n)
+    X, Y = np.meshgrid(xs, xs)
+    pts = np.stack([X, Y], -1)
+    yg = pts @ M.T
+    dx = xs[1] - xs[0]
+    mu = oracle.ipm(yg, dx * dx, -2.0, -2.0, 4.0, 32)
+    np.testing.assert_allclose(mu, 1.0 / abs(np.linalg.det(M)), rtol=1e-12)
+
+
+def test_ipm_conserves_area_of_a_curved_mapping():
+    xs = np.linspace(0.0, 1.0, 65)
+    X, Y = np.meshgrid(xs, xs)
+    yg = np.stack([2.0 + 3.0 * X + 0.2 * np.sin(5 * Y), 2.0 + 2.5 * Y + 0.15 * np.cos(4 * X)], -1)
+    mu = oracle.ipm(yg, (xs[1] - xs[0]) ** 2, 0.0, 0.0, 8.0, 16)
+    assert abs(mu.sum() * (8.0 / 16) ** 2 - 1.0) <= 1e-12
+
+
+def test_ipm_point_lens_matches_analytic_magnification():
+    """Point lens: the IPM map of a fine grid approaches the pixel average of
+    mu(u) = (u^2+2)/(u sqrt(u^2+4)) (sum of both images) away from the caustic."""
+    n = 2048   # even: no grid point on the lens
+    xs = np.linspace(-3.0, 3.0, n)
+    X, Y = np.meshgrid(xs, xs)
+    r2 = X * X + Y * Y
+    yg = np.stack([X - X / r2, Y - Y / r2], -1)
+    side, npix = 2.0, 8
+    mu = oracle.ipm(yg, (xs[1] - xs[0]) ** 2, -1.0, -1.0, side, npix)
+    h = side / npix
+    g = (np.arange(64) + 0.5) / 64
+    for v in range(npix):
+        for u in range(npix):
+            cx, cy = -1.0 + (u + g) * h, -1.0 + (v + g[:, None]) * h
+            uu = np.hypot(cx, cy)
+            if uu.min() < 0.35:
+                continue   # near the caustic point
+            ana = ((uu ** 2 + 2) / (uu * np.sqrt(uu ** 2 + 4))).mean()
+            assert abs(mu[v, u] / ana - 1) < 2e-3, (u, v, mu[v, u], ana)
