@@ -177,6 +177,35 @@ LENS_API lens_status lens_deflect(lens_plan *plan, const lens_field *field, cons
 LENS_API lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *grid,
                      const lens_map_desc *map, const lens_opts *opts, void *stream);
 
+/* A source-plane magnification map for inverse polygon mapping:
+ * mu[v*npix + u] (FP64, device) is accumulated (+=), pixel (u, v) as in
+ * lens_map_desc. */
+typedef struct {
+  double y1min, y2min;  /* lower-left corner of the map */
+  double side;          /* side length, > 0 */
+  int32_t npix;         /* pixels per side, npix*npix <= INT32_MAX */
+  double *mu;           /* [npix][npix] FP64 (device) */
+} lens_ipm_desc;
+
+/*
+ * Inverse polygon mapping (Section 2.3, first order as in Section 2.4): the
+ * rays of `grid` are deflected (as lens_deflect, by FMM or direct sum) and
+ * taken as the corners of the (nx-1) x (ny-1) image-plane cells of area
+ * dx*dy between adjacent rays.  Each cell maps to a quadrilateral in the
+ * source plane whose area is shared among the pixels it overlaps in
+ * proportion to the overlap areas, so map->mu receives the magnification
+ * (sum of image areas over pixel area).  A cell whose quadrilateral folds
+ * (its edges cross: the cell straddles a critical curve), has zero area or
+ * spans more than 65536 pixels gives a quarter of its area to the pixel of
+ * each corner.  Contributions are summed in fixed point (2^-40 of a pixel's
+ * magnification), so the map does not depend on summation order.  Rays are
+ * processed in chunks of whole rows of at most opts->max_rays_per_chunk rays
+ * (default: one pass); the deflected corners need nx*ny*16 bytes of scratch
+ * per pass.  `plan` may be NULL as in lens_deflect.
+ */
+LENS_API lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                                  const lens_ipm_desc *map, const lens_opts *opts, void *stream);
+
 /*
  * Empirical autotuner for one field and ray grid: the expansion order p, the
  * leaf level and, for LENS_MIXED, fp32_levels (Appendix A leaves p and the

@@ -17,10 +17,11 @@ from typing import Optional
 
 from . import _lib
 from ._lib import (LENS_DIRECT, LENS_FMM, LENS_FP64, LENS_MIXED, LensError, LensField, LensGrid,
+                   LensIpmDesc,
                    LensMapDesc, LensOpts)
 
-__all__ = ["Grid", "MapDesc", "Plan", "autotune", "deflect", "deflect_backward", "irs_map",
-           "irs_map_batched", "LensDeflect", "LensError", "release_cached", "version"]
+__all__ = ["Grid", "MapDesc", "Plan", "autotune", "deflect", "deflect_backward", "ipm_map",
+           "irs_map", "irs_map_batched", "LensDeflect", "LensError", "release_cached", "version"]
 
 
 @dataclass
@@ -204,6 +205,33 @@ def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
     _lib.check(lib.lens_map(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
                             ctypes.byref(md), ctypes.byref(o), _stream()))
     return counts
+
+
+def ipm_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, kappa_s=0.0,
+            gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0, max_rays_per_chunk=0,
+            plan: Optional[Plan] = None, mu=None, fp32_levels=0):
+    """Inverse polygon mapping: the grid rays are the corners of image-plane
+    cells whose areas are shared among the source pixels their mapped
+    quadrilaterals overlap.  Returns the float64 [npix, npix] magnification
+    map (accumulated into ``mu`` if given), indexed [v, u]."""
+    torch = _torch()
+    lib = _lib.load()
+    if plan is None:
+        f = _field(star_xy, star_m, kappa_s, gamma)
+    else:  # the plan supplies the stars, the call the smooth terms
+        f = LensField(0, None, None, float(kappa_s), float(gamma))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if mu is None:
+        mu = torch.zeros((map.npix, map.npix), dtype=torch.float64, device=dev)
+    elif mu.dtype != torch.float64 or not mu.is_cuda or not mu.is_contiguous() \
+            or mu.shape != (map.npix, map.npix):
+        raise ValueError("mu must be a contiguous float64 [npix, npix] GPU tensor")
+    md = LensIpmDesc(map.y1min, map.y2min, map.side, map.npix, mu.data_ptr())
+    g = grid.c()
+    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk, fp32_levels)
+    _lib.check(lib.lens_map_ipm(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
+                                ctypes.byref(md), ctypes.byref(o), _stream()))
+    return mu
 
 
 def irs_map_batched(fields, grids, maps, counts=None, method="fmm", precision="mixed", p=12,

@@ -41,6 +41,11 @@ class LensMapDesc(ctypes.Structure):
                 ("npix", ctypes.c_int32), ("counts", ctypes.c_void_p)]
 
 
+class LensIpmDesc(ctypes.Structure):
+    _fields_ = [("y1min", ctypes.c_double), ("y2min", ctypes.c_double), ("side", ctypes.c_double),
+                ("npix", ctypes.c_int32), ("mu", ctypes.c_void_p)]
+
+
 class LensOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("order_p", ctypes.c_int32), ("leaf_level", ctypes.c_int32),
@@ -87,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.lens_deflect_backward.restype = ctypes.c_int
     lib.lens_map_batched.argtypes = [I32, P(LensField), P(LensGrid), P(LensMapDesc), P(LensOpts), V]
     lib.lens_map_batched.restype = ctypes.c_int
+    lib.lens_map_ipm.argtypes = [V, P(LensField), P(LensGrid), P(LensIpmDesc), P(LensOpts), V]
+    lib.lens_map_ipm.restype = ctypes.c_int
     lib.lens_autotune.argtypes = [P(LensField), P(LensGrid), P(LensMapDesc), D, P(LensOpts), V,
                                   P(LensOpts), P(D), P(D)]
     lib.lens_autotune.restype = ctypes.c_int

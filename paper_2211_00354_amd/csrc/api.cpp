@@ -1466,6 +1466,84 @@ lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *
   });
 }
 
+lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                         const lens_ipm_desc *map, const lens_opts *opts, void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    const lens_opts o = resolve_opts(opts);
+    FieldView fv = field_for(plan, field);
+    if (plan) check_plan_device(plan);
+    if (!grid) fail(LENS_EINVAL, "grid is NULL");
+    check_grid(grid);
+    if (!map) fail(LENS_EINVAL, "map is NULL");
+    if (map->npix <= 0) fail(LENS_EINVAL, "map.npix must be > 0");
+    if ((int64_t)map->npix * map->npix > (int64_t)std::numeric_limits<int32_t>::max())
+      fail(LENS_EINVAL, "map.npix^2 exceeds 2^31-1");
+    if (!is_finite(map->y1min) || !is_finite(map->y2min) || !is_finite(map->side) || !(map->side > 0))
+      fail(LENS_EINVAL, "map placement must be finite with side > 0");
+    if (!map->mu) fail(LENS_EINVAL, "map.mu is NULL");
+    const int64_t nx = grid->nx, ny = grid->ny;
+    if (nx * ny > (int64_t)std::numeric_limits<uint32_t>::max() - 1)
+      fail(LENS_EINVAL, "a grid may hold at most 2^32-2 rays");
+    if (nx < 2 || ny < 2) return;  // no cells
+    const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
+    const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
+    const double S = (double)map->npix / map->side;
+    const double cell_px = grid->dx * grid->dy * S * S;
+    // cell rows per pass (each pass deflects its rows plus the next one)
+    const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(ny - 1, o.max_rays_per_chunk / nx - 1));
+    Scratch sc(st);
+    const int64_t npx = (int64_t)map->npix * map->npix;
+    auto *acc = sc.get<unsigned long long>((size_t)npx);
+    launch_ipm_zero(acc, npx, st);
+    double *ybuf = sc.get<double>((size_t)(rows + 1) * nx * 2);
+    lens_plan *P = plan;
+    lens_plan *owned = nullptr;
+    const bool direct = o.method == LENS_DIRECT || fv.f.n_stars == 0;
+    if (!P && !direct) {
+      double bb[4];
+      grid_bbox(*grid, 0, ny, bb);
+      const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
+      owned = P = build_plan(fv.f, bb, grid, (double)(nx * ny) / area, o, st);
+    }
+    try {
+      for (int64_t j0 = 0; j0 < ny - 1; j0 += rows) {
+        const int64_t j1 = std::min(ny - 1, j0 + rows);  // cell rows [j0, j1) need ray rows [j0, j1]
+        // the kernels write ray (i, j) at y_out[2 (j nx + i)]: shift the base
+        // so that row j0 lands at the start of ybuf
+        double *y_out = reinterpret_cast<double *>(reinterpret_cast<uintptr_t>(ybuf) -
+                                                   (uintptr_t)(j0 * nx) * 2 * sizeof(double));
+        if (direct) {
+          DirectArgs d{};
+          d.n_stars = fv.f.n_stars;
+          d.sxy = fv.f.xy;
+          d.sm = fv.f.m;
+          d.grid_mode = 1;
+          d.grid = *grid;
+          d.n_rays = (j1 + 1 - j0) * nx;
+          d.ray_offset = j0 * nx;
+          d.c1 = c1;
+          d.c2 = c2;
+          d.y_out = y_out;
+          StageTimer tm("direct", st);
+          launch_direct(d, st);
+        } else {
+          fmm_grid_rows(*P, *grid, j0, j1 + 1, c1, c2, y_out, nullptr, 0.0, st);
+        }
+        StageTimer tm("ipm", st);
+        launch_ipm_cells(ybuf, nx, j0, j0, j1, cell_px, map->y1min, map->y2min, S, map->npix,
+                         65536, acc, st);
+      }
+      StageTimer tm("ipm", st);
+      launch_ipm_finish(acc, npx, map->mu, st);
+    } catch (...) {
+      if (owned) lens_plan_destroy(owned);
+      throw;
+    }
+    if (owned) release_owned(owned, st);
+  });
+}
+
 lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid,
                                   const double *rays_xy, int64_t n_rays, const double *grad_y,
                                   double *grad_xy, double *grad_m, const lens_opts *opts,

@@ -156,3 +156,22 @@ def test_batched_rejects_bad_tol():
     o = _opts(order_p=0, tol=float("inf"))
     assert lib.lens_map_batched(1, f, g, m, ctypes.byref(o), None) == _lib.LENS_EINVAL
     assert "tol" in lib.lens_last_error().decode()
+
+
+@pytest.mark.parametrize("npix,side,mu,msg", [
+    (0, 1.0, 8, "npix"),
+    (50000, 1.0, 8, "npix"),
+    (4, 0.0, 8, "side"),
+    (4, float("nan"), 8, "side"),
+    (4, 1.0, 0, "mu"),
+])
+def test_ipm_map_rejects_bad_maps(npix, side, mu, msg):
+    lib = _lib.load()
+    f = _lib.LensField(0, None, None, 0.0, 0.0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 4, 4)
+    md = _lib.LensIpmDesc(0.0, 0.0, side, npix, ctypes.c_void_p(mu) if mu else None)
+    o = _opts()
+    st = lib.lens_map_ipm(None, ctypes.byref(f), ctypes.byref(g), ctypes.byref(md), ctypes.byref(o),
+                          None)
+    assert st == _lib.LENS_EINVAL
+    assert msg in lib.lens_last_error().decode()

@@ -698,3 +698,51 @@ def test_call_graph_replays_match_eager(lf):
     _lib.profile_enable(False)
     np.testing.assert_array_equal(host(counts), 4 * one)
     lf.release_cached()
+
+
+# ----------------------------------------------------------------------- IPM
+
+def _ipm_case():
+    f, g, _ = wl.small_disk()
+    # a 4x4 map over a caustic-rich part of the source plane (folded cells)
+    return f, g, lf_mapdesc(-2.0, -2.0, 4.0, 128)
+
+
+def lf_mapdesc(y1min, y2min, side, npix):
+    import paper_2211_00354_amd as lfm
+    return lfm.MapDesc(y1min, y2min, side, npix)
+
+
+def test_ipm_kernel_matches_oracle_on_the_same_rays(lf):
+    """Same deflected corners on both sides (the FP64 direct sum): the GPU's
+    cell apportioning equals the oracle's up to the fixed-point rounding."""
+    f, g, md = _ipm_case()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    _say("ipm direct", g.nx, g.ny, md.npix)
+    mu = host(lf.ipm_map(xy, m, grid=lfgrid(g), map=md, kappa_s=f.kappa_s, gamma=f.gamma,
+                         method="direct"))
+    y = host(lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma, method="direct"))
+    ref = oracle.ipm(y.reshape(g.ny, g.nx, 2), g.dx * g.dy, md.y1min, md.y2min, md.side, md.npix)
+    assert np.abs(mu - ref).max() <= 1e-9 * max(1.0, ref.max())
+    assert ref.max() > 10 and (ref > 0).mean() > 0.5
+    # chunked passes give the same map exactly (integer accumulation)
+    mu2 = host(lf.ipm_map(xy, m, grid=lfgrid(g), map=md, kappa_s=f.kappa_s, gamma=f.gamma,
+                          method="direct", max_rays_per_chunk=37 * g.nx))
+    np.testing.assert_array_equal(mu, mu2)
+
+
+@pytest.mark.parametrize("prec,p", [("fp64", 20), ("mixed", 12)])
+def test_ipm_fmm_against_oracle(lf, prec, p):
+    """End to end: FMM deflection + GPU IPM against the oracle's deflection
+    and IPM; folds near caustics may classify differently, so the test
+    bounds the total (L1) difference."""
+    f, g, md = _ipm_case()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    _say("ipm fmm", prec, p)
+    mu = host(lf.ipm_map(xy, m, grid=lfgrid(g), map=md, kappa_s=f.kappa_s, gamma=f.gamma,
+                         precision=prec, p=p))
+    yo, _, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
+    ref = oracle.ipm(yo.reshape(g.ny, g.nx, 2), g.dx * g.dy, md.y1min, md.y2min, md.side, md.npix)
+    l1 = np.abs(mu - ref).sum() / ref.sum()
+    print(f"ipm {prec} p={p}: relative L1 {l1:.2e}")
+    assert l1 <= (1e-7 if prec == "fp64" else 1e-4)
