@@ -84,9 +84,10 @@ def main():
     ap.add_argument("--no-direct", action="store_true", help="skip the FP64 direct comparator")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps of the mixed FMM only (for rocprofv3)")
-    ap.add_argument("--workload", choices=("deflect", "map"), default="deflect",
+    ap.add_argument("--workload", choices=("deflect", "map", "ipm"), default="deflect",
                     help="deflect: 1e6 stars, 8192^2 rays (the headline metric); "
-                         "map: 5e6 stars, 16384^2 rays into a 2000^2 map")
+                         "map: 5e6 stars, 16384^2 rays shot into a 2000^2 map (IRS); "
+                         "ipm: the same field and grid, inverse polygon mapping")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="with --profile-only: also run one device-to-device copy of this many "
                          "MiB, the reference for scaling FETCH_SIZE/WRITE_SIZE counters")
@@ -104,7 +105,7 @@ def main():
     import workloads as wl
 
     torch.cuda.set_device(0)
-    if args.workload == "map":
+    if args.workload in ("map", "ipm"):
         return bench_map(args)
     log("generating workload")
     f, g = wl.powerlaw_disk()
@@ -259,6 +260,8 @@ def main():
 
 
 MAP_METRIC = "rays/s shot into a 2000x2000 magnification map at N_*=5e6, mu=50 (mixed FMM)"
+IPM_METRIC = ("corner rays/s mapped into a 2000x2000 IPM magnification map at N_*=5e6, mu=50 "
+              "(mixed FMM)")
 
 
 def bench_map(args):
@@ -288,9 +291,16 @@ def bench_map(args):
     kw = dict(kappa_s=f.kappa_s, gamma=f.gamma, precision="mixed", p=p, fp32_levels=fl,
               leaf_level=args.leaf)
 
+    ipm = args.workload == "ipm"
+    mu = torch.zeros((mp.npix, mp.npix), dtype=torch.float64, device="cuda")
+
     def step():
-        counts.zero_()
-        lf.irs_map(xy, m, grid=grid, map=md, counts=counts, **kw)
+        if ipm:
+            mu.zero_()
+            lf.ipm_map(xy, m, grid=grid, map=md, mu=mu, **kw)
+        else:
+            counts.zero_()
+            lf.irs_map(xy, m, grid=grid, map=md, counts=counts, **kw)
 
     def timed_steps():
         torch.cuda.synchronize()
@@ -319,13 +329,14 @@ def bench_map(args):
     leaf = info["leaf_level"]
     pairs = near_pairs(info, f, g)
     flops = PAIR_FLOPS * pairs + (8 * p + 2) * g.n
-    ev_ms, ev_n = prof.get("eval_map", (float("nan"), 1))
+    ev_ms, ev_n = prof.get("eval" if ipm else "eval_map", (float("nan"), 1))
     ev_avg = ev_ms / max(ev_n, 1)
     achieved = flops / (ev_avg * 1e-3)
     extra = {"leaf_level": leaf, "p": p, "fp32_levels": fl, "autotune": tuned, "autotune_s": tune_s,
              "near_pairs_per_ray": pairs / g.n,
              "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
-             "eval_flops_per_launch": flops, "mean_count": float(counts.double().mean()),
+             "eval_flops_per_launch": flops,
+             "map_mean": float(mu.mean()) if ipm else float(counts.double().mean()),
              "profiled_eager_ms_per_step": ms_prof}
     cpu = None
     if not args.no_cpu:
@@ -350,16 +361,22 @@ def bench_map(args):
         log(f"oracle: {dt:.1f} s on {nthr} threads; reassignment estimate "
             f"{extra['bin_reassignment_estimate']:.2e}")
     plan.close()
+    if ipm:
+        ip_ms, ip_n = prof.get("ipm", (float("nan"), 1))
+        extra["ipm_kernel_ms"] = ip_ms / max(ip_n, 1)
     out = {
-        "metric": MAP_METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "metric": IPM_METRIC if ipm else MAP_METRIC, "value": value, "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32/f64 mixed", "data": "synthetic",
         "config": {"workload": "N_*=5e6 equal masses (kappa_*=0.1, kappa_s=0.75, gamma=0.05), "
-                               "16384x16384 rays into a 2000x2000 map, mixed FMM p=%d" % p,
+                               "16384x16384 rays into a 2000x2000 %s map, mixed FMM p=%d"
+                               % ("IPM" if ipm else "IRS", p),
                    "n_stars": f.n, "n_rays": g.n, "p": p, "leaf_level": leaf},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-                     "kernel": "k_eval (fused L2P + P2P + smooth term + binning)",
+                     "kernel": ("k_eval (fused L2P + P2P + smooth term), corners for IPM" if ipm else
+                                "k_eval (fused L2P + P2P + smooth term + binning)"),
                      "eval_ms_avg": ev_avg},
         "cpu_baseline": cpu,
         "extra": extra,

@@ -196,8 +196,8 @@ typedef struct {
  * proportion to the overlap areas, so map->mu receives the magnification
  * (sum of image areas over pixel area).  A cell whose quadrilateral folds
  * (its edges cross: the cell straddles a critical curve), has zero area or
- * spans more than 65536 pixels gives a quarter of its area to the pixel of
- * each corner.  Contributions are summed in fixed point (2^-40 of a pixel's
+ * whose bounding box covers more than 64 map pixels (a cell next to a star)
+ * gives a quarter of its area to the pixel of each corner.  Contributions are summed in fixed point (2^-40 of a pixel's
  * magnification), so the map does not depend on summation order.  Rays are
  * processed in chunks of whole rows of at most opts->max_rays_per_chunk rays
  * (default: one pass); the deflected corners need nx*ny*16 bytes of scratch

@@ -43,9 +43,10 @@
  *    pixel P receives dx dy |Q n P| / |Q|, and mu[P] accumulates that over
  *    the pixel area, so mu is the magnification sum S_i / S_pixel of the
  *    paper.  A quadrilateral whose edges cross (the cell straddles a critical
- *    curve) or whose area is zero is treated at zeroth order: each corner
- *    carries a quarter of the cell's area to the pixel it falls in (the IRS
- *    rule).  Overlaps are found by clipping Q against each pixel square of
+ *    curve), whose area is zero, or whose bounding box covers more than
+ *    max_pixels pixels of the map (a cell next to a star, stretched over much
+ *    of the map) is treated at zeroth order: each corner carries a quarter of
+ *    the cell's area to the pixel it falls in (the IRS rule).  Overlaps are found by clipping Q against each pixel square of
  *    its bounding box (Sutherland-Hodgman) and measuring the clipped polygon
  *    by the shoelace formula, in pixel units (p = (y - ymin) S).
  *
@@ -309,11 +310,13 @@ static void add_corner(double *mu, int32_t npix, const double *p, double w) {
 /*
  * IPM magnification of the (nx-1) x (ny-1) cells spanned by the mapped grid
  * y[ny][nx][2] (row-major, y[(j*nx + i)*2 + c]), accumulated into
- * mu[v*npix + u] (+=).  cell_area = dx * dy.  Returns 0 or -1.
+ * mu[v*npix + u] (+=).  cell_area = dx * dy; max_pixels >= 1 caps the
+ * pixels a cell is apportioned over exactly.  Returns 0 or -1.
  */
 int oracle_ipm(int64_t nx, int64_t ny, const double *y, double cell_area, double y1min,
-               double y2min, double side, int32_t npix, double *mu) {
-  if (nx < 0 || ny < 0 || npix <= 0 || !(side > 0.0) || !(cell_area >= 0.0)) return -1;
+               double y2min, double side, int32_t npix, int64_t max_pixels, double *mu) {
+  if (nx < 0 || ny < 0 || npix <= 0 || !(side > 0.0) || !(cell_area >= 0.0) || max_pixels < 1)
+    return -1;
   const double S = (double)npix / side;
   const double cell_px = cell_area * S * S; /* cell area in pixel units */
   for (int64_t j = 0; j + 1 < ny; ++j)
@@ -329,10 +332,6 @@ int oracle_ipm(int64_t nx, int64_t ny, const double *y, double cell_area, double
       if (!finite) continue;
       const double area = fabs(poly_area(4, (const double (*)[2])q));
       const int folded = segments_cross(q[0], q[1], q[2], q[3]) || segments_cross(q[1], q[2], q[3], q[0]);
-      if (folded || !(area > 0.0)) {
-        for (int k = 0; k < 4; ++k) add_corner(mu, npix, q[k], 0.25 * cell_px);
-        continue;
-      }
       double lo0 = q[0][0], hi0 = q[0][0], lo1 = q[0][1], hi1 = q[0][1];
       for (int k = 1; k < 4; ++k) {
         lo0 = fmin(lo0, q[k][0]);
@@ -340,11 +339,23 @@ int oracle_ipm(int64_t nx, int64_t ny, const double *y, double cell_area, double
         lo1 = fmin(lo1, q[k][1]);
         hi1 = fmax(hi1, q[k][1]);
       }
-      if (hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix) continue;
+      const int outside = hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix;
       const int64_t u0 = lo0 < 0.0 ? 0 : (int64_t)floor(lo0);
       const int64_t v0 = lo1 < 0.0 ? 0 : (int64_t)floor(lo1);
       const int64_t u1 = hi0 >= (double)npix ? npix - 1 : (int64_t)floor(hi0);
       const int64_t v1 = hi1 >= (double)npix ? npix - 1 : (int64_t)floor(hi1);
+      if (folded || !(area > 0.0) || (!outside && (u1 - u0 + 1) * (v1 - v0 + 1) > max_pixels)) {
+        for (int k = 0; k < 4; ++k) add_corner(mu, npix, q[k], 0.25 * cell_px);
+        continue;
+      }
+      if (outside) continue;
+      if (u0 == u1 && v0 == v1 && lo0 >= 0.0 && lo1 >= 0.0 && hi0 < (double)npix &&
+          hi1 < (double)npix) {
+        /* wholly inside one pixel: the whole cell (exactly; a ratio of two
+         * rounded areas would not give 1 for a sliver-thin quadrilateral) */
+        mu[v0 * npix + u0] += cell_px;
+        continue;
+      }
       for (int64_t v = v0; v <= v1; ++v)
         for (int64_t u = u0; u <= u1; ++u) {
           const double ov = quad_pixel_overlap((const double (*)[2])q, (double)u, (double)v);

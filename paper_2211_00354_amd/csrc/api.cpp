@@ -68,6 +68,10 @@ namespace {
 // Section 2.4, are kept as an option; a map needs no per-ray memory)
 constexpr int64_t kDefaultChunk = std::numeric_limits<int64_t>::max();
 constexpr int kDefaultFp32Levels = 2;
+// IPM: a cell whose quadrilateral's bounding box covers more map pixels than
+// this is apportioned to its corners (cells next to a star stretch over much
+// of the map; exact clipping there costs far more than the area they carry)
+constexpr int32_t kIpmMaxPixels = 64;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -1532,7 +1536,7 @@ lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_gr
         }
         StageTimer tm("ipm", st);
         launch_ipm_cells(ybuf, nx, j0, j0, j1, cell_px, map->y1min, map->y2min, S, map->npix,
-                         65536, acc, st);
+                         kIpmMaxPixels, acc, st);
       }
       StageTimer tm("ipm", st);
       launch_ipm_finish(acc, npx, map->mu, st);

@@ -5,12 +5,13 @@
 // pixels Q overlaps in proportion to the overlap areas: pixel P receives
 // dx dy |Q n P| / |Q|; divided by the pixel area that is the magnification
 // sum S_i / S_pixel.  A quadrilateral whose edges cross (a cell on a critical
-// curve) or whose area is zero goes to its corners: a quarter of the cell to
-// each corner's pixel (the zeroth-order, inverse-ray-shooting rule).
+// curve), whose area is zero or whose bounding box covers more than
+// max_pixels map pixels goes to its corners: a quarter of the cell to each
+// corner's pixel (the zeroth-order, inverse-ray-shooting rule).
 //
 // Geometry in pixel units p = (y - ymin) S, S = npix/side.  Overlaps come
-// from clipping Q against the pixel square (Sutherland-Hodgman) and the
-// shoelace area of the result.  Contributions are summed as fixed-point
+// from Green's theorem as a sum of four edge terms (see quad_pixel_overlap),
+// which needs no per-thread polygon storage.  Contributions are summed as fixed-point
 // integers (units of 2^-40 of a pixel's magnification) with 64-bit atomics,
 // so the map does not depend on the order of the additions; a final pass adds
 // them to the caller's FP64 map.  One thread per cell; a cell inside one
@@ -39,66 +40,65 @@ __device__ __forceinline__ bool segments_cross(const double (&a)[2], const doubl
   return ((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) && ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0));
 }
 
-// Twice the signed area of the first n vertices, summed in vertex order.
-template <int N>
-__device__ __forceinline__ double shoelace2(int n, const double (&x)[N], const double (&y)[N]) {
+// Twice the signed area of a quadrilateral (shoelace, vertex order).
+__device__ __forceinline__ double shoelace4(const double (&q)[4][2]) {
   double s = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const int k1 = k + 1 < n ? k + 1 : 0;
-    s += x[k] * y[k1] - x[k1] * y[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int k1 = (k + 1) & 3;
+    s += q[k][0] * q[k1][1] - q[k1][0] * q[k][1];
   }
   return s;
 }
 
-// Keep the part of polygon (ix, iy)[n] with coordinate c >= bound (ge) or
-// <= bound (!ge); writes (ox, oy), returns the new vertex count.
-__device__ __forceinline__ int clip_half(int n, const double (&ix)[12], const double (&iy)[12],
-                                         double (&ox)[12], double (&oy)[12], int c, double bound,
-                                         bool ge) {
-  int m = 0;
-  for (int k = 0; k < n; ++k) {
-    const int ks = k > 0 ? k - 1 : n - 1;
-    const double sx = ix[ks], sy = iy[ks], ex = ix[k], ey = iy[k];
-    const double sc = c == 0 ? sx : sy, ec = c == 0 ? ex : ey;
-    const bool sin_ = ge ? sc >= bound : sc <= bound;
-    const bool ein = ge ? ec >= bound : ec <= bound;
-    if (ein != sin_) {
-      const double t = (bound - sc) / (ec - sc);
-      if (c == 0) {
-        ox[m] = bound;
-        oy[m] = sy + t * (ey - sy);
-      } else {
-        ox[m] = sx + t * (ex - sx);
-        oy[m] = bound;
-      }
-      ++m;
-    }
-    if (ein) {
-      ox[m] = ex;
-      oy[m] = ey;
-      ++m;
-    }
+__device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
+
+// Signed contribution of edge a -> b to the area of (polygon n unit square):
+// the line integral of clamp01(x) dy over the edge's part with 0 <= y <= 1.
+// On that part x(y) = lx + (y - ly) k is linear, so clamp01(x(y)) is linear
+// between the heights where x crosses 0 and 1 and the trapezoid rule on those
+// pieces is exact.  k = dx/dy and kinv = dy/dx (vertical: kinv unused) depend
+// only on the edge's direction, not on the pixel.
+__device__ __forceinline__ double edge_term(double ax, double ay, double bx, double by, double k,
+                                            double kinv, bool vertical) {
+  if (ay == by) return 0.0;
+  const bool up = by > ay;
+  const double lx = up ? ax : bx, ly = up ? ay : by, hy = up ? by : ay;
+  const double y0 = fmax(ly, 0.0), y1 = fmin(hy, 1.0);
+  if (!(y0 < y1)) return 0.0;
+  double s0 = y1, s1 = y1;  // breakpoints strictly inside (y0, y1), else y1
+  if (!vertical) {
+    const double ya = ly + (0.0 - lx) * kinv, yb = ly + (1.0 - lx) * kinv;
+    const double lo = fmin(ya, yb), hi = fmax(ya, yb);
+    if (lo > y0 && lo < y1) s0 = lo;
+    if (hi > y0 && hi < y1) s1 = hi;
+    if (s0 == y1) s0 = s1, s1 = y1;
   }
-  return m;
+  const double x0 = clamp01(lx + (y0 - ly) * k);
+  const double xa = clamp01(lx + (s0 - ly) * k);
+  const double xb = clamp01(lx + (s1 - ly) * k);
+  const double x1 = clamp01(lx + (y1 - ly) * k);
+  const double v = 0.5 * ((x0 + xa) * (s0 - y0) + (xa + xb) * (s1 - s0) + (xb + x1) * (y1 - s1));
+  return up ? v : -v;
 }
 
 // Area of quadrilateral q (pixel units) inside the square [u,u+1] x [v,v+1].
+// By Green's theorem the area of (Q n B) for the unit square B is the line
+// integral of clamp01(x) dy over the boundary of Q restricted to 0 <= y <= 1
+// (d/dx clamp01 is the indicator of 0 < x < 1): a sum of four edge terms,
+// with no clipped polygon to store.  Signed by Q's orientation; |.| taken.
 __device__ double quad_pixel_overlap(const double (&q)[4][2], double u, double v) {
-  double ax[12], ay[12], bx[12], by[12];
-  for (int k = 0; k < 4; ++k) {
-    ax[k] = q[k][0] - u;
-    ay[k] = q[k][1] - v;
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int e1 = (e + 1) & 3;
+    const double dx = q[e1][0] - q[e][0], dy = q[e1][1] - q[e][1];
+    const bool vertical = dx == 0.0;
+    const double k = dy != 0.0 ? dx * rcp_f64(dy) : 0.0;
+    const double kinv = vertical ? 0.0 : dy * rcp_f64(dx);
+    s += edge_term(q[e][0] - u, q[e][1] - v, q[e1][0] - u, q[e1][1] - v, k, kinv, vertical);
   }
-  int n = 4;
-  n = clip_half(n, ax, ay, bx, by, 0, 0.0, true);
-  n = clip_half(n, bx, by, ax, ay, 0, 1.0, false);
-  n = clip_half(n, ax, ay, bx, by, 1, 0.0, true);
-  n = clip_half(n, bx, by, ax, ay, 1, 1.0, false);
-  return n >= 3 ? fabs(0.5 * shoelace2(n, ax, ay)) : 0.0;
-}
-
-__device__ __forceinline__ void add_fixed(unsigned long long *acc, int64_t k, double value) {
-  atomicAdd(&acc[k], (unsigned long long)llrint(value * kFix));
+  return fabs(s);
 }
 
 __device__ __forceinline__ int64_t pixel_of(const double (&p)[2], int32_t npix) {
@@ -108,87 +108,191 @@ __device__ __forceinline__ int64_t pixel_of(const double (&p)[2], int32_t npix) 
   return (int64_t)f2 * npix + (int64_t)f1;
 }
 
-// One thread per cell of rows [j0, j1) (all nx - 1 columns); y holds rows
-// [ybase, ...) of the mapped grid, row-major with nx rays per row.
-__global__ __launch_bounds__(kThreads) void k_ipm(const double *__restrict__ y, int64_t nx,
-                                                  int64_t ybase, int64_t j0, int64_t j1,
-                                                  double cell_px, double y1min, double y2min,
-                                                  double S, int32_t npix, int32_t max_pixels,
-                                                  unsigned long long *__restrict__ acc) {
-  const int64_t ncell = (nx - 1) * (j1 - j0);
-  const int lane = threadIdx.x & 63;
-  const unsigned long long q_cell = (unsigned long long)llrint(cell_px * kFix);
-  for (int64_t base = (int64_t)blockIdx.x * kThreads; base < ncell;
-       base += (int64_t)gridDim.x * kThreads) {  // uniform per wave
-    const int64_t c = base + threadIdx.x;
-    int64_t fast_key = -1;
-    if (c < ncell) {
-      const int64_t j = j0 + c / (nx - 1), i = c % (nx - 1);
-      const int64_t r0 = (j - ybase) * nx + i, r1 = r0 + nx;
-      const int64_t id[4] = {r0, r0 + 1, r1 + 1, r1};
-      double q[4][2];
-      bool finite = true;
+struct IpmArgs {
+  const double *y;      // rows [ybase, ...) of the mapped grid, nx rays per row
+  int64_t nx, ybase, j0, j1;  // cells of rows [j0, j1), all nx - 1 columns
+  double cell_px, y1min, y2min, S;
+  int32_t npix, max_pixels;
+  unsigned long long *acc;
+};
+
+// Corners of cell (i, j) (pixel units); false if any is not finite.
+__device__ __forceinline__ bool load_quad(const IpmArgs &a, int64_t i, int64_t j,
+                                          double (&q)[4][2]) {
+  const int64_t r0 = (j - a.ybase) * a.nx + i, r1 = r0 + a.nx;
+  const int64_t id[4] = {r0, r0 + 1, r1 + 1, r1};
+  bool finite = true;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        q[k][0] = (y[2 * id[k]] - y1min) * S;
-        q[k][1] = (y[2 * id[k] + 1] - y2min) * S;
-        finite = finite && isfinite(q[k][0]) && isfinite(q[k][1]);
-      }
-      if (finite) {
-        double xs[4], ys[4];
+  for (int k = 0; k < 4; ++k) {
+    q[k][0] = (a.y[2 * id[k]] - a.y1min) * a.S;
+    q[k][1] = (a.y[2 * id[k] + 1] - a.y2min) * a.S;
+    finite = finite && isfinite(q[k][0]) && isfinite(q[k][1]);
+  }
+  return finite;
+}
+
+__device__ __forceinline__ double quad_area(const double (&q)[4][2]) {
+  return fabs(0.5 * shoelace4(q));
+}
+
+// Pixel bounding box of q clamped to the map; false if it misses the map.
+__device__ __forceinline__ bool quad_bbox(const double (&q)[4][2], int32_t npix, int64_t &u0,
+                                          int64_t &v0, int64_t &u1, int64_t &v1, bool &inside) {
+  double lo0 = q[0][0], hi0 = q[0][0], lo1 = q[0][1], hi1 = q[0][1];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          xs[k] = q[k][0];
-          ys[k] = q[k][1];
-        }
-        const double area = fabs(0.5 * shoelace2(4, xs, ys));
-        const bool folded = segments_cross(q[0], q[1], q[2], q[3]) || segments_cross(q[1], q[2], q[3], q[0]);
-        double lo0 = q[0][0], hi0 = q[0][0], lo1 = q[0][1], hi1 = q[0][1];
-#pragma unroll
-        for (int k = 1; k < 4; ++k) {
-          lo0 = fmin(lo0, q[k][0]);
-          hi0 = fmax(hi0, q[k][0]);
-          lo1 = fmin(lo1, q[k][1]);
-          hi1 = fmax(hi1, q[k][1]);
-        }
-        const int64_t u0 = lo0 < 0.0 ? 0 : (int64_t)floor(lo0);
-        const int64_t v0 = lo1 < 0.0 ? 0 : (int64_t)floor(lo1);
-        const int64_t u1 = hi0 >= (double)npix ? npix - 1 : (int64_t)floor(hi0);
-        const int64_t v1 = hi1 >= (double)npix ? npix - 1 : (int64_t)floor(hi1);
-        const bool outside = hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix;
-        const int64_t npx = (u1 - u0 + 1) * (v1 - v0 + 1);
-        if (folded || !(area > 0.0) || (!outside && npx > max_pixels)) {
-          // zeroth order: a quarter of the cell to each corner's pixel (also
-          // for a cell stretched over more than max_pixels pixels)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int64_t pk = pixel_of(q[k], npix);
-            if (pk >= 0) add_fixed(acc, pk, 0.25 * cell_px);
-          }
-        } else if (!outside) {
-          if (u0 == u1 && v0 == v1 && lo0 >= 0.0 && lo1 >= 0.0 && hi0 < (double)npix &&
-              hi1 < (double)npix) {
-            fast_key = v0 * npix + u0;  // wholly inside one pixel
-          } else {
-            for (int64_t v = v0; v <= v1; ++v)
-              for (int64_t u = u0; u <= u1; ++u) {
-                const double ov = quad_pixel_overlap(q, (double)u, (double)v);
-                if (ov > 0.0) add_fixed(acc, v * npix + u, cell_px * (ov / area));
-              }
-          }
-        }
-      }
+  for (int k = 1; k < 4; ++k) {
+    lo0 = fmin(lo0, q[k][0]);
+    hi0 = fmax(hi0, q[k][0]);
+    lo1 = fmin(lo1, q[k][1]);
+    hi1 = fmax(hi1, q[k][1]);
+  }
+  u0 = lo0 < 0.0 ? 0 : (int64_t)floor(lo0);
+  v0 = lo1 < 0.0 ? 0 : (int64_t)floor(lo1);
+  u1 = hi0 >= (double)npix ? npix - 1 : (int64_t)floor(hi0);
+  v1 = hi1 >= (double)npix ? npix - 1 : (int64_t)floor(hi1);
+  inside = lo0 >= 0.0 && lo1 >= 0.0 && hi0 < (double)npix && hi1 < (double)npix;
+  return !(hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix);
+}
+
+// Workgroup-local sums of pixel contributions: an LDS hash table of pixels,
+// flushed to the map once per workgroup, so the many cells of a patch that
+// land in the same pixels (all of them, away from stars; those around a
+// star's caustic, near one) cost few global atomics.
+constexpr int kTable = 2048;
+constexpr int kPatch = 64;  // a workgroup takes kPatch x kPatch cells
+
+__device__ __forceinline__ void table_add(int32_t *tkey, unsigned long long *tval,
+                                          unsigned long long *__restrict__ acc, int32_t key,
+                                          unsigned long long v) {
+  const uint32_t h = ((uint32_t)key * 2654435761u) >> 21;  // 11 bits
+  for (int probe = 0; probe < 16; ++probe) {
+    const int slot = (int)((h + (uint32_t)probe) & (kTable - 1));
+    int32_t k = tkey[slot];
+    if (k == -1) {
+      const int32_t old = atomicCAS(&tkey[slot], -1, key);
+      k = old == -1 ? key : old;
     }
-    // cells wholly inside one pixel all add cell_px: one atomic per pixel
-    uint64_t pending = __ballot(fast_key >= 0);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int64_t k = __shfl(fast_key, leader);
-      const uint64_t same = __ballot(fast_key == k);
-      if (lane == leader) atomicAdd(&acc[k], q_cell * (unsigned long long)__popcll(same));
-      pending &= ~same;
+    if (k == key) {
+      atomicAdd(&tval[slot], v);
+      return;
     }
   }
+  atomicAdd(&acc[key], v);  // crowded table
+}
+
+// One workgroup per kPatch x kPatch patch of cells, taken 256 cells at a
+// time, one thread per cell.  A cell inside one pixel adds the whole cell; a
+// folded, degenerate or too wide cell goes to its corners.  A cell over
+// several pixels (at most max_pixels) is apportioned by its overlaps; those
+// (cell, pixel) pairs of the 256 cells are numbered by a scan and shared out
+// evenly over the workgroup's threads, so a few wide cells near a star do
+// not hold a whole wave.
+__device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t *wsum, int32_t *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t v = __shfl_up(inc, d);
+    if (lane >= d) inc += v;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < kThreads / 64; ++q) {
+    if (q < w) off += wsum[q];
+    tot += wsum[q];
+  }
+  *total = tot;
+  return off + inc - x;
+}
+
+__global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
+  __shared__ int32_t tkey[kTable];
+  __shared__ unsigned long long tval[kTable];
+  __shared__ double sq[kThreads][8];  // wide cells of the batch: corners,
+  __shared__ double sarea[kThreads];   // area,
+  __shared__ int32_t sbox[kThreads][3];  // u0, v0, columns of the bounding box
+  __shared__ int32_t sfirst[kThreads + 1];  // first pair index of each cell
+  __shared__ int32_t wsum[kThreads / 64];
+  const int t = threadIdx.x;
+  for (int e = t; e < kTable; e += kThreads) {
+    tkey[e] = -1;
+    tval[e] = 0ull;
+  }
+  __syncthreads();
+  const int64_t ncx = a.nx - 1;
+  const int64_t npx_x = (ncx + kPatch - 1) / kPatch;
+  const int64_t pi = blockIdx.x % npx_x, pj = blockIdx.x / npx_x;
+  const int32_t npix = a.npix;
+  const unsigned long long q_cell = (unsigned long long)llrint(a.cell_px * kFix);
+  const unsigned long long q_quarter = (unsigned long long)llrint(0.25 * a.cell_px * kFix);
+  for (int base = 0; base < kPatch * kPatch; base += kThreads) {
+    const int k = base + t;
+    const int64_t i = pi * kPatch + (k % kPatch), j = a.j0 + pj * kPatch + (k / kPatch);
+    int32_t npairs = 0;
+    double q[4][2];
+    if (i < ncx && j < a.j1 && load_quad(a, i, j, q)) {
+      const double area = quad_area(q);
+      const bool folded = segments_cross(q[0], q[1], q[2], q[3]) || segments_cross(q[1], q[2], q[3], q[0]);
+      int64_t u0, v0, u1, v1;
+      bool inside;
+      const bool outside = !quad_bbox(q, npix, u0, v0, u1, v1, inside);
+      const int64_t npx = (u1 - u0 + 1) * (v1 - v0 + 1);
+      if (folded || !(area > 0.0) || (!outside && npx > a.max_pixels)) {
+        // zeroth order: a quarter of the cell to each corner's pixel
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t pk = pixel_of(q[c], npix);
+          if (pk >= 0) table_add(tkey, tval, a.acc, (int32_t)pk, q_quarter);
+        }
+      } else if (!outside) {
+        if (u0 == u1 && v0 == v1 && inside) {
+          table_add(tkey, tval, a.acc, (int32_t)(v0 * npix + u0), q_cell);  // wholly inside
+        } else {
+          npairs = (int32_t)npx;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            sq[t][2 * c] = q[c][0];
+            sq[t][2 * c + 1] = q[c][1];
+          }
+          sarea[t] = area;
+          sbox[t][0] = (int32_t)u0;
+          sbox[t][1] = (int32_t)v0;
+          sbox[t][2] = (int32_t)(u1 - u0 + 1);
+        }
+      }
+    }
+    int32_t total;
+    const int32_t first = block_excl_scan(npairs, wsum, &total);
+    sfirst[t] = first;
+    if (t == kThreads - 1) sfirst[kThreads] = first + npairs;
+    __syncthreads();
+    for (int32_t w = t; w < total; w += kThreads) {
+      // the cell holding pair w: the last with sfirst <= w (cells without
+      // pairs share their successor's start, so the last one is the owner)
+      int lo = 0, hi = kThreads - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sfirst[mid] <= w) lo = mid; else hi = mid - 1;
+      }
+      const int32_t local = w - sfirst[lo];
+      const int32_t u = sbox[lo][0] + local % sbox[lo][2], v = sbox[lo][1] + local / sbox[lo][2];
+      double cq[4][2];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        cq[c][0] = sq[lo][2 * c];
+        cq[c][1] = sq[lo][2 * c + 1];
+      }
+      const double ov = quad_pixel_overlap(cq, (double)u, (double)v);
+      if (ov > 0.0)
+        table_add(tkey, tval, a.acc, v * npix + u,
+                  (unsigned long long)llrint(a.cell_px * (ov / sarea[lo]) * kFix));
+    }
+    __syncthreads();  // the batch's shared cells are consumed
+  }
+  for (int e = t; e < kTable; e += kThreads)
+    if (tkey[e] >= 0) atomicAdd(&a.acc[tkey[e]], tval[e]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_ipm_finish(const unsigned long long *__restrict__ acc,
@@ -219,10 +323,12 @@ void launch_ipm_zero(unsigned long long *acc, int64_t n, hipStream_t stream) {
 void launch_ipm_cells(const double *y, int64_t nx, int64_t ybase, int64_t j0, int64_t j1,
                       double cell_px, double y1min, double y2min, double S, int32_t npix,
                       int32_t max_pixels, unsigned long long *acc, hipStream_t stream) {
-  const int64_t ncell = (nx - 1) * (j1 - j0);
-  if (ncell <= 0) return;
-  hipLaunchKernelGGL(k_ipm, dim3(grid_for(ncell)), dim3(kThreads), 0, stream, y, nx, ybase, j0, j1,
-                     cell_px, y1min, y2min, S, npix, max_pixels, acc);
+  const int64_t ncx = nx - 1, nrows = j1 - j0;
+  if (ncx <= 0 || nrows <= 0) return;
+  const int64_t patches = ((ncx + kPatch - 1) / kPatch) * ((nrows + kPatch - 1) / kPatch);
+  if (patches > 0x7fffffff) fail(LENS_EUNSUPPORTED, "IPM pass too large");
+  IpmArgs a{y, nx, ybase, j0, j1, cell_px, y1min, y2min, S, npix, max_pixels, acc};
+  hipLaunchKernelGGL(k_ipm, dim3((unsigned)patches), dim3(kThreads), 0, stream, a);
   LENS_HIP(hipGetLastError());
 }
 

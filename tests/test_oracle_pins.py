@@ -426,11 +426,11 @@ def _convex_overlap_exact(poly, u, v):
                    for k in range(len(hull)))) / 2
 
 
-def _one_cell(corners, dx=0.5, dy=0.25, npix=8, side=8.0):
+def _one_cell(corners, dx=0.5, dy=0.25, npix=8, side=8.0, max_pixels=64):
     """A 2x2 grid (one cell) whose corners map to `corners` (source plane,
     map [0, side)^2 so pixel units equal source units)."""
     y = np.array([[corners[0], corners[1]], [corners[3], corners[2]]], dtype=np.float64)
-    return oracle.ipm(y, dx * dy, 0.0, 0.0, side, npix)
+    return oracle.ipm(y, dx * dy, 0.0, 0.0, side, npix, max_pixels=max_pixels)
 
 
 @pytest.mark.parametrize("corners", [
@@ -468,6 +468,18 @@ def test_ipm_concave_cell_splits_into_triangles():
             ov = _convex_overlap_exact(t1, u, v) + _convex_overlap_exact(t2, u, v)
             want = float(F(1, 8) * ov / area)
             assert abs(mu[v, u] - want) <= 1e-15 + 1e-13 * want
+
+
+def test_ipm_stretched_cell_goes_to_its_corners():
+    corners = [(1.25, 1.5), (5.75, 2.0), (4.5, 6.625), (0.5, 3.25)]   # bbox 6 x 6 pixels
+    exact = _one_cell(corners)
+    capped = _one_cell(corners, max_pixels=35)
+    want = np.zeros((8, 8))
+    for x, y in corners:
+        want[int(y), int(x)] += 0.125 / 4
+    np.testing.assert_allclose(capped, want, rtol=0, atol=1e-16)
+    assert np.count_nonzero(exact) > 4
+    np.testing.assert_array_equal(_one_cell(corners, max_pixels=36), exact)
 
 
 def test_ipm_folded_cell_goes_to_its_corners():
