@@ -374,14 +374,28 @@ void plan_enqueue(lens_plan *P, const double *xy, const double *q, hipStream_t s
   const OpTables &T = op_tables(P->p, st);
   {
     StageTimer tm("upward", st);
-    // from the stars or by M2M, level by level as source_windows decided
-    for (int l = L; l >= 2; --l) {
-      double *out = static_cast<double *>(P->mp[l].ptr);
-      float *out32 = static_cast<float *>(P->mp32[l].ptr);
-      if (P->direct[l])
-        launch_p2m(P->g, l, P->swin[l], sxy, sm, P->qdim, leaf_start, P->p, out, out32, N, st);
-      else
-        launch_m2m(l, P->p, P->mp_at(l + 1), out, out32, T.m2m, st);
+    // from the stars or by M2M, as source_windows decided; runs of M2M
+    // levels go up to four levels per launch
+    for (int l = L; l >= 2;) {
+      if (P->direct[l]) {
+        launch_p2m(P->g, l, P->swin[l], sxy, sm, P->qdim, leaf_start, P->p,
+                   static_cast<double *>(P->mp[l].ptr), static_cast<float *>(P->mp32[l].ptr), N, st);
+        --l;
+        continue;
+      }
+      M2MChain c{};
+      c.level = l;
+      c.p = P->p;
+      c.child = P->mp_at(l + 1);
+      const int kmax = m2m_chain_levels(l);
+      c.nlev = 0;
+      while (c.nlev < kmax && l - c.nlev >= 2 && !P->direct[l - c.nlev]) {
+        c.out[c.nlev] = static_cast<double *>(P->mp[l - c.nlev].ptr);
+        c.out32[c.nlev] = static_cast<float *>(P->mp32[l - c.nlev].ptr);
+        ++c.nlev;
+      }
+      launch_m2m_chain(c, st);
+      l -= c.nlev;
     }
   }
   P->last_stream = st;
@@ -484,7 +498,19 @@ void downward_enqueue(const lens_plan &P, const LocalSet &ls, hipStream_t st) {
     d.loc = ls.at(l);
     launch_l2l(d, T, st);
   };
-  for (int l = 3; l < first_fused && l <= L; ++l) l2l(l);
+  // coarse L2L sweep, up to three levels per launch
+  for (int l = 3; l < first_fused && l <= L;) {
+    L2LChain c{};
+    c.level = l - 1;
+    c.p = P.p;
+    c.nlev = std::min(kMaxL2LChain, std::min(first_fused, L + 1) - l);
+    for (int j = 0; j <= c.nlev; ++j) {
+      c.win[j] = ls.win[l - 1 + j];
+      c.loc[j] = ls.at(l - 1 + j);
+    }
+    launch_l2l_chain(c, T, st);
+    l += c.nlev;
+  }
   for (int l = first_fused; l <= L; ++l) {
     M2LBatch one;
     one.p = P.p;

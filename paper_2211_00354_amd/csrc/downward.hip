@@ -67,6 +67,78 @@ __global__ __launch_bounds__(kThreads) void k_l2l(DownArgs a, const double *__re
   a.loc[2 * idx + 1] = acc.im;
 }
 
+// L2L down up to three levels in one launch: a 64-thread workgroup owns one
+// box of the chain's top level (its locals final) and its descendants: at
+// depth j, thread t < 4^j takes descendant (t mod 2^j, t div 2^j) of the
+// 2^j x 2^j block, adds the shifted locals of its parent (the previous
+// depth's result, kept in LDS) to its own M2L locals and stores them.  A box
+// outside its level's window is skipped; its children lie outside theirs.
+//
+// The shift needs no table: with the child centre at d = (a - 1/2) +
+// i(c - 1/2) parent half-sides from the parent's (child (2x + a, 2y + c)),
+// the child gets c_j += sum_{l>=j} C(l,j) d^(l-j) 2^-l b_l, the coefficients
+// of B(w + d) for B(w) = sum_l 2^-l b_l w^l, formed by Horner-style synthetic
+// division (p(p-1)/2 updates b_j += d b_(j+1), exact products).
+template <int PMAX>
+__global__ __launch_bounds__(64) void k_l2l_tile(L2LChain c) {
+  __shared__ double2 bufA[16 * PMAX];  // depth-2 results
+  __shared__ double2 bufB[4 * PMAX];   // depth-1 results
+  const int lane = threadIdx.x;
+  const int p = c.p;
+  const int64_t rb = blockIdx.x;
+  const int64_t RX = c.win[0].bx0 + rb % c.win[0].nbx, RY = c.win[0].by0 + rb / c.win[0].nbx;
+  for (int j = 1; j <= c.nlev; ++j) {
+    const int side = 1 << j;
+    if (lane < side * side) {
+      const int dx = lane % side, dy = lane / side;
+      const int64_t X = RX * side + dx, Y = RY * side + dy;
+      const Window &w = c.win[j];
+      if (X >= w.bx0 && X < w.bx0 + w.nbx && Y >= w.by0 && Y < w.by0 + w.nby) {
+        double2 *dst = reinterpret_cast<double2 *>(c.loc[j]) + ((Y - w.by0) * w.nbx + (X - w.bx0)) * p;
+        const double dr = (double)(X & 1) - 0.5, di = (double)(Y & 1) - 0.5;
+        cplx b[PMAX];
+        // parent from global memory (depth 1) or LDS, through separate loads
+        // so that no pointer mixes the two address spaces
+        auto load = [&](auto parent_coef) {
+#pragma unroll
+          for (int l = 0; l < PMAX; ++l)
+            if (l < p) {
+              const double2 v = parent_coef(l);
+              b[l] = cplx{ldexp(v.x, -l), ldexp(v.y, -l)};
+            }
+        };
+        if (j == 1) {
+          const double2 *root = reinterpret_cast<const double2 *>(c.loc[0]) + rb * p;
+          load([&](int l) { return root[l]; });
+        } else {
+          const double2 *lp = (j == 2 ? bufB : bufA) + ((dy >> 1) * (side >> 1) + (dx >> 1)) * PMAX;
+          load([&](int l) { return lp[l]; });
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < PMAX; ++k)
+          if (k + 1 < p) {
+#pragma unroll
+            for (int i = PMAX - 2; i >= k; --i)
+              if (i + 1 < p) {
+                b[i].re = fma(dr, b[i + 1].re, fma(-di, b[i + 1].im, b[i].re));
+                b[i].im = fma(dr, b[i + 1].im, fma(di, b[i + 1].re, b[i].im));
+              }
+          }
+        double2 *keep = j == 1 ? bufB : bufA;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i)
+          if (i < p) {
+            const double2 v = dst[i];
+            const double2 r = make_double2(v.x + b[i].re, v.y + b[i].im);
+            dst[i] = r;
+            if (j < c.nlev) keep[lane * PMAX + i] = r;
+          }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------- M2L on MFMA
 
 template <typename T>
@@ -444,6 +516,16 @@ void launch_l2l(const DownArgs &a, const OpTables &t, hipStream_t stream) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_l2l, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                      stream, a, t.l2l);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_l2l_chain(const L2LChain &c, const OpTables &t, hipStream_t stream) {
+  if (c.nlev < 1 || c.nlev > kMaxL2LChain) fail(LENS_EINVAL, "L2L chain: bad level count");
+  const int64_t n = c.win[0].count();
+  if (n == 0) return;
+  LENS_PMAX_DISPATCH(c.p, hipLaunchKernelGGL((k_l2l_tile<PM>), dim3((unsigned)n), dim3(64), 0,
+                                             stream, c));
+  (void)t;
   LENS_HIP(hipGetLastError());
 }
 

@@ -145,8 +145,18 @@ void build_l2l_bfrag(int p, int ks_count, int nt_count, std::vector<double> &out
 void launch_p2m(Geometry g, int level, Window win, const double *sxy, const double *sq, int qdim,
                 const int32_t *leaf_start, int p, double *mp, float *mp32, int64_t n_sources,
                 hipStream_t stream);
-void launch_m2m(int level, int p, const double *child, double *parent, float *parent32,
-                const double *m2m, hipStream_t stream);
+// M2M of levels level, level-1, ..., level-nlev+1 in one launch; the child
+// level (level+1) is dense, [n][n][p] complex; out[i] / out32[i] (optional)
+// receive level - i, dense.
+constexpr int kMaxM2MChain = 4;
+struct M2MChain {
+  int level, nlev, p;
+  const double *child;
+  double *out[kMaxM2MChain];
+  float *out32[kMaxM2MChain];
+};
+int m2m_chain_levels(int level);  // most levels one launch can take from `level` down
+void launch_m2m_chain(const M2MChain &c, hipStream_t stream);
 
 // Downward pass (downward.hip): local expansions of `win` at `level` from the
 // parent's locals (level >= 3) and the multipoles of the interaction list.
@@ -162,6 +172,16 @@ struct DownArgs {
 };
 // loc += L2L(parent locals), FP64 (levels >= 3).
 void launch_l2l(const DownArgs &a, const OpTables &t, hipStream_t stream);
+// L2L down a chain of levels in one launch: the locals of `level` are final;
+// levels level+1 .. level+nlev (nlev <= 3) get loc += L2L(parent) in turn.
+// win[j] / loc[j]: window and locals [win][p] of level + j.
+constexpr int kMaxL2LChain = 3;
+struct L2LChain {
+  int level, nlev, p;
+  Window win[kMaxL2LChain + 1];
+  double *loc[kMaxL2LChain + 1];
+};
+void launch_l2l_chain(const L2LChain &c, const OpTables &t, hipStream_t stream);
 
 // M2L of several levels in one launch: loc = (1/s) sum over the interaction
 // list (FP64 or FP32 arithmetic); runs on MFMA when the order's tile fits the

@@ -214,37 +214,94 @@ __global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Windo
   }
 }
 
-// One thread per (parent box at `level`, output coefficient l); child
-// quadrant q = a + 2c is the child (2ix + a, 2iy + c) at level + 1.  Table
-// layout M[q][k][l] (complex, zero for k > l).
-__global__ __launch_bounds__(kThreads) void k_m2m(int level, int p,
-                                                  const double *__restrict__ child,
-                                                  double *__restrict__ parent,
-                                                  float *__restrict__ parent32,
-                                                  const double *__restrict__ tab) {
-  const int64_t nb = int64_t(1) << level;
-  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (idx >= nb * nb * p) return;
-  const int64_t b = idx / p;
-  const int l = (int)(idx - b * p);
-  const int64_t ix = b % nb, iy = b / nb;
-  const int64_t ncb = nb * 2;
-  cplx acc = {0.0, 0.0};
-  for (int q = 0; q < 4; ++q) {
-    const int64_t cb = (2 * iy + (q >> 1)) * ncb + (2 * ix + (q & 1));
-    const double *src = child + 2 * cb * p;
-    const double *t = tab + (size_t)q * p * p * 2;
-    for (int k = 0; k <= l; ++k) {
-      const cplx a = {src[2 * k], src[2 * k + 1]};
-      const cplx m = {t[((size_t)k * p + l) * 2], t[((size_t)k * p + l) * 2 + 1]};
-      acc = cmad(m, a, acc);
+// M2M for up to four consecutive levels in one launch.  A 256-thread
+// workgroup owns a T x T tile of parent boxes at the finest level of the
+// launch (T = min(8, boxes per side)); four neighbouring lanes take the four
+// children of one parent, each shifting its child's p coefficients (held in
+// registers) to the parent's centre, and the four shifted expansions are
+// summed across the lanes.  The tile's parents are kept in LDS and the next
+// coarser level's (T/2)^2 parents formed from them, and so on, so a tile of
+// 8 x 8 boxes yields its 4 x 4, 2 x 2 and 1 x 1 ancestors in the same launch.
+//
+// The shift needs no table: in child-size units the child centre sits at
+// d = (a - 1/2) + i(c - 1/2) from the parent's (quadrant q = a + 2c, child
+// (2x + a, 2y + c)), and the parent's rescaled coefficients are
+// a_l = 2^-l sum_q sum_{k<=l} C(l,k) d^(l-k) a_k(child q).  The binomial sums
+// are formed by repeated synthetic division (p(p-1)/2 updates
+// a_j += d a_(j-1)); d's parts are +-1/2, so every product in them is exact.
+template <int PMAX>
+__global__ __launch_bounds__(kThreads) void k_m2m_tile(M2MChain c) {
+  __shared__ double2 bufA[64 * PMAX];  // stage 0 and 2 results
+  __shared__ double2 bufB[16 * PMAX];  // stage 1 results
+  const int tid = threadIdx.x;
+  const int q = tid & 3, par = tid >> 2;  // child quadrant, parent in the tile
+  const int p = c.p;
+  const int64_t n = int64_t(1) << c.level;
+  const int T = n < 8 ? (int)n : 8;
+  const int64_t tiles = n / T;
+  const int64_t tbx = blockIdx.x % tiles, tby = blockIdx.x / tiles;
+  const double dr = (q & 1) - 0.5, di = (q >> 1) - 0.5;
+  for (int st = 0; st < c.nlev; ++st) {
+    const int Ts = T >> st;      // parents per tile side at this stage
+    const int64_t ns = n >> st;  // boxes per side at this level
+    // whole waves stay in step for the cross-lane sums below
+    if ((tid & ~63) < 4 * Ts * Ts) {
+      const bool on = par < Ts * Ts;
+      const int tx = on ? par % Ts : 0, ty = on ? par / Ts : 0;
+      cplx a[PMAX];
+      if (st == 0) {
+        const int64_t cb = (2 * (tby * T + ty) + (q >> 1)) * (2 * n) + 2 * (tbx * T + tx) + (q & 1);
+        const double2 *src = reinterpret_cast<const double2 *>(c.child) + cb * p;
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k)
+          if (k < p) {
+            const double2 v = on ? src[k] : make_double2(0.0, 0.0);
+            a[k] = cplx{v.x, v.y};
+          }
+      } else {
+        const double2 *src = (st == 2 ? bufB : bufA) + ((2 * ty + (q >> 1)) * (2 * Ts) + 2 * tx + (q & 1)) * PMAX;
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k)
+          if (k < p) {
+            const double2 v = on ? src[k] : make_double2(0.0, 0.0);
+            a[k] = cplx{v.x, v.y};
+          }
+      }
+#pragma unroll
+      for (int k = 0; k + 1 < PMAX; ++k)
+        if (k + 1 < p) {
+#pragma unroll
+          for (int j = PMAX - 1; j > k; --j)
+            if (j < p) {
+              a[j].re = fma(dr, a[j - 1].re, fma(-di, a[j - 1].im, a[j].re));
+              a[j].im = fma(dr, a[j - 1].im, fma(di, a[j - 1].re, a[j].im));
+            }
+        }
+      // sum over the four children (lanes 4i .. 4i+3), in a fixed order
+#pragma unroll
+      for (int l = 0; l < PMAX; ++l)
+        if (l < p) {
+          double re = a[l].re + __shfl_xor(a[l].re, 1);
+          double im = a[l].im + __shfl_xor(a[l].im, 1);
+          re += __shfl_xor(re, 2);
+          im += __shfl_xor(im, 2);
+          a[l] = cplx{ldexp(re, -l), ldexp(im, -l)};
+        }
+      if (on && q == 0) {
+        const int64_t box = (tby * Ts + ty) * ns + tbx * Ts + tx;
+        double2 *gout = reinterpret_cast<double2 *>(c.out[st]) + box * p;
+        float2 *gout32 = c.out32[st] ? reinterpret_cast<float2 *>(c.out32[st]) + box * p : nullptr;
+        double2 *keep = st == 1 ? bufB : bufA;
+#pragma unroll
+        for (int l = 0; l < PMAX; ++l)
+          if (l < p) {
+            gout[l] = make_double2(a[l].re, a[l].im);
+            if (gout32) gout32[l] = make_float2((float)a[l].re, (float)a[l].im);
+            if (st + 1 < c.nlev) keep[par * PMAX + l] = make_double2(a[l].re, a[l].im);
+          }
+      }
     }
-  }
-  parent[2 * idx] = acc.re;
-  parent[2 * idx + 1] = acc.im;
-  if (parent32) {
-    parent32[2 * idx] = (float)acc.re;
-    parent32[2 * idx + 1] = (float)acc.im;
+    __syncthreads();
   }
 }
 
@@ -292,11 +349,23 @@ void launch_p2m(Geometry g, int level, Window win, const double *sxy, const doub
   LENS_HIP(hipGetLastError());
 }
 
-void launch_m2m(int level, int p, const double *child, double *parent, float *parent32,
-                const double *m2m, hipStream_t stream) {
-  const int64_t nb = int64_t(1) << level;
-  hipLaunchKernelGGL(k_m2m, dim3(blocks_for(nb * nb * p)), dim3(kThreads), 0, stream, level, p,
-                     child, parent, parent32, m2m);
+int m2m_chain_levels(int level) {
+  // T = min(8, 2^level) parents per tile side; T halves per fused level
+  int T = level >= 3 ? 8 : (1 << level), k = 1;
+  while (T > 1 && k < kMaxM2MChain) {
+    T >>= 1;
+    ++k;
+  }
+  return k;
+}
+
+void launch_m2m_chain(const M2MChain &c, hipStream_t stream) {
+  if (c.nlev < 1 || c.nlev > m2m_chain_levels(c.level))
+    fail(LENS_EINVAL, "M2M chain: bad level count");
+  const int64_t n = int64_t(1) << c.level;
+  const int64_t T = n < 8 ? n : 8;
+  const unsigned blocks = (unsigned)((n / T) * (n / T));
+  LENS_PMAX_DISPATCH(c.p, hipLaunchKernelGGL((k_m2m_tile<PM>), dim3(blocks), dim3(kThreads), 0, stream, c));
   LENS_HIP(hipGetLastError());
 }
 
