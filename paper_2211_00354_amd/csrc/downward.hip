@@ -186,10 +186,18 @@ __constant__ IList kIL = make_ilist();
 // each quadrant class holds (TILE/2)^2 targets = MT M-tiles of 16.  KS
 // K-steps of 4 cover the 2p interleaved input coefficients, NT N-tiles of 16
 // the 2p outputs.  One launch serves several levels (M2L of different levels
-// is independent): blockIdx.x indexes the concatenated tile lists.
+// is independent): blockIdx.x indexes the concatenated tile lists.  Up to
+// moderate orders the register budget is set for three or more waves per
+// SIMD (the accumulators then live in VGPRs, not AGPRs), which keeps several
+// workgroups per CU in flight; larger orders keep the compiler's choice.
+template <typename T, int TILE, int KS>
+constexpr int m2l_min_waves() {
+  return KS <= (sizeof(T) == 4 ? 8 : 6) ? 3 : 1;
+}
 template <typename T, int TILE, int KS, bool FUSE>
-__global__ __launch_bounds__(kThreads) void k_m2l_mfma(M2LBatch bt, const T *__restrict__ bfrag,
-                                                       const double *__restrict__ l2l_frag) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(m2l_min_waves<T, TILE, KS>()))) void k_m2l_mfma(
+    M2LBatch bt, const T *__restrict__ bfrag, const double *__restrict__ l2l_frag) {
   constexpr int S = TILE + 4;            // source tile side
   constexpr int H = TILE / 2;            // targets per quadrant class per side
   constexpr int MT = H * H / 16;         // M-tiles per wave
@@ -213,8 +221,36 @@ __global__ __launch_bounds__(kThreads) void k_m2l_mfma(M2LBatch bt, const T *__r
   // (zero outside the stored window swin, which holds every source of the
   // level's targets): all of a thread's loads are issued before its LDS stores
   constexpr int KP = 4 * KS;
-  constexpr int NE = S * S * KP, NIT = (NE + kThreads - 1) / kThreads;
-  {
+  if ((twop & 3) == 0) {
+    // 16-byte loads (2p a multiple of 4: every box record is 16-byte aligned)
+    constexpr int K4 = KS;  // float4 chunks per padded record
+    constexpr int NE4 = S * S * K4, NIT4 = (NE4 + kThreads - 1) / kThreads;
+    const int k4n = twop >> 2;
+    using V4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
+    V4 v[NIT4];
+#pragma unroll
+    for (int it = 0; it < NIT4; ++it) {
+      const int e = it * kThreads + threadIdx.x;
+      const int k4 = e % K4, bl = e / K4;
+      const int bx = bl % S, by = bl / S;
+      const int64_t gx = tx0 - 2 + bx - a.swin.bx0, gy = ty0 - 2 + by - a.swin.by0;
+      v[it] = V4{0, 0, 0, 0};
+      if (e < NE4 && k4 < k4n && gx >= 0 && gy >= 0 && gx < a.swin.nbx && gy < a.swin.nby)
+        v[it] = reinterpret_cast<const V4 *>(mp + (gy * a.swin.nbx + gx) * twop)[k4];
+    }
+#pragma unroll
+    for (int it = 0; it < NIT4; ++it) {
+      const int e = it * kThreads + threadIdx.x;
+      if (e < NE4) {
+        T *d = lds + (e / K4) * REC + 4 * (e % K4);
+        d[0] = v[it].x;
+        d[1] = v[it].y;
+        d[2] = v[it].z;
+        d[3] = v[it].w;
+      }
+    }
+  } else {
+    constexpr int NE = S * S * KP, NIT = (NE + kThreads - 1) / kThreads;
     T v[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -306,6 +342,20 @@ __global__ __launch_bounds__(kThreads) void k_m2l_mfma(M2LBatch bt, const T *__r
       }
     }
   } else {
+    // FP32 M2L part first to LDS (in the FP64 result layout), so that its
+    // accumulators are free before the L2L ones are live
+    float *xch = reinterpret_cast<float *>(lds_raw) + (size_t)wave * MT * 16 * NT * 16;
+    if constexpr (std::is_same<T, float>::value) {
+      __syncthreads();  // the source tile is no longer read
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            xch[(mt * 16 + M::row(lane, r)) * (NT * 16) + nt * 16 + (lane & 15)] = acc[mt][nt][r];
+      __syncthreads();
+    }
     // L2L on FP64 MFMA: A = the targets' parent locals, B = L2L fragments of
     // this wave's quadrant; accumulated apart from the M2L part.
     using M64 = Mfma<double>;
@@ -338,16 +388,6 @@ __global__ __launch_bounds__(kThreads) void k_m2l_mfma(M2LBatch bt, const T *__r
     }
     // bring the M2L part into the FP64 result layout (same for FP64 M2L)
     if constexpr (std::is_same<T, float>::value) {
-      __syncthreads();  // the source tile is no longer read
-      float *xch = reinterpret_cast<float *>(lds_raw) + (size_t)wave * MT * 16 * NT * 16;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-            xch[(mt * 16 + M::row(lane, r)) * (NT * 16) + nt * 16 + (lane & 15)] = acc[mt][nt][r];
-      __syncthreads();
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
