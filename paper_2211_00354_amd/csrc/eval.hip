@@ -180,17 +180,23 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
       acc_t ax[R], ay[R];
       int64_t oidx[R];
       bool act[R];
+      // grid rays: position of slot r's ray; recomputed after the pair loop
+      // rather than kept live through it (fewer registers)
+      auto grid_ray = [&](int r, int lxx, int lyy, double &x, double &y, int64_t &o) {
+        const int32_t t = pos + r;  // wave-uniform tile index
+        const int32_t ty = t / TW, tx = t - ty * TW;
+        const int32_t ci = tx * TX + lxx, cj = ty * TY + lyy;
+        const bool on = t < pend && ci < W && cj < H;
+        const int64_t i = i0 + (on ? ci : 0), j = j0 + (on ? cj : 0);
+        x = grid_coord(a.grid.x0, a.grid.dx, i);
+        y = grid_coord(a.grid.y0, a.grid.dy, j);
+        o = j * a.grid.nx + i;
+        return on;
+      };
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (GRID) {
-          const int32_t t = pos + r;  // wave-uniform tile index
-          const int32_t ty = t / TW, tx = t - ty * TW;
-          const int32_t ci = tx * TX + lx, cj = ty * TY + ly;
-          act[r] = t < pend && ci < W && cj < H;
-          const int64_t i = i0 + (act[r] ? ci : 0), j = j0 + (act[r] ? cj : 0);
-          rx[r] = grid_coord(a.grid.x0, a.grid.dx, i);
-          ry[r] = grid_coord(a.grid.y0, a.grid.dy, j);
-          oidx[r] = j * a.grid.nx + i;
+          act[r] = grid_ray(r, lx, ly, rx[r], ry[r], oidx[r]);
         } else {
           const int32_t idx = pos + r * kWave + lane;
           act[r] = idx < min(nr, pos + RPC);
@@ -234,6 +240,14 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
         for (; i < re[d]; ++i) star(sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i]);
       }
 
+      if (GRID) {
+        // the lane's tile position, opaque to the optimiser so that the ray
+        // positions are recomputed here, not carried through the pair loop
+        int lx2 = lx, ly2 = ly;
+        asm volatile("" : "+v"(lx2), "+v"(ly2));
+#pragma unroll
+        for (int r = 0; r < R; ++r) act[r] = grid_ray(r, lx2, ly2, rx[r], ry[r], oidx[r]);
+      }
       // far field: Horner over the R rays, one LDS read per coefficient
       cplx w[R], f[R];
 #pragma unroll
