@@ -200,9 +200,12 @@ bool aligned_geometry(const lens_grid &g, const double dom[4], int leaf_level, d
   bool found = false;
   double best_cost = 0;
   for (const Cand &c : cands) {
-    // boxes to the left of / below the grid origin needed to reach the domain
-    const double mx = std::max(0.0, std::ceil((g.x0 - dom[0]) / c.s));
-    const double my = std::max(0.0, std::ceil((g.y0 - dom[1]) / c.s));
+    // boxes to the left of / below the grid origin needed to reach the domain,
+    // rounded up to a multiple of 4 so that the rays' boxes start at an index
+    // divisible by 4 (the M2L tiles of the two finest levels start at even
+    // box indices; an odd start would cost one more row and column of tiles)
+    const double mx = 4.0 * std::ceil(std::max(0.0, std::ceil((g.x0 - dom[0]) / c.s)) / 4.0);
+    const double my = 4.0 * std::ceil(std::max(0.0, std::ceil((g.y0 - dom[1]) / c.s)) / 4.0);
     const double x0 = g.x0 - mx * c.s, y0 = g.y0 - my * c.s;
     const double need = std::max(dom[2] - x0, dom[3] - y0) * (1.0 + 1e-12);
     int L = 2;
@@ -227,11 +230,15 @@ bool aligned_geometry(const lens_grid &g, const double dom[4], int leaf_level, d
   return found;
 }
 
+// Boxes of `level` that hold points of bb: the host and the kernels place a
+// point with the same correctly rounded division, which is monotone in the
+// coordinate, so the boxes of bb's corners bound those of every point in it
+// (and a box in a level's window has its parent in the window above).
 Window window_for(const lens_plan &P, int level, const double bb[4]) {
   const int64_t n = int64_t(1) << level;
   const double s = std::ldexp(P.g.side, -level);
-  int64_t x0 = box_coord_host(bb[0], P.g.x0, s, n) - 1, x1 = box_coord_host(bb[2], P.g.x0, s, n) + 1;
-  int64_t y0 = box_coord_host(bb[1], P.g.y0, s, n) - 1, y1 = box_coord_host(bb[3], P.g.y0, s, n) + 1;
+  int64_t x0 = box_coord_host(bb[0], P.g.x0, s, n), x1 = box_coord_host(bb[2], P.g.x0, s, n);
+  int64_t y0 = box_coord_host(bb[1], P.g.y0, s, n), y1 = box_coord_host(bb[3], P.g.y0, s, n);
   x0 = std::max<int64_t>(x0, 0);
   y0 = std::max<int64_t>(y0, 0);
   x1 = std::min<int64_t>(x1, n - 1);
@@ -240,8 +247,8 @@ Window window_for(const lens_plan &P, int level, const double bb[4]) {
 }
 
 // Multipole storage per level.  M2L sources of a target box lie within 3
-// boxes of it, so level l needs the multipoles of the target window (rays'
-// boxes plus one) grown by 3 boxes.  Where that covers under a quarter of the
+// boxes of it, so level l needs the multipoles of the target window (the
+// rays' boxes) grown by 3 boxes (4 are kept, see below).  Where that covers under a quarter of the
 // level, and at every finer level, only that window is stored and formed
 // from the stars ("windowed" levels); the coarser ("dense") levels reach down
 // at least to where boxes hold ~512 sources, so that forming the finest of
@@ -256,8 +263,10 @@ void source_windows(lens_plan *P) {
   for (int l = L; l >= 2; --l) {
     const int64_t n = int64_t(1) << l;
     Window w = window_for(*P, l, P->target);
-    const int64_t x0 = std::max<int64_t>(w.bx0 - 3, 0), y0 = std::max<int64_t>(w.by0 - 3, 0);
-    const int64_t x1 = std::min<int64_t>(w.bx0 + w.nbx + 3, n), y1 = std::min<int64_t>(w.by0 + w.nby + 3, n);
+    // 3 boxes of M2L sources, plus one for rays that check_inside admits
+    // just outside the target (within its tolerance)
+    const int64_t x0 = std::max<int64_t>(w.bx0 - 4, 0), y0 = std::max<int64_t>(w.by0 - 4, 0);
+    const int64_t x1 = std::min<int64_t>(w.bx0 + w.nbx + 4, n), y1 = std::min<int64_t>(w.by0 + w.nby + 4, n);
     P->swin[l] = Window{x0, y0, x1 - x0, y1 - y0};
     if (P->swin[l].count() * 4 <= n * n && lw == l + 1) lw = l;
   }
