@@ -367,9 +367,11 @@ __global__ __launch_bounds__(kThreads) void k_gather_rays(const uint32_t *__rest
 }
 
 // start[b] = lower_bound of box b in the sorted keys, b = 0..nbox, in two
-// steps: every kBoxStride-th box searches the whole array, then each box
-// searches only between its two neighbouring coarse bounds.
-constexpr int64_t kBoxStride = 256;
+// steps: every kBoxStride-th box searches the whole array; then a workgroup
+// per stride of boxes counts the keys between its two coarse bounds per box
+// (LDS histogram) and writes their exclusive prefix, so each key is read once
+// and each entry written once, with no per-box search.
+constexpr int64_t kBoxStride = kThreads;
 
 __global__ __launch_bounds__(kThreads) void k_box_starts_coarse(const uint32_t *__restrict__ keys,
                                                                 int64_t n, int64_t nbox,
@@ -393,19 +395,19 @@ __global__ __launch_bounds__(kThreads) void k_box_starts(const uint32_t *__restr
                                                          int64_t nbox,
                                                          const int32_t *__restrict__ coarse,
                                                          int32_t *__restrict__ start) {
-  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (b > nbox) return;
-  const int64_t c = b / kBoxStride;
-  int64_t lo = coarse[c], hi = coarse[c + 1];
-  // the bound of box b lies between those of boxes c*stride and (c+1)*stride
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)keys[mid] < b)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  start[b] = (int32_t)lo;
+  __shared__ uint32_t cnt[kBoxStride];
+  __shared__ uint32_t sh[kWaves];
+  const int t = threadIdx.x;
+  const int64_t c = blockIdx.x, b0 = c * kBoxStride;
+  cnt[t] = 0;
+  __syncthreads();
+  // the keys in [lo, hi) are those of boxes [b0, b0 + stride)
+  const int32_t lo = coarse[c], hi = coarse[c + 1];
+  for (int64_t j = (int64_t)lo + t; j < hi; j += kThreads) atomicAdd(&cnt[keys[j] - b0], 1u);
+  __syncthreads();
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan(cnt[t], sh, &tot);
+  if (b0 + t <= nbox) start[b0 + t] = lo + (int32_t)ex;
 }
 
 inline unsigned blocks_for(int64_t n, int per = kThreads) {
@@ -512,8 +514,8 @@ void launch_box_starts(const uint32_t *sorted_keys, int64_t n, int64_t nbox, int
   const int64_t nc = nbox / kBoxStride + 2;
   hipLaunchKernelGGL(k_box_starts_coarse, dim3(blocks_for(nc)), dim3(kThreads), 0, stream,
                      sorted_keys, n, nbox, coarse);
-  hipLaunchKernelGGL(k_box_starts, dim3(blocks_for(nbox + 1)), dim3(kThreads), 0, stream,
-                     sorted_keys, nbox, coarse, start);
+  hipLaunchKernelGGL(k_box_starts, dim3((unsigned)(nbox / kBoxStride + 1)), dim3(kThreads), 0,
+                     stream, sorted_keys, nbox, coarse, start);
   LENS_HIP(hipGetLastError());
 }
 
