@@ -15,7 +15,8 @@
 //   * far field: f(z) = sum_l b~_l w^l, w = (z - c)/s, by Horner in FP64,
 //     alpha_far = conj(f);
 //   * y = (1-kappa_s-gamma, 1-kappa_s+gamma) * x - alpha in FP64, written as
-//     [n][2] or binned into the map with an integer atomic.
+//     [n][2] or binned into the map: counts are summed per unit in an LDS
+//     table and added to the map with one integer atomic per distinct pixel.
 // Units are spread over a bounded grid; consecutive units (neighbouring
 // boxes, which share stars) go to the same XCD so that they share its L2.
 #include "device_common.h"
@@ -67,21 +68,41 @@ __device__ __forceinline__ void pair_update(const C (&rx)[R], const C (&ry)[R], 
   }
 }
 
-// Add one count for every lane whose key is >= 0 to counts[key], one atomic
-// per distinct key of the wave: the lanes holding the first pending key are
-// found with a ballot and their count added by one lane.  Neighbouring rays
-// mostly land in one pixel, so a wave of rays issues a few atomics, not 64.
-// (Merging the R slots of a wave into one loop issues fewer atomics but
-// measured slower: each round then needs R ballots.)
-__device__ __forceinline__ void wave_add_counts(int32_t key, int32_t *__restrict__ counts) {
-  uint64_t pending = __ballot(key >= 0);
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int32_t k = __builtin_amdgcn_readlane(key, leader);
-    const uint64_t same = __ballot(key == k);
-    if ((int)threadIdx.x == leader) atomicAdd(&counts[k], (int32_t)__popcll(same));
-    pending &= ~same;
+// Map counts of a work unit are first summed in a small per-wave table in
+// LDS (pixel key -> count, open addressing with two probes; a ray whose
+// pixel finds both probed slots taken by other pixels goes straight to the
+// global map), then added to the map with one atomic per distinct pixel.
+constexpr int kMapTableBits = 9;
+constexpr int kMapTable = 1 << kMapTableBits;
+
+__device__ __forceinline__ void map_table_add(int32_t *hkey, uint32_t *hval, int32_t key,
+                                              int32_t *__restrict__ counts) {
+  uint32_t slot = ((uint32_t)key * 2654435761u) >> (32 - kMapTableBits);
+#pragma unroll
+  for (int probe = 0; probe < 2; ++probe) {
+    const int32_t prev = atomicCAS(&hkey[slot], -1, key);
+    if (prev == -1 || prev == key) {
+      atomicAdd(&hval[slot], 1u);
+      return;
+    }
+    slot = (slot + 1) & (kMapTable - 1);
   }
+  atomicAdd(&counts[key], 1);
+}
+
+__device__ __forceinline__ void map_table_flush(int32_t *hkey, uint32_t *hval,
+                                                int32_t *__restrict__ counts, int lane) {
+  __syncthreads();
+#pragma unroll
+  for (int e = lane; e < kMapTable; e += 64) {
+    const int32_t k = hkey[e];
+    if (k >= 0) {
+      atomicAdd(&counts[k], (int32_t)hval[e]);
+      hkey[e] = -1;
+      hval[e] = 0;
+    }
+  }
+  __syncthreads();
 }
 
 template <int PMAX, bool MIXED, bool MAP, bool GRID, int R>
@@ -98,7 +119,15 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
                                                 int32_t *__restrict__ counts) {
   // the box's local expansion, read by every lane (LDS broadcast)
   __shared__ double2 lds_loc[PMAX];
+  __shared__ int32_t hkey[MAP ? kMapTable : 1];
+  __shared__ uint32_t hval[MAP ? kMapTable : 1];
   const int lane = threadIdx.x;
+  if (MAP) {
+    for (int e = lane; e < kMapTable; e += 64) {
+      hkey[e] = -1;
+      hval[e] = 0;
+    }
+  }
   // unit counts fit in 31 bits (checked at launch)
   const uint32_t CH = (uint32_t)a.chunks_per_box;
   const uint32_t nbx = (uint32_t)a.win.nbx;
@@ -285,9 +314,11 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
       }
       if (MAP) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) wave_add_counts(key[r], counts);
+        for (int r = 0; r < R; ++r)
+          if (key[r] >= 0) map_table_add(hkey, hval, key[r], counts);
       }
     }
+    if (MAP) map_table_flush(hkey, hval, counts, lane);
   }
 }
 
