@@ -69,17 +69,18 @@ __device__ __forceinline__ void pair_update(const C (&rx)[R], const C (&ry)[R], 
 }
 
 // Map counts of a work unit are first summed in a small per-wave table in
-// LDS (pixel key -> count, open addressing with two probes; a ray whose
-// pixel finds both probed slots taken by other pixels goes straight to the
-// global map), then added to the map with one atomic per distinct pixel.
-constexpr int kMapTableBits = 9;
+// LDS (pixel key -> count, open addressing with four linear probes; a ray
+// whose pixel finds all probed slots taken by other pixels goes straight to
+// the global map), then added to the map with one atomic per distinct pixel.
+// A unit's rays land on a compact patch of pixels, so 256 entries suffice.
+constexpr int kMapTableBits = 8;
 constexpr int kMapTable = 1 << kMapTableBits;
 
 __device__ __forceinline__ void map_table_add(int32_t *hkey, uint32_t *hval, int32_t key,
                                               int32_t *__restrict__ counts) {
   uint32_t slot = ((uint32_t)key * 2654435761u) >> (32 - kMapTableBits);
 #pragma unroll
-  for (int probe = 0; probe < 2; ++probe) {
+  for (int probe = 0; probe < 4; ++probe) {
     const int32_t prev = atomicCAS(&hkey[slot], -1, key);
     if (prev == -1 || prev == key) {
       atomicAdd(&hval[slot], 1u);
@@ -277,16 +278,20 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
 #pragma unroll
         for (int r = 0; r < R; ++r) act[r] = grid_ray(r, lx2, ly2, rx[r], ry[r], oidx[r]);
       }
-      // far field: Horner over the R rays, one LDS read per coefficient
+      // far field: Horner over the R rays from the top coefficient down, one
+      // LDS read per coefficient
       cplx w[R], f[R];
+      {
+        const double2 top = lds_loc[p - 1];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        w[r] = cplx{(rx[r] - cx) * inv_s, (ry[r] - cy) * inv_s};
-        f[r] = cplx{0.0, 0.0};
+        for (int r = 0; r < R; ++r) {
+          w[r] = cplx{(rx[r] - cx) * inv_s, (ry[r] - cy) * inv_s};
+          f[r] = cplx{top.x, top.y};
+        }
       }
 #pragma unroll
-      for (int l = PMAX - 1; l >= 0; --l)
-        if (l < p) {
+      for (int l = PMAX - 2; l >= 0; --l)
+        if (l < p - 1) {
           const double2 c = lds_loc[l];
 #pragma unroll
           for (int r = 0; r < R; ++r) f[r] = cmad(f[r], w[r], cplx{c.x, c.y});
