@@ -106,8 +106,11 @@ __device__ __forceinline__ void map_table_flush(int32_t *hkey, uint32_t *hval,
   __syncthreads();
 }
 
+// The mixed kernels are compiled for five waves per SIMD (at most 96 VGPRs;
+// the R = 4 instances spill a few bytes of per-lane scratch outside the pair
+// loop), which measured faster than four waves without spills.
 template <int PMAX, bool MIXED, bool MAP, bool GRID, int R>
-__global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__restrict__ loc,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 1))) void k_eval(EvalArgs a, const double *__restrict__ loc,
                                                 const double *__restrict__ sxy,
                                                 const double *__restrict__ sm,
                                                 const int32_t *__restrict__ leaf_start,
@@ -188,6 +191,10 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
     }
     const double cx = a.g.x0 + ((double)gx + 0.5) * s;
     const double cy = a.g.y0 + ((double)gy + 0.5) * s;
+    // grid: offsets of the box's first ray column / row from the centre
+    const double ox0 = GRID ? grid_coord(a.grid.x0, a.grid.dx, i0) - cx : 0.0;
+    const double oy0 = GRID ? grid_coord(a.grid.y0, a.grid.dy, j0) - cy : 0.0;
+    const double c1cx = a.c1 * cx, c2cy = a.c2 * cy;
     __syncthreads();  // the previous unit's reads of lds_loc are done
     if (lane < p) lds_loc[lane] = reinterpret_cast<const double2 *>(loc + 2 * (int64_t)b * p)[lane];
     __syncthreads();
@@ -270,13 +277,31 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
         for (; i < re[d]; ++i) star(sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i]);
       }
 
+      // ray offsets from the box centre (FP64).  Grid rays: recomputed here
+      // from the lane's tile position (opaque to the optimiser, so that
+      // nothing of the rays is carried through the pair loop) as the first
+      // ray column's offset plus whole cells, one rounding each
+      double dxr[R], dyr[R];
       if (GRID) {
-        // the lane's tile position, opaque to the optimiser so that the ray
-        // positions are recomputed here, not carried through the pair loop
         int lx2 = lx, ly2 = ly;
         asm volatile("" : "+v"(lx2), "+v"(ly2));
 #pragma unroll
-        for (int r = 0; r < R; ++r) act[r] = grid_ray(r, lx2, ly2, rx[r], ry[r], oidx[r]);
+        for (int r = 0; r < R; ++r) {
+          const int32_t t = pos + r;
+          const int32_t ty = t / TW, tx = t - ty * TW;
+          const int32_t ci = tx * TX + lx2, cj = ty * TY + ly2;
+          act[r] = t < pend && ci < W && cj < H;
+          const int32_t cc = act[r] ? ci : 0, rr = act[r] ? cj : 0;
+          dxr[r] = fma((double)cc, a.grid.dx, ox0);
+          dyr[r] = fma((double)rr, a.grid.dy, oy0);
+          oidx[r] = (int64_t)(j0 + rr) * a.grid.nx + (i0 + cc);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          dxr[r] = rx[r] - cx;
+          dyr[r] = ry[r] - cy;
+        }
       }
       // far field: Horner over the R rays from the top coefficient down, one
       // LDS read per coefficient
@@ -285,25 +310,27 @@ __global__ __launch_bounds__(kWave) void k_eval(EvalArgs a, const double *__rest
         const double2 top = lds_loc[p - 1];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          w[r] = cplx{(rx[r] - cx) * inv_s, (ry[r] - cy) * inv_s};
+          w[r] = cplx{dxr[r] * inv_s, dyr[r] * inv_s};
           f[r] = cplx{top.x, top.y};
         }
       }
+      // a runtime trip count (the order-guarded unrolled form keeps one
+      // spilled branch mask per level)
+#pragma unroll 2
+      for (int l = p - 2; l >= 0; --l) {
+        const double2 c = lds_loc[l];
 #pragma unroll
-      for (int l = PMAX - 2; l >= 0; --l)
-        if (l < p - 1) {
-          const double2 c = lds_loc[l];
-#pragma unroll
-          for (int r = 0; r < R; ++r) f[r] = cmad(f[r], w[r], cplx{c.x, c.y});
-        }
+        for (int r = 0; r < R; ++r) f[r] = cmad(f[r], w[r], cplx{c.x, c.y});
+      }
 
       int32_t key[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const double al1 = f[r].re + (double)ax[r];
         const double al2 = (double)ay[r] - f[r].im;
-        const double y1 = a.c1 * rx[r] - al1;
-        const double y2 = a.c2 * ry[r] - al2;
+        // grid: c x = c cx + c (x - cx)
+        const double y1 = GRID ? fma(a.c1, dxr[r], c1cx) - al1 : a.c1 * rx[r] - al1;
+        const double y2 = GRID ? fma(a.c2, dyr[r], c2cy) - al2 : a.c2 * ry[r] - al2;
         if (MAP) {
           key[r] = -1;
           const double t1 = (y1 - a.y1min) * a.S;
