@@ -121,6 +121,29 @@ def test_fmm_leaf_levels(lf, leaf):
     assert rel_l2(y, yo, ao) <= 1e-9
 
 
+@pytest.mark.parametrize("precision,p,tol", [("fp64", 36, 1e-9), ("fp64", 26, 1e-8),
+                                              ("mixed", 16, 1e-5)])
+def test_fmm_deep_tree_high_order(lf, precision, p, tol):
+    """Many stars, so that several dense levels are formed by the fused M2M
+    chains (up to four levels per launch) and the coarse L2L chain spans
+    several levels, at orders that use the largest register buckets; checked
+    on a strided sample of rays against the oracle's direct sum."""
+    rng = np.random.default_rng(41)
+    n = 200_000
+    radius = math.sqrt(n / 0.4)
+    xy = wl.uniform_disk(rng, n, radius)
+    m = wl.powerlaw_masses(rng, n)
+    g = wl.centred_grid(1.2 * radius, 1.2 * radius, 640, 640)
+    _say("fmm deep tree", precision, p)
+    y = host(lf.deflect(dev_tensor(xy), dev_tensor(m), grid=lfgrid(g), kappa_s=0.1, gamma=0.2,
+                        precision=precision, p=p))
+    idx = g.strided(16, 5)
+    yo, ao, _ = oracle.deflect(xy, m, g.rays(idx), 0.1, 0.2)
+    err = rel_l2(y[idx], yo, ao)
+    print("deep tree", precision, p, "rel l2", err)
+    assert err <= tol
+
+
 def test_fmm_error_falls_with_order(lf):
     """The truncation error must fall at least geometrically with p."""
     f = wl.random_field(3000, 30.0, seed=7, masses="powerlaw")
