@@ -15,8 +15,10 @@
 // integers (units of 2^-40 of a pixel's magnification) with 64-bit atomics,
 // so the map does not depend on the order of the additions; a final pass adds
 // them to the caller's FP64 map.  One thread per cell; a cell inside one
-// pixel (the common case) adds the same amount, so those are aggregated per
-// wave with a ballot loop (one atomic per distinct pixel).
+// pixel (the common case) adds the whole cell; sums go through an LDS table
+// of pixels per workgroup (one global atomic per distinct pixel).  For a
+// convex quadrilateral, pixels of its bounding box that lie outside one of
+// its edge lines are skipped before the overlap sum.
 #include "device_common.h"
 
 namespace lensfmm {
@@ -87,18 +89,59 @@ __device__ __forceinline__ double edge_term(double ax, double ay, double bx, dou
 // integral of clamp01(x) dy over the boundary of Q restricted to 0 <= y <= 1
 // (d/dx clamp01 is the indicator of 0 < x < 1): a sum of four edge terms,
 // with no clipped polygon to store.  Signed by Q's orientation; |.| taken.
-__device__ double quad_pixel_overlap(const double (&q)[4][2], double u, double v) {
+__device__ double quad_pixel_overlap(const double (&q)[4][2], const double (&k)[4],
+                                    const double (&kinv)[4], double u, double v) {
   double s = 0.0;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int e1 = (e + 1) & 3;
-    const double dx = q[e1][0] - q[e][0], dy = q[e1][1] - q[e][1];
-    const bool vertical = dx == 0.0;
-    const double k = dy != 0.0 ? dx * rcp_f64(dy) : 0.0;
-    const double kinv = vertical ? 0.0 : dy * rcp_f64(dx);
-    s += edge_term(q[e][0] - u, q[e][1] - v, q[e1][0] - u, q[e1][1] - v, k, kinv, vertical);
+    const bool vertical = q[e1][0] == q[e][0];
+    s += edge_term(q[e][0] - u, q[e][1] - v, q[e1][0] - u, q[e1][1] - v, k[e], kinv[e], vertical);
   }
   return fabs(s);
+}
+
+// Per-edge slopes of q for edge_term: k = dx/dy (0 for a horizontal edge),
+// kinv = dy/dx (0 for a vertical one).  They depend only on the cell.
+__device__ __forceinline__ void edge_slopes(const double (&q)[4][2], double (&k)[4],
+                                            double (&kinv)[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int e1 = (e + 1) & 3;
+    const double dx = q[e1][0] - q[e][0], dy = q[e1][1] - q[e][1];
+    k[e] = dy != 0.0 ? dx * rcp_f64(dy) : 0.0;
+    kinv[e] = dx == 0.0 ? 0.0 : dy * rcp_f64(dx);
+  }
+}
+
+// Orientation of a convex q (+1 counter-clockwise, -1 clockwise), or 0 if q
+// is not convex.
+__device__ __forceinline__ int convex_orientation(const double (&q)[4][2]) {
+  int pos = 0, neg = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int e1 = (e + 1) & 3, e2 = (e + 2) & 3;
+    const double c = orient2(q[e][0], q[e][1], q[e1][0], q[e1][1], q[e2][0], q[e2][1]);
+    pos += c > 0.0;
+    neg += c < 0.0;
+  }
+  return neg == 0 ? 1 : (pos == 0 ? -1 : 0);
+}
+
+// True if the pixel [u,u+1] x [v,v+1] lies (by more than a rounding margin)
+// outside one of the edge lines of the convex q of orientation o, so that
+// their overlap is empty: the largest value over the pixel of the edge's
+// signed distance function is its value at the centre plus (|dx| + |dy|)/2.
+__device__ __forceinline__ bool convex_misses(const double (&q)[4][2], int o, double u, double v) {
+  const double uc = u + 0.5, vc = v + 0.5;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int e1 = (e + 1) & 3;
+    const double dx = q[e1][0] - q[e][0], dy = q[e1][1] - q[e][1];
+    const double f = (double)o * (dx * (vc - q[e][1]) - dy * (uc - q[e][0]));
+    if (f + (0.5 + 1e-9) * (fabs(dx) + fabs(dy)) < 0.0) return true;
+  }
+  return false;
 }
 
 __device__ __forceinline__ int64_t pixel_of(const double (&p)[2], int32_t npix) {
@@ -158,13 +201,13 @@ __device__ __forceinline__ bool quad_bbox(const double (&q)[4][2], int32_t npix,
 // flushed to the map once per workgroup, so the many cells of a patch that
 // land in the same pixels (all of them, away from stars; those around a
 // star's caustic, near one) cost few global atomics.
-constexpr int kTable = 2048;
+constexpr int kTable = 1024;
 constexpr int kPatch = 64;  // a workgroup takes kPatch x kPatch cells
 
 __device__ __forceinline__ void table_add(int32_t *tkey, unsigned long long *tval,
                                           unsigned long long *__restrict__ acc, int32_t key,
                                           unsigned long long v) {
-  const uint32_t h = ((uint32_t)key * 2654435761u) >> 21;  // 11 bits
+  const uint32_t h = ((uint32_t)key * 2654435761u) >> 22;  // 10 bits
   for (int probe = 0; probe < 16; ++probe) {
     const int slot = (int)((h + (uint32_t)probe) & (kTable - 1));
     int32_t k = tkey[slot];
@@ -211,7 +254,9 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
   __shared__ int32_t tkey[kTable];
   __shared__ unsigned long long tval[kTable];
   __shared__ double sq[kThreads][8];  // wide cells of the batch: corners,
-  __shared__ double sarea[kThreads];   // area,
+  __shared__ double sk[kThreads][8];   // edge slopes (k, kinv),
+  __shared__ double sinv[kThreads];    // 1 / area,
+  __shared__ int32_t sorient[kThreads];  // orientation if convex, else 0,
   __shared__ int32_t sbox[kThreads][3];  // u0, v0, columns of the bounding box
   __shared__ int32_t sfirst[kThreads + 1];  // first pair index of each cell
   __shared__ int32_t wsum[kThreads / 64];
@@ -256,7 +301,15 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
             sq[t][2 * c] = q[c][0];
             sq[t][2 * c + 1] = q[c][1];
           }
-          sarea[t] = area;
+          double k[4], kinv[4];
+          edge_slopes(q, k, kinv);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            sk[t][e] = k[e];
+            sk[t][4 + e] = kinv[e];
+          }
+          sinv[t] = 1.0 / area;
+          sorient[t] = convex_orientation(q);
           sbox[t][0] = (int32_t)u0;
           sbox[t][1] = (int32_t)v0;
           sbox[t][2] = (int32_t)(u1 - u0 + 1);
@@ -284,10 +337,18 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
         cq[c][0] = sq[lo][2 * c];
         cq[c][1] = sq[lo][2 * c + 1];
       }
-      const double ov = quad_pixel_overlap(cq, (double)u, (double)v);
+      const int o = sorient[lo];
+      if (o != 0 && convex_misses(cq, o, (double)u, (double)v)) continue;
+      double k[4], kinv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        k[e] = sk[lo][e];
+        kinv[e] = sk[lo][4 + e];
+      }
+      const double ov = quad_pixel_overlap(cq, k, kinv, (double)u, (double)v);
       if (ov > 0.0)
         table_add(tkey, tval, a.acc, v * npix + u,
-                  (unsigned long long)llrint(a.cell_px * (ov / sarea[lo]) * kFix));
+                  (unsigned long long)llrint(a.cell_px * (ov * sinv[lo]) * kFix));
     }
     __syncthreads();  // the batch's shared cells are consumed
   }

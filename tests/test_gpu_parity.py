@@ -316,6 +316,24 @@ def test_fmm_map_equals_binned_deflect(lf, prec, p):
     np.testing.assert_array_equal(counts, c2)
 
 
+def test_fmm_map_fine_pixels_equals_binned_deflect(lf):
+    """Pixels much smaller than the ray spacing: nearly every ray of a work
+    unit lands in a pixel of its own, so the per-unit LDS pixel table fills
+    and most counts take its overflow path to the global map."""
+    f, g, mp = wl.small_disk()
+    npix = 4096
+    md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, npix)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    _say("fmm map fine pixels")
+    counts = host(lf.irs_map(xy, m, grid=lfgrid(g), map=md, kappa_s=f.kappa_s, gamma=f.gamma,
+                             precision="mixed", p=16))
+    y = host(lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma,
+                        precision="mixed", p=16))
+    mine, n_in = oracle.bin_rays(y, mp.y1min, mp.y2min, mp.side, npix)
+    assert n_in > 1000
+    np.testing.assert_array_equal(counts, mine)
+
+
 # -------------------------------------------------------- the N_*=1e6 field
 
 def test_powerlaw_disk_reduced(lf):
