@@ -321,34 +321,51 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
     sfirst[t] = first;
     if (t == kThreads - 1) sfirst[kThreads] = first + npairs;
     __syncthreads();
-    for (int32_t w = t; w < total; w += kThreads) {
-      // the cell holding pair w: the last with sfirst <= w (cells without
-      // pairs share their successor's start, so the last one is the owner)
+    // each thread takes a contiguous range of the batch's pairs, so its
+    // owner cell changes rarely: found once by search, then walked forward,
+    // with the cell's corners and slopes kept in registers meanwhile
+    const int32_t chunk = (total + kThreads - 1) / kThreads;
+    int32_t w = t * chunk;
+    const int32_t wend = min(total, w + chunk);
+    if (w < wend) {
       int lo = 0, hi = kThreads - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (sfirst[mid] <= w) lo = mid; else hi = mid - 1;
       }
-      const int32_t local = w - sfirst[lo];
-      const int32_t u = sbox[lo][0] + local % sbox[lo][2], v = sbox[lo][1] + local / sbox[lo][2];
-      double cq[4][2];
+      int cur = -1;
+      double cq[4][2], k[4], kinv[4], inv = 0.0;
+      int o = 0;
+      int32_t bu = 0, bv = 0, bw = 1;
+      for (; w < wend; ++w) {
+        // sfirst[lo] <= w < sfirst[lo + 1] (cells without pairs are skipped)
+        while (w >= sfirst[lo + 1]) ++lo;
+        if (lo != cur) {
+          cur = lo;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        cq[c][0] = sq[lo][2 * c];
-        cq[c][1] = sq[lo][2 * c + 1];
-      }
-      const int o = sorient[lo];
-      if (o != 0 && convex_misses(cq, o, (double)u, (double)v)) continue;
-      double k[4], kinv[4];
+          for (int c = 0; c < 4; ++c) {
+            cq[c][0] = sq[lo][2 * c];
+            cq[c][1] = sq[lo][2 * c + 1];
+          }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        k[e] = sk[lo][e];
-        kinv[e] = sk[lo][4 + e];
+          for (int e = 0; e < 4; ++e) {
+            k[e] = sk[lo][e];
+            kinv[e] = sk[lo][4 + e];
+          }
+          inv = sinv[lo];
+          o = sorient[lo];
+          bu = sbox[lo][0];
+          bv = sbox[lo][1];
+          bw = sbox[lo][2];
+        }
+        const int32_t local = w - sfirst[lo];
+        const int32_t u = bu + local % bw, v = bv + local / bw;
+        if (o != 0 && convex_misses(cq, o, (double)u, (double)v)) continue;
+        const double ov = quad_pixel_overlap(cq, k, kinv, (double)u, (double)v);
+        if (ov > 0.0)
+          table_add(tkey, tval, a.acc, v * npix + u,
+                    (unsigned long long)llrint(a.cell_px * (ov * inv) * kFix));
       }
-      const double ov = quad_pixel_overlap(cq, k, kinv, (double)u, (double)v);
-      if (ov > 0.0)
-        table_add(tkey, tval, a.acc, v * npix + u,
-                  (unsigned long long)llrint(a.cell_px * (ov * sinv[lo]) * kFix));
     }
     __syncthreads();  // the batch's shared cells are consumed
   }
