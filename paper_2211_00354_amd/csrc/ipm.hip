@@ -200,7 +200,10 @@ __device__ __forceinline__ bool quad_bbox(const double (&q)[4][2], int32_t npix,
 // Workgroup-local sums of pixel contributions: an LDS hash table of pixels,
 // flushed to the map once per workgroup, so the many cells of a patch that
 // land in the same pixels (all of them, away from stars; those around a
-// star's caustic, near one) cost few global atomics.
+// star's caustic, near one) cost few global atomics.  Two probes, then the
+// global map: patches near a star touch more pixels than the table holds,
+// and long probe chains there (a wave waits for its slowest lane) cost more
+// than the atomics they save.
 constexpr int kTable = 1024;
 constexpr int kPatch = 64;  // a workgroup takes kPatch x kPatch cells
 
@@ -208,7 +211,7 @@ __device__ __forceinline__ void table_add(int32_t *tkey, unsigned long long *tva
                                           unsigned long long *__restrict__ acc, int32_t key,
                                           unsigned long long v) {
   const uint32_t h = ((uint32_t)key * 2654435761u) >> 22;  // 10 bits
-  for (int probe = 0; probe < 16; ++probe) {
+  for (int probe = 0; probe < 2; ++probe) {
     const int slot = (int)((h + (uint32_t)probe) & (kTable - 1));
     int32_t k = tkey[slot];
     if (k == -1) {
