@@ -205,7 +205,7 @@ __device__ __forceinline__ bool quad_bbox(const double (&q)[4][2], int32_t npix,
 // and long probe chains there (a wave waits for its slowest lane) cost more
 // than the atomics they save.
 constexpr int kTable = 1024;
-constexpr int kPatch = 64;  // a workgroup takes kPatch x kPatch cells
+constexpr int kPatch = 32;  // a workgroup takes kPatch x kPatch cells
 
 __device__ __forceinline__ void table_add(int32_t *tkey, unsigned long long *tval,
                                           unsigned long long *__restrict__ acc, int32_t key,
