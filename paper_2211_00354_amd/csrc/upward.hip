@@ -1,10 +1,12 @@
 // Upward pass (Appendix A, upward passes 1 and 2): P2M forms the order-p
 // multipole of every leaf box from its sources (stars with real masses, or
 // rays with complex charges for the adjoint); M2M shifts the four children's
-// multipoles to their parent's centre, level by level toward the root.  The
-// two levels above the leaves are also formed straight from the stars (a
-// star then enters three expansions), which replaces the two largest M2M
-// sweeps with passes over the stars.  Everything runs in FP64.
+// multipoles to their parent's centre toward the root.  Levels whose boxes
+// hold a few sources on average, and the windowed fine levels, are formed
+// straight from the stars (a star then enters several expansions), which
+// replaces the largest M2M sweeps with passes over the stars; the coarser
+// dense levels come from M2M, up to four levels per launch.  Everything runs
+// in FP64.
 //
 // Coefficients are box-size rescaled: a~_k = sum_{i in box} m_i w_i^k,
 // w_i = (z_i - c)/s, stored box-major as [box][p] complex (re, im).
