@@ -59,28 +59,27 @@ __device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 
 // the line integral of clamp01(x) dy over the edge's part with 0 <= y <= 1.
 // On that part x(y) = lx + (y - ly) k is linear, so clamp01(x(y)) is linear
 // between the heights where x crosses 0 and 1 and the trapezoid rule on those
-// pieces is exact.  k = dx/dy and kinv = dy/dx (vertical: kinv unused) depend
+// pieces is exact.  k = dx/dy and kinv = dy/dx (0 for a vertical edge) depend
 // only on the edge's direction, not on the pixel.
 __device__ __forceinline__ double edge_term(double ax, double ay, double bx, double by, double k,
-                                            double kinv, bool vertical) {
+                                            double kinv) {
   if (ay == by) return 0.0;
   const bool up = by > ay;
   const double lx = up ? ax : bx, ly = up ? ay : by, hy = up ? by : ay;
   const double y0 = fmax(ly, 0.0), y1 = fmin(hy, 1.0);
   if (!(y0 < y1)) return 0.0;
-  double s0 = y1, s1 = y1;  // breakpoints strictly inside (y0, y1), else y1
-  if (!vertical) {
-    const double ya = ly + (0.0 - lx) * kinv, yb = ly + (1.0 - lx) * kinv;
-    const double lo = fmin(ya, yb), hi = fmax(ya, yb);
-    if (lo > y0 && lo < y1) s0 = lo;
-    if (hi > y0 && hi < y1) s1 = hi;
-    if (s0 == y1) s0 = s1, s1 = y1;
-  }
-  const double x0 = clamp01(lx + (y0 - ly) * k);
-  const double xa = clamp01(lx + (s0 - ly) * k);
-  const double xb = clamp01(lx + (s1 - ly) * k);
-  const double x1 = clamp01(lx + (y1 - ly) * k);
-  const double v = 0.5 * ((x0 + xa) * (s0 - y0) + (xa + xb) * (s1 - s0) + (xb + x1) * (y1 - s1));
+  // breakpoints (heights where x = 0 and x = 1); a vertical edge has kinv =
+  // 0, so both fall at ly <= y0 and are ignored, as they should be
+  const double ya = fma(-lx, kinv, ly), yb = ya + kinv;
+  const double lo = fmin(ya, yb), hi = fmax(ya, yb);
+  double s0 = (lo > y0 && lo < y1) ? lo : y1;
+  double s1 = (hi > y0 && hi < y1) ? hi : y1;
+  if (s0 == y1) s0 = s1, s1 = y1;
+  const double x0 = clamp01(fma(y0 - ly, k, lx));
+  const double xa = clamp01(fma(s0 - ly, k, lx));
+  const double xb = clamp01(fma(s1 - ly, k, lx));
+  const double x1 = clamp01(fma(y1 - ly, k, lx));
+  const double v = 0.5 * fma(x0 + xa, s0 - y0, fma(xa + xb, s1 - s0, (xb + x1) * (y1 - s1)));
   return up ? v : -v;
 }
 
@@ -95,8 +94,7 @@ __device__ double quad_pixel_overlap(const double (&q)[4][2], const double (&k)[
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int e1 = (e + 1) & 3;
-    const bool vertical = q[e1][0] == q[e][0];
-    s += edge_term(q[e][0] - u, q[e][1] - v, q[e1][0] - u, q[e1][1] - v, k[e], kinv[e], vertical);
+    s += edge_term(q[e][0] - u, q[e][1] - v, q[e1][0] - u, q[e1][1] - v, k[e], kinv[e]);
   }
   return fabs(s);
 }
