@@ -137,15 +137,14 @@ __global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window
 // the wave so that the lanes share the rows' sources evenly (lane t takes
 // sources t, t+64, ... of the concatenated rows), each lane accumulating all
 // p coefficients with running powers m w^k.  The 64 partial expansions are
-// then summed through LDS in lane order, so the result is deterministic.
+// then summed by a fixed cross-lane butterfly, so the result is
+// deterministic (and no LDS buffer limits the waves per CU).
 template <int PMAX, int QDIM>
 __global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Window win,
                                                     const double *__restrict__ sxy,
                                                     const double *__restrict__ sq,
                                                     const int32_t *__restrict__ leaf_start, int p,
                                                     double *__restrict__ mp, float *__restrict__ mp32) {
-  constexpr int STR = 2 * PMAX + 1;  // odd stride: the column sums hit distinct banks
-  __shared__ double part[kWave * STR];
   __shared__ int32_t row_first[kWave], row_pre[kWave];
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
@@ -200,20 +199,26 @@ __global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Windo
         }
     }
   }
-  __syncthreads();
+  // sum of the lanes' partial expansions by a fixed butterfly (the same
+  // order on every run), no LDS buffer
 #pragma unroll
   for (int k = 0; k < PMAX; ++k)
     if (k < p) {
-      part[lane * STR + 2 * k] = acc[k].re;
-      part[lane * STR + 2 * k + 1] = acc[k].im;
+      double re = acc[k].re, im = acc[k].im;
+#pragma unroll
+      for (int d = kWave / 2; d >= 1; d >>= 1) {
+        re += __shfl_xor(re, d);
+        im += __shfl_xor(im, d);
+      }
+      if (lane == 0) {
+        mp[b * 2 * p + 2 * k] = re;
+        mp[b * 2 * p + 2 * k + 1] = im;
+        if (mp32) {
+          mp32[b * 2 * p + 2 * k] = (float)re;
+          mp32[b * 2 * p + 2 * k + 1] = (float)im;
+        }
+      }
     }
-  __syncthreads();
-  if (lane < 2 * p) {
-    double t = 0.0;
-    for (int j = 0; j < kWave; ++j) t += part[j * STR + lane];
-    mp[b * 2 * p + lane] = t;
-    if (mp32) mp32[b * 2 * p + lane] = (float)t;
-  }
 }
 
 // M2M for up to four consecutive levels in one launch.  A 256-thread
