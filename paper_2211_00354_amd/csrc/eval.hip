@@ -354,23 +354,31 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
   }
 }
 
-// first ray column (row) of every box column (row) of the window
-__global__ __launch_bounds__(kThreads) void k_grid_ranges(double x0, double dx, int64_t lo_i,
-                                                          int64_t hi_i, double origin, double s,
-                                                          int64_t nL, int64_t b0, int64_t nb,
-                                                          int32_t *__restrict__ out) {
+// first ray column (row) of every box column (row) of the window: columns in
+// blockIdx.y = 0, rows in blockIdx.y = 1 (one launch)
+struct GridAxis {
+  double x0, dx;       // grid origin and step along the axis
+  int64_t lo_i, hi_i;  // ray index range searched
+  double origin;       // root square origin along the axis
+  int64_t b0, nb;      // first window box and window size along the axis
+  int32_t *out;        // [nb + 1]
+};
+
+__global__ __launch_bounds__(kThreads) void k_grid_ranges(GridAxis ax, GridAxis ay, double s,
+                                                          int64_t nL) {
+  const GridAxis &a = blockIdx.y == 0 ? ax : ay;
   const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (c > nb) return;
-  const int64_t B = b0 + c;
-  int64_t lo = lo_i, hi = hi_i;
+  if (c > a.nb) return;
+  const int64_t B = a.b0 + c;
+  int64_t lo = a.lo_i, hi = a.hi_i;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if (box_coord(grid_coord(x0, dx, mid), origin, s, nL) < B)
+    if (box_coord(grid_coord(a.x0, a.dx, mid), a.origin, s, nL) < B)
       lo = mid + 1;
     else
       hi = mid;
   }
-  out[c] = (int32_t)lo;
+  a.out[c] = (int32_t)lo;
 }
 
 __global__ __launch_bounds__(kThreads) void k_ray_keys(const double *__restrict__ rxy, int64_t n,
@@ -485,12 +493,11 @@ void launch_grid_ranges(const lens_grid &grid, Geometry g, Window win, int64_t j
                         hipStream_t stream) {
   const int64_t nL = int64_t(1) << g.L;
   const double s = ldexp(g.side, -g.L);
-  hipLaunchKernelGGL(k_grid_ranges, dim3((unsigned)((win.nbx + 1 + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, stream, grid.x0, grid.dx, (int64_t)0, grid.nx, g.x0, s, nL,
-                     win.bx0, win.nbx, col_start);
-  hipLaunchKernelGGL(k_grid_ranges, dim3((unsigned)((win.nby + 1 + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, stream, grid.y0, grid.dy, j_begin, j_end, g.y0, s, nL,
-                     win.by0, win.nby, row_start);
+  const GridAxis ax{grid.x0, grid.dx, 0, grid.nx, g.x0, win.bx0, win.nbx, col_start};
+  const GridAxis ay{grid.y0, grid.dy, j_begin, j_end, g.y0, win.by0, win.nby, row_start};
+  const int64_t nmax = std::max(win.nbx, win.nby) + 1;
+  hipLaunchKernelGGL(k_grid_ranges, dim3((unsigned)((nmax + kThreads - 1) / kThreads), 2),
+                     dim3(kThreads), 0, stream, ax, ay, s, nL);
   LENS_HIP(hipGetLastError());
 }
 

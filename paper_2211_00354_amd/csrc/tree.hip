@@ -208,21 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_tile_sums(const uint32_t *__r
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_sums(uint32_t *__restrict__ sums, size_t n) {
-  __shared__ uint32_t sh[kWaves];
-  uint32_t carry = 0;
-  for (size_t base = 0; base < n; base += kThreads) {
-    const size_t i = base + threadIdx.x;
-    const uint32_t x = (i < n) ? sums[i] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(x, sh, &tot);
-    if (i < n) sums[i] = carry + ex;
-    carry += tot;
-  }
-}
-
+// Scan of one tile; the tile's offset is the sum of the earlier tiles' sums
+// (read directly: tiles are few, so this replaces a separate scan of the sums).
 __global__ __launch_bounds__(kThreads) void k_scan_tiles(const uint32_t *__restrict__ in, size_t n,
-                                                         const uint32_t *__restrict__ offs,
+                                                         const uint32_t *__restrict__ sums,
                                                          uint32_t *__restrict__ out) {
   // thread t owns the kScanItems consecutive elements [t*items, (t+1)*items)
   __shared__ uint32_t tile[kScanTile];
@@ -240,9 +229,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_tiles(const uint32_t *__restr
     loc[j] = s;
     s += tile[threadIdx.x * kScanItems + j];
   }
+  uint32_t before = 0;
+  for (unsigned i = threadIdx.x; i < blockIdx.x; i += kThreads) before += sums[i];
+  uint32_t tile_off;
+  (void)block_excl_scan(before, sh, &tile_off);
   uint32_t tot;
   const uint32_t ex = block_excl_scan(s, sh, &tot);
-  const uint32_t off = offs[blockIdx.x] + ex;
+  const uint32_t off = tile_off + ex;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) tile[threadIdx.x * kScanItems + j] = off + loc[j];
   __syncthreads();
@@ -467,7 +460,6 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *t
   if (n == 0) return;
   const size_t nb = (n + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(kThreads), 0, stream, in, n, tmp);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kThreads), 0, stream, tmp, nb);
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kThreads), 0, stream, in, n, tmp, out);
   LENS_HIP(hipGetLastError());
 }
