@@ -127,14 +127,25 @@ int64_t box_coord_host(double x, double origin, double s, int64_t nbox) {
   return (int64_t)std::floor(t);
 }
 
+// Pinned host landing buffer for the bounding-box read-back (one per host
+// thread, kept for the process): a direct DMA, no staging through pageable
+// memory on the one wait of a plan-less call.
+double *bbox_landing() {
+  thread_local double *buf = nullptr;
+  if (!buf) LENS_HIP(hipHostMalloc(reinterpret_cast<void **>(&buf), 4 * sizeof(double), hipHostMallocDefault));
+  return buf;
+}
+
 void device_bbox(const double *xy, int64_t n, hipStream_t st, double out[4]) {
   Scratch sc(st);
   const int parts = bbox_parts(n);
   double *partial = sc.get<double>((size_t)parts * 4);
   double *o4 = sc.get<double>(4);
   launch_bbox(xy, n, partial, parts, o4, st);
-  LENS_HIP(hipMemcpyAsync(out, o4, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  double *landing = bbox_landing();
+  LENS_HIP(hipMemcpyAsync(landing, o4, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
   LENS_HIP(hipStreamSynchronize(st));
+  std::copy(landing, landing + 4, out);
   for (int c = 0; c < 4; ++c)
     if (!is_finite(out[c])) fail(LENS_EINVAL, "non-finite coordinates in the input positions");
 }
