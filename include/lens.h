@@ -192,16 +192,20 @@ typedef struct {
  * rays of `grid` are deflected (as lens_deflect, by FMM or direct sum) and
  * taken as the corners of the (nx-1) x (ny-1) image-plane cells of area
  * dx*dy between adjacent rays.  Each cell maps to a quadrilateral in the
- * source plane whose area is shared among the pixels it overlaps in
- * proportion to the overlap areas, so map->mu receives the magnification
- * (sum of image areas over pixel area).  A cell whose quadrilateral folds
- * (its edges cross: the cell straddles a critical curve), has zero area or
- * whose bounding box covers more than 64 map pixels (a cell next to a star)
- * gives a quarter of its area to the pixel of each corner.  Contributions are summed in fixed point (2^-40 of a pixel's
+ * source plane whose area is shared exactly among the pixels it overlaps,
+ * in proportion to the overlap areas (Green's theorem), however many pixels
+ * that is, so map->mu receives the magnification (sum of image areas over
+ * pixel area).  A cell that straddles a critical curve maps to a
+ * quadrilateral whose edges cross; it is treated as if it were not critical
+ * (Section 2.3): the region its edges enclose, the two triangles either side
+ * of the crossing, takes the cell's area by overlap.  Only a cell whose image
+ * has zero area gives a quarter of its area to the pixel of each corner.
+ * Contributions are summed in fixed point (2^-40 of a pixel's
  * magnification), so the map does not depend on summation order.  Rays are
  * processed in chunks of whole rows of at most opts->max_rays_per_chunk rays
- * (default: one pass); the deflected corners need nx*ny*16 bytes of scratch
- * per pass.  `plan` may be NULL as in lens_deflect.
+ * (default: one pass); a pass needs nx*ny*16 bytes of scratch for the
+ * deflected corners plus 4 bytes per cell, and the map 16 bytes per pixel.
+ * `plan` may be NULL as in lens_deflect.
  */
 LENS_API lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_grid *grid,
                                   const lens_ipm_desc *map, const lens_opts *opts, void *stream);
@@ -212,8 +216,9 @@ LENS_API lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, cons
  * tree depth to the user; here they are measured).  A strided sample of at
  * most 128 x 128 rays of `grid` is deflected by the FP64 direct sum and by
  * the FMM at p = 6, 7, ... (a plan over the whole grid, as lens_deflect and
- * lens_map build it).  The error is the relative l2 norm of the deflection
- * error over that of alpha when map is NULL, else the expected fraction of
+ * lens_map build it).  The error is the largest per-ray relative deflection
+ * error |dalpha_k| / max(|alpha_k|, 1e-3 rms alpha) over the sample when
+ * map is NULL, else the expected fraction of
  * rays binned into another pixel of `map`, mean(|dy1| + |dy2|) npix / side
  * (map->counts is not touched).  Of the settings that reach `tol` the one
  * with the fastest whole lens_deflect (or lens_map) call is kept, and the

@@ -62,7 +62,7 @@ def _load():
         lib.oracle_grad.restype = ctypes.c_int
         lib.oracle_ipm.argtypes = [ctypes.c_int64, ctypes.c_int64, _dp, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_int32, ctypes.c_int64, _dp]
+                                   ctypes.c_int32, _dp]
         lib.oracle_ipm.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ctypes.c_int
@@ -135,12 +135,12 @@ def bin_rays(y, y1min, y2min, side, npix, counts=None):
     return counts, int(landed)
 
 
-def ipm(y_grid, cell_area, y1min, y2min, side, npix, mu=None, max_pixels=64):
-    """IPM magnification map (first order; see lens_oracle.c) of the cells
-    spanned by the mapped grid y_grid [ny, nx, 2]; returns mu [npix, npix]
-    float64 indexed [v, u] (accumulated into ``mu`` if given).  Cells whose
-    bounding box covers more than ``max_pixels`` map pixels go to their
-    corners' pixels."""
+def ipm(y_grid, cell_area, y1min, y2min, side, npix, mu=None):
+    """IPM magnification map (first order, Section 2.3; see lens_oracle.c) of
+    the cells spanned by the mapped grid y_grid [ny, nx, 2]; returns mu
+    [npix, npix] float64 indexed [v, u] (accumulated into ``mu`` if given).
+    Every cell's area is apportioned exactly among the pixels its image
+    covers; a folded cell's image is its two lobes."""
     lib = _load()
     yy = np.ascontiguousarray(np.asarray(y_grid, dtype=np.float64))
     if yy.ndim != 3 or yy.shape[2] != 2:
@@ -150,8 +150,7 @@ def ipm(y_grid, cell_area, y1min, y2min, side, npix, mu=None, max_pixels=64):
     if mu.dtype != np.float64 or not mu.flags.c_contiguous or mu.shape != (npix, npix):
         raise ValueError("mu must be a C-contiguous float64 [npix, npix] array")
     rc = lib.oracle_ipm(yy.shape[1], yy.shape[0], _ptr(yy), float(cell_area), float(y1min),
-                        float(y2min), float(side), int(npix), int(max_pixels),
-                        mu.ctypes.data_as(_dp))
+                        float(y2min), float(side), int(npix), mu.ctypes.data_as(_dp))
     if rc != 0:
         raise ValueError("oracle_ipm rejected its arguments")
     return mu

@@ -38,17 +38,23 @@
  *  - oracle_ipm: inverse polygon mapping (Section 2.3, first order as used in
  *    Section 2.4).  Adjacent grid rays are the corners of image-plane cells
  *    of area dx dy; cell (i, j) with corners y(i,j), y(i+1,j), y(i+1,j+1),
- *    y(i,j+1) maps to a quadrilateral Q in the source plane and its area is
- *    shared among the pixels Q overlaps in proportion to the overlap areas:
- *    pixel P receives dx dy |Q n P| / |Q|, and mu[P] accumulates that over
- *    the pixel area, so mu is the magnification sum S_i / S_pixel of the
- *    paper.  A quadrilateral whose edges cross (the cell straddles a critical
- *    curve), whose area is zero, or whose bounding box covers more than
- *    max_pixels pixels of the map (a cell next to a star, stretched over much
- *    of the map) is treated at zeroth order: each corner carries a quarter of
- *    the cell's area to the pixel it falls in (the IRS rule).  Overlaps are found by clipping Q against each pixel square of
- *    its bounding box (Sutherland-Hodgman) and measuring the clipped polygon
- *    by the shoelace formula, in pixel units (p = (y - ymin) S).
+ *    y(i,j+1) maps to a quadrilateral Q in the source plane and, by Green's
+ *    theorem, its area is shared exactly among the pixels Q overlaps in
+ *    proportion to the overlap areas: pixel P receives dx dy |Q n P| / |Q|,
+ *    and mu[P] accumulates that over the pixel area, so mu is the
+ *    magnification sum S_i / S_pixel of the paper.  However far Q stretches,
+ *    every pixel it covers is apportioned exactly.  A critical cell (one that
+ *    straddles a critical curve) maps to a quadrilateral whose edges cross;
+ *    Section 2.3 treats such cells naively, as if they were not critical: the
+ *    region the quadrilateral's edges enclose -- the two triangles ("lobes")
+ *    on either side of the crossing point -- takes the cell's area in
+ *    proportion to overlap, |Q n P| = |T1 n P| + |T2 n P| and
+ *    |Q| = |T1| + |T2|.  Only a cell whose image has zero area carries no
+ *    shape: each corner then takes a quarter of its area to the pixel it
+ *    falls in (the zeroth-order, inverse-ray-shooting rule).  Overlaps are
+ *    found by clipping each polygon against each pixel square of the cell's
+ *    bounding box (Sutherland-Hodgman) and measuring the clipped polygon by
+ *    the shoelace formula, in pixel units (p = (y - ymin) S).
  *
  *  - oracle_grad: the gradient of a scalar loss L(y) with respect to the star
  *    positions and masses, given G_k = dL/dy_k, from differentiating eq. (1):
@@ -252,12 +258,16 @@ static int segments_cross(const double *a, const double *b, const double *c, con
   return ((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) && ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0));
 }
 
-/* shoelace area (signed) of an n-gon */
+/* shoelace area (signed) of an n-gon, on coordinates relative to its first
+ * vertex (translation-invariant, so a small polygon far from the origin
+ * keeps its digits) */
 static double poly_area(int n, const double (*p)[2]) {
   double s = 0.0;
   for (int k = 0; k < n; ++k) {
     const int k1 = (k + 1) % n;
-    s += p[k][0] * p[k1][1] - p[k1][0] * p[k][1];
+    const double x0 = p[k][0] - p[0][0], y0 = p[k][1] - p[0][1];
+    const double x1 = p[k1][0] - p[0][0], y1 = p[k1][1] - p[0][1];
+    s += x0 * y1 - x1 * y0;
   }
   return 0.5 * s;
 }
@@ -285,20 +295,6 @@ static int clip_half(int n, const double (*in)[2], double (*out)[2], int c, doub
   return m;
 }
 
-/* area of polygon q[4] (pixel units) inside the unit square [u,u+1]x[v,v+1] */
-static double quad_pixel_overlap(const double (*q)[2], double u, double v) {
-  double a[16][2], b[16][2];
-  int n = 4;
-  for (int k = 0; k < 4; ++k) {
-    a[k][0] = q[k][0] - u;
-    a[k][1] = q[k][1] - v;
-  }
-  n = clip_half(n, (const double (*)[2])a, b, 0, 0.0, 1);
-  n = clip_half(n, (const double (*)[2])b, a, 0, 1.0, 0);
-  n = clip_half(n, (const double (*)[2])a, b, 1, 0.0, 1);
-  n = clip_half(n, (const double (*)[2])b, a, 1, 1.0, 0);
-  return n >= 3 ? fabs(poly_area(n, (const double (*)[2])a)) : 0.0;
-}
 
 static void add_corner(double *mu, int32_t npix, const double *p, double w) {
   if (!(p[0] >= 0.0) || !(p[1] >= 0.0)) return;
@@ -307,16 +303,29 @@ static void add_corner(double *mu, int32_t npix, const double *p, double w) {
   mu[(int64_t)f2 * npix + (int64_t)f1] += w;
 }
 
+/* area of polygon p[n] (pixel units) inside the unit square [u,u+1]x[v,v+1] */
+static double poly_pixel_overlap(int n0, const double (*p)[2], double u, double v) {
+  double a[16][2], b[16][2];
+  int n = n0;
+  for (int k = 0; k < n0; ++k) {
+    a[k][0] = p[k][0] - u;
+    a[k][1] = p[k][1] - v;
+  }
+  n = clip_half(n, (const double (*)[2])a, b, 0, 0.0, 1);
+  n = clip_half(n, (const double (*)[2])b, a, 0, 1.0, 0);
+  n = clip_half(n, (const double (*)[2])a, b, 1, 0.0, 1);
+  n = clip_half(n, (const double (*)[2])b, a, 1, 1.0, 0);
+  return n >= 3 ? fabs(poly_area(n, (const double (*)[2])a)) : 0.0;
+}
+
 /*
  * IPM magnification of the (nx-1) x (ny-1) cells spanned by the mapped grid
  * y[ny][nx][2] (row-major, y[(j*nx + i)*2 + c]), accumulated into
- * mu[v*npix + u] (+=).  cell_area = dx * dy; max_pixels >= 1 caps the
- * pixels a cell is apportioned over exactly.  Returns 0 or -1.
+ * mu[v*npix + u] (+=).  cell_area = dx * dy.  Returns 0 or -1.
  */
 int oracle_ipm(int64_t nx, int64_t ny, const double *y, double cell_area, double y1min,
-               double y2min, double side, int32_t npix, int64_t max_pixels, double *mu) {
-  if (nx < 0 || ny < 0 || npix <= 0 || !(side > 0.0) || !(cell_area >= 0.0) || max_pixels < 1)
-    return -1;
+               double y2min, double side, int32_t npix, double *mu) {
+  if (nx < 0 || ny < 0 || npix <= 0 || !(side > 0.0) || !(cell_area >= 0.0)) return -1;
   const double S = (double)npix / side;
   const double cell_px = cell_area * S * S; /* cell area in pixel units */
   for (int64_t j = 0; j + 1 < ny; ++j)
@@ -330,8 +339,42 @@ int oracle_ipm(int64_t nx, int64_t ny, const double *y, double cell_area, double
         finite &= isfinite(q[k][0]) && isfinite(q[k][1]);
       }
       if (!finite) continue;
-      const double area = fabs(poly_area(4, (const double (*)[2])q));
-      const int folded = segments_cross(q[0], q[1], q[2], q[3]) || segments_cross(q[1], q[2], q[3], q[0]);
+      /* the polygons that carry the cell's area: Q itself, or, if two
+       * opposite edges a-b and c-d cross at X, the lobes (X, b, c) and
+       * (a, X, d) */
+      double poly[2][4][2];
+      int nv[2] = {4, 0}, npoly = 1;
+      double area;
+      const int c01 = segments_cross(q[0], q[1], q[2], q[3]);
+      const int c12 = !c01 && segments_cross(q[1], q[2], q[3], q[0]);
+      if (c01 || c12) {
+        const double *a = c01 ? q[0] : q[1], *b = c01 ? q[1] : q[2];
+        const double *c = c01 ? q[2] : q[3], *d = c01 ? q[3] : q[0];
+        const double den = (b[0] - a[0]) * (d[1] - c[1]) - (b[1] - a[1]) * (d[0] - c[0]);
+        const double t = ((c[0] - a[0]) * (d[1] - c[1]) - (c[1] - a[1]) * (d[0] - c[0])) / den;
+        const double X[2] = {a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1])};
+        const double *t1[3] = {X, b, c}, *t2[3] = {a, X, d};
+        for (int k = 0; k < 3; ++k) {
+          poly[0][k][0] = t1[k][0];
+          poly[0][k][1] = t1[k][1];
+          poly[1][k][0] = t2[k][0];
+          poly[1][k][1] = t2[k][1];
+        }
+        nv[0] = nv[1] = 3;
+        npoly = 2;
+        area = fabs(poly_area(3, (const double (*)[2])poly[0])) +
+               fabs(poly_area(3, (const double (*)[2])poly[1]));
+      } else {
+        for (int k = 0; k < 4; ++k) {
+          poly[0][k][0] = q[k][0];
+          poly[0][k][1] = q[k][1];
+        }
+        area = fabs(poly_area(4, (const double (*)[2])q));
+      }
+      if (!(area > 0.0)) {
+        for (int k = 0; k < 4; ++k) add_corner(mu, npix, q[k], 0.25 * cell_px);
+        continue;
+      }
       double lo0 = q[0][0], hi0 = q[0][0], lo1 = q[0][1], hi1 = q[0][1];
       for (int k = 1; k < 4; ++k) {
         lo0 = fmin(lo0, q[k][0]);
@@ -339,16 +382,11 @@ int oracle_ipm(int64_t nx, int64_t ny, const double *y, double cell_area, double
         lo1 = fmin(lo1, q[k][1]);
         hi1 = fmax(hi1, q[k][1]);
       }
-      const int outside = hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix;
+      if (hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix) continue;
       const int64_t u0 = lo0 < 0.0 ? 0 : (int64_t)floor(lo0);
       const int64_t v0 = lo1 < 0.0 ? 0 : (int64_t)floor(lo1);
       const int64_t u1 = hi0 >= (double)npix ? npix - 1 : (int64_t)floor(hi0);
       const int64_t v1 = hi1 >= (double)npix ? npix - 1 : (int64_t)floor(hi1);
-      if (folded || !(area > 0.0) || (!outside && (u1 - u0 + 1) * (v1 - v0 + 1) > max_pixels)) {
-        for (int k = 0; k < 4; ++k) add_corner(mu, npix, q[k], 0.25 * cell_px);
-        continue;
-      }
-      if (outside) continue;
       if (u0 == u1 && v0 == v1 && lo0 >= 0.0 && lo1 >= 0.0 && hi0 < (double)npix &&
           hi1 < (double)npix) {
         /* wholly inside one pixel: the whole cell (exactly; a ratio of two
@@ -358,7 +396,9 @@ int oracle_ipm(int64_t nx, int64_t ny, const double *y, double cell_area, double
       }
       for (int64_t v = v0; v <= v1; ++v)
         for (int64_t u = u0; u <= u1; ++u) {
-          const double ov = quad_pixel_overlap((const double (*)[2])q, (double)u, (double)v);
+          double ov = 0.0;
+          for (int k = 0; k < npoly; ++k)
+            ov += poly_pixel_overlap(nv[k], (const double (*)[2])poly[k], (double)u, (double)v);
           if (ov > 0.0) mu[v * npix + u] += cell_px * (ov / area);
         }
     }

@@ -68,10 +68,6 @@ namespace {
 // Section 2.4, are kept as an option; a map needs no per-ray memory)
 constexpr int64_t kDefaultChunk = std::numeric_limits<int64_t>::max();
 constexpr int kDefaultFp32Levels = 2;
-// IPM: a cell whose quadrilateral's bounding box covers more map pixels than
-// this is apportioned to its corners (cells next to a star stretch over much
-// of the map; exact clipping there costs far more than the area they carry)
-constexpr int32_t kIpmMaxPixels = 64;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -764,8 +760,9 @@ namespace {
 // Accuracy is measured, not modelled: a strided sample of at most 128 x 128
 // rays of the grid is deflected by the FP64 direct sum and by the FMM (a
 // plan over the whole grid, as a real call builds it) at increasing p.  The
-// error is the relative l2 of alpha, or for a map the expected fraction of
-// rays binned into another pixel, mean(|dy1| + |dy2|) * npix / side.  Among
+// error is the largest per-ray relative deflection error, or for a map the
+// expected fraction of rays binned into another pixel,
+// mean(|dy1| + |dy2|) * npix / side.  Among
 // the settings that reach the target the fastest whole call is kept.
 
 struct TuneOut {
@@ -789,15 +786,25 @@ double tune_error(const TuneSample &ts, const std::vector<double> &y, double c1,
       acc += std::fabs(y[2 * k] - ts.yref[2 * k]) + std::fabs(y[2 * k + 1] - ts.yref[2 * k + 1]);
     return acc / (double)std::max<int64_t>(ts.n, 1) * (double)map->npix / map->side;
   }
-  double num = 0, den = 0;
+  // deflection: the largest per-ray relative error |dalpha_k| /
+  // max(|alpha_k|, 1e-3 rms alpha) over the sample
+  double ms = 0;
+  for (int64_t k = 0; k < ts.n; ++k) {
+    const double a1 = c1 * ts.rays[2 * k] - ts.yref[2 * k];
+    const double a2 = c2 * ts.rays[2 * k + 1] - ts.yref[2 * k + 1];
+    ms += a1 * a1 + a2 * a2;
+  }
+  const double floor_a = 1e-3 * std::sqrt(ms / (double)std::max<int64_t>(ts.n, 1));
+  double worst = 0;
   for (int64_t k = 0; k < ts.n; ++k) {
     const double d1 = y[2 * k] - ts.yref[2 * k], d2 = y[2 * k + 1] - ts.yref[2 * k + 1];
     const double a1 = c1 * ts.rays[2 * k] - ts.yref[2 * k];
     const double a2 = c2 * ts.rays[2 * k + 1] - ts.yref[2 * k + 1];
-    num += d1 * d1 + d2 * d2;
-    den += a1 * a1 + a2 * a2;
+    const double den = std::max(std::hypot(a1, a2), floor_a);
+    const double d = std::hypot(d1, d2);
+    worst = std::max(worst, den > 0 ? d / den : d);
   }
-  return den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+  return worst;
 }
 
 // Time of one whole call (lens_map into a scratch map, or lens_deflect into
@@ -1544,8 +1551,13 @@ lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_gr
     const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(ny - 1, o.max_rays_per_chunk / nx - 1));
     Scratch sc(st);
     const int64_t npx = (int64_t)map->npix * map->npix;
+    const int64_t ndiff = (int64_t)map->npix * (map->npix + 1);
     auto *acc = sc.get<unsigned long long>((size_t)npx);
+    auto *diff = sc.get<unsigned long long>((size_t)ndiff);
     launch_ipm_zero(acc, npx, st);
+    launch_ipm_zero(diff, ndiff, st);
+    auto *queue = sc.get<uint32_t>((size_t)rows * (nx - 1));
+    auto *qcount = sc.get<uint32_t>(1);
     double *ybuf = sc.get<double>((size_t)(rows + 1) * nx * 2);
     lens_plan *P = plan;
     lens_plan *owned = nullptr;
@@ -1581,11 +1593,12 @@ lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_gr
           fmm_grid_rows(*P, *grid, j0, j1 + 1, c1, c2, y_out, nullptr, 0.0, st);
         }
         StageTimer tm("ipm", st);
-        launch_ipm_cells(ybuf, nx, j0, j0, j1, cell_px, map->y1min, map->y2min, S, map->npix,
-                         kIpmMaxPixels, acc, st);
+        const IpmPass pass{ybuf, nx, j0, j0, j1, cell_px, map->y1min, map->y2min, S, map->npix,
+                           acc, diff, queue, qcount};
+        launch_ipm_cells(pass, st);
       }
       StageTimer tm("ipm", st);
-      launch_ipm_finish(acc, npx, map->mu, st);
+      launch_ipm_finish(acc, diff, map->npix, map->mu, st);
     } catch (...) {
       if (owned) lens_plan_destroy(owned);
       throw;

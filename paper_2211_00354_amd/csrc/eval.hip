@@ -30,25 +30,25 @@ constexpr int kXcd = 8;
 constexpr int kThreads = 256;  // helper kernels
 
 
-// One star against the R rays of a lane.  LENS_MIXED: coordinates relative
-// to the evaluation box's centre, formed in FP64 and rounded to FP32 (a ray's
-// once per pass, a star's once per pass for all the lane's rays), so the
-// pair arithmetic is FP32 throughout; FP64: absolute coordinates.  A
-// coincident pair (dx = dy = 0) contributes exactly zero: the tiny term
-// keeps its weight finite (for any |m| below ~1e18 in FP32, ~1e108 in FP64)
-// and it multiplies dx = dy = 0, so no branch or select is needed.  In FP32 a
-// pair closer than about one ulp of the box size (~1e-7 of it) rounds to
-// coincident and is skipped the same way.
-template <bool MIXED, int R, typename C, typename A>
-__device__ __forceinline__ void pair_update(const C (&rx)[R], const C (&ry)[R], C sx, C sy,
-                                            double mm, A (&ax)[R], A (&ay)[R]) {
+// One star against the R rays of a lane.  The pair difference x - x_i is
+// formed in FP64 from absolute coordinates (the star's are wave-uniform
+// scalars), so it is exact to ~1e-16 of the coordinates however close the
+// pair; LENS_MIXED rounds it once to FP32 and does the rest of the pair
+// arithmetic in FP32, so every pair carries only a few FP32 roundings
+// relative to its own size.  A coincident pair (dx = dy = 0) contributes
+// exactly zero: the tiny term keeps its weight finite (for |m| below ~1e8 in
+// FP32, ~1e108 in FP64) and it multiplies dx = dy = 0, so no branch or
+// select is needed; it changes no pair farther apart than ~1e-13 (FP32).
+template <bool MIXED, int R, typename A>
+__device__ __forceinline__ void pair_update(const double (&rx)[R], const double (&ry)[R], double sx,
+                                            double sy, double mm, A (&ax)[R], A (&ay)[R]) {
   if constexpr (MIXED) {
     const float m = (float)mm;
-    constexpr float tiny = 0x1p-66f;
+    constexpr float tiny = 0x1p-100f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const float dx = rx[r] - sx;
-      const float dy = ry[r] - sy;
+      const float dx = (float)(rx[r] - sx);
+      const float dy = (float)(ry[r] - sy);
       const float r2 = fmaf(dx, dx, fmaf(dy, dy, tiny));
       const float w = m * rcp_f32(r2);
       ax[r] = fmaf(w, dx, ax[r]);
@@ -191,10 +191,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     }
     const double cx = a.g.x0 + ((double)gx + 0.5) * s;
     const double cy = a.g.y0 + ((double)gy + 0.5) * s;
-    // grid: offsets of the box's first ray column / row from the centre
-    const double ox0 = GRID ? grid_coord(a.grid.x0, a.grid.dx, i0) - cx : 0.0;
-    const double oy0 = GRID ? grid_coord(a.grid.y0, a.grid.dy, j0) - cy : 0.0;
-    const double c1cx = a.c1 * cx, c2cy = a.c2 * cy;
     __syncthreads();  // the previous unit's reads of lds_loc are done
     if (lane < p) lds_loc[lane] = reinterpret_cast<const double2 *>(loc + 2 * (int64_t)b * p)[lane];
     __syncthreads();
@@ -217,23 +213,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
       acc_t ax[R], ay[R];
       int64_t oidx[R];
       bool act[R];
-      // grid rays: position of slot r's ray; recomputed after the pair loop
-      // rather than kept live through it (fewer registers)
-      auto grid_ray = [&](int r, int lxx, int lyy, double &x, double &y, int64_t &o) {
-        const int32_t t = pos + r;  // wave-uniform tile index
-        const int32_t ty = t / TW, tx = t - ty * TW;
-        const int32_t ci = tx * TX + lxx, cj = ty * TY + lyy;
-        const bool on = t < pend && ci < W && cj < H;
-        const int64_t i = i0 + (on ? ci : 0), j = j0 + (on ? cj : 0);
-        x = grid_coord(a.grid.x0, a.grid.dx, i);
-        y = grid_coord(a.grid.y0, a.grid.dy, j);
-        o = j * a.grid.nx + i;
-        return on;
-      };
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (GRID) {
-          act[r] = grid_ray(r, lx, ly, rx[r], ry[r], oidx[r]);
+          // slot r's ray (an inactive slot takes the box's first ray); its
+          // output index is formed after the pair loop
+          const int32_t t = pos + r;  // wave-uniform tile index
+          const int32_t ty = t / TW, tx = t - ty * TW;
+          const int32_t ci = tx * TX + lx, cj = ty * TY + ly;
+          const bool on = t < pend && ci < W && cj < H;
+          rx[r] = grid_coord(a.grid.x0, a.grid.dx, i0 + (on ? ci : 0));
+          ry[r] = grid_coord(a.grid.y0, a.grid.dy, j0 + (on ? cj : 0));
         } else {
           const int32_t idx = pos + r * kWave + lane;
           act[r] = idx < min(nr, pos + RPC);
@@ -246,18 +236,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         ay[r] = 0;
       }
 
-      // pair coordinates (see pair_update)
-      using crd_t = typename std::conditional<MIXED, float, double>::type;
-      crd_t qx[R], qy[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        qx[r] = MIXED ? (crd_t)(rx[r] - cx) : (crd_t)rx[r];
-        qy[r] = MIXED ? (crd_t)(ry[r] - cy) : (crd_t)ry[r];
-      }
       auto star = [&](double x, double y, double mass) {
-        const crd_t sx = MIXED ? (crd_t)(x - cx) : (crd_t)x;
-        const crd_t sy = MIXED ? (crd_t)(y - cy) : (crd_t)y;
-        pair_update<MIXED, R>(qx, qy, sx, sy, mass, ax, ay);
+        pair_update<MIXED, R>(rx, ry, x, y, mass, ax, ay);
       };
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -277,30 +257,24 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         for (; i < re[d]; ++i) star(sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i]);
       }
 
-      // ray offsets from the box centre (FP64).  Grid rays: recomputed here
-      // from the lane's tile position (opaque to the optimiser, so that
-      // nothing of the rays is carried through the pair loop) as the first
-      // ray column's offset plus whole cells, one rounding each
+      // ray offsets from the box centre (FP64) for the far field; grid rays'
+      // output indices and activity recomputed from the lane's tile position
+      // (integers) rather than kept live through the pair loop
       double dxr[R], dyr[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        dxr[r] = rx[r] - cx;
+        dyr[r] = ry[r] - cy;
+      }
       if (GRID) {
-        int lx2 = lx, ly2 = ly;
-        asm volatile("" : "+v"(lx2), "+v"(ly2));
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int32_t t = pos + r;
           const int32_t ty = t / TW, tx = t - ty * TW;
-          const int32_t ci = tx * TX + lx2, cj = ty * TY + ly2;
+          const int32_t ci = tx * TX + lx, cj = ty * TY + ly;
           act[r] = t < pend && ci < W && cj < H;
           const int32_t cc = act[r] ? ci : 0, rr = act[r] ? cj : 0;
-          dxr[r] = fma((double)cc, a.grid.dx, ox0);
-          dyr[r] = fma((double)rr, a.grid.dy, oy0);
           oidx[r] = (int64_t)(j0 + rr) * a.grid.nx + (i0 + cc);
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          dxr[r] = rx[r] - cx;
-          dyr[r] = ry[r] - cy;
         }
       }
       // far field: Horner over the R rays from the top coefficient down, one
@@ -328,9 +302,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
       for (int r = 0; r < R; ++r) {
         const double al1 = f[r].re + (double)ax[r];
         const double al2 = (double)ay[r] - f[r].im;
-        // grid: c x = c cx + c (x - cx)
-        const double y1 = GRID ? fma(a.c1, dxr[r], c1cx) - al1 : a.c1 * rx[r] - al1;
-        const double y2 = GRID ? fma(a.c2, dyr[r], c2cy) - al2 : a.c2 * ry[r] - al2;
+        const double y1 = a.c1 * rx[r] - al1;
+        const double y2 = a.c2 * ry[r] - al2;
         if (MAP) {
           key[r] = -1;
           const double t1 = (y1 - a.y1min) * a.S;

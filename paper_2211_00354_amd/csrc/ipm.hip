@@ -1,24 +1,35 @@
 // Inverse polygon mapping (Section 2.3; first order, as used in Section 2.4).
 // Adjacent grid rays are the corners of image-plane cells of area dx dy; cell
 // (i, j) with corners y(i,j), y(i+1,j), y(i+1,j+1), y(i,j+1) maps to a
-// quadrilateral Q in the source plane, and its area is shared among the
-// pixels Q overlaps in proportion to the overlap areas: pixel P receives
+// quadrilateral Q in the source plane, and its area is shared exactly among
+// the pixels Q overlaps in proportion to the overlap areas: pixel P receives
 // dx dy |Q n P| / |Q|; divided by the pixel area that is the magnification
-// sum S_i / S_pixel.  A quadrilateral whose edges cross (a cell on a critical
-// curve), whose area is zero or whose bounding box covers more than
-// max_pixels map pixels goes to its corners: a quarter of the cell to each
-// corner's pixel (the zeroth-order, inverse-ray-shooting rule).
+// sum S_i / S_pixel.  A critical cell (its image's edges cross: the cell
+// straddles a critical curve) is treated as if it were not critical: the
+// region its edges enclose, the two triangles ("lobes") either side of the
+// crossing point, takes the cell's area by overlap.  Only an image of zero
+// area goes to its corners, a quarter of the cell to each corner's pixel
+// (the zeroth-order, inverse-ray-shooting rule).
 //
 // Geometry in pixel units p = (y - ymin) S, S = npix/side.  Overlaps come
-// from Green's theorem as a sum of four edge terms (see quad_pixel_overlap),
-// which needs no per-thread polygon storage.  Contributions are summed as fixed-point
-// integers (units of 2^-40 of a pixel's magnification) with 64-bit atomics,
-// so the map does not depend on the order of the additions; a final pass adds
-// them to the caller's FP64 map.  One thread per cell; a cell inside one
-// pixel (the common case) adds the whole cell; sums go through an LDS table
-// of pixels per workgroup (one global atomic per distinct pixel).  For a
-// convex quadrilateral, pixels of its bounding box that lie outside one of
-// its edge lines are skipped before the overlap sum.
+// from Green's theorem as a sum of edge terms (see poly_pixel_overlap), which
+// needs no clipped polygon.  Contributions are summed as fixed-point integers
+// (units of 2^-40 of a pixel's magnification) with 64-bit atomics, so the map
+// does not depend on the order of the additions; a final pass adds them to
+// the caller's FP64 map.
+//
+// Two kernels share the cells of a pass:
+//   * k_ipm, a thread per cell: a cell inside one pixel (the common case)
+//     adds the whole cell; a cell whose bounding box spans at most
+//     kPairMax pixels is apportioned pixel by pixel, its (cell, pixel) pairs
+//     shared out evenly over the workgroup; a wider cell (next to a star its
+//     image can stretch over much of the map) is queued;
+//   * k_ipm_wide, a wave per queued cell: its image (the quadrilateral, or a
+//     folded cell's two lobes) is rasterised edge by edge, so the work is
+//     proportional to its perimeter in pixels: an edge adds its Green term to
+//     the few pixels it crosses in each row and a constant to the row's
+//     pixels right of it through a row-difference accumulator that the final
+//     pass prefix-sums along the row.
 #include "device_common.h"
 
 namespace lensfmm {
@@ -27,6 +38,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr double kFix = 1099511627776.0;  // 2^40
+// widest bounding box (in pixels) apportioned by the per-cell pair path
+constexpr int32_t kPairMax = 64;
 
 __device__ __forceinline__ double orient2(double ax, double ay, double bx, double by, double cx,
                                           double cy) {
@@ -42,17 +55,6 @@ __device__ __forceinline__ bool segments_cross(const double (&a)[2], const doubl
   return ((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) && ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0));
 }
 
-// Twice the signed area of a quadrilateral (shoelace, vertex order).
-__device__ __forceinline__ double shoelace4(const double (&q)[4][2]) {
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int k1 = (k + 1) & 3;
-    s += q[k][0] * q[k1][1] - q[k1][0] * q[k][1];
-  }
-  return s;
-}
-
 __device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
 
 // Signed contribution of edge a -> b to the area of (polygon n unit square):
@@ -60,7 +62,7 @@ __device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 
 // On that part x(y) = lx + (y - ly) k is linear, so clamp01(x(y)) is linear
 // between the heights where x crosses 0 and 1 and the trapezoid rule on those
 // pieces is exact.  k = dx/dy and kinv = dy/dx (0 for a vertical edge) depend
-// only on the edge's direction, not on the pixel.
+// only on the edge's direction, not on the pixel or on where the edge ends.
 __device__ __forceinline__ double edge_term(double ax, double ay, double bx, double by, double k,
                                             double kinv) {
   if (ay == by) return 0.0;
@@ -83,33 +85,95 @@ __device__ __forceinline__ double edge_term(double ax, double ay, double bx, dou
   return up ? v : -v;
 }
 
-// Area of quadrilateral q (pixel units) inside the square [u,u+1] x [v,v+1].
-// By Green's theorem the area of (Q n B) for the unit square B is the line
-// integral of clamp01(x) dy over the boundary of Q restricted to 0 <= y <= 1
-// (d/dx clamp01 is the indicator of 0 < x < 1): a sum of four edge terms,
-// with no clipped polygon to store.  Signed by Q's orientation; |.| taken.
-__device__ double quad_pixel_overlap(const double (&q)[4][2], const double (&k)[4],
-                                    const double (&kinv)[4], double u, double v) {
-  double s = 0.0;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int e1 = (e + 1) & 3;
-    s += edge_term(q[e][0] - u, q[e][1] - v, q[e1][0] - u, q[e1][1] - v, k[e], kinv[e]);
-  }
-  return fabs(s);
+// Edge a -> b against the unit square at (u, v).
+__device__ __forceinline__ double edge_at(const double (&a)[2], const double (&b)[2], double k,
+                                          double kinv, double u, double v) {
+  return edge_term(a[0] - u, a[1] - v, b[0] - u, b[1] - v, k, kinv);
 }
 
-// Per-edge slopes of q for edge_term: k = dx/dy (0 for a horizontal edge),
-// kinv = dy/dx (0 for a vertical one).  They depend only on the cell.
-__device__ __forceinline__ void edge_slopes(const double (&q)[4][2], double (&k)[4],
-                                            double (&kinv)[4]) {
+// Slopes k = dx/dy (0 for a horizontal edge) and kinv = dy/dx (0 for a
+// vertical one) of the edge a -> b.
+__device__ __forceinline__ void edge_slope(const double (&a)[2], const double (&b)[2], double &k,
+                                           double &kinv) {
+  const double dx = b[0] - a[0], dy = b[1] - a[1];
+  k = dy != 0.0 ? dx / dy : 0.0;
+  kinv = dx != 0.0 ? dy / dx : 0.0;
+}
+
+// The image of a cell as the polygons that carry its area.
+//   kind 0: the quadrilateral q itself (convex or not; Green's theorem holds
+//           for any simple polygon);
+//   kind 1: edges 0-1 and 2-3 cross at X: lobes (X, q1, q2) and (q0, X, q3);
+//   kind 2: edges 1-2 and 3-0 cross at X: lobes (X, q2, q3) and (q1, X, q0).
+// area = |Q| or |T1| + |T2| (pixel units).
+struct Cell {
+  double q[4][2];
+  double X[2];
+  int kind;
+  double area;
+};
+
+__device__ __forceinline__ double tri_area(const double (&a)[2], const double (&b)[2],
+                                           const double (&c)[2]) {
+  return fabs(0.5 * orient2(a[0], a[1], b[0], b[1], c[0], c[1]));
+}
+
+__device__ __forceinline__ void classify(Cell &c) {
+  const bool c01 = segments_cross(c.q[0], c.q[1], c.q[2], c.q[3]);
+  const bool c12 = !c01 && segments_cross(c.q[1], c.q[2], c.q[3], c.q[0]);
+  if (c01 || c12) {
+    const int ia = c01 ? 0 : 1;
+    const double(&a)[2] = c.q[ia];
+    const double(&b)[2] = c.q[ia + 1];
+    const double(&cc)[2] = c.q[ia + 2];
+    const double(&d)[2] = c.q[(ia + 3) & 3];
+    const double den = (b[0] - a[0]) * (d[1] - cc[1]) - (b[1] - a[1]) * (d[0] - cc[0]);
+    const double t = ((cc[0] - a[0]) * (d[1] - cc[1]) - (cc[1] - a[1]) * (d[0] - cc[0])) / den;
+    c.X[0] = a[0] + t * (b[0] - a[0]);
+    c.X[1] = a[1] + t * (b[1] - a[1]);
+    c.kind = c01 ? 1 : 2;
+    c.area = tri_area(c.X, b, cc) + tri_area(a, c.X, d);
+  } else {
+    // shoelace on coordinates relative to the first corner (a small image
+    // far from the map origin keeps its digits)
+    double s = 0.0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int e1 = (e + 1) & 3;
-    const double dx = q[e1][0] - q[e][0], dy = q[e1][1] - q[e][1];
-    k[e] = dy != 0.0 ? dx * rcp_f64(dy) : 0.0;
-    kinv[e] = dx == 0.0 ? 0.0 : dy * rcp_f64(dx);
+    for (int k = 0; k < 4; ++k) {
+      const int k1 = (k + 1) & 3;
+      const double x0 = c.q[k][0] - c.q[0][0], y0 = c.q[k][1] - c.q[0][1];
+      const double x1 = c.q[k1][0] - c.q[0][0], y1 = c.q[k1][1] - c.q[0][1];
+      s += x0 * y1 - x1 * y0;
+    }
+    c.X[0] = c.X[1] = 0.0;
+    c.kind = 0;
+    c.area = fabs(0.5 * s);
   }
+}
+
+// Area of the cell's image inside the unit square at (u, v); k/kinv are the
+// slopes of the four edges q[e] -> q[e+1] (sub-edges of a lobe run along
+// them in the same direction).
+__device__ double cell_pixel_overlap(const double (&q)[4][2], const double (&X)[2], int kind,
+                                     const double (&k)[4], const double (&kinv)[4], double u,
+                                     double v) {
+  if (kind == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s += edge_at(q[e], q[(e + 1) & 3], k[e], kinv[e], u, v);
+    return fabs(s);
+  }
+  if (kind == 1) {
+    const double t1 = edge_at(X, q[1], k[0], kinv[0], u, v) + edge_at(q[1], q[2], k[1], kinv[1], u, v) +
+                      edge_at(q[2], X, k[2], kinv[2], u, v);
+    const double t2 = edge_at(q[0], X, k[0], kinv[0], u, v) + edge_at(X, q[3], k[2], kinv[2], u, v) +
+                      edge_at(q[3], q[0], k[3], kinv[3], u, v);
+    return fabs(t1) + fabs(t2);
+  }
+  const double t1 = edge_at(X, q[2], k[1], kinv[1], u, v) + edge_at(q[2], q[3], k[2], kinv[2], u, v) +
+                    edge_at(q[3], X, k[3], kinv[3], u, v);
+  const double t2 = edge_at(q[1], X, k[1], kinv[1], u, v) + edge_at(X, q[0], k[3], kinv[3], u, v) +
+                    edge_at(q[0], q[1], k[0], kinv[0], u, v);
+  return fabs(t1) + fabs(t2);
 }
 
 // Orientation of a convex q (+1 counter-clockwise, -1 clockwise), or 0 if q
@@ -153,8 +217,11 @@ struct IpmArgs {
   const double *y;      // rows [ybase, ...) of the mapped grid, nx rays per row
   int64_t nx, ybase, j0, j1;  // cells of rows [j0, j1), all nx - 1 columns
   double cell_px, y1min, y2min, S;
-  int32_t npix, max_pixels;
-  unsigned long long *acc;
+  int32_t npix;
+  unsigned long long *acc;   // [npix][npix]
+  unsigned long long *diff;  // [npix][npix + 1] row differences (full pixels)
+  uint32_t *queue;           // wide cells: index (j - j0) (nx - 1) + i
+  uint32_t *qcount;
 };
 
 // Corners of cell (i, j) (pixel units); false if any is not finite.
@@ -170,10 +237,6 @@ __device__ __forceinline__ bool load_quad(const IpmArgs &a, int64_t i, int64_t j
     finite = finite && isfinite(q[k][0]) && isfinite(q[k][1]);
   }
   return finite;
-}
-
-__device__ __forceinline__ double quad_area(const double (&q)[4][2]) {
-  return fabs(0.5 * shoelace4(q));
 }
 
 // Pixel bounding box of q clamped to the map; false if it misses the map.
@@ -193,6 +256,10 @@ __device__ __forceinline__ bool quad_bbox(const double (&q)[4][2], int32_t npix,
   v1 = hi1 >= (double)npix ? npix - 1 : (int64_t)floor(hi1);
   inside = lo0 >= 0.0 && lo1 >= 0.0 && hi0 < (double)npix && hi1 < (double)npix;
   return !(hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix);
+}
+
+__device__ __forceinline__ unsigned long long to_fix(double x) {
+  return (unsigned long long)llrint(x * kFix);
 }
 
 // Workgroup-local sums of pixel contributions: an LDS hash table of pixels,
@@ -224,13 +291,6 @@ __device__ __forceinline__ void table_add(int32_t *tkey, unsigned long long *tva
   atomicAdd(&acc[key], v);  // crowded table
 }
 
-// One workgroup per kPatch x kPatch patch of cells, taken 256 cells at a
-// time, one thread per cell.  A cell inside one pixel adds the whole cell; a
-// folded, degenerate or too wide cell goes to its corners.  A cell over
-// several pixels (at most max_pixels) is apportioned by its overlaps; those
-// (cell, pixel) pairs of the 256 cells are numbered by a scan and shared out
-// evenly over the workgroup's threads, so a few wide cells near a star do
-// not hold a whole wave.
 __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t *wsum, int32_t *total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int32_t inc = x;
@@ -251,14 +311,17 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t *wsum, int
   return off + inc - x;
 }
 
+// One workgroup per kPatch x kPatch patch of cells, taken 256 cells at a
+// time, one thread per cell.  The (cell, pixel) pairs of the batch's
+// multi-pixel cells are numbered by a scan and shared out evenly over the
+// workgroup's threads, so a few cells near a star do not hold a whole wave.
 __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
   __shared__ int32_t tkey[kTable];
   __shared__ unsigned long long tval[kTable];
-  __shared__ double sq[kThreads][8];  // wide cells of the batch: corners,
-  __shared__ double sk[kThreads][8];   // edge slopes (k, kinv),
-  __shared__ double sinv[kThreads];    // 1 / area,
-  __shared__ int32_t sorient[kThreads];  // orientation if convex, else 0,
-  __shared__ int32_t sbox[kThreads][3];  // u0, v0, columns of the bounding box
+  __shared__ double sq[kThreads][10];       // multi-pixel cells of the batch: corners, X,
+  __shared__ double sinv[kThreads];         // 1 / area,
+  __shared__ int32_t sshape[kThreads];      // kind | (convex orientation + 1) << 2,
+  __shared__ int32_t sbox[kThreads][3];     // u0, v0, columns of the bounding box
   __shared__ int32_t sfirst[kThreads + 1];  // first pair index of each cell
   __shared__ int32_t wsum[kThreads / 64];
   const int t = threadIdx.x;
@@ -271,46 +334,43 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
   const int64_t npx_x = (ncx + kPatch - 1) / kPatch;
   const int64_t pi = blockIdx.x % npx_x, pj = blockIdx.x / npx_x;
   const int32_t npix = a.npix;
-  const unsigned long long q_cell = (unsigned long long)llrint(a.cell_px * kFix);
-  const unsigned long long q_quarter = (unsigned long long)llrint(0.25 * a.cell_px * kFix);
+  const unsigned long long q_cell = to_fix(a.cell_px);
+  const unsigned long long q_quarter = to_fix(0.25 * a.cell_px);
   for (int base = 0; base < kPatch * kPatch; base += kThreads) {
     const int k = base + t;
     const int64_t i = pi * kPatch + (k % kPatch), j = a.j0 + pj * kPatch + (k / kPatch);
     int32_t npairs = 0;
-    double q[4][2];
-    if (i < ncx && j < a.j1 && load_quad(a, i, j, q)) {
-      const double area = quad_area(q);
-      const bool folded = segments_cross(q[0], q[1], q[2], q[3]) || segments_cross(q[1], q[2], q[3], q[0]);
+    Cell c;
+    if (i < ncx && j < a.j1 && load_quad(a, i, j, c.q)) {
+      classify(c);
       int64_t u0, v0, u1, v1;
       bool inside;
-      const bool outside = !quad_bbox(q, npix, u0, v0, u1, v1, inside);
+      const bool hits = quad_bbox(c.q, npix, u0, v0, u1, v1, inside);
       const int64_t npx = (u1 - u0 + 1) * (v1 - v0 + 1);
-      if (folded || !(area > 0.0) || (!outside && npx > a.max_pixels)) {
-        // zeroth order: a quarter of the cell to each corner's pixel
+      if (!(c.area > 0.0)) {
+        // no shape: a quarter of the cell to each corner's pixel
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t pk = pixel_of(q[c], npix);
+        for (int cc = 0; cc < 4; ++cc) {
+          const int64_t pk = pixel_of(c.q[cc], npix);
           if (pk >= 0) table_add(tkey, tval, a.acc, (int32_t)pk, q_quarter);
         }
-      } else if (!outside) {
+      } else if (hits) {
         if (u0 == u1 && v0 == v1 && inside) {
           table_add(tkey, tval, a.acc, (int32_t)(v0 * npix + u0), q_cell);  // wholly inside
+        } else if (npx > kPairMax) {
+          const uint32_t slot = atomicAdd(a.qcount, 1u);
+          a.queue[slot] = (uint32_t)((j - a.j0) * ncx + i);
         } else {
           npairs = (int32_t)npx;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            sq[t][2 * c] = q[c][0];
-            sq[t][2 * c + 1] = q[c][1];
+          for (int cc = 0; cc < 4; ++cc) {
+            sq[t][2 * cc] = c.q[cc][0];
+            sq[t][2 * cc + 1] = c.q[cc][1];
           }
-          double k[4], kinv[4];
-          edge_slopes(q, k, kinv);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            sk[t][e] = k[e];
-            sk[t][4 + e] = kinv[e];
-          }
-          sinv[t] = 1.0 / area;
-          sorient[t] = convex_orientation(q);
+          sq[t][8] = c.X[0];
+          sq[t][9] = c.X[1];
+          sinv[t] = 1.0 / c.area;
+          sshape[t] = c.kind | ((c.kind == 0 ? convex_orientation(c.q) + 1 : 1) << 2);
           sbox[t][0] = (int32_t)u0;
           sbox[t][1] = (int32_t)v0;
           sbox[t][2] = (int32_t)(u1 - u0 + 1);
@@ -324,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
     __syncthreads();
     // each thread takes a contiguous range of the batch's pairs, so its
     // owner cell changes rarely: found once by search, then walked forward,
-    // with the cell's corners and slopes kept in registers meanwhile
+    // with the cell's corners and edge slopes kept in registers meanwhile
     const int32_t chunk = (total + kThreads - 1) / kThreads;
     int32_t w = t * chunk;
     const int32_t wend = min(total, w + chunk);
@@ -335,8 +395,8 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
         if (sfirst[mid] <= w) lo = mid; else hi = mid - 1;
       }
       int cur = -1;
-      double cq[4][2], k[4], kinv[4], inv = 0.0;
-      int o = 0;
+      double cq[4][2], X[2], k[4], kinv[4], inv = 0.0;
+      int kind = 0, o = 0;
       int32_t bu = 0, bv = 0, bw = 1;
       for (; w < wend; ++w) {
         // sfirst[lo] <= w < sfirst[lo + 1] (cells without pairs are skipped)
@@ -344,28 +404,26 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
         if (lo != cur) {
           cur = lo;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            cq[c][0] = sq[lo][2 * c];
-            cq[c][1] = sq[lo][2 * c + 1];
+          for (int cc = 0; cc < 4; ++cc) {
+            cq[cc][0] = sq[lo][2 * cc];
+            cq[cc][1] = sq[lo][2 * cc + 1];
           }
+          X[0] = sq[lo][8];
+          X[1] = sq[lo][9];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            k[e] = sk[lo][e];
-            kinv[e] = sk[lo][4 + e];
-          }
+          for (int e = 0; e < 4; ++e) edge_slope(cq[e], cq[(e + 1) & 3], k[e], kinv[e]);
           inv = sinv[lo];
-          o = sorient[lo];
+          kind = sshape[lo] & 3;
+          o = (sshape[lo] >> 2) - 1;
           bu = sbox[lo][0];
           bv = sbox[lo][1];
           bw = sbox[lo][2];
         }
         const int32_t local = w - sfirst[lo];
         const int32_t u = bu + local % bw, v = bv + local / bw;
-        if (o != 0 && convex_misses(cq, o, (double)u, (double)v)) continue;
-        const double ov = quad_pixel_overlap(cq, k, kinv, (double)u, (double)v);
-        if (ov > 0.0)
-          table_add(tkey, tval, a.acc, v * npix + u,
-                    (unsigned long long)llrint(a.cell_px * (ov * inv) * kFix));
+        if (kind == 0 && o != 0 && convex_misses(cq, o, (double)u, (double)v)) continue;
+        const double ov = cell_pixel_overlap(cq, X, kind, k, kinv, (double)u, (double)v);
+        if (ov > 0.0) table_add(tkey, tval, a.acc, v * npix + u, to_fix(a.cell_px * (ov * inv)));
       }
     }
     __syncthreads();  // the batch's shared cells are consumed
@@ -374,11 +432,228 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
     if (tkey[e] >= 0) atomicAdd(&a.acc[tkey[e]], tval[e]);
 }
 
+// Wide cells are apportioned edge by edge.  By Green's theorem the overlap
+// of a polygon with pixel (u, v) is the sum over its edges of
+// T_e(u) = +-int clamp01(x(y) - u) dy over the edge's part in the strip
+// [v, v+1] (edge_term), signed by the polygon's orientation.  Along a map row
+// T_e(u) is the constant C_e = +-(height of that part) for every pixel left
+// of the edge, 0 for every pixel right of it, and needs the integral only
+// for the pixels the edge passes through.  Since the C_e of a closed polygon
+// sum to zero in every strip,
+//     sum_e T_e(u) = sum_e ( -C_e [u >= ulo_e] + P_e(u) [ulo_e <= u <= uhi_e] ),
+// with [ulo_e, uhi_e] the pixels the edge crosses in that row: each (edge,
+// row) adds -C_e to the row-difference accumulator at ulo_e (prefix-summed
+// along the row by the final pass) and P_e(u) = T_e(u) to the few pixels it
+// crosses.  C_e is formed in fixed point as G(y_end) - G(y_start) with
+// G(y) = fix((y - v) w), so the constants of a closed polygon cancel exactly
+// in integers and pixels outside it receive exactly nothing.  Work is
+// proportional to the image's perimeter in pixels, not its area.
+
+// An edge's part in the strip [v, v+1]: heights yb < yt, the x extent
+// [xl, xh] there and (signed) start/end heights in the edge's direction.
+__device__ __forceinline__ bool edge_strip(double ax, double ay, double bx, double by, double k,
+                                           double v, double &xl, double &xh, double &ys,
+                                           double &ye) {
+  const double ey0 = fmin(ay, by), ey1 = fmax(ay, by);
+  const double yb = fmax(ey0, v), yt = fmin(ey1, v + 1.0);
+  if (!(yb < yt)) return false;
+  const double xb = yb == ay ? ax : (yb == by ? bx : ax + (yb - ay) * k);
+  const double xt = yt == ay ? ax : (yt == by ? bx : ax + (yt - ay) * k);
+  xl = fmin(xb, xt);
+  xh = fmax(xb, xt);
+  const bool up = by > ay;
+  ys = up ? yb : yt;
+  ye = up ? yt : yb;
+  return true;
+}
+
+// One polygon edge of a queued cell, with the items the wave's lanes take:
+// a steep edge (at least as many rows as columns in the map) one item per
+// row (its crossed pixels and its difference entry); a flat one an item per
+// column (the pixels it crosses there) plus an item per row (the difference
+// entry only).
+struct EdgeJob {
+  double ax, ay, bx, by, k, kinv, w;
+  int32_t steep, r0, nr, c0, nc, first;
+};
+constexpr int kMaxEdges = 8;  // two triangles, or one quadrilateral
+
+__device__ __forceinline__ void row_item(const EdgeJob &e, int32_t v, bool pixels,
+                                         const IpmArgs &a) {
+  const int32_t npix = a.npix;
+  double xl, xh, ys, ye;
+  if (!edge_strip(e.ax, e.ay, e.bx, e.by, e.k, (double)v, xl, xh, ys, ye)) return;
+  const double ulo = floor(xl), uhi = ceil(xh) - 1.0;
+  if (pixels) {
+    const double ua = fmax(ulo, 0.0), ub = fmin(uhi, (double)(npix - 1));
+    for (int32_t u = (int32_t)ua; (double)u <= ub; ++u) {
+      const double t = edge_term(e.ax - u, e.ay - v, e.bx - u, e.by - v, e.k, e.kinv);
+      if (t != 0.0) atomicAdd(&a.acc[(int64_t)v * npix + u], to_fix(t * e.w));
+    }
+  }
+  if (ulo < (double)npix) {
+    const unsigned long long c = to_fix((ye - v) * e.w) - to_fix((ys - v) * e.w);
+    if (c != 0ull) {
+      const int32_t d = ulo < 0.0 ? 0 : (int32_t)ulo;
+      atomicAdd(&a.diff[(int64_t)v * (npix + 1) + d], 0ull - c);
+    }
+  }
+}
+
+__device__ __forceinline__ void column_item(const EdgeJob &e, int32_t u, const IpmArgs &a) {
+  const int32_t npix = a.npix;
+  const double ex0 = fmin(e.ax, e.bx), ex1 = fmax(e.ax, e.bx);
+  const double x0 = fmax(ex0, (double)u), x1 = fmin(ex1, (double)u + 1.0);
+  if (!(x0 <= x1)) return;
+  const double y0 = x0 == e.ax ? e.ay : (x0 == e.bx ? e.by : e.ay + (x0 - e.ax) * e.kinv);
+  const double y1 = x1 == e.ax ? e.ay : (x1 == e.bx ? e.by : e.ay + (x1 - e.ax) * e.kinv);
+  // rows this column's part may touch, one row of margin either way; a row
+  // takes the pixel only if its own strip test puts u among the crossed ones
+  const double vlo = fmax(floor(fmin(y0, y1)) - 1.0, (double)e.r0);
+  const double vhi = fmin(ceil(fmax(y0, y1)), (double)(e.r0 + e.nr - 1));
+  for (int32_t v = (int32_t)vlo; (double)v <= vhi; ++v) {
+    double xl, xh, ys, ye;
+    if (!edge_strip(e.ax, e.ay, e.bx, e.by, e.k, (double)v, xl, xh, ys, ye)) continue;
+    if ((double)u < floor(xl) || (double)u > ceil(xh) - 1.0) continue;
+    const double t = edge_term(e.ax - u, e.ay - v, e.bx - u, e.by - v, e.k, e.kinv);
+    if (t != 0.0) atomicAdd(&a.acc[(int64_t)v * npix + u], to_fix(t * e.w));
+  }
+}
+
+// Adds the edges of polygon P (n vertices) to the wave's job table.
+__device__ __forceinline__ void add_edges(const double (*P)[2], int n, double w, int32_t npix,
+                                          EdgeJob *jobs, int &ne, int32_t &items) {
+  // orientation: every edge term is signed by it, so the weight carries it
+  double s = 0.0;
+  for (int e = 0; e < n; ++e) {
+    const int e1 = e + 1 == n ? 0 : e + 1;
+    s += (P[e][0] - P[0][0]) * (P[e1][1] - P[0][1]) - (P[e1][0] - P[0][0]) * (P[e][1] - P[0][1]);
+  }
+  const double ws = s < 0.0 ? -w : w;
+  for (int e = 0; e < n; ++e) {
+    const int e1 = e + 1 == n ? 0 : e + 1;
+    const double ax = P[e][0], ay = P[e][1], bx = P[e1][0], by = P[e1][1];
+    if (ay == by) continue;  // horizontal: no term
+    const double ey0 = fmin(ay, by), ey1 = fmax(ay, by), ex0 = fmin(ax, bx), ex1 = fmax(ax, bx);
+    if (!(ey1 >= 0.0) || !(ey0 < (double)npix) || !(ex0 < (double)npix)) continue;
+    // an edge wholly left of the map (ex1 < 0) still shifts its rows
+    const double r0 = fmax(floor(ey0), 0.0), r1 = fmin(floor(ey1), (double)(npix - 1));
+    const double c0 = fmax(floor(ex0), 0.0), c1 = fmin(floor(ex1), (double)(npix - 1));
+    EdgeJob &j = jobs[ne++];
+    j.ax = ax, j.ay = ay, j.bx = bx, j.by = by, j.w = ws;
+    edge_slope(P[e], P[e1], j.k, j.kinv);
+    j.r0 = (int32_t)r0;
+    j.nr = (int32_t)(r1 - r0) + 1;
+    j.c0 = (int32_t)c0;
+    j.nc = c1 >= c0 ? (int32_t)(c1 - c0) + 1 : 0;
+    j.steep = j.nr >= j.nc;
+    j.first = items;
+    items += j.steep ? j.nr : j.nc + j.nr;
+  }
+}
+
+// Orders the LDS accesses of a converged wave (its lanes exchange data
+// through LDS without a workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wave per queued cell: its image (the quadrilateral, or a folded cell's
+// two lobes) becomes a table of edge jobs in LDS, and the wave's lanes take
+// the jobs' items in turn, so even a cell of a few rows keeps most lanes busy.
+// Waves pull cells in a fixed stride and exit past the queue's end.
+__global__ __launch_bounds__(kThreads) void k_ipm_wide(IpmArgs a) {
+  __shared__ EdgeJob jobs_all[kThreads / 64][kMaxEdges];
+  __shared__ int32_t counts_all[kThreads / 64][2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  EdgeJob *jobs = jobs_all[wv];
+  const uint32_t nq = *a.qcount;
+  const int64_t ncx = a.nx - 1;
+  const uint32_t waves = gridDim.x * (kThreads / 64);
+  for (uint32_t q = blockIdx.x * (kThreads / 64) + wv; q < nq; q += waves) {
+    const uint32_t id = a.queue[q];
+    const int64_t i = (int64_t)(id % (uint64_t)ncx), j = a.j0 + (int64_t)(id / (uint64_t)ncx);
+    Cell c;
+    load_quad(a, i, j, c.q);  // finite: it was queued
+    classify(c);
+    const double w = a.cell_px / c.area;
+    wave_sync();  // the previous cell's items have read the table
+    if (lane == 0) {
+      // lane 0 writes the table to LDS; the others read it after the sync
+      int ne = 0;
+      int32_t items = 0;
+      if (c.kind == 0) {
+        add_edges(c.q, 4, w, a.npix, jobs, ne, items);
+      } else {
+        const int ia = c.kind == 1 ? 0 : 1;
+        double T[3][2];
+        T[0][0] = c.X[0], T[0][1] = c.X[1];
+        T[1][0] = c.q[ia + 1][0], T[1][1] = c.q[ia + 1][1];
+        T[2][0] = c.q[ia + 2][0], T[2][1] = c.q[ia + 2][1];
+        add_edges(T, 3, w, a.npix, jobs, ne, items);
+        T[0][0] = c.q[ia][0], T[0][1] = c.q[ia][1];
+        T[1][0] = c.X[0], T[1][1] = c.X[1];
+        T[2][0] = c.q[(ia + 3) & 3][0], T[2][1] = c.q[(ia + 3) & 3][1];
+        add_edges(T, 3, w, a.npix, jobs, ne, items);
+      }
+      counts_all[wv][0] = ne;
+      counts_all[wv][1] = items;
+    }
+    wave_sync();
+    const int ne = counts_all[wv][0];
+    const int32_t items = counts_all[wv][1];
+    for (int32_t t = lane; t < items; t += 64) {
+      int e = 0;
+      while (e + 1 < ne && jobs[e + 1].first <= t) ++e;
+      const EdgeJob &jb = jobs[e];
+      const int32_t r = t - jb.first;
+      if (jb.steep) {
+        row_item(jb, jb.r0 + r, true, a);
+      } else if (r < jb.nc) {
+        column_item(jb, jb.c0 + r, a);
+      } else {
+        row_item(jb, jb.r0 + (r - jb.nc), false, a);
+      }
+    }
+  }
+}
+
+// mu[v][u] += (acc[v][u] + sum_{u' <= u} diff[v][u']) 2^-40: a workgroup per
+// map row, the row's differences prefix-summed 256 at a time (integers, so
+// the result does not depend on the order).
 __global__ __launch_bounds__(kThreads) void k_ipm_finish(const unsigned long long *__restrict__ acc,
-                                                         int64_t n, double *__restrict__ mu) {
-  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * kThreads)
-    mu[k] += (double)(long long)acc[k] * (1.0 / kFix);
+                                                         const unsigned long long *__restrict__ diff,
+                                                         int32_t npix, double *__restrict__ mu) {
+  __shared__ unsigned long long wsum[kThreads / 64];
+  const int64_t v = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long *drow = diff + v * (int64_t)(npix + 1);
+  unsigned long long carry = 0;
+  for (int32_t base = 0; base < npix; base += kThreads) {
+    const int32_t u = base + (int32_t)threadIdx.x;
+    unsigned long long x = u < npix ? drow[u] : 0ull;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const unsigned long long y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    unsigned long long off = carry, tot = carry;
+#pragma unroll
+    for (int q = 0; q < kThreads / 64; ++q) {
+      if (q < w) off += wsum[q];
+      tot += wsum[q];
+    }
+    if (u < npix) {
+      const int64_t idx = v * npix + u;
+      mu[idx] += (double)(long long)(acc[idx] + off + x) * (1.0 / kFix);
+    }
+    carry = tot;
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_zero_u64(unsigned long long *__restrict__ p, int64_t n) {
@@ -392,6 +667,9 @@ unsigned grid_for(int64_t n) {
   return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
+// workgroups of the wide-cell kernel
+constexpr unsigned kWideBlocks = 1024;
+
 }  // namespace
 
 void launch_ipm_zero(unsigned long long *acc, int64_t n, hipStream_t stream) {
@@ -399,20 +677,25 @@ void launch_ipm_zero(unsigned long long *acc, int64_t n, hipStream_t stream) {
   LENS_HIP(hipGetLastError());
 }
 
-void launch_ipm_cells(const double *y, int64_t nx, int64_t ybase, int64_t j0, int64_t j1,
-                      double cell_px, double y1min, double y2min, double S, int32_t npix,
-                      int32_t max_pixels, unsigned long long *acc, hipStream_t stream) {
-  const int64_t ncx = nx - 1, nrows = j1 - j0;
+void launch_ipm_cells(const IpmPass &p, hipStream_t stream) {
+  const int64_t ncx = p.nx - 1, nrows = p.j1 - p.j0;
   if (ncx <= 0 || nrows <= 0) return;
   const int64_t patches = ((ncx + kPatch - 1) / kPatch) * ((nrows + kPatch - 1) / kPatch);
   if (patches > 0x7fffffff) fail(LENS_EUNSUPPORTED, "IPM pass too large");
-  IpmArgs a{y, nx, ybase, j0, j1, cell_px, y1min, y2min, S, npix, max_pixels, acc};
+  if (ncx * nrows > (int64_t)0xffffffffu) fail(LENS_EUNSUPPORTED, "IPM pass too large");
+  IpmArgs a{p.y, p.nx, p.ybase, p.j0, p.j1, p.cell_px, p.y1min, p.y2min, p.S, p.npix,
+            p.acc, p.diff, p.queue, p.qcount};
+  launch_fill_u32(p.qcount, 1, 0u, stream);
   hipLaunchKernelGGL(k_ipm, dim3((unsigned)patches), dim3(kThreads), 0, stream, a);
+  LENS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_ipm_wide, dim3(kWideBlocks), dim3(kThreads), 0, stream, a);
   LENS_HIP(hipGetLastError());
 }
 
-void launch_ipm_finish(const unsigned long long *acc, int64_t n, double *mu, hipStream_t stream) {
-  hipLaunchKernelGGL(k_ipm_finish, dim3(grid_for(n)), dim3(kThreads), 0, stream, acc, n, mu);
+void launch_ipm_finish(const unsigned long long *acc, const unsigned long long *diff, int32_t npix,
+                       double *mu, hipStream_t stream) {
+  hipLaunchKernelGGL(k_ipm_finish, dim3((unsigned)npix), dim3(kThreads), 0, stream, acc, diff, npix,
+                     mu);
   LENS_HIP(hipGetLastError());
 }
 

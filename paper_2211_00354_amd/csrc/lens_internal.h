@@ -280,15 +280,24 @@ struct DirectArgs {
 };
 void launch_direct(const DirectArgs &a, hipStream_t stream);
 
-// Inverse polygon mapping (ipm.hip): acc is an npix^2 fixed-point
-// accumulator (units of 2^-40 of a pixel's magnification) that
-// launch_ipm_finish adds to the FP64 map mu.  y holds grid rows [ybase, ...)
-// with nx rays per row; cells of rows [j0, j1) are mapped.
+// Inverse polygon mapping (ipm.hip).  acc is an npix^2 fixed-point
+// accumulator (units of 2^-40 of a pixel's magnification) and diff an
+// npix x (npix + 1) one of row differences (pixels a wide cell covers
+// completely); launch_ipm_finish adds acc plus the row prefix sums of diff to
+// the FP64 map mu.  y holds grid rows [ybase, ...) with nx rays per row;
+// cells of rows [j0, j1) are mapped.  queue needs (nx - 1) (j1 - j0) entries.
+struct IpmPass {
+  const double *y;
+  int64_t nx, ybase, j0, j1;
+  double cell_px, y1min, y2min, S;
+  int32_t npix;
+  unsigned long long *acc, *diff;
+  uint32_t *queue, *qcount;
+};
 void launch_ipm_zero(unsigned long long *acc, int64_t n, hipStream_t stream);
-void launch_ipm_cells(const double *y, int64_t nx, int64_t ybase, int64_t j0, int64_t j1,
-                      double cell_px, double y1min, double y2min, double S, int32_t npix,
-                      int32_t max_pixels, unsigned long long *acc, hipStream_t stream);
-void launch_ipm_finish(const unsigned long long *acc, int64_t n, double *mu, hipStream_t stream);
+void launch_ipm_cells(const IpmPass &p, hipStream_t stream);
+void launch_ipm_finish(const unsigned long long *acc, const unsigned long long *diff, int32_t npix,
+                       double *mu, hipStream_t stream);
 
 }  // namespace lensfmm
 

@@ -38,6 +38,35 @@ def rel_l2(y, y_ref, alpha_ref):
     return float(np.linalg.norm(y - y_ref) / (den if den > 0 else 1.0))
 
 
+def ray_errors(y, y_ref, alpha_ref):
+    """Per-ray relative deflection error |dalpha_k| / max(|alpha_k|, 1e-3 rms
+    alpha): its maximum and 99.9th percentile over the rays compared."""
+    d = np.hypot(*(np.asarray(y) - y_ref).reshape(-1, 2).T)
+    a = np.hypot(*np.asarray(alpha_ref).reshape(-1, 2).T)
+    if d.size == 0:
+        return 0.0, 0.0
+    rms = float(np.sqrt(np.mean(a * a)))
+    r = d / np.maximum(a, max(1e-3 * rms, 1e-300))
+    return float(r.max()), float(np.percentile(r, 99.9))
+
+
+def check(y, y_ref, alpha_ref, tol, label="", ray_tol=None):
+    """Relative l2 error of alpha within tol, and the per-ray maximum and
+    99.9th percentile within ray_tol (default: tol).  A looser ray_tol is
+    given only where a test runs a deliberately low order p: the truncation
+    error is absolute (~ rho^p of the far field), so relative to a ray whose
+    deflection nearly cancels it can be far above the l2 average."""
+    rt = tol if ray_tol is None else ray_tol
+    e = rel_l2(y, y_ref, alpha_ref)
+    mx, p999 = ray_errors(y, y_ref, alpha_ref)
+    print(f"[err] {label} rel_l2 {e:.2e} (tol {tol:.0e}) ray_max {mx:.2e} ray_p99.9 {p999:.2e} "
+          f"(tol {rt:.0e})", flush=True)
+    assert e <= tol, (label, "rel_l2", e)
+    assert mx <= rt, (label, "ray max", mx)
+    assert p999 <= rt, (label, "ray p99.9", p999)
+    return e
+
+
 def lfgrid(g: wl.Grid):
     import paper_2211_00354_amd as lf
     return lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny)
@@ -51,9 +80,8 @@ def test_direct_small_disk_matches_oracle(lf):
     y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
                         gamma=f.gamma, method="direct"))
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
-    err = rel_l2(y, yo, ao)
-    print("direct rel l2", err)
-    assert err <= 1e-13
+    # per ray: the FP64 sums of 1000 terms lose digits where alpha cancels
+    check(y, yo, ao, 1e-13, "direct small_disk", ray_tol=1e-12)
     assert np.max(np.abs(y - yo)) <= 1e-11 * np.max(np.abs(ao))
 
 
@@ -74,7 +102,7 @@ def test_direct_explicit_rays_edge_cases(lf, n):
     if n == 0:
         np.testing.assert_array_equal(y, yo)
     else:
-        assert rel_l2(y, yo, ao) <= 1e-13
+        check(y, yo, ao, 1e-13)
 
 
 def test_direct_map_small_disk(lf):
@@ -97,18 +125,25 @@ def test_direct_map_small_disk(lf):
 
 # --------------------------------------------------------------------- FMM
 
-@pytest.mark.parametrize("precision,p,tol", [
-    ("fp64", 12, 1e-6), ("fp64", 20, 1e-8), ("fp64", 30, 1e-10), ("mixed", 12, 1e-5),
+@pytest.mark.parametrize("precision,p,fl,tol,ray_tol", [
+    ("fp64", 12, 0, 1e-6, 2e-3), ("fp64", 20, 0, 1e-8, 2e-6), ("fp64", 36, 0, 1e-10, 1e-10),
+    ("mixed", 12, 0, 1e-5, 2e-3), ("mixed", 18, 0, 1e-5, 3e-4), ("mixed", 18, -1, 1e-5, 5e-5),
 ])
-def test_fmm_small_disk(lf, precision, p, tol):
+def test_fmm_small_disk(lf, precision, p, fl, tol, ray_tol):
+    """The small disk (kappa_* = 1.41) at several orders.  Per ray, p = 12
+    leaves up to ~7e-4 where alpha nearly cancels (near the disk centre); the
+    targets (1e-5 mixed, 1e-10 FP64) are met per ray at p = 18 and 36.  The
+    two FP32 M2L levels of the default mixed path carry FP32 rounding of
+    partial fields that are large there next to the cancelled total (~1e-4
+    per ray); with every M2L level in FP64 (fp32_levels = -1) what is left is
+    the FP32 near field, ~1e-7 of the near stars' pull (~1) against a total
+    cancelled to ~5e-3 (the metric's floor, 1e-3 rms alpha): 2.5e-5."""
     f, g, _ = wl.small_disk()
     _say("fmm small_disk", precision, p)
     y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
-                        gamma=f.gamma, precision=precision, p=p))
+                        gamma=f.gamma, precision=precision, p=p, fp32_levels=fl))
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
-    err = rel_l2(y, yo, ao)
-    print("fmm", precision, p, "rel l2", err)
-    assert err <= tol
+    check(y, yo, ao, tol, f"fmm small_disk {precision} p={p} fl={fl}", ray_tol)
 
 
 @pytest.mark.parametrize("leaf", [2, 3, 4, 6, 8])
@@ -116,9 +151,9 @@ def test_fmm_leaf_levels(lf, leaf):
     f, g, _ = wl.small_disk()
     _say("fmm leaf level", leaf)
     y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
-                        gamma=f.gamma, precision="fp64", p=24, leaf_level=leaf))
+                        gamma=f.gamma, precision="fp64", p=30, leaf_level=leaf))
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
-    assert rel_l2(y, yo, ao) <= 1e-9
+    check(y, yo, ao, 1e-9, f"leaf level {leaf}")
 
 
 @pytest.mark.parametrize("precision,p,tol", [("fp64", 36, 1e-9), ("fp64", 26, 1e-8),
@@ -139,9 +174,7 @@ def test_fmm_deep_tree_high_order(lf, precision, p, tol):
                         precision=precision, p=p))
     idx = g.strided(16, 5)
     yo, ao, _ = oracle.deflect(xy, m, g.rays(idx), 0.1, 0.2)
-    err = rel_l2(y[idx], yo, ao)
-    print("deep tree", precision, p, "rel l2", err)
-    assert err <= tol
+    check(y[idx], yo, ao, tol, f"deep tree {precision} p={p}")
 
 
 def test_fmm_error_falls_with_order(lf):
@@ -169,12 +202,15 @@ def test_fmm_ragged_grid_offset(lf):
     _say("fmm ragged grid")
     for prec, tol in (("fp64", 1e-9), ("mixed", 1e-5)):
         y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), grid=lfgrid(g), kappa_s=f.kappa_s,
-                            gamma=f.gamma, precision=prec, p=24 if prec == "fp64" else 12))
+                            gamma=f.gamma, precision=prec, p=24 if prec == "fp64" else 16,
+                            fp32_levels=-1))
         yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
-        assert rel_l2(y, yo, ao) <= tol, prec
+        # mixed: the FP32 near field against deflections that cancel
+        # (kappa_* = 4 here) leaves ~2e-5 per ray at the floor
+        check(y, yo, ao, tol, f"ragged {prec}", 5e-5 if prec == "mixed" else None)
 
 
-@pytest.mark.parametrize("prec,p,tol", [("fp64", 24, 1e-9), ("mixed", 12, 1e-5)])
+@pytest.mark.parametrize("prec,p,tol", [("fp64", 28, 1e-9), ("mixed", 16, 1e-5)])
 def test_fmm_explicit_rays(lf, prec, p, tol):
     f = wl.random_field(4000, 20.0, seed=12, masses="powerlaw")
     rng = np.random.default_rng(13)
@@ -183,7 +219,7 @@ def test_fmm_explicit_rays(lf, prec, p, tol):
     y = host(lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), rays=dev_tensor(rays), precision=prec,
                         p=p))
     yo, ao, _ = oracle.deflect(f.xy, f.m, rays)
-    assert rel_l2(y, yo, ao) <= tol
+    check(y, yo, ao, tol)
 
 
 @pytest.mark.parametrize("case", ["one", "two", "three", "seventeen", "cluster", "onstar",
@@ -205,7 +241,7 @@ def test_fmm_tiny_edge_cases(lf, case):
     _say("fmm tiny", case)
     # mass concentrated at a box corner is the worst case of the truncation
     # bound, so the mixed path runs at p = 16 here
-    for prec, p, tol in (("fp64", 24, 1e-9), ("mixed", 16, 1e-5)):
+    for prec, p, tol in (("fp64", 32, 1e-9), ("mixed", 16, 1e-5)):
         y = host(lf.deflect(dev_tensor(xy.reshape(-1, 2)), dev_tensor(m), rays=dev_tensor(rays),
                             kappa_s=0.05, gamma=0.2, precision=prec, p=p))
         yo, ao, _ = oracle.deflect(xy, m, rays, 0.05, 0.2)
@@ -213,14 +249,50 @@ def test_fmm_tiny_edge_cases(lf, case):
         if case == "empty":
             np.testing.assert_array_equal(y, yo)
         else:
-            assert rel_l2(y, yo, ao) <= tol, (prec, rel_l2(y, yo, ao))
+            check(y, yo, ao, tol)
+
+
+@pytest.mark.parametrize("prec,p,tol", [("mixed", 20, 1e-5), ("fp64", 36, 1e-10)])
+def test_fmm_close_pairs(lf, prec, p, tol):
+    """Rays 1e-7 to 1e-3 Einstein radii from a star, on a grid and as
+    explicit rays: the pair difference is formed in FP64 from absolute
+    coordinates, so a close pair keeps its relative accuracy in the mixed
+    path too (an FP32 box-relative difference would be off by ~1e-7 Einstein
+    radii and drop a pair at 1e-7 altogether)."""
+    rng = np.random.default_rng(303)
+    n = 60
+    xy = rng.uniform(-4.5, 4.5, (n, 2))
+    m = rng.uniform(0.2, 1.5, n)
+    g = wl.centred_grid(10.0, 10.0, 256, 256)
+    rays_g = g.rays()
+    offs = np.repeat([1e-7, 1e-6, 1e-5, 1e-4, 1e-3], 5)
+    ang = rng.uniform(0.0, 2 * np.pi, 25)
+    unit = np.stack([np.cos(ang), np.sin(ang)], 1)
+    pick = rng.choice(g.n, 25, replace=False)
+    xy[:25] = rays_g[pick] + offs[:, None] * unit       # stars next to grid rays
+    kw = dict(kappa_s=0.1, gamma=0.2)
+    _say("close pairs grid", prec, p)
+    y = host(lf.deflect(dev_tensor(xy), dev_tensor(m), grid=lfgrid(g), precision=prec, p=p, **kw))
+    yo, ao, skipped = oracle.deflect(xy, m, rays_g, **kw)
+    assert skipped == 0
+    check(y, yo, ao, tol, f"close pairs grid {prec}")
+    k = pick[0]
+    assert abs(np.hypot(*(y[k] - yo[k])) / np.hypot(*ao[k])) <= tol   # the 1e-7 pair itself
+    # explicit rays next to stars 25..49
+    rays = xy[25:50] + offs[:, None] * unit[::-1]
+    rays = np.concatenate([rays, rng.uniform(-5, 5, (2000, 2))])
+    _say("close pairs explicit", prec, p)
+    y = host(lf.deflect(dev_tensor(xy), dev_tensor(m), rays=dev_tensor(rays), precision=prec, p=p,
+                        **kw))
+    yo, ao, _ = oracle.deflect(xy, m, rays, **kw)
+    check(y, yo, ao, tol, f"close pairs explicit {prec}")
 
 
 def test_fmm_rays_on_box_edges(lf):
     """Rays exactly on leaf-box edges and corners (several boxes are valid)."""
     f = wl.random_field(500, 10.0, seed=21)
     plan = lf.Plan(dev_tensor(f.xy), dev_tensor(f.m), ray_box=(-10, -10, 10, 10), precision="fp64",
-                   p=24, leaf_level=4)
+                   p=30, leaf_level=4)
     info = plan.info()
     s = info["root_side"] / 2 ** info["leaf_level"]
     ii = np.arange(2, 14)
@@ -232,7 +304,7 @@ def test_fmm_rays_on_box_edges(lf):
     _say("fmm box edges", rays.shape)
     y = host(lf.deflect(rays=dev_tensor(rays), plan=plan))
     yo, ao, _ = oracle.deflect(f.xy, f.m, rays)
-    assert rel_l2(y, yo, ao) <= 1e-9
+    check(y, yo, ao, 1e-9)
     plan.close()
 
 
@@ -246,17 +318,17 @@ def test_fmm_determinism_and_plan_reuse(lf):
         b = host(lf.deflect(xy, m, grid=lfgrid(g), precision=prec, kappa_s=0.2, gamma=0.1))
         np.testing.assert_array_equal(a, b)
     bb = (g.x0, g.y0, g.x0 + g.nx * g.dx, g.y0 + g.ny * g.dy)
-    plan = lf.Plan(xy, m, ray_box=bb, precision="mixed", p=12)
+    plan = lf.Plan(xy, m, ray_box=bb, precision="mixed", p=16, fp32_levels=-1)
     yo0, ao0, _ = oracle.deflect(f.xy, f.m, g.rays(), 0.0, 0.0)
     for ks, gm in ((0.0, 0.0), (0.3, -0.2)):
         y = host(lf.deflect(grid=lfgrid(g), plan=plan, kappa_s=ks, gamma=gm))
         yo, _, _ = oracle.deflect(f.xy, f.m, g.rays(), ks, gm)
-        assert rel_l2(y, yo, ao0) <= 1e-5
+        check(y, yo, ao0, 1e-5)
     plan.close()
 
 
-@pytest.mark.parametrize("prec,p,fl,tol", [("fp64", 28, 0, 1e-10), ("mixed", 16, 0, 1e-6),
-                                           ("mixed", 16, -1, 1e-6)])
+@pytest.mark.parametrize("prec,p,fl,tol", [("fp64", 36, 0, 1e-10), ("mixed", 20, 0, 1e-5),
+                                           ("mixed", 20, -1, 1e-5)])
 def test_small_ray_region_in_wide_field(lf, prec, p, fl, tol):
     """Rays in a 20 x 15 box inside a star disk of radius ~816: the finer
     levels then hold only their source windows, formed straight from the
@@ -275,11 +347,14 @@ def test_small_ray_region_in_wide_field(lf, prec, p, fl, tol):
     yd = host(lf.deflect(xy, m, grid=lfgrid(g), method="direct", **kw))
     ad = g.rays() * [0.7, 1.1] - yd
     y = host(lf.deflect(xy, m, grid=lfgrid(g), precision=prec, p=p, fp32_levels=fl, **kw))
-    assert rel_l2(y, yd, ad) <= tol, rel_l2(y, yd, ad)
+    # two FP32 M2L levels leave ~2e-5 per ray here (the coarse levels carry
+    # large partial fields); all-FP64 M2L meets 1e-5
+    check(y, yd, ad, tol, f"small ray region {prec} p={p} fl={fl}",
+          1e-4 if (prec == "mixed" and fl == 0) else None)
     # the oracle on a few rays pins the direct sum here too
     idx = g.strided(97, 5)
     yo, ao, _ = oracle.deflect(xy_h, m_h, g.rays(idx), **kw)
-    assert rel_l2(yd[idx], yo, ao) <= 1e-13
+    check(yd[idx], yo, ao, 1e-13)
 
 
 def test_plan_rejects_rays_outside_its_ray_box(lf):
@@ -341,13 +416,12 @@ def test_powerlaw_disk_reduced(lf):
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
     idx = g.strided(8, 3)
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), f.kappa_s, f.gamma)
-    for prec, p, tol in (("mixed", 12, 1e-5), ("fp64", 12, 1e-6), ("fp64", 30, 1e-10)):
+    for prec, p, tol, rt in (("mixed", 12, 1e-5, 1e-5), ("fp64", 12, 1e-6, 1e-5),
+                             ("fp64", 30, 1e-10, 1e-10)):
         _say("powerlaw_disk reduced", prec, p)
         y = host(lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma,
                             precision=prec, p=p))
-        err = rel_l2(y[idx], yo, ao)
-        print(prec, p, err)
-        assert err <= tol
+        check(y[idx], yo, ao, tol, f"powerlaw_disk reduced {prec} p={p}", rt)
 
 
 def test_powerlaw_disk_full_size_sampled(lf):
@@ -362,9 +436,63 @@ def test_powerlaw_disk_full_size_sampled(lf):
     ys = host(y[idx])
     assert bool(torch.isfinite(y).all())
     yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx.cpu().numpy()), f.kappa_s, f.gamma)
-    err = rel_l2(ys, yo, ao)
-    print("powerlaw_disk full mixed rel l2", err)
-    assert err <= 1e-5
+    check(ys, yo, ao, 1e-5, "powerlaw_disk full mixed p=12")
+
+
+def test_powerlaw_disk_full_size_fp64_target(lf):
+    """The benchmark field in FP64 at p = 30, the order that reaches the 1e-10
+    target: on a strided sample against the oracle, per ray."""
+    import torch
+    f, g = wl.powerlaw_disk()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    _say("powerlaw_disk full fp64 p=30")
+    y = lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma, precision="fp64", p=30)
+    idx = g.strided(128, 37)
+    ys = host(y[torch.from_numpy(idx).cuda()])
+    del y
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), f.kappa_s, f.gamma)
+    check(ys, yo, ao, 1e-10, "powerlaw_disk full fp64 p=30")
+
+
+def test_powerlaw_disk_full_size_every_ray_against_direct(lf):
+    """Every one of the 8192^2 rays of the benchmark against the GPU's FP64
+    direct sum (itself pinned to the oracle on a sample here), mixed, in the
+    launch the benchmark times.  At p = 12 (the benchmark's order) the
+    relative l2 error is ~1e-7 and 99.9% of rays are within 3e-6, but ~3600
+    rays near the disk centre, where alpha cancels to ~0.3 Einstein radii,
+    reach 1e-4 (truncation, the same in FP64); at p = 13 every ray is within
+    1e-5."""
+    import torch
+    f, g = wl.powerlaw_disk()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    kw = dict(kappa_s=f.kappa_s, gamma=f.gamma)
+    _say("powerlaw_disk every ray: FP64 direct (~30 s)")
+    yd = lf.deflect(xy, m, grid=lfgrid(g), method="direct", **kw)
+    idx = g.strided(512, 100)
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), **kw)
+    check(host(yd[torch.from_numpy(idx).cuda()]), yo, ao, 1e-13, "direct sample")
+    # |alpha| with c x formed exactly as the kernels do (dyadic grid)
+    n = g.n
+    i = torch.arange(n, device="cuda", dtype=torch.int64)
+    x1 = g.x0 + ((i % g.nx).double() + 0.5) * g.dx
+    x2 = g.y0 + ((i // g.nx).double() + 0.5) * g.dy
+    amag = torch.hypot((1 - f.kappa_s - f.gamma) * x1 - yd[:, 0],
+                       (1 - f.kappa_s + f.gamma) * x2 - yd[:, 1])
+    del x1, x2, i
+    rms = float(torch.sqrt(torch.mean(amag * amag)))
+    den = torch.clamp(amag, min=1e-3 * rms)
+    y = torch.empty_like(yd)
+    for p, ray_tol in ((12, 2e-4), (13, 1e-5)):
+        _say("powerlaw_disk every ray: mixed p", p)
+        lf.deflect(xy, m, grid=lfgrid(g), precision="mixed", p=p, out=y, **kw)
+        d = torch.hypot(y[:, 0] - yd[:, 0], y[:, 1] - yd[:, 1])
+        r = d / den
+        rel = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(amag))
+        mx = float(r.max())
+        p999 = float(torch.topk(r, n // 1000).values.min())
+        print(f"[err] every ray mixed p={p}: rel_l2 {rel:.2e} ray_max {mx:.2e} "
+              f"ray_p99.9 {p999:.2e} rays over 1e-5: {int((r > 1e-5).sum())}", flush=True)
+        assert rel <= 1e-5 and p999 <= 1e-5 and mx <= ray_tol, (p, rel, p999, mx)
 
 
 # ------------------------------------------------------------------- adjoint
@@ -473,12 +601,13 @@ def test_batched_maps_equal_single_maps_and_replay(lf):
         grids.append(lfgrid(g))
         maps.append(lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix))
     _say("batched 6 fields")
-    got = [host(c) for c in lf.irs_map_batched(fields, grids, maps)]
+    kw = dict(p=16)   # per ray within 1e-5 of the oracle (p = 12 leaves ~1.5e-5 on one field)
+    got = [host(c) for c in lf.irs_map_batched(fields, grids, maps, **kw)]
     for k, ((xy, m, ks, gm), g, mp) in enumerate(zip(fields, grids, maps)):
-        single = host(lf.irs_map(xy, m, grid=g, map=mp, kappa_s=ks, gamma=gm))
+        single = host(lf.irs_map(xy, m, grid=g, map=mp, kappa_s=ks, gamma=gm, **kw))
         np.testing.assert_array_equal(got[k], single)
         # the map is the oracle's binning of the GPU's own y
-        y = host(lf.deflect(xy, m, grid=g, kappa_s=ks, gamma=gm))
+        y = host(lf.deflect(xy, m, grid=g, kappa_s=ks, gamma=gm, **kw))
         mine, _ = oracle.bin_rays(y, mp.y1min, mp.y2min, mp.side, mp.npix)
         np.testing.assert_array_equal(got[k], mine)
         # and the oracle's y moves few rays (sampled rays)
@@ -486,19 +615,19 @@ def test_batched_maps_equal_single_maps_and_replay(lf):
         gg = cases[k][1]
         idx = gg.strided(8, 3)
         yo, ao, _ = oracle.deflect(f.xy, f.m, gg.rays(idx), f.kappa_s, f.gamma)
-        assert rel_l2(y[idx], yo, ao) <= 1e-5
+        check(y[idx], yo, ao, 1e-5)
     # replaying the cached graph accumulates into the same maps
     counts = [torch.from_numpy(c).cuda() for c in got]
-    again = [host(c) for c in lf.irs_map_batched(fields, grids, maps, counts=counts)]
+    again = [host(c) for c in lf.irs_map_batched(fields, grids, maps, counts=counts, **kw)]
     for a, b in zip(again, got):
         np.testing.assert_array_equal(a, 2 * b)
     # moving the stars outside the captured trees forces a rebuild, still exact
     xy0 = fields[0][0]
     xy0.mul_(1.5)
     fresh = [torch.zeros_like(c) for c in counts]
-    out = lf.irs_map_batched(fields, grids, maps, counts=fresh)
+    out = lf.irs_map_batched(fields, grids, maps, counts=fresh, **kw)
     single = host(lf.irs_map(xy0, fields[0][1], grid=grids[0], map=maps[0], kappa_s=fields[0][2],
-                             gamma=fields[0][3]))
+                             gamma=fields[0][3], **kw))
     np.testing.assert_array_equal(host(out[0]), single)
     lf.release_cached()
 
@@ -644,7 +773,7 @@ def test_autotune_deflect_reaches_tol(lf):
                             leaf_level=t["leaf_level"], fp32_levels=t["fp32_levels"], **kw))
         idx = g.strided(41, 7)
         yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), **kw)
-        assert rel_l2(y[idx], yo, ao) <= 3 * tol
+        check(y[idx], yo, ao, 3 * tol, f"autotuned {prec}")
 
 
 def test_autotune_high_magnification_map(lf):
@@ -726,7 +855,7 @@ def test_call_graph_replays_match_eager(lf):
     out = host(lf.deflect(xy, m, grid=lfgrid(g), out=y, **kw))
     np.testing.assert_array_equal(out, ref2)
     yo, ao, _ = oracle.deflect(host(xy), host(m), g.rays(g.strided(37, 3)), 0.2, 0.1)
-    assert rel_l2(out[g.strided(37, 3)], yo, ao) <= 1e-5
+    check(out[g.strided(37, 3)], yo, ao, 1e-5)
     # maps accumulate through the replays
     md = lf.MapDesc(-10.0, -10.0, 20.0, 128)
     counts = torch.zeros((128, 128), dtype=torch.int32, device="cuda")
@@ -754,12 +883,16 @@ def lf_mapdesc(y1min, y2min, side, npix):
     return lfm.MapDesc(y1min, y2min, side, npix)
 
 
-def test_ipm_kernel_matches_oracle_on_the_same_rays(lf):
+@pytest.mark.parametrize("npix,side", [(128, 4.0), (512, 4.0), (1024, 2.0)])
+def test_ipm_kernel_matches_oracle_on_the_same_rays(lf, npix, side):
     """Same deflected corners on both sides (the FP64 direct sum): the GPU's
-    cell apportioning equals the oracle's up to the fixed-point rounding."""
-    f, g, md = _ipm_case()
+    cell apportioning equals the oracle's up to the fixed-point rounding.
+    With fine pixels many cells span more than 64 pixels (the wide-cell
+    kernel) and many fold (the lobes)."""
+    f, g, _ = wl.small_disk()
+    md = lf_mapdesc(-side / 2, -side / 2, side, npix)
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
-    _say("ipm direct", g.nx, g.ny, md.npix)
+    _say("ipm direct", g.nx, g.ny, md.npix, side)
     mu = host(lf.ipm_map(xy, m, grid=lfgrid(g), map=md, kappa_s=f.kappa_s, gamma=f.gamma,
                          method="direct"))
     y = host(lf.deflect(xy, m, grid=lfgrid(g), kappa_s=f.kappa_s, gamma=f.gamma, method="direct"))
@@ -772,13 +905,12 @@ def test_ipm_kernel_matches_oracle_on_the_same_rays(lf):
     np.testing.assert_array_equal(mu, mu2)
 
 
-@pytest.mark.parametrize("prec,p", [("fp64", 20), ("mixed", 16)])
+@pytest.mark.parametrize("prec,p", [("fp64", 20), ("mixed", 12)])
 def test_ipm_fmm_against_oracle(lf, prec, p):
     """End to end: FMM deflection + GPU IPM against the oracle's deflection
-    and IPM.  Cells that fold or stretch over more than 64 pixels go to their
-    corners, a rule that jumps as corners move, so near caustics a deflection
-    error can move a cell's whole area; the test bounds the total (L1)
-    difference (at p = 12 mixed it is ~1.2e-4, at p = 16 ~4e-5)."""
+    and IPM.  Every cell is apportioned by overlap (folded ones over their
+    lobes), so the map moves continuously with the corners and the relative
+    L1 difference follows the deflection error."""
     f, g, md = _ipm_case()
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
     _say("ipm fmm", prec, p)
@@ -789,6 +921,33 @@ def test_ipm_fmm_against_oracle(lf, prec, p):
     l1 = np.abs(mu - ref).sum() / ref.sum()
     print(f"ipm {prec} p={p}: relative L1 {l1:.2e}")
     assert l1 <= (1e-7 if prec == "fp64" else 1e-4)
+
+
+def test_ipm_against_dense_irs(lf):
+    """The small-disk IPM map (512^2 corner rays, a 128^2 map over [-2,2]^2)
+    against an inverse-ray-shooting map of the same field shot with 16 times
+    more rays per side (8192^2, FP64 direct sum), the best available stand-in
+    for the exact map: the first-order IPM must be far closer to it than IRS
+    with the IPM's own rays."""
+    f, g, md = _ipm_case()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    _say("ipm vs dense irs")
+    kw = dict(kappa_s=f.kappa_s, gamma=f.gamma)
+    mu = host(lf.ipm_map(xy, m, grid=lfgrid(g), map=md, method="direct", **kw))
+    pix = (md.side / md.npix) ** 2
+
+    def irs(k):
+        # k^2 rays per IPM cell, over exactly the region the cells cover
+        gg = wl.Grid(g.x0 + g.dx / 2, g.y0 + g.dy / 2, g.dx / k, g.dy / k, (g.nx - 1) * k,
+                     (g.ny - 1) * k)
+        c = host(lf.irs_map(xy, m, grid=lfgrid(gg), map=md, method="direct", **kw))
+        return c * gg.dx * gg.dy / pix
+    dense = irs(16)
+    l1_ipm = np.abs(mu - dense).sum() / dense.sum()
+    l1_irs = np.abs(irs(1) - dense).sum() / dense.sum()
+    l1_8 = np.abs(irs(8) - dense).sum() / dense.sum()
+    print(f"ipm vs 16x irs: IPM L1 {l1_ipm:.4f}, IRS(1x) L1 {l1_irs:.4f}, IRS(8x) L1 {l1_8:.4f}")
+    assert l1_ipm <= l1_irs / 5
 
 
 def test_ipm_high_magnification_full_size(lf):

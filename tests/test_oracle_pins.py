@@ -426,11 +426,15 @@ def _convex_overlap_exact(poly, u, v):
                    for k in range(len(hull)))) / 2
 
 
-def _one_cell(corners, dx=0.5, dy=0.25, npix=8, side=8.0, max_pixels=64):
+def _one_cell(corners, dx=0.5, dy=0.25, npix=8, side=8.0):
     """A 2x2 grid (one cell) whose corners map to `corners` (source plane,
-    map [0, side)^2 so pixel units equal source units)."""
+    map [0, side)^2 so pixel units equal source units when side == npix)."""
     y = np.array([[corners[0], corners[1]], [corners[3], corners[2]]], dtype=np.float64)
-    return oracle.ipm(y, dx * dy, 0.0, 0.0, side, npix, max_pixels=max_pixels)
+    return oracle.ipm(y, dx * dy, 0.0, 0.0, side, npix)
+
+
+def _tri_area(t):
+    return abs((t[1][0] - t[0][0]) * (t[2][1] - t[0][1]) - (t[1][1] - t[0][1]) * (t[2][0] - t[0][0])) / 2
 
 
 @pytest.mark.parametrize("corners", [
@@ -470,25 +474,113 @@ def test_ipm_concave_cell_splits_into_triangles():
             assert abs(mu[v, u] - want) <= 1e-15 + 1e-13 * want
 
 
-def test_ipm_stretched_cell_goes_to_its_corners():
-    corners = [(1.25, 1.5), (5.75, 2.0), (4.5, 6.625), (0.5, 3.25)]   # bbox 6 x 6 pixels
-    exact = _one_cell(corners)
-    capped = _one_cell(corners, max_pixels=35)
-    want = np.zeros((8, 8))
-    for x, y in corners:
-        want[int(y), int(x)] += 0.125 / 4
-    np.testing.assert_allclose(capped, want, rtol=0, atol=1e-16)
-    assert np.count_nonzero(exact) > 4
-    np.testing.assert_array_equal(_one_cell(corners, max_pixels=36), exact)
+def test_ipm_wide_cell_is_apportioned_exactly():
+    """A cell stretched over ~600 pixels of a 32^2 map (as next to a star) is
+    still shared exactly by overlap: Section 2.3 apportions every cell."""
+    corners = [(2.25, 3.5), (29.75, 6.125), (27.5, 25.625), (4.5, 21.25)]
+    mu = _one_cell(corners, npix=32, side=32.0)
+    F = Fraction
+    poly = [(F(x), F(y)) for x, y in corners]
+    area = abs(sum(poly[k][0] * poly[(k + 1) % 4][1] - poly[(k + 1) % 4][0] * poly[k][1]
+                   for k in range(4))) / 2
+    for v in range(32):
+        for u in range(32):
+            want = float(F(1, 8) * _convex_overlap_exact(poly, u, v) / area)
+            assert abs(mu[v, u] - want) <= 1e-15 + 1e-12 * want, (u, v, mu[v, u], want)
+    assert np.count_nonzero(mu) > 500
+    assert abs(mu.sum() - 0.125) <= 1e-13
 
 
-def test_ipm_folded_cell_goes_to_its_corners():
-    corners = [(1.5, 1.5), (5.5, 5.5), (5.5, 1.5), (1.5, 5.5)]   # a bow tie
+@pytest.mark.parametrize("corners", [
+    [(1.5, 1.5), (5.5, 5.5), (5.5, 1.5), (1.5, 5.5)],            # edges 0-1 and 2-3 cross
+    [(1.25, 2.0), (6.5, 1.5), (1.75, 6.25), (5.75, 5.5)],         # edges 1-2 and 3-0 cross
+])
+def test_ipm_folded_cell_spreads_over_its_lobes(corners):
+    """A critical cell (its image's edges cross) is treated as if it were not
+    critical (Section 2.3): the region its edges enclose, the two triangles
+    on either side of the crossing point, takes the cell's area by overlap."""
+    mu = _one_cell(corners)
+    F = Fraction
+    P = [(F(x), F(y)) for x, y in corners]
+
+    def crossing(a, b, c, d):
+        den = (b[0] - a[0]) * (d[1] - c[1]) - (b[1] - a[1]) * (d[0] - c[0])
+        t = ((c[0] - a[0]) * (d[1] - c[1]) - (c[1] - a[1]) * (d[0] - c[0])) / den
+        return (a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1])), 0 < t < 1
+    X, ok = crossing(P[0], P[1], P[2], P[3])
+    if ok:
+        lobes = [[X, P[1], P[2]], [P[0], X, P[3]]]
+    else:
+        X, ok = crossing(P[1], P[2], P[3], P[0])
+        lobes = [[P[0], P[1], X], [X, P[2], P[3]]]
+    assert ok
+    area = sum(_tri_area(t) for t in lobes)
+    for v in range(8):
+        for u in range(8):
+            ov = sum(_convex_overlap_exact(t, u, v) for t in lobes)
+            want = float(F(1, 8) * ov / area)
+            assert abs(mu[v, u] - want) <= 1e-15 + 1e-13 * want, (u, v, mu[v, u], want)
+    assert abs(mu.sum() - 0.125) <= 1e-14
+
+
+def test_ipm_zero_area_cell_goes_to_its_corners():
+    corners = [(1.5, 1.5), (3.5, 3.5), (5.5, 5.5), (2.5, 2.5)]   # all on one line
     mu = _one_cell(corners)
     want = np.zeros((8, 8))
     for x, y in corners:
         want[int(y), int(x)] += 0.125 / 4
     np.testing.assert_allclose(mu, want, rtol=0, atol=1e-16)
+
+
+def _point_lens_pixel_average(npix, side):
+    """Exact pixel averages of the point lens's total magnification
+    mu(u) = (u^2+2)/(u sqrt(u^2+4)) over an npix^2 map centred on the lens
+    (midpoint rule, 64^2 points per pixel; 2048^2 around the caustic point,
+    where mu ~ 1/u)."""
+    h = side / npix
+    lo = -side / 2
+
+    def mu(x, y):
+        u = np.hypot(x, y)
+        return (u * u + 2) / (u * np.sqrt(u * u + 4))
+    g = (np.arange(64) + 0.5) / 64 * h
+    ref = np.empty((npix, npix))
+    xs = (lo + np.arange(npix)[:, None] * h + g[None, :]).ravel()
+    for v in range(npix):
+        ys = lo + v * h + g
+        ref[v] = mu(xs[None, :], ys[:, None]).reshape(64, npix, 64).mean(axis=(0, 2))
+    c = npix // 2
+    g2 = (np.arange(2048) + 0.5) / 2048 * h
+    for v in range(c - 2, c + 2):
+        for u in range(c - 2, c + 2):
+            ref[v, u] = mu(lo + u * h + g2[None, :], lo + v * h + g2[:, None]).mean()
+    return ref
+
+
+@pytest.mark.parametrize("n,bound", [(384, 7.5e-3), (768, 3e-3)])
+def test_ipm_point_lens_whole_map_against_analytic(n, bound):
+    """External pin of the whole first-order IPM, folded cells included: a
+    point lens shot with n^2 grid rays over [-3,3]^2 (n0 = 1 and 4 rays per
+    unlensed pixel) into a 128^2 map over [-1,1]^2 that contains the caustic
+    point (cells along the Einstein ring fold).  Against the analytic
+    pixel-averaged magnification the relative L1 error is 6.4e-3 and 1.5e-3
+    (a zeroth-order treatment of the folded cells gives 8.6e-3 at n0 = 1,
+    and inverse ray shooting of the same rays 0.30 and 0.10)."""
+    npix, side = 128, 2.0
+    ref = _point_lens_pixel_average(npix, side)
+    dx = 6.0 / n
+    xs = -3.0 + (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(xs, xs)
+    r2 = X * X + Y * Y
+    yg = np.stack([X - X / r2, Y - Y / r2], -1)
+    mu = oracle.ipm(yg, dx * dx, -1.0, -1.0, side, npix)
+    l1 = np.abs(mu - ref).sum() / ref.sum()
+    counts, _ = oracle.bin_rays(yg.reshape(-1, 2), -1.0, -1.0, side, npix)
+    irs = counts * dx * dx / (side / npix) ** 2
+    l1_irs = np.abs(irs - ref).sum() / ref.sum()
+    print(f"point lens n={n}: IPM L1 {l1:.2e}, IRS L1 {l1_irs:.2e}")
+    assert l1 <= bound
+    assert l1 <= l1_irs / 20
 
 
 @pytest.mark.parametrize("M", [((0.7, 0.0), (0.0, 1.3)), ((0.45, -0.62), (0.81, 0.2)),
