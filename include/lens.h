@@ -167,6 +167,32 @@ LENS_API lens_status lens_deflect(lens_plan *plan, const lens_field *field, cons
                          const double *rays_xy, int64_t n_rays, double *y_out, const lens_opts *opts,
                          void *stream);
 
+/* Device scratch held by the allocation-free entry point (per GPU, for the
+ * life of the process). */
+#define LENS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * lens_deflect for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same result as lens_deflect(plan, field, grid, NULL, nx*ny, y_out, opts,
+ * stream) -- bit for bit -- for a grid of rays and an existing plan (which
+ * holds the star side, built once by lens_plan_create).  The per-call
+ * buffers (local expansions of every level, ray ranges) live in a static
+ * device array of LENS_NOALLOC_SCRATCH_BYTES per GPU instead of the
+ * library's pool; the grid is evaluated in bands of whole rows whose buffers
+ * fit, one after another on `stream`.  No hipMalloc, hipFree or pool call is
+ * made and the stage profiler records nothing.  Every call on one GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (on different
+ * streams, or from different threads) race and must not be made.
+ * LENS_ENOMEM (nothing enqueued) if even a single grid row needs more than
+ * LENS_NOALLOC_SCRATCH_BYTES; LENS_EINVAL for a NULL plan or grid, or rays
+ * outside the plan's region.  opts->method = LENS_DIRECT sums directly (no
+ * scratch).  All pointers as in lens_deflect.
+ */
+LENS_API lens_status lens_deflect_noalloc(lens_plan *plan, const lens_field *field,
+                                          const lens_grid *grid, double *y_out,
+                                          const lens_opts *opts, void *stream);
+
 /*
  * Inverse ray shooting: deflect every ray of `grid` and add it to the map
  * (see lens_map_desc).  Rays are processed in chunks of whole grid rows of at

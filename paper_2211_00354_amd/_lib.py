@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH):
     lib.lens_plan_info.restype = ctypes.c_int
     lib.lens_deflect.argtypes = [V, P(LensField), P(LensGrid), V, I64, V, P(LensOpts), V]
     lib.lens_deflect.restype = ctypes.c_int
+    lib.lens_deflect_noalloc.argtypes = [V, P(LensField), P(LensGrid), V, P(LensOpts), V]
+    lib.lens_deflect_noalloc.restype = ctypes.c_int
     lib.lens_map.argtypes = [V, P(LensField), P(LensGrid), P(LensMapDesc), P(LensOpts), V]
     lib.lens_map.restype = ctypes.c_int
     lib.lens_last_error.argtypes = []

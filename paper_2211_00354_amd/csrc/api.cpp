@@ -609,16 +609,56 @@ struct GridExec {
   }
 };
 
+// Bytes of per-call device memory the evaluation of grid rows [j0, j1)
+// needs: the locals of every level over the rows' windows and the ray
+// ranges of the leaf window (each piece aligned to 256 bytes).
+constexpr size_t kAlign = 256;
+size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+size_t gridexec_bytes(const lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1) {
+  double bb[4];
+  grid_bbox(grid, j0, j1, bb);
+  size_t total = 0;
+  for (int l = 2; l <= P.g.L; ++l) total += align_up((size_t)window_for(P, l, bb).count() * P.p * 16);
+  const Window wl = window_for(P, P.g.L, bb);
+  total += align_up((size_t)(wl.nbx + 1) * sizeof(int32_t));
+  total += align_up((size_t)(wl.nby + 1) * sizeof(int32_t));
+  return total;
+}
+
+// Windows, buffers and launch shape of grid rows [j0, j1).  Buffers come
+// from the pool, or, if `region` is given, are carved from it in order
+// (gridexec_bytes of them; the GridExec then owns nothing).
 void gridexec_alloc(const lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, GridExec &ge,
-                    hipStream_t st) {
+                    hipStream_t st, char *region = nullptr) {
   ge.j0 = j0;
   ge.j1 = j1;
   grid_bbox(grid, j0, j1, ge.bb);
   check_inside(P, ge.bb);
-  locals_alloc(P, ge.bb, ge.ls, st);
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    DevBuf b;
+    b.ptr = region + off;
+    b.bytes = bytes;
+    off += align_up(bytes);
+    return b;
+  };
+  if (region) {
+    const int L = P.g.L;
+    ge.ls.win.assign(L + 1, Window{0, 0, 0, 0});
+    ge.ls.loc.assign(L + 1, DevBuf{});
+    for (int l = 2; l <= L; ++l) {
+      ge.ls.win[l] = window_for(P, l, ge.bb);
+      ge.ls.loc[l] = carve((size_t)ge.ls.win[l].count() * P.p * 16);
+    }
+  } else {
+    locals_alloc(P, ge.bb, ge.ls, st);
+  }
   const Window wl = ge.ls.win[P.g.L];
-  ge.col_start = pool_get((size_t)(wl.nbx + 1) * sizeof(int32_t), st);
-  ge.row_start = pool_get((size_t)(wl.nby + 1) * sizeof(int32_t), st);
+  ge.col_start = region ? carve((size_t)(wl.nbx + 1) * sizeof(int32_t))
+                        : pool_get((size_t)(wl.nbx + 1) * sizeof(int32_t), st);
+  ge.row_start = region ? carve((size_t)(wl.nby + 1) * sizeof(int32_t))
+                        : pool_get((size_t)(wl.nby + 1) * sizeof(int32_t), st);
   EvalArgs &ea = ge.ea;
   fill_star_side(P, wl, ge.ls.at(P.g.L), ea);
   ea.grid_mode = 1;
@@ -1311,6 +1351,73 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
 }
 
 }  // namespace
+
+namespace lensfmm {
+
+// Grid deflection with a plan into a caller-provided device region: no
+// device memory is allocated.  The grid is split into bands of whole rows
+// whose per-call buffers (locals of every level, ray ranges) fit in
+// `bytes`, evaluated one after another on the stream in the same region.
+// Every band is planned on the host before anything is enqueued.
+void deflect_grid_no_alloc(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                           double *y_out, const lens_opts *opts, char *region, size_t bytes,
+                           hipStream_t st) {
+  if (!plan) fail(LENS_EINVAL, "plan is NULL (the allocation-free deflection needs a plan)");
+  const lens_opts o = resolve_opts(opts);
+  FieldView fv = field_for(plan, field);
+  check_plan_device(plan);
+  if (!grid) fail(LENS_EINVAL, "grid is NULL");
+  check_grid(grid);
+  const int64_t n = grid->nx * grid->ny;
+  if (n > (int64_t)std::numeric_limits<uint32_t>::max() - 1) fail(LENS_EINVAL, "grid exceeds 2^32-2 rays");
+  if (n == 0) return;
+  if (!y_out) fail(LENS_EINVAL, "y_out is NULL");
+  const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
+  const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
+  NoTiming quiet;  // no stage events either
+  if (o.method == LENS_DIRECT || fv.f.n_stars == 0) {
+    DirectArgs d{};
+    d.n_stars = fv.f.n_stars;
+    d.sxy = fv.f.xy;
+    d.sm = fv.f.m;
+    d.grid_mode = 1;
+    d.grid = *grid;
+    d.n_rays = n;
+    d.c1 = c1;
+    d.c2 = c2;
+    d.y_out = y_out;
+    launch_direct(d, st);
+    return;
+  }
+  if (!op_tables_if_built(plan->p))
+    fail(LENS_EUNSUPPORTED, "operator tables of the plan's order are not on this device");
+  double bb[4];
+  grid_bbox(*grid, 0, grid->ny, bb);
+  check_inside(*plan, bb);
+  std::vector<std::pair<int64_t, int64_t>> bands;
+  for (int64_t j0 = 0; j0 < grid->ny;) {
+    const size_t one = gridexec_bytes(*plan, *grid, j0, j0 + 1);
+    if (one > bytes)
+      fail(LENS_ENOMEM, "one grid row needs " + std::to_string(one) +
+                            " bytes of scratch, more than the allocation-free entry point's " +
+                            std::to_string(bytes) + " (use lens_deflect)");
+    int64_t lo = j0 + 1, hi = grid->ny;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (gridexec_bytes(*plan, *grid, j0, mid) <= bytes) lo = mid; else hi = mid - 1;
+    }
+    bands.emplace_back(j0, lo);
+    j0 = lo;
+  }
+  for (const auto &b : bands) {
+    GridExec ge;
+    gridexec_alloc(*plan, *grid, b.first, b.second, ge, st, region);
+    gridexec_enqueue(*plan, ge, c1, c2, y_out, nullptr, st);
+  }
+  plan->last_stream = st;
+}
+
+}  // namespace lensfmm
 
 extern "C" {
 

@@ -131,6 +131,9 @@ struct OpTables {
   double *l2l_frag = nullptr;  // L2L as FP64 MFMA B fragments: [4][ks][nt][64]
 };
 const OpTables &op_tables(int p, hipStream_t stream);
+// The tables of order p on the current device if already built, else
+// nullptr (never allocates).
+const OpTables *op_tables_if_built(int p);
 
 // Host-side table builders (also exported for tests through lens_debug_*).
 void build_m2m_table(int p, std::vector<double> &out);
@@ -308,6 +311,20 @@ namespace lensfmm {
 bool profiling_enabled();
 // While a thread captures a HIP graph, StageTimer records nothing.
 void set_capturing(bool on);
+// Scope in which this thread's StageTimers record nothing (calls that must
+// not create runtime objects).
+struct NoTiming {
+  NoTiming();
+  ~NoTiming();
+  NoTiming(const NoTiming &) = delete;
+  NoTiming &operator=(const NoTiming &) = delete;
+};
+
+// Grid deflection with a plan into a caller-provided device region of
+// `bytes` bytes (allocates no device memory); see lens_deflect_noalloc.
+void deflect_grid_no_alloc(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                           double *y_out, const lens_opts *opts, char *region, size_t bytes,
+                           hipStream_t st);
 struct StageTimer {
   const char *name;
   hipStream_t stream;

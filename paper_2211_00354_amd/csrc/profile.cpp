@@ -39,8 +39,13 @@ void resolve_locked() {
 }  // namespace
 
 thread_local bool t_capturing = false;
+thread_local int t_no_timing = 0;
 void set_capturing(bool on) { t_capturing = on; }
-bool profiling_enabled() { return !t_capturing && g_on.load(std::memory_order_relaxed); }
+NoTiming::NoTiming() { ++t_no_timing; }
+NoTiming::~NoTiming() { --t_no_timing; }
+bool profiling_enabled() {
+  return !t_capturing && t_no_timing == 0 && g_on.load(std::memory_order_relaxed);
+}
 
 StageTimer::StageTimer(const char *n, hipStream_t s) : name(n), stream(s) {
   if (!profiling_enabled()) return;

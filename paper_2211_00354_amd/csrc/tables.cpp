@@ -181,6 +181,14 @@ T *upload(const std::vector<T> &h) {
 }
 }  // namespace
 
+const OpTables *op_tables_if_built(int p) {
+  int dev = 0;
+  LENS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  auto it = g_tabs.find(std::make_pair(dev, p));
+  return it == g_tabs.end() ? nullptr : &it->second;
+}
+
 const OpTables &op_tables(int p, hipStream_t stream) {
   (void)stream;
   int dev = 0;
