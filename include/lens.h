@@ -102,7 +102,9 @@ typedef struct {
 typedef struct {
   int32_t method;       /* LENS_FMM or LENS_DIRECT */
   int32_t precision;    /* LENS_FP64 or LENS_MIXED (LENS_DIRECT is always FP64) */
-  int32_t order_p;      /* expansion terms p in [1, LENS_MAX_ORDER]; 0 = 12 */
+  int32_t order_p;      /* expansion terms p in [1, LENS_MAX_ORDER]; 0 = chosen
+                           by the autotuner for `tol` (tol > 0, LENS_FMM;
+                           see lens_autotune), else 12 */
   int32_t leaf_level;   /* quadtree leaf level in [2, LENS_MAX_LEVEL]; 0 = chosen
                            by the library's cost model */
   int64_t max_rays_per_chunk;  /* lens_map: rays per chunk; 0 = the whole grid
@@ -111,10 +113,16 @@ typedef struct {
                            levels runs on FP32 MFMA, coarser levels on FP64;
                            0 = 2 levels, -1 = none (all M2L in FP64), at most
                            LENS_MAX_LEVEL.  Ignored for LENS_FP64. */
-  double tol;           /* lens_map_batched with order_p = 0 and tol > 0: each
-                           field's p, leaf level and fp32_levels are chosen by
-                           lens_autotune for this expected bin-reassignment
-                           fraction; otherwise unused */
+  double tol;           /* with order_p = 0: the target of the autotuner --
+                           the largest per-ray relative deflection error
+                           (lens_deflect, lens_plan_create with a grid) or the
+                           expected bin-reassignment fraction (lens_map,
+                           lens_map_ipm, lens_map_batched).  The first call
+                           for a problem measures (it waits on the stream); the
+                           choice is kept in-process and in an on-disk cache
+                           ($LENS_TUNE_CACHE, "off" to disable; default
+                           ~/.cache/lensfmm/autotune.txt) keyed by a coarse
+                           description of the problem.  Unused otherwise */
 } lens_opts;
 
 /* Fill *o with the defaults (FMM, mixed, p = 12, automatic leaf level). */
@@ -140,7 +148,9 @@ LENS_API lens_status lens_plan_create(const lens_field *field, const double *ray
                                       const lens_grid *grid, const lens_opts *opts, void *stream,
                                       lens_plan **out);
 
-/* Release a plan (waits for the plan's last stream to finish first). */
+/* Release a plan.  Does not wait: its device buffers return to the library's
+ * pool ordered after the work last enqueued with the plan (a later reuse on
+ * another stream waits for that work). */
 LENS_API void lens_plan_destroy(lens_plan *plan);
 
 /* Query a plan: expansion order, leaf level, root square (x0, y0, side). */
@@ -148,9 +158,17 @@ LENS_API lens_status lens_plan_info(const lens_plan *plan, int32_t *order_p, int
                            double *root_x0, double *root_y0, double *root_side);
 
 /*
- * Deflect rays: y_out[k][2] = y(x_k) (FP64, device).  Rays come from `grid`
- * (then rays_xy must be NULL and n_rays = grid->nx * grid->ny) or from the
- * explicit device array rays_xy[n_rays][2] (then grid must be NULL).
+ * Deflect rays: y_out[k][2] = y(x_k) (FP64, device), and, if dfdz_out is not
+ * NULL, dfdz_out[k][2] = f'(z_k) = -sum_i m_i / (z_k - z_i)^2 (real, imaginary
+ * parts; FP64, device), the derivative that Appendix A's expansions give in
+ * closed form.  With alpha = conj(f) the deflection Jacobian is
+ * d(alpha1, alpha2)/d(x1, x2) = [[Re f', -Im f'], [-Im f', -Re f']], so the
+ * lens map's Jacobian determinant is (1 - kappa_s)^2 - |gamma + conj(f')|^2
+ * (for the shear along x1).  A ray exactly on a star skips that pair in f'
+ * too; LENS_MIXED sums the near field of f' in FP32 (valid for pairs farther
+ * apart than ~1e-9 Einstein radii).  Rays come from `grid` (then rays_xy must
+ * be NULL and n_rays = grid->nx * grid->ny) or from the explicit device array
+ * rays_xy[n_rays][2] (then grid must be NULL).
  * `plan` may be NULL: the library then builds the star tree for this call,
  * waiting on the stream once to read back the stars' (and, for explicit
  * rays, the rays') bounding box.  Grid calls without a plan are cached: from
@@ -161,11 +179,12 @@ LENS_API lens_status lens_plan_info(const lens_plan *plan, int32_t *order_p, int
  * With a plan, the plan's (sorted) stars, expansion order, leaf level and
  * precision are used and opts->method still selects FMM or direct; `field`
  * may then be NULL (the plan's kappa_s and gamma apply) or supply only
- * kappa_s and gamma (its star pointers are ignored).
+ * kappa_s and gamma (its star pointers are ignored).  Grid calls with a plan
+ * do not wait on the stream.
  */
 LENS_API lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_grid *grid,
-                         const double *rays_xy, int64_t n_rays, double *y_out, const lens_opts *opts,
-                         void *stream);
+                                  const double *rays_xy, int64_t n_rays, double *y_out,
+                                  double *dfdz_out, const lens_opts *opts, void *stream);
 
 /* Device scratch held by the allocation-free entry point (per GPU, for the
  * life of the process). */
@@ -240,17 +259,22 @@ LENS_API lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, cons
  * Empirical autotuner for one field and ray grid: the expansion order p, the
  * leaf level and, for LENS_MIXED, fp32_levels (Appendix A leaves p and the
  * tree depth to the user; here they are measured).  A strided sample of at
- * most 128 x 128 rays of `grid` is deflected by the FP64 direct sum and by
+ * most 256 x 256 rays of `grid` is deflected by the FP64 direct sum and by
  * the FMM at p = 6, 7, ... (a plan over the whole grid, as lens_deflect and
  * lens_map build it).  The error is the largest per-ray relative deflection
  * error |dalpha_k| / max(|alpha_k|, 1e-3 rms alpha) over the sample when
  * map is NULL, else the expected fraction of
  * rays binned into another pixel of `map`, mean(|dy1| + |dy2|) npix / side
- * (map->counts is not touched).  Of the settings that reach `tol` the one
+ * (map->counts is not touched).  A setting reaches `tol` when its sampled
+ * error is at most 0.5 tol (a margin for the rays outside the sample).  Of
+ * the settings that reach `tol` the one
  * with the fastest whole lens_deflect (or lens_map) call is kept, and the
  * leaf level one either side of the library's choice is timed too (unless
  * base->leaf_level is set).  base: method and precision.  Runs full calls on
- * scratch memory and synchronises `stream`.  *out receives the chosen
+ * scratch memory and synchronises `stream`.  The choice is cached, as for
+ * order_p = 0 (in-process by the call's arrays and parameters, on disk by a
+ * coarse description of the problem): a cached answer returns without
+ * measuring (from the disk cache with err_out and ms_out NaN).  *out receives the chosen
  * options; err_out and ms_out (may be NULL) the sampled error and the time
  * of one call in ms.  LENS_EUNSUPPORTED if no p up to LENS_MAX_ORDER reaches
  * tol; *out then holds the most accurate setting tried.
@@ -277,19 +301,26 @@ LENS_API int32_t lens_profile_read(int32_t cap, const char **names, double *tota
  * grad_y[k][2] = dL/dy_k for the rays of `grid` (rays_xy NULL) or of
  * rays_xy[n_rays][2] (grid NULL), writes
  *     grad_xy[i][2] = dL/d(x_i),  grad_m[i] = dL/dm_i      (FP64, device)
- * for every star of `field` (kappa_s and gamma do not enter).  With
- * g_k = dL/dy1_k + i dL/dy2_k and h(z) = sum_k g_k / (z - z_k):
+ * for every star, in the caller's star order (kappa_s and gamma do not
+ * enter).  With g_k = dL/dy1_k + i dL/dy2_k and h(z) = sum_k g_k / (z - z_k):
  * dL/dm_i = Re h(z_i) and dL/dx_i + i dL/dy_i = m_i conj(h'(z_i)), from
  * differentiating eq. 1.  LENS_FMM evaluates h and h' by the fast multipole
  * method with the rays as sources (complex charges) and the stars as
- * targets; LENS_DIRECT sums them directly in FP64.  A ray exactly on a star
- * is skipped, as in the forward map.  Waits on `stream` to read back the
- * bounding boxes of the stars and the rays (FMM).
+ * targets; LENS_DIRECT sums them directly in FP64 over the field's star
+ * arrays (field required).  A ray exactly on a star is skipped, as in the
+ * forward map.
+ * With a `plan` (the forward call's; `field` may then be NULL) the stars,
+ * their tree, expansion order, precision and quadtree geometry come from the
+ * plan: the rays' tree takes the plan's geometry and the stars need no sort,
+ * so a grid call does not wait on the stream (explicit rays: one read-back of
+ * their bounding box, which must lie in the plan's root square).  Without a
+ * plan the call waits on the stream to read back the bounding boxes of the
+ * stars and the rays (FMM).
  */
-LENS_API lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid,
-                                           const double *rays_xy, int64_t n_rays,
-                                           const double *grad_y, double *grad_xy, double *grad_m,
-                                           const lens_opts *opts, void *stream);
+LENS_API lens_status lens_deflect_backward(lens_plan *plan, const lens_field *field,
+                                           const lens_grid *grid, const double *rays_xy,
+                                           int64_t n_rays, const double *grad_y, double *grad_xy,
+                                           double *grad_m, const lens_opts *opts, void *stream);
 
 /*
  * Inverse ray shooting for n_fields independent fields in one call: the rays

@@ -76,7 +76,7 @@ def _stream():
 
 
 def _opts(method="fmm", precision="mixed", p=12, leaf_level=0, max_rays_per_chunk=0,
-          fp32_levels=0) -> LensOpts:
+          fp32_levels=0, tol=0.0) -> LensOpts:
     o = LensOpts()
     _lib.load().lens_opts_default(ctypes.byref(o))
     o.method = {"fmm": LENS_FMM, "direct": LENS_DIRECT}[method]
@@ -85,6 +85,7 @@ def _opts(method="fmm", precision="mixed", p=12, leaf_level=0, max_rays_per_chun
     o.leaf_level = int(leaf_level)
     o.max_rays_per_chunk = int(max_rays_per_chunk)
     o.fp32_levels = int(fp32_levels)
+    o.tol = float(tol)
     return o
 
 
@@ -108,12 +109,13 @@ class Plan:
     """
 
     def __init__(self, star_xy, star_m, kappa_s=0.0, gamma=0.0, ray_box=None, grid=None,
-                 precision="mixed", p=12, leaf_level=0, fp32_levels=0):
+                 precision="mixed", p=12, leaf_level=0, fp32_levels=0, tol=0.0):
         lib = _lib.load()
         self._f = _field(star_xy, star_m, kappa_s, gamma)
+        self.n_stars = int(self._f.n_stars)
         self.precision = precision
         self.kappa_s, self.gamma = float(kappa_s), float(gamma)
-        o = _opts("fmm", precision, p, leaf_level, fp32_levels=fp32_levels)
+        o = _opts("fmm", precision, p, leaf_level, fp32_levels=fp32_levels, tol=tol)
         box = (ctypes.c_double * 4)(*ray_box) if ray_box is not None else None
         g = ctypes.byref(grid.c()) if grid is not None else None
         h = ctypes.c_void_p()
@@ -147,11 +149,17 @@ class Plan:
 
 def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, kappa_s=0.0,
             gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0,
-            plan: Optional[Plan] = None, out=None, fp32_levels=0):
+            plan: Optional[Plan] = None, out=None, fp32_levels=0, want_dfdz=False, dfdz_out=None,
+            tol=0.0):
     """Lens-map rays: returns y [n, 2] float64 on the GPU (eq. 1 + smooth term).
 
     Rays come from ``grid`` or from the explicit tensor ``rays`` [n, 2].  With
     ``plan`` the plan's stars are used; ``kappa_s``/``gamma`` still apply.
+    With ``want_dfdz`` (or a ``dfdz_out`` tensor) returns (y, dfdz) where
+    dfdz [n, 2] holds f'(z) = -sum m/(z - z_i)^2 (real, imaginary).
+    ``p=0`` with ``tol > 0`` lets the library's autotuner choose p, the leaf
+    level and the FP32 levels for that per-ray deflection error (measured
+    once, then cached in-process and on disk).
     """
     torch = _torch()
     lib = _lib.load()
@@ -176,17 +184,29 @@ def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, k
         _check_tensor(out, "out", 2)
         if out.numel() != 2 * n:
             raise ValueError("out must be [n, 2]")
-    o = _opts(method, precision, p, leaf_level, fp32_levels=fp32_levels)
+    want = want_dfdz or dfdz_out is not None
+    if want:
+        if dfdz_out is None:
+            dfdz_out = torch.empty((n, 2), dtype=torch.float64, device=dev)
+        else:
+            _check_tensor(dfdz_out, "dfdz_out", 2)
+            if dfdz_out.numel() != 2 * n:
+                raise ValueError("dfdz_out must be [n, 2]")
+    o = _opts(method, precision, p, leaf_level, fp32_levels=fp32_levels, tol=tol)
     _lib.check(lib.lens_deflect(plan.handle if plan else None, ctypes.byref(f), gp, rp, n,
-                                out.data_ptr() if n else None, ctypes.byref(o), _stream()))
-    return out
+                                out.data_ptr() if n else None,
+                                dfdz_out.data_ptr() if (want and n) else None, ctypes.byref(o),
+                                _stream()))
+    return (out, dfdz_out) if want else out
 
 
 def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, kappa_s=0.0,
             gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0,
-            max_rays_per_chunk=0, plan: Optional[Plan] = None, counts=None, fp32_levels=0):
+            max_rays_per_chunk=0, plan: Optional[Plan] = None, counts=None, fp32_levels=0,
+            tol=0.0):
     """Inverse ray shooting into an int32 [npix, npix] count map (accumulated
-    into ``counts`` if given, indexed [v, u])."""
+    into ``counts`` if given, indexed [v, u]).  ``p=0`` with ``tol > 0``: the
+    autotuner's setting for that expected bin-reassignment fraction."""
     torch = _torch()
     lib = _lib.load()
     if plan is None:
@@ -201,7 +221,7 @@ def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
         raise ValueError("counts must be a contiguous int32 [npix, npix] GPU tensor")
     md = LensMapDesc(map.y1min, map.y2min, map.side, map.npix, counts.data_ptr())
     g = grid.c()
-    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk, fp32_levels)
+    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk, fp32_levels, tol)
     _lib.check(lib.lens_map(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
                             ctypes.byref(md), ctypes.byref(o), _stream()))
     return counts
@@ -209,7 +229,7 @@ def irs_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
 
 def ipm_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, kappa_s=0.0,
             gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0, max_rays_per_chunk=0,
-            plan: Optional[Plan] = None, mu=None, fp32_levels=0):
+            plan: Optional[Plan] = None, mu=None, fp32_levels=0, tol=0.0):
     """Inverse polygon mapping: the grid rays are the corners of image-plane
     cells whose areas are shared among the source pixels their mapped
     quadrilaterals overlap.  Returns the float64 [npix, npix] magnification
@@ -228,7 +248,7 @@ def ipm_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
         raise ValueError("mu must be a contiguous float64 [npix, npix] GPU tensor")
     md = LensIpmDesc(map.y1min, map.y2min, map.side, map.npix, mu.data_ptr())
     g = grid.c()
-    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk, fp32_levels)
+    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk, fp32_levels, tol)
     _lib.check(lib.lens_map_ipm(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
                                 ctypes.byref(md), ctypes.byref(o), _stream()))
     return mu
@@ -295,15 +315,21 @@ def release_cached():
 
 
 def deflect_backward(star_xy, star_m, grad_y, grid: Optional[Grid] = None, rays=None,
-                     method="fmm", precision="mixed", p=12, leaf_level=0):
+                     method="fmm", precision="mixed", p=12, leaf_level=0,
+                     plan: Optional["Plan"] = None):
     """Gradient of a loss with respect to the lenses: given grad_y = dL/dy
     [n, 2] for the rays of ``grid`` or ``rays``, returns (dL/d star_xy [N, 2],
-    dL/d star_m [N]) as float64 GPU tensors."""
+    dL/d star_m [N]) as float64 GPU tensors.  With ``plan`` (the forward
+    call's) its star tree, order and precision are reused (star_xy/star_m
+    may then be None for the FMM)."""
     torch = _torch()
     lib = _lib.load()
     if (grid is None) == (rays is None):
         raise ValueError("give exactly one of grid and rays")
-    f = _field(star_xy, star_m, 0.0, 0.0)
+    if star_xy is None and plan is not None:
+        f = LensField(plan.n_stars, None, None, 0.0, 0.0)
+    else:
+        f = _field(star_xy, star_m, 0.0, 0.0)
     if grid is not None:
         n = int(grid.nx) * int(grid.ny)
         g = grid.c()
@@ -319,7 +345,7 @@ def deflect_backward(star_xy, star_m, grad_y, grid: Optional[Grid] = None, rays=
     gxy = torch.empty((f.n_stars, 2), dtype=torch.float64, device=dev)
     gm = torch.empty((f.n_stars,), dtype=torch.float64, device=dev)
     o = _opts(method, precision, p, leaf_level)
-    _lib.check(lib.lens_deflect_backward(ctypes.byref(f), gp, rp, n,
+    _lib.check(lib.lens_deflect_backward(plan.handle if plan else None, ctypes.byref(f), gp, rp, n,
                                          grad_y.data_ptr() if n else None,
                                          gxy.data_ptr() if f.n_stars else None,
                                          gm.data_ptr() if f.n_stars else None, ctypes.byref(o),
@@ -338,10 +364,21 @@ def _autograd_function():
         @staticmethod
         def forward(ctx, star_xy, star_m, rays=None, grid=None, kappa_s=0.0, gamma=0.0,
                     method="fmm", precision="mixed", p=12, leaf_level=0):
+            plan = None
+            if method == "fmm" and star_m.numel() > 0:
+                # the forward's plan (star tree) is kept for the backward
+                if rays is not None and rays.numel() > 0:
+                    lo, hi = rays.amin(0).tolist(), rays.amax(0).tolist()
+                    box = (lo[0], lo[1], hi[0], hi[1])
+                else:
+                    box = None
+                plan = Plan(star_xy, star_m, kappa_s=kappa_s, gamma=gamma, ray_box=box,
+                            grid=grid, precision=precision, p=p, leaf_level=leaf_level)
             y = deflect(star_xy, star_m, grid=grid, rays=rays, kappa_s=kappa_s, gamma=gamma,
-                        method=method, precision=precision, p=p, leaf_level=leaf_level)
+                        method=method, precision=precision, p=p, leaf_level=leaf_level, plan=plan)
             ctx.save_for_backward(star_xy, star_m, rays if rays is not None else star_m)
             ctx.has_rays = rays is not None
+            ctx.plan = plan
             ctx.cfg = (grid, method, precision, p, leaf_level)
             return y
 
@@ -351,7 +388,11 @@ def _autograd_function():
             grid, method, precision, p, leaf_level = ctx.cfg
             gxy, gm = deflect_backward(star_xy, star_m, grad_y.contiguous(), grid=grid,
                                        rays=rays if ctx.has_rays else None, method=method,
-                                       precision=precision, p=p, leaf_level=leaf_level)
+                                       precision=precision, p=p, leaf_level=leaf_level,
+                                       plan=ctx.plan)
+            if ctx.plan is not None:
+                ctx.plan.close()   # released behind the backward's work (no wait)
+                ctx.plan = None
             return gxy, gm, None, None, None, None, None, None, None, None
 
     return LensDeflect

@@ -80,7 +80,7 @@ def load(path: str = LIB_PATH):
     lib.lens_plan_destroy.restype = None
     lib.lens_plan_info.argtypes = [V, P(I32), P(I32), P(D), P(D), P(D)]
     lib.lens_plan_info.restype = ctypes.c_int
-    lib.lens_deflect.argtypes = [V, P(LensField), P(LensGrid), V, I64, V, P(LensOpts), V]
+    lib.lens_deflect.argtypes = [V, P(LensField), P(LensGrid), V, I64, V, V, P(LensOpts), V]
     lib.lens_deflect.restype = ctypes.c_int
     lib.lens_deflect_noalloc.argtypes = [V, P(LensField), P(LensGrid), V, P(LensOpts), V]
     lib.lens_deflect_noalloc.restype = ctypes.c_int
@@ -90,7 +90,8 @@ def load(path: str = LIB_PATH):
     lib.lens_last_error.restype = ctypes.c_char_p
     lib.lens_version.argtypes = []
     lib.lens_version.restype = ctypes.c_char_p
-    lib.lens_deflect_backward.argtypes = [P(LensField), P(LensGrid), V, I64, V, V, V, P(LensOpts), V]
+    lib.lens_deflect_backward.argtypes = [V, P(LensField), P(LensGrid), V, I64, V, V, V, P(LensOpts),
+                                          V]
     lib.lens_deflect_backward.restype = ctypes.c_int
     lib.lens_map_batched.argtypes = [I32, P(LensField), P(LensGrid), P(LensMapDesc), P(LensOpts), V]
     lib.lens_map_batched.restype = ctypes.c_int

@@ -57,7 +57,8 @@ __global__ __launch_bounds__(kWave) void k_eval_adj(
     EvalArgs a, const double *__restrict__ loc, const double *__restrict__ sxy,
     const double *__restrict__ sq, const int32_t *__restrict__ leaf_start,
     const double *__restrict__ txy, const double *__restrict__ tm, const uint32_t *__restrict__ tperm,
-    const int32_t *__restrict__ tstart, double *__restrict__ grad_xy, double *__restrict__ grad_m) {
+    const int32_t *__restrict__ tstart, int32_t tglobal, double *__restrict__ grad_xy,
+    double *__restrict__ grad_m) {
   const int lane = threadIdx.x;
   const uint32_t CH = (uint32_t)a.chunks_per_box;
   const uint32_t nbx = (uint32_t)a.win.nbx;
@@ -73,7 +74,10 @@ __global__ __launch_bounds__(kWave) void k_eval_adj(
     const uint32_t b = u / CH, c0 = u - b * CH;
     const uint32_t byw = b / nbx, bxw = b - byw * nbx;
     const int64_t gx = a.win.bx0 + bxw, gy = a.win.by0 + byw;
-    const int32_t t0 = tstart[b], nt = tstart[b + 1] - t0;
+    // target starts per window box, or (tglobal) per box of the whole leaf
+    // level, row-major (a forward plan's leaf starts)
+    const int64_t tb = tglobal ? gy * nL + gx : (int64_t)b;
+    const int32_t t0 = tstart[tb], nt = tstart[tb + 1] - t0;
     if (nt == 0 || (int64_t)c0 * RPC >= nt) continue;  // uniform
 
     int32_t rs[3], re[3];
@@ -199,8 +203,8 @@ void adj_launch(const EvalArgs &a, const AdjArgs &d, hipStream_t stream) {
   const int64_t units = a.win.count() * a.chunks_per_box;
   const int64_t nblk = units < 65536 ? units : 65536;
   hipLaunchKernelGGL((k_eval_adj<PM, MIXED, R>), dim3((unsigned)nblk), dim3(kWave), 0, stream, a,
-                     a.loc, a.sxy, d.sq, a.leaf_start, d.txy, d.tm, d.tperm, d.tstart, d.grad_xy,
-                     d.grad_m);
+                     a.loc, a.sxy, d.sq, a.leaf_start, d.txy, d.tm, d.tperm, d.tstart,
+                     (int32_t)d.tglobal, d.grad_xy, d.grad_m);
 }
 
 }  // namespace

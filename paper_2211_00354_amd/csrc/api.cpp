@@ -12,10 +12,16 @@
 // calls read one bounding box back from the device.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <string>
 #include <limits>
 #include <memory>
 #include <mutex>
+
+#include <sys/stat.h>
 
 #include "lens_internal.h"
 
@@ -32,6 +38,8 @@ struct lens_plan {
   double kappa_s = 0, gamma = 0;
   double domain[4] = {0, 0, 0, 0};
   double target[4] = {0, 0, 0, 0};  // every ray evaluated with the plan lies in this box
+  double star_bb[4] = {0, 0, 0, 0};  // the sources' bounding box (n_stars > 0)
+  const uint32_t *perm = nullptr;    // sorted position -> caller's source index
   // Levels 2..dense_top hold the multipoles of every box; a finer level only
   // those of its source window swin[l] (the boxes that can be M2L sources
   // for targets in the box above), each formed straight from the stars.
@@ -383,6 +391,7 @@ void plan_enqueue(lens_plan *P, const double *xy, const double *q, hipStream_t s
     const bool in_tmp = radix_sort_pairs(k, v, kt, vt, N, 2 * L, static_cast<uint32_t *>(P->cnt.ptr),
                                          static_cast<uint32_t *>(P->scan_tmp.ptr), st);
     const uint32_t *ks = in_tmp ? kt : k, *vs = in_tmp ? vt : v;
+    P->perm = vs;
     launch_gather_stars(vs, xy, q, P->qdim, N, sxy, sm, st);
     // all zero when N = 0
     launch_box_starts(ks, N, nbox, leaf_start, static_cast<int32_t *>(P->box_coarse.ptr), st);
@@ -437,6 +446,7 @@ lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_gri
       else
         device_bbox(f.xy, f.n_stars, st, sb);
       sbp = sb;
+      std::copy(sb, sb + 4, P->star_bb);
     }
     plan_geometry(P, f.n_stars, sbp, ray_box, align, rays_density, o);
     (void)op_tables(o.order_p, st);
@@ -685,12 +695,13 @@ void gridexec_alloc(const lens_plan &P, const lens_grid &grid, int64_t j0, int64
 
 // Kernels only: downward pass, ray ranges, evaluation (y_out or map).
 void gridexec_enqueue(const lens_plan &P, GridExec &ge, double c1, double c2, double *y_out,
-                      const lens_map_desc *map, hipStream_t st) {
+                      const lens_map_desc *map, hipStream_t st, double *dfdz = nullptr) {
   downward_enqueue(P, ge.ls, st);
   EvalArgs ea = ge.ea;
   ea.c1 = c1;
   ea.c2 = c2;
   ea.y_out = y_out;
+  ea.dfdz_out = dfdz;
   if (map) {
     ea.counts = map->counts;
     ea.y1min = map->y1min;
@@ -706,12 +717,13 @@ void gridexec_enqueue(const lens_plan &P, GridExec &ge, double c1, double c2, do
 
 // Grid rows [j0, j1) through the FMM path (deflect: y_out; map: binning).
 void fmm_grid_rows(lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, double c1, double c2,
-                   double *y_out, const lens_map_desc *map, double S, hipStream_t st) {
+                   double *y_out, const lens_map_desc *map, double S, hipStream_t st,
+                   double *dfdz = nullptr) {
   (void)S;
   GridExec ge;
   try {
     gridexec_alloc(P, grid, j0, j1, ge, st);
-    gridexec_enqueue(P, ge, c1, c2, y_out, map, st);
+    gridexec_enqueue(P, ge, c1, c2, y_out, map, st, dfdz);
   } catch (...) {
     ge.put_all(st);
     throw;
@@ -723,7 +735,8 @@ void fmm_grid_rows(lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, 
 // Explicit rays: sorted by leaf box of the window, evaluated box by box,
 // written back in the caller's order.
 void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4], double c1, double c2,
-                  double *y_out, hipStream_t st) {
+                  double *y_out, hipStream_t st,
+                  double *dfdz = nullptr) {
   Scratch sc(st);
   check_inside(P, bb);
   double *loc = nullptr;
@@ -751,6 +764,7 @@ void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4
   ea.c1 = c1;
   ea.c2 = c2;
   ea.y_out = y_out;
+  ea.dfdz_out = dfdz;
   // explicit rays: shape for the mean box occupancy; fuller boxes loop
   const int64_t per = (n + wl.count() - 1) / std::max<int64_t>(wl.count(), 1);
   eval_shape(std::max<int64_t>(per, 1), &ea.rays_per_lane, &ea.chunks_per_box);
@@ -797,7 +811,7 @@ void check_plan_device(const lens_plan *plan) {
 namespace {
 
 // ------------------------------------------------------------- autotuner
-// Accuracy is measured, not modelled: a strided sample of at most 128 x 128
+// Accuracy is measured, not modelled: a strided sample of at most 256 x 256
 // rays of the grid is deflected by the FP64 direct sum and by the FMM (a
 // plan over the whole grid, as a real call builds it) at increasing p.  The
 // error is the largest per-ray relative deflection error, or for a map the
@@ -859,7 +873,7 @@ double tune_time(const lens_field &f, const lens_grid &g, const lens_map_desc *m
   auto call = [&] {
     const lens_status r = map ? lens_map(nullptr, &f, &g, &md, &o, st)
                               : lens_deflect(nullptr, &f, &g, nullptr, g.nx * g.ny,
-                                             static_cast<double *>(scratch), &o, st);
+                                             static_cast<double *>(scratch), nullptr, &o, st);
     if (r != LENS_OK) fail(r, last_error());
   };
   call();
@@ -883,6 +897,12 @@ double tune_time(const lens_field &f, const lens_grid &g, const lens_map_desc *m
   return ms;
 }
 
+// A setting qualifies when its sampled error is below this fraction of the
+// target: the margin covers the rays outside the sample (the errors are
+// heavy-tailed -- a few rays near stars dominate the mean -- so the sampled
+// error of one setting can differ by ~2x between disjoint samples).
+constexpr double kTuneMargin = 0.5;
+
 TuneOut autotune_field(const lens_field &f, const lens_grid &g, const lens_map_desc *map,
                        double tol, const lens_opts &base, hipStream_t st) {
   TuneOut best;
@@ -893,7 +913,7 @@ TuneOut autotune_field(const lens_field &f, const lens_grid &g, const lens_map_d
   }
   Scratch sc(st);
   TuneSample ts;
-  const int64_t sx = std::max<int64_t>(1, g.nx / 128), sy = std::max<int64_t>(1, g.ny / 128);
+  const int64_t sx = std::max<int64_t>(1, g.nx / 256), sy = std::max<int64_t>(1, g.ny / 256);
   for (int64_t j = sy / 2; j < g.ny; j += sy)
     for (int64_t i = sx / 2; i < g.nx; i += sx) {
       ts.rays.push_back(grid_x(g, i));
@@ -963,7 +983,7 @@ TuneOut autotune_field(const lens_field &f, const lens_grid &g, const lens_map_d
         most.o = o;
         most.err = e;
       }
-      if (e <= tol) {
+      if (e <= kTuneMargin * tol) {
         TuneOut t;
         t.o = o;
         t.err = e;
@@ -1002,7 +1022,7 @@ TuneOut autotune_field(const lens_field &f, const lens_grid &g, const lens_map_d
       const double ms = tune_time(f, g, map, o, scratch, st);
       if (ms < best.ms) {
         const double e = measure(o);
-        if (e <= tol) {
+        if (e <= kTuneMargin * tol) {
           best.o = o;
           best.ms = ms;
           best.err = e;
@@ -1011,6 +1031,196 @@ TuneOut autotune_field(const lens_field &f, const lens_grid &g, const lens_map_d
     }
   }
   return best;
+}
+
+// cache keys: words of the call's arguments
+void key_push(std::vector<uint64_t> &k, double v) {
+  uint64_t w;
+  std::memcpy(&w, &v, 8);
+  k.push_back(w);
+}
+void key_push(std::vector<uint64_t> &k, int64_t v) { k.push_back((uint64_t)v); }
+void key_push(std::vector<uint64_t> &k, const void *p) { k.push_back((uint64_t)(uintptr_t)p); }
+
+// ------------------------------------------------- automatic order (tol)
+// order_p = 0 with tol > 0 asks for the autotuner's setting.  Results are
+// kept in-process (by the call's arrays, sizes and parameters) and on disk
+// (by a coarse description of the problem: precision, target, tol, N_*,
+// rays per star, smooth terms and pixel scale, rounded), so a later process
+// with a similar field reuses the measured order without measuring.  The
+// file is $LENS_TUNE_CACHE (empty or "off": no disk cache), else
+// $XDG_CACHE_HOME/lensfmm/autotune.txt, else ~/.cache/lensfmm/autotune.txt.
+
+std::mutex g_tune_mu;
+std::vector<std::pair<std::vector<uint64_t>, TuneOut>> g_tuned;  // most recent last
+bool g_disk_loaded = false;
+std::map<std::string, lens_opts> g_disk;
+
+std::string tune_cache_path() {
+  const char *e = std::getenv("LENS_TUNE_CACHE");
+  if (e) return (std::string(e) == "off") ? std::string() : std::string(e);
+  const char *x = std::getenv("XDG_CACHE_HOME");
+  if (x && *x) return std::string(x) + "/lensfmm/autotune.txt";
+  const char *h = std::getenv("HOME");
+  if (h && *h) return std::string(h) + "/.cache/lensfmm/autotune.txt";
+  return std::string();
+}
+
+// coarse description of a tuning problem (the on-disk key)
+std::string tune_disk_key(int device, const lens_field &f, const lens_grid &g,
+                          const lens_map_desc *map, const lens_opts &o) {
+  hipDeviceProp_t prop{};
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+  (void)hipGetLastError();
+  auto r2 = [](double v) { return std::lround(2.0 * std::log2(std::max(v, 1e-300))); };
+  auto r100 = [](double v) { return std::lround(100.0 * v); };
+  const double rays = (double)(g.nx * g.ny);
+  std::string k = arch.substr(0, arch.find(':')) + (o.precision == LENS_MIXED ? " mixed" : " fp64") +
+                  (map ? " map" : " deflect") + " tol " + std::to_string(std::lround(8.0 * std::log2(o.tol))) +
+                  " n " + std::to_string(r2((double)f.n_stars)) +
+                  " rps " + std::to_string(r2(rays / std::max<double>((double)f.n_stars, 1.0))) +
+                  " ks " + std::to_string(r100(f.kappa_s)) + " g " + std::to_string(r100(f.gamma)) +
+                  " leaf " + std::to_string(o.leaf_level);
+  if (map) k += " px " + std::to_string(r2(map->side / map->npix / std::sqrt(g.dx * g.dy)));
+  return k;
+}
+
+void load_disk_locked() {
+  if (g_disk_loaded) return;
+  g_disk_loaded = true;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE *fp = std::fopen(path.c_str(), "r");
+  if (!fp) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, fp)) {
+    // key | p fp32_levels leaf_level
+    char *bar = std::strchr(line, '|');
+    if (!bar) continue;
+    *bar = 0;
+    int p = 0, fl = 0, L = 0;
+    if (std::sscanf(bar + 1, "%d %d %d", &p, &fl, &L) != 3) continue;
+    if (p < 1 || p > LENS_MAX_ORDER || L < 0 || L > LENS_MAX_LEVEL) continue;
+    lens_opts o;
+    lens_opts_default(&o);
+    o.order_p = p;
+    o.fp32_levels = fl;
+    o.leaf_level = L;
+    g_disk[std::string(line)] = o;
+  }
+  std::fclose(fp);
+}
+
+void save_disk_locked(const std::string &key, const lens_opts &o) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    // create the directory chain (best effort; failures only skip caching)
+    std::string dir = path.substr(0, slash);
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+  }
+  FILE *fp = std::fopen(path.c_str(), "a");
+  if (!fp) return;
+  std::fprintf(fp, "%s|%d %d %d\n", key.c_str(), o.order_p, o.fp32_levels, o.leaf_level);
+  std::fclose(fp);
+}
+
+// The autotuner's choice for a problem, measured once per process (and
+// once per machine, through the disk cache; a disk hit carries no measured
+// error or time: NaN).  opts: the caller's method, precision, leaf level and
+// fp32_levels unless tuned.
+TuneOut tuned_cached(const lens_field &f, const lens_grid &g, const lens_map_desc *map,
+                     const lens_opts &user, hipStream_t st) {
+  lens_opts base = user;
+  base.order_p = 0;
+  int dev = 0;
+  LENS_HIP(hipGetDevice(&dev));
+  std::vector<uint64_t> key;
+  key_push(key, (int64_t)dev);
+  key_push(key, (const void *)f.xy);
+  key_push(key, (const void *)f.m);
+  key_push(key, f.n_stars);
+  key_push(key, f.kappa_s);
+  key_push(key, f.gamma);
+  key_push(key, g.x0);
+  key_push(key, g.y0);
+  key_push(key, g.dx);
+  key_push(key, g.dy);
+  key_push(key, g.nx);
+  key_push(key, g.ny);
+  key_push(key, (int64_t)(map != nullptr));
+  if (map) {
+    key_push(key, map->y1min);
+    key_push(key, map->y2min);
+    key_push(key, map->side);
+    key_push(key, (int64_t)map->npix);
+  }
+  key_push(key, user.tol);
+  key_push(key, (int64_t)user.method);
+  key_push(key, (int64_t)user.precision);
+  key_push(key, (int64_t)user.leaf_level);
+  key_push(key, (int64_t)user.fp32_levels);
+  const std::string dkey = tune_disk_key(dev, f, g, map, user);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (size_t i = 0; i < g_tuned.size(); ++i)
+      if (g_tuned[i].first == key) {
+        auto e = g_tuned[i];
+        g_tuned.erase(g_tuned.begin() + (long)i);
+        g_tuned.push_back(e);
+        return e.second;
+      }
+    load_disk_locked();
+    auto it = g_disk.find(dkey);
+    if (it != g_disk.end()) {
+      TuneOut t;
+      t.o = base;
+      t.o.order_p = it->second.order_p;
+      t.o.fp32_levels = it->second.fp32_levels;
+      t.o.leaf_level = it->second.leaf_level;
+      t.err = t.ms = std::numeric_limits<double>::quiet_NaN();
+      t.met = true;
+      g_tuned.emplace_back(key, t);
+      if (g_tuned.size() > 32) g_tuned.erase(g_tuned.begin());
+      return t;
+    }
+  }
+  const TuneOut t = autotune_field(f, g, map, user.tol, base, st);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.emplace_back(key, t);
+  if (g_tuned.size() > 32) g_tuned.erase(g_tuned.begin());
+  if (t.met && user.method == LENS_FMM) {
+    g_disk[dkey] = t.o;
+    save_disk_locked(dkey, t.o);
+  }
+  return t;
+}
+
+// The options a call with order_p = 0 and tol > 0 runs with (the most
+// accurate setting tried if none reached tol).
+lens_opts auto_opts(const lens_field &f, const lens_grid &g, const lens_map_desc *map,
+                    const lens_opts &user, hipStream_t st) {
+  const TuneOut t = tuned_cached(f, g, map, user, st);
+  return resolve_opts(&t.o);
+}
+
+bool wants_auto(const lens_opts *o) {
+  return o && o->order_p == 0 && o->tol > 0 && std::isfinite(o->tol) && o->method == LENS_FMM;
+}
+
+// A 128 x 128 grid over the box bb, standing in for explicit rays when tuning.
+lens_grid tuning_grid(const double bb[4]) {
+  lens_grid g{};
+  g.nx = g.ny = 128;
+  const double w = std::max(bb[2] - bb[0], 1e-12), h = std::max(bb[3] - bb[1], 1e-12);
+  g.dx = w / 128.0;
+  g.dy = h / 128.0;
+  g.x0 = bb[0];
+  g.y0 = bb[1];
+  return g;
 }
 
 // ------------------------------------------------------- batched fields
@@ -1055,13 +1265,6 @@ struct BatchExec {
 std::mutex g_batch_mu;
 std::vector<std::unique_ptr<BatchExec>> g_batches;
 
-void key_push(std::vector<uint64_t> &k, double v) {
-  uint64_t w;
-  std::memcpy(&w, &v, 8);
-  k.push_back(w);
-}
-void key_push(std::vector<uint64_t> &k, int64_t v) { k.push_back((uint64_t)v); }
-void key_push(std::vector<uint64_t> &k, const void *p) { k.push_back((uint64_t)(uintptr_t)p); }
 
 std::vector<uint64_t> batch_key(int dev, int n, const lens_field *f, const lens_grid *g,
                                 const lens_map_desc *m, const lens_opts &o) {
@@ -1114,8 +1317,7 @@ std::unique_ptr<BatchExec> batch_build(int n, const lens_field *f, const lens_gr
     if (f[i].n_stars == 0 || o.method == LENS_DIRECT) continue;
     lens_opts oi = o;
     if (tune) {
-      const TuneOut t = autotune_field(f[i], g[i], &m[i], tune_base.tol, tune_base, st);
-      oi = resolve_opts(&t.o);  // the most accurate setting if none reached tol
+      oi = auto_opts(f[i], g[i], &m[i], tune_base, st);
       (void)op_tables(oi.order_p, st);
     }
     auto *P = new lens_plan();
@@ -1127,6 +1329,7 @@ std::unique_ptr<BatchExec> batch_build(int n, const lens_field *f, const lens_gr
     grid_bbox(g[i], 0, g[i].ny, gb);
     const double area = std::max((gb[2] - gb[0]) * (gb[3] - gb[1]), 1e-300);
     plan_geometry(P, f[i].n_stars, &bbox[4 * i], gb, &g[i], (double)(g[i].nx * g[i].ny) / area, oi);
+    std::copy(&bbox[4 * i], &bbox[4 * i] + 4, P->star_bb);
     plan_alloc(P, st);
     B->ge[i] = std::make_unique<GridExec>();
     gridexec_alloc(*P, g[i], 0, g[i].ny, *B->ge[i], st);
@@ -1272,7 +1475,8 @@ std::vector<uint64_t> call_key(const lens_field &f, const lens_grid &g, const le
 // The whole grid in one pass through the call-graph cache (see above).
 void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &o, double c1,
                    double c2, double *y_out, const lens_map_desc *map, double S,
-                   hipStream_t st) {
+                   hipStream_t st,
+                   double *dfdz = nullptr) {
   double sb[4];
   device_bbox(f.xy, f.n_stars, st, sb);
   double bb[4];
@@ -1282,7 +1486,7 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   auto eager = [&] {
     lens_plan *P = build_plan(f, bb, &grid, density, o, st, nullptr, sb);
     try {
-      fmm_grid_rows(*P, grid, 0, grid.ny, c1, c2, y_out, map, S, st);
+      fmm_grid_rows(*P, grid, 0, grid.ny, c1, c2, y_out, map, S, st, dfdz);
     } catch (...) {
       lens_plan_destroy(P);
       throw;
@@ -1295,6 +1499,7 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   LENS_HIP(hipGetDevice(&probe.device));
   plan_geometry(&probe, f.n_stars, sb, bb, &grid, density, o);
   auto key = call_key(f, grid, o, y_out, map, probe, st);
+  key_push(key, (const void *)dfdz);
   std::lock_guard<std::mutex> lk(g_call_mu);
   for (size_t i = 0; i < g_calls.size(); ++i)
     if (g_calls[i]->key == key) {
@@ -1318,6 +1523,7 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   P->kappa_s = f.kappa_s;
   P->gamma = f.gamma;
   plan_geometry(P, f.n_stars, sb, bb, &grid, density, o);
+  std::copy(sb, sb + 4, P->star_bb);
   (void)op_tables(o.order_p, st);
   plan_alloc(P, st);
   gridexec_alloc(*P, grid, 0, grid.ny, c->ge, st);
@@ -1331,7 +1537,7 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   }
   try {
     plan_enqueue(P, f.xy, f.m, c->origin);
-    gridexec_enqueue(*P, c->ge, c1, c2, y_out, map, c->origin);
+    gridexec_enqueue(*P, c->ge, c1, c2, y_out, map, c->origin, dfdz);
   } catch (...) {
     hipGraph_t tmp = nullptr;
     (void)hipStreamEndCapture(c->origin, &tmp);
@@ -1440,7 +1646,13 @@ lens_status lens_plan_create(const lens_field *field, const double *ray_box, con
   return guarded([&] {
     if (!out) fail(LENS_EINVAL, "out is NULL");
     check_field(field);
-    const lens_opts o = resolve_opts(opts);
+    lens_opts o = resolve_opts(opts);
+    if (wants_auto(opts) && field->n_stars > 0) {
+      if (!grid || grid->nx * grid->ny == 0)
+        fail(LENS_EINVAL, "order_p = 0 with tol > 0 needs a grid to tune on");
+      check_grid(grid);
+      o = auto_opts(*field, *grid, nullptr, *opts, (hipStream_t)stream);
+    }
     double gbox[4];
     if (grid) {
       check_grid(grid);
@@ -1473,7 +1685,9 @@ lens_status lens_plan_create(const lens_field *field, const double *ray_box, con
 
 void lens_plan_destroy(lens_plan *plan) {
   if (!plan) return;
-  plan->release();
+  // stream-ordered: the buffers go back to the pool behind the plan's last
+  // work, and a later reuse on another stream waits for it
+  plan->put_all(plan->last_stream);
   delete plan;
 }
 
@@ -1490,11 +1704,11 @@ lens_status lens_plan_info(const lens_plan *plan, int32_t *order_p, int32_t *lea
 }
 
 lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_grid *grid,
-                         const double *rays_xy, int64_t n_rays, double *y_out, const lens_opts *opts,
-                         void *stream) {
+                         const double *rays_xy, int64_t n_rays, double *y_out, double *dfdz_out,
+                         const lens_opts *opts, void *stream) {
   return guarded([&] {
     hipStream_t st = (hipStream_t)stream;
-    const lens_opts o = resolve_opts(opts);
+    lens_opts o = resolve_opts(opts);
     FieldView fv = field_for(plan, field);
     if (plan) check_plan_device(plan);
     if ((grid == nullptr) == (rays_xy == nullptr) && !(grid == nullptr && n_rays == 0))
@@ -1523,13 +1737,15 @@ lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_gr
       d.c1 = c1;
       d.c2 = c2;
       d.y_out = y_out;
+      d.dfdz_out = dfdz_out;
       StageTimer tm("direct", st);
       launch_direct(d, st);
       return;
     }
 
     if (!plan && grid) {
-      fmm_grid_call(fv.f, *grid, o, c1, c2, y_out, nullptr, 0.0, st);
+      if (wants_auto(opts)) o = auto_opts(fv.f, *grid, nullptr, *opts, st);
+      fmm_grid_call(fv.f, *grid, o, c1, c2, y_out, nullptr, 0.0, st, dfdz_out);
       return;
     }
     double bb[4];
@@ -1538,6 +1754,7 @@ lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_gr
     } else {
       device_bbox(rays_xy, n_rays, st, bb);
     }
+    if (!plan && wants_auto(opts)) o = auto_opts(fv.f, tuning_grid(bb), nullptr, *opts, st);
     lens_plan *P = plan;
     lens_plan *owned = nullptr;
     if (!P) {
@@ -1546,9 +1763,9 @@ lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_gr
     }
     try {
       if (grid)
-        fmm_grid_rows(*P, *grid, 0, grid->ny, c1, c2, y_out, nullptr, 0.0, st);
+        fmm_grid_rows(*P, *grid, 0, grid->ny, c1, c2, y_out, nullptr, 0.0, st, dfdz_out);
       else
-        fmm_explicit(*P, rays_xy, n_rays, bb, c1, c2, y_out, st);
+        fmm_explicit(*P, rays_xy, n_rays, bb, c1, c2, y_out, st, dfdz_out);
     } catch (...) {
       if (owned) lens_plan_destroy(owned);
       throw;
@@ -1561,7 +1778,7 @@ lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *
                      const lens_map_desc *map, const lens_opts *opts, void *stream) {
   return guarded([&] {
     hipStream_t st = (hipStream_t)stream;
-    const lens_opts o = resolve_opts(opts);
+    lens_opts o = resolve_opts(opts);
     FieldView fv = field_for(plan, field);
     if (plan) check_plan_device(plan);
     if (!grid) fail(LENS_EINVAL, "grid is NULL");
@@ -1580,6 +1797,7 @@ lens_status lens_map(lens_plan *plan, const lens_field *field, const lens_grid *
     const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
     const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
     const double S = (double)map->npix / map->side;
+    if (!plan && fv.f.n_stars > 0 && wants_auto(opts)) o = auto_opts(fv.f, *grid, map, *opts, st);
     const int64_t rows = std::max<int64_t>(1, o.max_rays_per_chunk / std::max<int64_t>(grid->nx, 1));
 
     if (o.method == LENS_DIRECT || fv.f.n_stars == 0) {
@@ -1634,7 +1852,7 @@ lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_gr
                          const lens_ipm_desc *map, const lens_opts *opts, void *stream) {
   return guarded([&] {
     hipStream_t st = (hipStream_t)stream;
-    const lens_opts o = resolve_opts(opts);
+    lens_opts o = resolve_opts(opts);
     FieldView fv = field_for(plan, field);
     if (plan) check_plan_device(plan);
     if (!grid) fail(LENS_EINVAL, "grid is NULL");
@@ -1654,6 +1872,11 @@ lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_gr
     const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
     const double S = (double)map->npix / map->side;
     const double cell_px = grid->dx * grid->dy * S * S;
+    if (!plan && fv.f.n_stars > 0 && wants_auto(opts)) {
+      // tuned for bin reassignment in a map of the same placement
+      const lens_map_desc md{map->y1min, map->y2min, map->side, map->npix, nullptr};
+      o = auto_opts(fv.f, *grid, &md, *opts, st);
+    }
     // cell rows per pass (each pass deflects its rows plus the next one)
     const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(ny - 1, o.max_rays_per_chunk / nx - 1));
     Scratch sc(st);
@@ -1714,14 +1937,82 @@ lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_gr
   });
 }
 
-lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid,
+}  // extern "C"
+
+namespace {
+
+// Adjoint FMM with a forward plan: the rays (charges g_k) are sources in a
+// tree of the plan's geometry, the plan's sorted stars are the targets (its
+// leaf starts locate each box's stars, its permutation the caller's order).
+void backward_with_plan(lens_plan &F, const double *rays, int64_t n_rays, const double rb[4],
+                        const double *grad_y, double *grad_xy, double *grad_m, hipStream_t st) {
+  const double x1 = F.g.x0 + F.g.side, y1 = F.g.y0 + F.g.side;
+  if (rb[0] < F.g.x0 || rb[1] < F.g.y0 || rb[2] > x1 || rb[3] > y1)
+    fail(LENS_EINVAL, "rays lie outside the plan's root square (pass ray_box to lens_plan_create)");
+  Scratch sc(st);
+  auto *A = new lens_plan();
+  try {
+    A->device = F.device;
+    A->qdim = 2;
+    A->p = F.p;
+    A->precision = F.precision;
+    A->fine_levels = F.fine_levels;
+    A->n_stars = n_rays;
+    A->g = F.g;
+    std::copy(F.star_bb, F.star_bb + 4, A->target);
+    A->domain[0] = F.g.x0, A->domain[1] = F.g.y0, A->domain[2] = x1, A->domain[3] = y1;
+    std::copy(rb, rb + 4, A->star_bb);
+    source_windows(A);
+    plan_alloc(A, st);
+    plan_enqueue(A, rays, grad_y, st);
+    double *loc = nullptr;
+    const Window wl = downward(*A, F.star_bb, sc, st, &loc);
+    EvalArgs ea{};
+    fill_star_side(*A, wl, loc, ea);
+    const int64_t per = (F.n_stars + wl.count() - 1) / std::max<int64_t>(wl.count(), 1);
+    ea.chunks_per_box =
+        std::max<int64_t>(1, (per + adj_targets_per_unit() - 1) / adj_targets_per_unit());
+    while (wl.count() * ea.chunks_per_box > (int64_t)0x7fffffff && ea.chunks_per_box > 1)
+      ea.chunks_per_box = (ea.chunks_per_box + 1) / 2;
+    AdjArgs d{static_cast<const double *>(A->sm.ptr), static_cast<const double *>(F.sxy.ptr),
+              static_cast<const double *>(F.sm.ptr), F.perm,
+              static_cast<const int32_t *>(F.leaf_start.ptr), grad_xy, grad_m, true};
+    StageTimer tme("eval_adjoint", st);
+    launch_eval_adj(ea, d, A->precision, st);
+  } catch (...) {
+    lens_plan_destroy(A);
+    throw;
+  }
+  release_owned(A, st);
+  F.last_stream = st;
+}
+
+// grad[0, n) = 0 by a kernel (no memset node if the caller captures a graph)
+void zero_f64(double *p, int64_t n, hipStream_t st) {
+  launch_fill_u32(reinterpret_cast<uint32_t *>(p), 2 * n, 0u, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+lens_status lens_deflect_backward(lens_plan *plan, const lens_field *field, const lens_grid *grid,
                                   const double *rays_xy, int64_t n_rays, const double *grad_y,
                                   double *grad_xy, double *grad_m, const lens_opts *opts,
                                   void *stream) {
   return guarded([&] {
     hipStream_t st = (hipStream_t)stream;
     const lens_opts o = resolve_opts(opts);
-    check_field(field);
+    if (plan) {
+      check_plan_device(plan);
+      if (plan->qdim != 1) fail(LENS_EINVAL, "plan is not a star plan");
+      if (field && field->n_stars != plan->n_stars)
+        fail(LENS_EINVAL, "field.n_stars differs from the plan's");
+      if (field && !is_finite(field->kappa_s + field->gamma))
+        fail(LENS_EINVAL, "kappa_s and gamma must be finite");
+    } else {
+      check_field(field);
+    }
     if ((grid == nullptr) == (rays_xy == nullptr) && !(grid == nullptr && n_rays == 0))
       fail(LENS_EINVAL, "give exactly one of grid and rays_xy");
     if (n_rays < 0) fail(LENS_EINVAL, "n_rays < 0");
@@ -1731,13 +2022,16 @@ lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid
     }
     if (n_rays > (int64_t)std::numeric_limits<int32_t>::max())
       fail(LENS_EINVAL, "n_rays exceeds 2^31-1");
-    const int64_t N = field->n_stars;
+    const int64_t N = plan ? plan->n_stars : field->n_stars;
     if (N == 0) return;
     if (!grad_xy || !grad_m) fail(LENS_EINVAL, "grad_xy / grad_m is NULL");
     if (n_rays > 0 && !grad_y) fail(LENS_EINVAL, "grad_y is NULL");
+    const bool direct = o.method == LENS_DIRECT;
+    if (direct && (!field || !field->xy || !field->m))
+      fail(LENS_EINVAL, "LENS_DIRECT needs the field's star arrays");
     if (n_rays == 0) {
-      LENS_HIP(hipMemsetAsync(grad_xy, 0, (size_t)N * 16, st));
-      LENS_HIP(hipMemsetAsync(grad_m, 0, (size_t)N * 8, st));
+      zero_f64(grad_xy, 2 * N, st);
+      zero_f64(grad_m, N, st);
       return;
     }
     Scratch sc(st);
@@ -1747,9 +2041,18 @@ lens_status lens_deflect_backward(const lens_field *field, const lens_grid *grid
       launch_grid_rays(*grid, r, st);
       rays = r;
     }
-    if (o.method == LENS_DIRECT) {
+    if (direct) {
       StageTimer tm("direct_adjoint", st);
       launch_direct_adj(N, field->xy, field->m, n_rays, rays, grad_y, grad_xy, grad_m, st);
+      return;
+    }
+    if (plan) {
+      double rb[4];
+      if (grid)
+        grid_bbox(*grid, 0, grid->ny, rb);
+      else
+        device_bbox(rays_xy, n_rays, st, rb);
+      backward_with_plan(*plan, rays, n_rays, rb, grad_y, grad_xy, grad_m, st);
       return;
     }
     // sources: the rays with complex charges g_k; targets: the stars
@@ -1856,6 +2159,7 @@ lens_status lens_map_batched(int32_t n_fields, const lens_field *fields, const l
     const bool tune = opts && opts->order_p == 0 && opts->tol > 0 && o.method == LENS_FMM;
     auto key = batch_key(dev, n_fields, fields, grids, maps, o);
     key_push(key, (int64_t)tune);
+    key_push(key, (const void *)st);  // replays on one stream are ordered; others get their own
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchExec *B = nullptr;
     for (auto it = g_batches.begin(); it != g_batches.end(); ++it) {
@@ -1902,7 +2206,9 @@ lens_status lens_autotune(const lens_field *field, const lens_grid *grid, const 
     if (!base) lens_opts_default(&ub);
     ub.method = b.method;
     ub.precision = b.precision;
-    const TuneOut t = autotune_field(*field, *grid, map, tol, ub, st);
+    ub.order_p = 0;
+    ub.tol = tol;
+    const TuneOut t = tuned_cached(*field, *grid, map, ub, st);
     *out = t.o;
     if (err_out) *err_out = t.err;
     if (ms_out) *ms_out = t.ms;

@@ -16,11 +16,12 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTile = 1024;
 
-template <int R, bool MAP, bool GRID>
+// DERIV also sums f'(z) = -sum m / (z - z_i)^2 (see the evaluation kernel).
+template <int R, bool MAP, bool GRID, bool DERIV>
 __global__ __launch_bounds__(kThreads) void k_direct(DirectArgs a) {
   __shared__ double tx[kTile], ty[kTile], tm[kTile];
   const int tid = threadIdx.x;
-  double rx[R], ry[R], ax[R], ay[R];
+  double rx[R], ry[R], ax[R], ay[R], dre[R], dim[R];
   int64_t rid[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -38,6 +39,8 @@ __global__ __launch_bounds__(kThreads) void k_direct(DirectArgs a) {
     if (!act) rid[r] = -1;
     ax[r] = 0.0;
     ay[r] = 0.0;
+    dre[r] = 0.0;
+    dim[r] = 0.0;
   }
   for (int64_t base = 0; base < a.n_stars; base += kTile) {
     const int cnt = (int)(a.n_stars - base < kTile ? a.n_stars - base : kTile);
@@ -58,9 +61,15 @@ __global__ __launch_bounds__(kThreads) void k_direct(DirectArgs a) {
         const double dx = rx[r] - sx;
         const double dy = ry[r] - sy;
         const double r2 = fma(dx, dx, fma(dy, dy, 0x1p-664));
-        const double w = m * rcp_f64(r2);
+        const double inv = rcp_f64(r2);
+        const double w = m * inv;
         ax[r] = fma(w, dx, ax[r]);
         ay[r] = fma(w, dy, ay[r]);
+        if (DERIV) {
+          const double t = r2 > 0x1p-664 ? w * inv : 0.0;
+          dre[r] = fma(-t, (dx - dy) * (dx + dy), dre[r]);
+          dim[r] = fma(t + t, dx * dy, dim[r]);
+        }
       }
     }
   }
@@ -80,6 +89,10 @@ __global__ __launch_bounds__(kThreads) void k_direct(DirectArgs a) {
     } else {
       a.y_out[2 * rid[r]] = y1;
       a.y_out[2 * rid[r] + 1] = y2;
+      if (DERIV) {
+        a.dfdz_out[2 * rid[r]] = dre[r];
+        a.dfdz_out[2 * rid[r] + 1] = dim[r];
+      }
     }
   }
 }
@@ -91,16 +104,21 @@ void launch_direct(const DirectArgs &a, hipStream_t stream) {
   constexpr int R = 2;
   const int64_t nblk = (a.n_rays + kThreads * R - 1) / (kThreads * R);
   const bool map = a.counts != nullptr;
+  const bool deriv = !map && a.dfdz_out != nullptr;
   if (a.grid_mode) {
     if (map)
-      hipLaunchKernelGGL((k_direct<R, true, true>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
+      hipLaunchKernelGGL((k_direct<R, true, true, false>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
+    else if (deriv)
+      hipLaunchKernelGGL((k_direct<R, false, true, true>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
     else
-      hipLaunchKernelGGL((k_direct<R, false, true>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
+      hipLaunchKernelGGL((k_direct<R, false, true, false>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
   } else {
     if (map)
-      hipLaunchKernelGGL((k_direct<R, true, false>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
+      hipLaunchKernelGGL((k_direct<R, true, false, false>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
+    else if (deriv)
+      hipLaunchKernelGGL((k_direct<R, false, false, true>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
     else
-      hipLaunchKernelGGL((k_direct<R, false, false>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
+      hipLaunchKernelGGL((k_direct<R, false, false, false>), dim3((unsigned)nblk), dim3(kThreads), 0, stream, a);
   }
   LENS_HIP(hipGetLastError());
 }

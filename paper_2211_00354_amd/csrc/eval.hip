@@ -39,9 +39,15 @@ constexpr int kThreads = 256;  // helper kernels
 // exactly zero: the tiny term keeps its weight finite (for |m| below ~1e8 in
 // FP32, ~1e108 in FP64) and it multiplies dx = dy = 0, so no branch or
 // select is needed; it changes no pair farther apart than ~1e-13 (FP32).
-template <bool MIXED, int R, typename A>
+//
+// DERIV also accumulates f'(z) = -sum m / (z - z_i)^2: with dz = dx + i dy,
+// 1/dz^2 = (dx^2 - dy^2 - 2i dx dy) / r^4, so f' gains -t (dx - dy)(dx + dy)
+// (real) and 2 t dx dy (imaginary), t = m / r^4; a coincident pair has
+// r2 = tiny exactly and gets t = 0.
+template <bool MIXED, bool DERIV, int R, typename A>
 __device__ __forceinline__ void pair_update(const double (&rx)[R], const double (&ry)[R], double sx,
-                                            double sy, double mm, A (&ax)[R], A (&ay)[R]) {
+                                            double sy, double mm, A (&ax)[R], A (&ay)[R],
+                                            A (&dre)[R], A (&dim)[R]) {
   if constexpr (MIXED) {
     const float m = (float)mm;
     constexpr float tiny = 0x1p-100f;
@@ -50,9 +56,15 @@ __device__ __forceinline__ void pair_update(const double (&rx)[R], const double 
       const float dx = (float)(rx[r] - sx);
       const float dy = (float)(ry[r] - sy);
       const float r2 = fmaf(dx, dx, fmaf(dy, dy, tiny));
-      const float w = m * rcp_f32(r2);
+      const float inv = rcp_f32(r2);
+      const float w = m * inv;
       ax[r] = fmaf(w, dx, ax[r]);
       ay[r] = fmaf(w, dy, ay[r]);
+      if constexpr (DERIV) {
+        const float t = r2 > tiny ? w * inv : 0.0f;
+        dre[r] = fmaf(-t, (dx - dy) * (dx + dy), dre[r]);
+        dim[r] = fmaf(t + t, dx * dy, dim[r]);
+      }
     }
   } else {
     constexpr double tiny = 0x1p-664;
@@ -61,9 +73,15 @@ __device__ __forceinline__ void pair_update(const double (&rx)[R], const double 
       const double dx = rx[r] - sx;
       const double dy = ry[r] - sy;
       const double r2 = fma(dx, dx, fma(dy, dy, tiny));
-      const double w = mm * rcp_f64(r2);
+      const double inv = rcp_f64(r2);
+      const double w = mm * inv;
       ax[r] = fma(w, dx, ax[r]);
       ay[r] = fma(w, dy, ay[r]);
+      if constexpr (DERIV) {
+        const double t = r2 > tiny ? w * inv : 0.0;
+        dre[r] = fma(-t, (dx - dy) * (dx + dy), dre[r]);
+        dim[r] = fma(t + t, dx * dy, dim[r]);
+      }
     }
   }
 }
@@ -109,8 +127,8 @@ __device__ __forceinline__ void map_table_flush(int32_t *hkey, uint32_t *hval,
 // The mixed kernels are compiled for five waves per SIMD (at most 96 VGPRs;
 // the R = 4 instances spill a few bytes of per-lane scratch outside the pair
 // loop), which measured faster than four waves without spills.
-template <int PMAX, bool MIXED, bool MAP, bool GRID, int R>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 1))) void k_eval(EvalArgs a, const double *__restrict__ loc,
+template <int PMAX, bool MIXED, bool MAP, bool GRID, int R, bool DERIV>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && !DERIV ? 5 : 1))) void k_eval(EvalArgs a, const double *__restrict__ loc,
                                                 const double *__restrict__ sxy,
                                                 const double *__restrict__ sm,
                                                 const int32_t *__restrict__ leaf_start,
@@ -210,7 +228,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     for (; pos < pend; pos += pstep) {
       double rx[R], ry[R];
       using acc_t = typename std::conditional<MIXED, float, double>::type;
-      acc_t ax[R], ay[R];
+      acc_t ax[R], ay[R], dre[R], dim[R];
       int64_t oidx[R];
       bool act[R];
 #pragma unroll
@@ -234,10 +252,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         }
         ax[r] = 0;
         ay[r] = 0;
+        dre[r] = 0;
+        dim[r] = 0;
       }
 
       auto star = [&](double x, double y, double mass) {
-        pair_update<MIXED, R>(rx, ry, x, y, mass, ax, ay);
+        pair_update<MIXED, DERIV, R>(rx, ry, x, y, mass, ax, ay, dre, dim);
       };
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -279,13 +299,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
       }
       // far field: Horner over the R rays from the top coefficient down, one
       // LDS read per coefficient
-      cplx w[R], f[R];
+      // (DERIV: the derivative sum g = sum l b_l w^(l-1) in the same sweep,
+      // g <- g w + f before f <- f w + b_l; f' = g / s)
+      cplx w[R], f[R], gd[R];
       {
         const double2 top = lds_loc[p - 1];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           w[r] = cplx{dxr[r] * inv_s, dyr[r] * inv_s};
           f[r] = cplx{top.x, top.y};
+          gd[r] = cplx{0.0, 0.0};
         }
       }
       // a runtime trip count (the order-guarded unrolled form keeps one
@@ -294,7 +317,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
       for (int l = p - 2; l >= 0; --l) {
         const double2 c = lds_loc[l];
 #pragma unroll
-        for (int r = 0; r < R; ++r) f[r] = cmad(f[r], w[r], cplx{c.x, c.y});
+        for (int r = 0; r < R; ++r) {
+          if (DERIV) gd[r] = cmad(gd[r], w[r], f[r]);
+          f[r] = cmad(f[r], w[r], cplx{c.x, c.y});
+        }
       }
 
       int32_t key[R];
@@ -315,6 +341,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
           }
         } else if (act[r]) {
           *reinterpret_cast<double2 *>(y_out + 2 * oidx[r]) = make_double2(y1, y2);
+          if (DERIV)
+            *reinterpret_cast<double2 *>(a.dfdz_out + 2 * oidx[r]) =
+                make_double2(fma(gd[r].re, inv_s, (double)dre[r]), fma(gd[r].im, inv_s, (double)dim[r]));
         }
       }
       if (MAP) {
@@ -372,18 +401,26 @@ __global__ __launch_bounds__(kThreads) void k_ray_keys(const double *__restrict_
 
 constexpr int64_t kMaxEvalBlocks = 256 * 32 * 4;  // CUs x waves per CU x sweeps in flight
 
-template <int PM, bool MIXED, bool MAP, bool GRID, int R>
+template <int PM, bool MIXED, bool MAP, bool GRID, int R, bool DERIV = false>
 void eval_launch_r(const EvalArgs &a, hipStream_t stream) {
   const int64_t units = a.win.count() * a.chunks_per_box;
   int64_t nblk = units < kMaxEvalBlocks ? units : kMaxEvalBlocks;
   if (nblk > kXcd) nblk = nblk / kXcd * kXcd;
-  hipLaunchKernelGGL((k_eval<PM, MIXED, MAP, GRID, R>), dim3((unsigned)nblk), dim3(kWave), 0, stream,
+  hipLaunchKernelGGL((k_eval<PM, MIXED, MAP, GRID, R, DERIV>), dim3((unsigned)nblk), dim3(kWave), 0, stream,
                      a, a.loc, a.sxy, a.sm, a.leaf_start, a.col_start, a.row_start, a.rxy, a.rperm,
                      a.ray_start, a.y_out, a.counts);
 }
 
 template <int PM, bool MIXED, bool MAP, bool GRID>
 void eval_launch(const EvalArgs &a, hipStream_t stream) {
+  if constexpr (!MAP) {
+    // f' wanted: one instance per order bucket, two rays per lane (the
+    // launch shape is chosen for R = 2 in that case)
+    if (a.dfdz_out) {
+      eval_launch_r<PM, MIXED, MAP, GRID, 2, true>(a, stream);
+      return;
+    }
+  }
   switch (a.rays_per_lane) {
     case 1: eval_launch_r<PM, MIXED, MAP, GRID, 1>(a, stream); break;
     case 2: eval_launch_r<PM, MIXED, MAP, GRID, 2>(a, stream); break;

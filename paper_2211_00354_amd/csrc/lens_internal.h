@@ -234,6 +234,7 @@ struct EvalArgs {
   int tile_shift;             // grid: a wave's 64 rays are a 2^tile_shift-wide tile
   double c1, c2;              // (1 - kappa_s - gamma), (1 - kappa_s + gamma)
   double *y_out;              // [n][2] or nullptr
+  double *dfdz_out;           // [n][2] f'(z) (deflection only) or nullptr
   // map
   int32_t *counts;
   double y1min, y2min, S;
@@ -255,9 +256,10 @@ struct AdjArgs {
   const double *txy;      // targets (stars) sorted by window box
   const double *tm;       // their masses
   const uint32_t *tperm;  // sorted position -> caller's star index
-  const int32_t *tstart;  // [win.count() + 1]
+  const int32_t *tstart;  // [win.count() + 1], or [4^L + 1] if tglobal
   double *grad_xy;        // [N][2]
   double *grad_m;         // [N]
+  bool tglobal = false;   // tstart indexed by global leaf box (a forward plan's)
 };
 void launch_eval_adj(const EvalArgs &a, const AdjArgs &d, int precision, hipStream_t stream);
 void launch_direct_adj(int64_t n_stars, const double *star_xy, const double *star_m, int64_t n_rays,
@@ -277,6 +279,7 @@ struct DirectArgs {
   int64_t ray_offset;    // first ray index (grid rows chunking)
   double c1, c2;
   double *y_out;
+  double *dfdz_out;      // [n][2] f'(z) or nullptr (not with counts)
   int32_t *counts;
   double y1min, y2min, S;
   int32_t npix;

@@ -208,8 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_tile_sums(const uint32_t *__r
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// Scan of one tile; the tile's offset is the sum of the earlier tiles' sums
-// (read directly: tiles are few, so this replaces a separate scan of the sums).
+// Scan of one tile.  The tile's offset is the sum of the earlier tiles'
+// sums, read directly when tiles are few (this replaces a separate scan of
+// the sums); with PRE the offsets come already scanned (many tiles).
+template <bool PRE>
 __global__ __launch_bounds__(kThreads) void k_scan_tiles(const uint32_t *__restrict__ in, size_t n,
                                                          const uint32_t *__restrict__ sums,
                                                          uint32_t *__restrict__ out) {
@@ -229,10 +231,14 @@ __global__ __launch_bounds__(kThreads) void k_scan_tiles(const uint32_t *__restr
     loc[j] = s;
     s += tile[threadIdx.x * kScanItems + j];
   }
-  uint32_t before = 0;
-  for (unsigned i = threadIdx.x; i < blockIdx.x; i += kThreads) before += sums[i];
   uint32_t tile_off;
-  (void)block_excl_scan(before, sh, &tile_off);
+  if (PRE) {
+    tile_off = sums[blockIdx.x];
+  } else {
+    uint32_t before = 0;
+    for (unsigned i = threadIdx.x; i < blockIdx.x; i += kThreads) before += sums[i];
+    (void)block_excl_scan(before, sh, &tile_off);
+  }
   uint32_t tot;
   const uint32_t ex = block_excl_scan(s, sh, &tot);
   const uint32_t off = tile_off + ex;
@@ -453,14 +459,30 @@ void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream) {
   LENS_HIP(hipGetLastError());
 }
 
-size_t scan_tmp_len(size_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+// Tiles up to which each tile sums its predecessors' totals itself; beyond,
+// the totals are scanned first (recursively), so the work stays linear.
+constexpr size_t kDirectTiles = 1024;
+
+size_t scan_tmp_len(size_t n) {
+  const size_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb <= kDirectTiles) return nb + 1;
+  return 2 * nb + scan_tmp_len(nb) + 1;
+}
 
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp,
                         hipStream_t stream) {
   if (n == 0) return;
   const size_t nb = (n + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(kThreads), 0, stream, in, n, tmp);
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kThreads), 0, stream, in, n, tmp, out);
+  if (nb <= kDirectTiles) {
+    hipLaunchKernelGGL(k_scan_tiles<false>, dim3((unsigned)nb), dim3(kThreads), 0, stream, in, n,
+                       tmp, out);
+  } else {
+    uint32_t *offs = tmp + nb;
+    exclusive_scan_u32(tmp, offs, nb, offs + nb, stream);
+    hipLaunchKernelGGL(k_scan_tiles<true>, dim3((unsigned)nb), dim3(kThreads), 0, stream, in, n,
+                       offs, out);
+  }
   LENS_HIP(hipGetLastError());
 }
 

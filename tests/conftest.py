@@ -9,6 +9,10 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    # the library's on-disk autotune cache: a fresh file per test session
+    import tempfile
+    os.environ.setdefault("LENS_TUNE_CACHE",
+                          os.path.join(tempfile.mkdtemp(prefix="lens_tune_"), "autotune.txt"))
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
     config.addinivalue_line("markers", "slow: long-running test")
 

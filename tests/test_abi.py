@@ -54,7 +54,7 @@ def test_deflect_rejects_bad_arguments(field, opts, msg):
     o = _opts(**opts)
     g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2)
     st = lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), None, 4, ctypes.c_void_p(8),
-                          ctypes.byref(o), None)
+                          None, ctypes.byref(o), None)
     assert st == _lib.LENS_EINVAL
     assert msg in lib.lens_last_error().decode()
 
@@ -71,7 +71,7 @@ def test_deflect_rejects_bad_grids(grid, n, msg):
     f = _lib.LensField(n_stars=0)
     g = _lib.LensGrid(*grid)
     st = lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), None, n, ctypes.c_void_p(8),
-                          None, None)
+                          None, None, None)
     assert st == _lib.LENS_EINVAL
     assert msg in lib.lens_last_error().decode()
 
@@ -81,13 +81,13 @@ def test_deflect_needs_exactly_one_ray_source_and_an_output():
     f = _lib.LensField(n_stars=0)
     g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2)
     assert lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), ctypes.c_void_p(8), 4,
-                            ctypes.c_void_p(8), None, None) == _lib.LENS_EINVAL
-    assert lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), None, 4, None, None,
+                            ctypes.c_void_p(8), None, None, None) == _lib.LENS_EINVAL
+    assert lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), None, 4, None, None, None,
                             None) == _lib.LENS_EINVAL
     assert b"y_out" in lib.lens_last_error()
     # zero rays is a no-op
     g0 = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 0, 3)
-    assert lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g0), None, 0, None, None,
+    assert lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g0), None, 0, None, None, None,
                             None) == _lib.LENS_OK
 
 

@@ -118,7 +118,9 @@ def test_direct_map_small_disk(lf):
     np.testing.assert_array_equal(counts, mine)
     yo, _, _ = oracle.deflect(f.xy, f.m, g.rays(), f.kappa_s, f.gamma)
     ref, _ = oracle.bin_rays(yo, mp.y1min, mp.y2min, mp.side, mp.npix)
-    assert np.abs(counts.astype(np.int64) - ref).sum() <= 2      # 0 expected
+    moved = int(np.abs(counts.astype(np.int64) - ref).sum())
+    print("direct map small_disk: counts differing from the oracle's binning:", moved)
+    assert moved == 0
     assert counts.sum() > 0
     del torch
 
@@ -286,6 +288,72 @@ def test_fmm_close_pairs(lf, prec, p, tol):
                         **kw))
     yo, ao, _ = oracle.deflect(xy, m, rays, **kw)
     check(y, yo, ao, tol, f"close pairs explicit {prec}")
+
+
+def _dfdz_from_jacobian(jac):
+    """f' from the oracle's deflection Jacobian (J11, J12, J22): with
+    alpha = conj(f), J11 = Re f' = -J22 and J12 = -Im f'."""
+    return np.stack([jac[:, 0], -jac[:, 1]], 1)
+
+
+@pytest.mark.parametrize("method,prec,p,fl,tol,ray_tol", [
+    ("direct", "fp64", 12, 0, 1e-12, 1e-12), ("fmm", "fp64", 36, 0, 1e-10, 1e-10),
+    ("fmm", "mixed", 18, -1, 1e-5, 5e-5), ("fmm", "mixed", 12, 0, 1e-5, 5e-3),
+])
+def test_dfdz_against_oracle_jacobian(lf, method, prec, p, fl, tol, ray_tol):
+    """f'(z) at the rays (the derivative Appendix A's expansions give in
+    closed form) against the oracle's deflection Jacobian, per ray relative to
+    max(|f'|, 1e-3 rms |f'|); y is unchanged by asking for f'.  The local
+    expansion's derivative converges one order slower than the expansion
+    (p = 12: 2e-3 per ray where f' nearly cancels); the mixed path's FP32 near
+    field leaves ~2e-5 per ray at the floor, as for alpha."""
+    f, g, _ = wl.small_disk()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    kw = dict(kappa_s=f.kappa_s, gamma=f.gamma, method=method, precision=prec, p=p,
+              fp32_levels=fl)
+    _say("dfdz grid", method, prec, p, fl)
+    y, d = lf.deflect(xy, m, grid=lfgrid(g), want_dfdz=True, **kw)
+    y0 = lf.deflect(xy, m, grid=lfgrid(g), **kw)
+    np.testing.assert_array_equal(host(y), host(y0))
+    idx = g.strided(3, 1)
+    jac = oracle.jacobian(f.xy, f.m, g.rays(idx))
+    dref = _dfdz_from_jacobian(jac)
+    check(host(d)[idx], dref, dref, tol, f"dfdz {method} {prec} p={p} fl={fl}", ray_tol)
+    # explicit rays, some exactly on stars (their pair is skipped in f' too)
+    rng = np.random.default_rng(8)
+    rays = np.concatenate([rng.uniform(-5, 5, (3000, 2)), f.xy[:7]])
+    _say("dfdz explicit", method, prec, p)
+    y, d = lf.deflect(xy, m, rays=dev_tensor(rays), want_dfdz=True, **kw)
+    dh = host(d)
+    assert np.all(np.isfinite(dh))
+    dref = _dfdz_from_jacobian(oracle.jacobian(f.xy, f.m, rays))
+    check(dh, dref, dref, tol, f"dfdz explicit {method} {prec}", ray_tol)
+
+
+def test_dfdz_chang_refsdal_critical_curve(lf):
+    """One star with shear (Chang-Refsdal): the GPU's f' gives
+    det A = (1 - kappa_s)^2 - |gamma + conj(f')|^2, which must vanish on the
+    critical curve |1/z^2 + gamma| = 1 - kappa_s (m = 1), sampled along rays
+    placed on it, and change sign across it."""
+    gam, ks = 0.3, 0.0
+    th = np.linspace(0.05, 2 * np.pi, 64, endpoint=False)
+    # on the curve: 1/z^2 = gamma + (1 - ks) e^{i phi}, solved for z
+    w = gam + (1 - ks) * np.exp(1j * th)
+    z = 1 / np.sqrt(w)
+    rays = np.stack([z.real, z.imag], 1)
+    out = np.stack([rays * 1.01, rays * 0.99])
+    xy = dev_tensor(np.zeros((1, 2)))
+    m = dev_tensor(np.ones(1))
+    _say("dfdz Chang-Refsdal")
+
+    def det_a(r, **kw):
+        _, d = lf.deflect(xy, m, rays=dev_tensor(r), kappa_s=ks, gamma=gam, want_dfdz=True, **kw)
+        fp = host(d)
+        c = fp[:, 0] - 1j * fp[:, 1]              # conj(f')
+        return (1 - ks) ** 2 - np.abs(gam + c) ** 2
+    for kw, tol in ((dict(method="direct"), 1e-12), (dict(precision="fp64", p=30), 1e-9)):
+        assert np.max(np.abs(det_a(rays, **kw))) <= tol, kw
+        assert np.all(det_a(out[0], **kw) * det_a(out[1], **kw) < 0), kw
 
 
 def test_fmm_rays_on_box_edges(lf):
@@ -586,6 +654,117 @@ def test_adjoint_invariants_and_autograd(lf):
     assert torch.autograd.gradcheck(fn, (xs, ms), eps=1e-6, atol=1e-6, rtol=1e-5)
 
 
+@pytest.mark.parametrize("prec,p,tol", [("fp64", 24, 1e-9), ("mixed", 12, 1e-5)])
+def test_backward_reuses_forward_plan(lf, prec, p, tol):
+    """lens_deflect_backward with the forward's plan (its star tree and
+    geometry; no star sort, no bounding-box wait for grid rays) against the
+    oracle gradient, for explicit and grid rays, and equal to the plan-less
+    adjoint within the same tolerance."""
+    f, rays, G, gxy, gm = _adjoint_case()
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    lo, hi = rays.min(0), rays.max(0)
+    plan = lf.Plan(xy, m, ray_box=(lo[0], lo[1], hi[0], hi[1]), precision=prec, p=p)
+    _say("backward with plan", prec, p)
+    a, b = lf.deflect_backward(None, None, dev_tensor(G), rays=dev_tensor(rays), plan=plan)
+    ea, eb = _grad_err(host(a), gxy), _grad_err(host(b), gm)
+    print(f"backward with plan {prec} p={p}: grad_xy {ea:.2e} grad_m {eb:.2e}")
+    assert ea <= tol and eb <= tol
+    a2, b2 = lf.deflect_backward(xy, m, dev_tensor(G), rays=dev_tensor(rays), precision=prec, p=p)
+    assert _grad_err(host(a), host(a2)) <= tol and _grad_err(host(b), host(b2)) <= tol
+    plan.close()
+    # grid rays
+    g = wl.Grid(x0=-6.0, y0=-5.5, dx=0.05, dy=0.07, nx=211, ny=157)
+    f2 = wl.random_field(300, 5.0, seed=61, masses="powerlaw")
+    Gg = np.random.default_rng(62).standard_normal((g.n, 2))
+    gx_ref, gm_ref = oracle.grad(f2.xy, f2.m, g.rays(), Gg)
+    plan = lf.Plan(dev_tensor(f2.xy), dev_tensor(f2.m), grid=lfgrid(g), precision=prec, p=p)
+    a, b = lf.deflect_backward(None, None, dev_tensor(Gg), grid=lfgrid(g), plan=plan)
+    assert _grad_err(host(a), gx_ref) <= tol and _grad_err(host(b), gm_ref) <= tol
+    # rays outside the plan's root square are refused
+    with pytest.raises(lf.LensError, match="outside"):
+        far = dev_tensor(np.array([[1e6, 0.0]]))
+        lf.deflect_backward(None, None, dev_tensor(np.ones((1, 2))), rays=far, plan=plan)
+    plan.close()
+
+
+def test_order_chosen_from_tol(lf):
+    """order_p = 0 with tol > 0: the autotuner picks p (once; later calls
+    reuse it) and the per-ray error meets tol on rays it did not sample."""
+    f = wl.random_field(30_000, 120.0, seed=64, masses="powerlaw", kappa_s=0.2, gamma=0.3)
+    g = wl.centred_grid(160.0, 160.0, 768, 768)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    kw = dict(kappa_s=f.kappa_s, gamma=f.gamma)
+    _say("order from tol")
+    y = host(lf.deflect(xy, m, grid=lfgrid(g), p=0, tol=1e-5, **kw))
+    y2 = host(lf.deflect(xy, m, grid=lfgrid(g), p=0, tol=1e-5, **kw))
+    np.testing.assert_array_equal(y, y2)
+    idx = g.strided(29, 5)
+    yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), **kw)
+    check(y[idx], yo, ao, 1e-5, "order from tol 1e-5")
+    plan = lf.Plan(xy, m, grid=lfgrid(g), p=0, tol=1e-5, **kw)
+    info = plan.info()
+    plan.close()
+    assert info["p"] >= 8
+    import os
+    path = os.environ["LENS_TUNE_CACHE"]
+    assert os.path.exists(path) and open(path).read().count("deflect") >= 1
+
+
+def test_tune_cache_is_reused_across_processes(lf, tmp_path):
+    """The on-disk autotune cache: a second process asking for the same kind
+    of problem gets the first one's setting without measuring (no line is
+    added to the cache)."""
+    import os
+    import subprocess
+    import sys
+    code = r"""
+import sys, torch
+sys.path.insert(0, %r)
+import paper_2211_00354_amd as lf, workloads as wl
+f = wl.random_field(20000, 100.0, seed=66, masses="powerlaw", kappa_s=0.1, gamma=0.2)
+g = wl.centred_grid(120.0, 120.0, 512, 512)
+xy = torch.from_numpy(f.xy).cuda(); m = torch.from_numpy(f.m).cuda()
+plan = lf.Plan(xy, m, grid=lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny), kappa_s=f.kappa_s,
+               gamma=f.gamma, p=0, tol=1e-5)
+i = plan.info(); plan.close(); torch.cuda.synchronize()
+print("TUNED", i["p"], i["leaf_level"])
+""" % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, LENS_TUNE_CACHE=str(tmp_path / "tune.txt"))
+    _say("tune cache: first process")
+    a = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert a.returncode == 0, a.stderr[-2000:]
+    lines = open(tmp_path / "tune.txt").read().splitlines()
+    assert len(lines) == 1
+    _say("tune cache: second process")
+    b = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert b.returncode == 0, b.stderr[-2000:]
+    tuned_a = [ln for ln in a.stdout.splitlines() if ln.startswith("TUNED")]
+    tuned_b = [ln for ln in b.stdout.splitlines() if ln.startswith("TUNED")]
+    print(tuned_a, tuned_b)
+    assert tuned_a == tuned_b and tuned_a
+    assert open(tmp_path / "tune.txt").read().splitlines() == lines
+
+
+def test_explicit_ray_sort_with_many_scan_tiles(lf):
+    """3.6e7 explicit rays: the radix sort's digit-count scan spans more than
+    1024 tiles and takes the recursive path (tile totals scanned first);
+    checked against the oracle on a sample."""
+    import torch
+    f = wl.random_field(5000, 40.0, seed=67, masses="powerlaw")
+    n = 36_000_000
+    gen = torch.Generator(device="cuda").manual_seed(68)
+    rays = (torch.rand((n, 2), generator=gen, device="cuda", dtype=torch.float64) - 0.5) * 80.0
+    _say("explicit rays", n)
+    y = lf.deflect(dev_tensor(f.xy), dev_tensor(f.m), rays=rays, precision="fp64", p=24)
+    idx = torch.arange(0, n, 4099, device="cuda")
+    rs, ys = host(rays[idx]), host(y[idx])
+    del y, rays
+    yo, ao, _ = oracle.deflect(f.xy, f.m, rs)
+    check(ys, yo, ao, 1e-9, "3.6e7 explicit rays fp64 p=24")
+
+
 # ------------------------------------------------------------------ batching
 
 def _batch_fields(n_fields, n_side, npix, seed, n_range):
@@ -644,19 +823,45 @@ def test_batched_field_batch_full_size(lf):
         grids.append(lfgrid(g))
         maps.append(lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix))
     _say("batched field_batch full")
-    got = lf.irs_map_batched(fields, grids, maps)
+    # p, leaf level and FP32 levels tuned per field for a 1e-4 expected
+    # reassignment (fields near the macro critical line need high orders)
+    kw = dict(p=0, tol=1e-4)
+    got = lf.irs_map_batched(fields, grids, maps, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     counts = [torch.zeros_like(c) for c in got]
-    lf.irs_map_batched(fields, grids, maps, counts=counts)
+    lf.irs_map_batched(fields, grids, maps, counts=counts, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rays = sum(g.nx * g.ny for g in grids)
     print(f"batched field_batch: {dt * 1e3:.2f} ms for {rays:.3e} rays -> {rays / dt:.3e} rays/s")
-    for k in (0, 17, 63):
+    # every field: the batched map equals the single-field map, and the
+    # single-field deflection (the same kernels) meets the oracle on a 64^2
+    # strided subset of its rays
+    worst = 0.0
+    for k, (f, g, mp) in enumerate(cases):
         xy, m, ks, gm = fields[k]
-        single = host(lf.irs_map(xy, m, grid=grids[k], map=maps[k], kappa_s=ks, gamma=gm))
+        single = host(lf.irs_map(xy, m, grid=grids[k], map=maps[k], kappa_s=ks, gamma=gm, **kw))
         np.testing.assert_array_equal(host(counts[k]), single)
+        # the field's tuned setting (the cached choice the batch used)
+        t = lf.autotune(xy, m, grids[k], map=maps[k], tol=1e-4, kappa_s=ks, gamma=gm)
+        y = lf.deflect(xy, m, grid=grids[k], kappa_s=ks, gamma=gm, p=t["p"],
+                       leaf_level=t["leaf_level"], fp32_levels=t["fp32_levels"])
+        idx = g.strided(32, 16)
+        ys = host(y[torch.from_numpy(idx).cuda()])
+        del y
+        yo, ao, _ = oracle.deflect(f.xy, f.m, g.rays(idx), f.kappa_s, f.gamma)
+        S = mp.npix / mp.side
+        est = float(np.abs(ys - yo).sum(1).mean() * S)
+        moved = int(np.count_nonzero(np.any(np.floor((ys - [mp.y1min, mp.y2min]) * S)
+                                            != np.floor((yo - [mp.y1min, mp.y2min]) * S), 1)))
+        e = rel_l2(ys, yo, ao)
+        mx, _ = ray_errors(ys, yo, ao)
+        worst = max(worst, est)
+        print(f"field {k}: N={f.n} p={t['p']} L={t['leaf_level']} fl={t['fp32_levels']} "
+              f"rel_l2 {e:.2e} ray_max {mx:.2e} reassignment {est:.2e} moved {moved}/{len(idx)}")
+        assert e <= 1e-5 and est <= 1e-4 and moved <= 2
+    print(f"batched field_batch: worst expected reassignment {worst:.2e}")
     lf.release_cached()
 
 
@@ -756,6 +961,67 @@ def test_clustered_lenses_full_gradient(lf):
             assert abs(cs - ref) <= 1e-9 * max(1.0, abs(ref)), (i, c, cs, ref)
 
 
+def test_clustered_lenses_gpu_forward_differences_and_invariants(lf):
+    """Clustered lenses (2000 clusters x 100 stars, 1e6 rays): the mixed
+    adjoint FMM gradient against central finite differences of the GPU's own
+    forward (FP64 FMM, p = 24) on 64 stars x 3 parameters, and the two
+    invariants on the GPU: translating every star by d changes L by
+    d . sum_k J(x_k) G_k, i.e. sum_i (dL/dx_i + i dL/dy_i) = conj(sum_k g_k f'(z_k))
+    with f' from the GPU, and scaling every mass by (1 + e) changes L by
+    -e sum_k G_k . alpha_k."""
+    import torch
+    f, rays, tn = wl.clustered_lenses()
+    xy, m, r = dev_tensor(f.xy), dev_tensor(f.m), dev_tensor(rays)
+    _say("clustered: forward + adjoint")
+    yd, fpd = lf.deflect(xy, m, rays=r, method="direct", want_dfdz=True)
+    t = yd + dev_tensor(tn)
+    G = 2 * (yd - t)
+    gd_xy, gd_m = lf.deflect_backward(xy, m, G, rays=r, method="direct")
+    gf_xy, gf_m = lf.deflect_backward(xy, m, G, rays=r, precision="mixed", p=12)
+    # translation: sum over stars of the position gradient
+    ghat = torch.complex(G[:, 0], G[:, 1])
+    fprime = torch.complex(fpd[:, 0], fpd[:, 1])
+    rhs = torch.conj((ghat * fprime).sum())
+    scale = float((ghat.abs() * fprime.abs()).sum())
+    for gxy, tol in ((gd_xy, 1e-12), (gf_xy, 1e-6)):
+        lhs = complex(float(gxy[:, 0].sum()), float(gxy[:, 1].sum()))
+        assert abs(lhs - complex(rhs)) <= tol * scale, (lhs, complex(rhs), scale)
+    # mass scaling: sum m dL/dm = -sum G . alpha, alpha = x - y (kappa_s = gamma = 0)
+    alpha = r - yd
+    mrhs = -float((G * alpha).sum())
+    mscale = float((G.abs() * alpha.abs()).sum())
+    for gm, tol in ((gd_m, 1e-12), (gf_m, 1e-6)):
+        assert abs(float((m * gm).sum()) - mrhs) <= tol * mscale
+    # central differences of the GPU forward (FP64 FMM) on 64 stars x 3,
+    # Richardson-extrapolated from steps h and 2h (a plain central difference
+    # of this loss converges as C h^2 with C up to ~1e8 for a star with a ray
+    # ~1e-4 away, and its rounding noise grows as 1/h)
+    sel = np.random.default_rng(6).choice(f.n, 64, replace=False)
+    h = 1e-6
+    fd = np.empty((64, 3))
+    _say("clustered: finite differences")
+    for j, i in enumerate(sel):
+        for c in range(3):
+            def fwd(step):
+                xy2, m2 = xy.clone(), m.clone()
+                if c < 2:
+                    xy2[i, c] += step
+                else:
+                    m2[i] += step
+                return lf.deflect(xy2, m2, rays=r, precision="fp64", p=24)
+
+            def central(hh):
+                yp, ym = fwd(+hh), fwd(-hh)
+                return float(((yp - ym) * (yp + ym - 2 * t)).sum()) / (2 * hh)
+            fd[j, c] = (4 * central(h) - central(2 * h)) / 3
+    ref_d = np.concatenate([host(gd_xy)[sel], host(gd_m)[sel][:, None]], 1)
+    ref_f = np.concatenate([host(gf_xy)[sel], host(gf_m)[sel][:, None]], 1)
+    e_d = np.linalg.norm(fd - ref_d) / np.linalg.norm(ref_d)
+    e_f = np.linalg.norm(fd - ref_f) / np.linalg.norm(ref_d)
+    print(f"finite differences vs FP64 direct adjoint {e_d:.2e}, vs mixed FMM adjoint {e_f:.2e}")
+    assert e_d <= 1e-5 and e_f <= 2e-5
+
+
 # ------------------------------------------------------------------ autotuner
 
 def test_autotune_deflect_reaches_tol(lf):
@@ -764,7 +1030,7 @@ def test_autotune_deflect_reaches_tol(lf):
     g = wl.centred_grid(200.0, 200.0, 1024, 1024)
     xy, m = dev_tensor(f.xy), dev_tensor(f.m)
     kw = dict(kappa_s=f.kappa_s, gamma=f.gamma)
-    for prec, tol in (("mixed", 1e-6), ("fp64", 1e-11)):
+    for prec, tol in (("mixed", 1e-5), ("fp64", 1e-10)):
         _say("autotune deflect", prec, tol)
         t = lf.autotune(xy, m, lfgrid(g), tol=tol, precision=prec, **kw)
         print("autotune", prec, tol, t)
@@ -795,7 +1061,7 @@ def test_autotune_high_magnification_map(lf):
     yo, _, _ = oracle.deflect(f.xy, f.m, rays, f.kappa_s, f.gamma)
     est = float(np.abs(ys - yo).sum(1).mean() * mp.npix / mp.side)
     print(f"high_magnification tuned: reassignment estimate {est:.2e} on {len(idx)} rays")
-    assert est <= 2e-4
+    assert est <= 1e-4
 
 
 def test_batched_autotuned_maps_against_direct(lf):

@@ -38,7 +38,7 @@ def test_noalloc_matches_lens_deflect(lf):
         gc = gr.c()
         print(f"[case] noalloc call {k}: {gr.nx}x{gr.ny}", flush=True)
         _call(lib, "lens_deflect", plan.handle, None, ctypes.byref(gc), None, n, ref.data_ptr(),
-              ctypes.byref(o), stream)
+              None, ctypes.byref(o), stream)
         _call(lib, "lens_deflect_noalloc", plan.handle, None, ctypes.byref(gc), out.data_ptr(),
               ctypes.byref(o), stream)
         torch.cuda.synchronize()
