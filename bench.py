@@ -113,11 +113,14 @@ def main():
     ap.add_argument("--no-direct", action="store_true", help="skip the FP64 direct comparator")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps of the mixed FMM only (for rocprofv3)")
-    ap.add_argument("--workload", choices=("deflect", "map", "ipm", "batch"), default="deflect",
+    ap.add_argument("--workload", choices=("deflect", "map", "ipm", "batch", "halo", "arc"),
+                    default="deflect",
                     help="deflect: 1e6 stars, 8192^2 rays (the headline metric); "
                          "map: 5e6 stars, 16384^2 rays shot into a 2000^2 map (IRS); "
                          "ipm: the same field and grid, inverse polygon mapping; "
-                         "batch: 64 fields of 1e4-2e5 stars, 2048^2 rays each, one graph")
+                         "batch: 64 fields of 1e4-2e5 stars, 2048^2 rays each, one graph; "
+                         "halo: 1.575e7 halo particles, 4000^2 rays (deflect, tol 1e-5); "
+                         "arc: 1.8e6 deflectors, 1.5e11 rays of a 15000x10 region, IPM map")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="with --profile-only: also run one device-to-device copy of this many "
                          "MiB, the reference for scaling FETCH_SIZE/WRITE_SIZE counters")
@@ -139,6 +142,8 @@ def main():
         return bench_map(args)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload in ("halo", "arc"):
+        return bench_application(args)
     log("generating workload")
     f, g = wl.powerlaw_disk()
     xy = torch.from_numpy(f.xy).cuda()
@@ -508,6 +513,113 @@ def bench_batch(args):
         "roofline": None,
         "cpu_baseline": cpu,
         "extra": extra,
+    }
+    print(json.dumps(out))
+
+
+APP_METRIC = {
+    "halo": "rays/s deflected by a 1.575e7-particle halo (mixed FMM, order chosen for 1e-5)",
+    "arc": "rays/s mapped by IPM over a 15000x10 anamorphic region (1.8e6 deflectors, mu=4200)",
+}
+
+
+def bench_application(args):
+    """The two application workloads, one whole call per step (plan built
+    inside the call).  halo: lens_deflect of 4000^2 rays through 1.575e7
+    particles, mixed precision, order and leaf level from the autotuner for
+    a 1e-5 per-ray error (tuned outside the timed region).  arc: one
+    lens_map_ipm call over 1.5e11 rays (passes of 2^28 rays), mixed
+    precision, p = 24 with every M2L level in FP64."""
+    import numpy as np
+    import torch
+
+    import paper_2211_00354_amd as lf
+    from paper_2211_00354_amd import _lib
+    import workloads as wl
+
+    log("generating workload")
+    halo = args.workload == "halo"
+    if halo:
+        f, g = wl.synthetic_halo()
+    else:
+        f, g, mp = wl.anamorphic_arc()
+    xy = torch.from_numpy(f.xy).cuda()
+    m = torch.from_numpy(f.m).cuda()
+    grid = lf.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny)
+    extra = {}
+    if halo:
+        t0 = time.perf_counter()
+        tuned = lf.autotune(xy, m, grid, tol=1e-5, kappa_s=f.kappa_s, gamma=f.gamma)
+        extra["autotune"], extra["autotune_s"] = tuned, time.perf_counter() - t0
+        log(f"autotune: {tuned}")
+        kw = dict(kappa_s=f.kappa_s, gamma=f.gamma, precision="mixed", p=tuned["p"],
+                  leaf_level=tuned["leaf_level"], fp32_levels=tuned["fp32_levels"])
+        y = torch.empty((g.n, 2), dtype=torch.float64, device="cuda")
+
+        def step():
+            lf.deflect(xy, m, grid=grid, out=y, **kw)
+        desc = ("1.575e7 halo particles (dark matter, gas, stars, 128 black holes; Einstein "
+                "radius ~30), 4000x4000 rays over [-45,45]^2, mixed FMM p=%d" % kw["p"])
+    else:
+        md = lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix)
+        kw = dict(kappa_s=f.kappa_s, gamma=f.gamma, precision="mixed", p=24, fp32_levels=-1)
+        mu = torch.zeros((mp.npix, mp.npix), dtype=torch.float64, device="cuda")
+
+        def step():
+            mu.zero_()
+            lf.ipm_map(xy, m, grid=grid, map=md, mu=mu, **kw)
+        desc = ("1.8e6 deflectors of 0.2 (kappa_*=0.0064) in a 15000-diameter disk, macro "
+                "mu=4200 (axis ratio 1500), 15000000x10000 rays over 15000x10 into a 4000x4000 "
+                "IPM map of 0.001 pixels, mixed FMM p=24, FP64 M2L")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    _lib.profile_enable(True)
+    step()
+    torch.cuda.synchronize()
+    prof = _lib.profile_read()
+    _lib.profile_enable(False)
+    extra["stage_ms_one_step"] = {k: v[0] for k, v in prof.items()}
+    value = g.n / (ms * 1e-3)
+    log(f"{args.workload}: {ms:.3f} ms/step -> {value:.3e} rays/s; stages {extra['stage_ms_one_step']}")
+    if not halo:
+        extra["map_mean_mu"] = float(mu.mean())
+        extra["mu_macro"] = f.meta["mu_macro"]
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        rng = np.random.default_rng(5)
+        idx = g.strided(128, 61) if halo else rng.integers(0, g.n, 1000)
+        rays = g.rays(idx)
+        plan = lf.Plan(xy, m, grid=grid, **kw)
+        ys = lf.deflect(rays=torch.from_numpy(rays).cuda(), plan=plan, kappa_s=f.kappa_s,
+                        gamma=f.gamma).cpu().numpy()
+        plan.close()
+        nthr = host_threads()
+        t1 = time.perf_counter()
+        yo, ao, _ = oracle.deflect(f.xy, f.m, rays, f.kappa_s, f.gamma, nthreads=nthr)
+        dt = time.perf_counter() - t1
+        cpu = {"value": len(idx) / dt, "unit": "rays/s", "cores": nthr, "kind": "oracle",
+               "sample": f"{len(idx)} rays of the grid against all {f.n} deflectors, FP64 "
+                         f"direct sum, {dt:.1f} s"}
+        if halo:
+            extra["ray_error"] = ray_error_stats(ys, yo, ao)
+        else:
+            S = mp.npix / mp.side
+            extra["bin_reassignment_estimate"] = float(np.abs(ys - yo).sum(1).mean() * S)
+    out = {
+        "metric": APP_METRIC[args.workload], "value": value, "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64 mixed", "data": "synthetic",
+        "config": {"workload": desc, "n_stars": f.n, "n_rays": g.n},
+        "roofline": None, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(out))
 

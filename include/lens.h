@@ -107,8 +107,9 @@ typedef struct {
                            see lens_autotune), else 12 */
   int32_t leaf_level;   /* quadtree leaf level in [2, LENS_MAX_LEVEL]; 0 = chosen
                            by the library's cost model */
-  int64_t max_rays_per_chunk;  /* lens_map: rays per chunk; 0 = the whole grid
-                                  in one pass (a map needs no per-ray memory) */
+  int64_t max_rays_per_chunk;  /* rays per pass of lens_map (0 = the whole
+                                  grid in one pass: a map needs no per-ray
+                                  memory) and lens_map_ipm (0 = 2^28) */
   int32_t fp32_levels;  /* LENS_MIXED: M2L of the finest fp32_levels quadtree
                            levels runs on FP32 MFMA, coarser levels on FP64;
                            0 = 2 levels, -1 = none (all M2L in FP64), at most
@@ -247,9 +248,12 @@ typedef struct {
  * has zero area gives a quarter of its area to the pixel of each corner.
  * Contributions are summed in fixed point (2^-40 of a pixel's
  * magnification), so the map does not depend on summation order.  Rays are
- * processed in chunks of whole rows of at most opts->max_rays_per_chunk rays
- * (default: one pass); a pass needs nx*ny*16 bytes of scratch for the
- * deflected corners plus 4 bytes per cell, and the map 16 bytes per pixel.
+ * processed in passes of whole rows of at most opts->max_rays_per_chunk rays
+ * (default 2^28; a pass also holds fewer than 2^32 cells), each pass
+ * deflecting its rows plus the first row of the next, so that a grid of any
+ * size (e.g. 1.5e11 rays) streams through one plan; a pass needs 16 bytes
+ * of scratch per ray for the deflected corners plus 4 bytes per cell, and
+ * the map 16 bytes per pixel.  The map does not depend on the pass size.
  * `plan` may be NULL as in lens_deflect.
  */
 LENS_API lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_grid *grid,

@@ -75,6 +75,10 @@ namespace {
 // lens_map rays per pass by default: all of them (the paper's bounded passes,
 // Section 2.4, are kept as an option; a map needs no per-ray memory)
 constexpr int64_t kDefaultChunk = std::numeric_limits<int64_t>::max();
+// Inverse polygon mapping: default rays per pass (16 bytes of deflected
+// corners each), and the most cells one pass may hold.
+constexpr int64_t kIpmPassRays = int64_t(1) << 28;
+constexpr int64_t kIpmPassCellsMax = (int64_t)std::numeric_limits<uint32_t>::max() - 1;
 constexpr int kDefaultFp32Levels = 2;
 
 bool is_finite(double v) { return std::isfinite(v); }
@@ -136,20 +140,29 @@ int64_t box_coord_host(double x, double origin, double s, int64_t nbox) {
 // memory on the one wait of a plan-less call.
 double *bbox_landing() {
   thread_local double *buf = nullptr;
-  if (!buf) LENS_HIP(hipHostMalloc(reinterpret_cast<void **>(&buf), 4 * sizeof(double), hipHostMallocDefault));
+  if (!buf) LENS_HIP(hipHostMalloc(reinterpret_cast<void **>(&buf), 5 * sizeof(double), hipHostMallocDefault));
   return buf;
 }
 
-void device_bbox(const double *xy, int64_t n, hipStream_t st, double out[4]) {
+// Bounding box of the points (one read-back); with count_box, also the
+// number of points inside that rectangle (same read-back).
+void device_bbox(const double *xy, int64_t n, hipStream_t st, double out[4],
+                 const double *count_box = nullptr, int64_t *count = nullptr) {
   Scratch sc(st);
   const int parts = bbox_parts(n);
   double *partial = sc.get<double>((size_t)parts * 4);
-  double *o4 = sc.get<double>(4);
-  launch_bbox(xy, n, partial, parts, o4, st);
+  double *o5 = sc.get<double>(5);
+  launch_bbox(xy, n, partial, parts, o5, st);
+  if (count_box) launch_count_in_box(xy, n, count_box, reinterpret_cast<unsigned long long *>(o5 + 4), st);
   double *landing = bbox_landing();
-  LENS_HIP(hipMemcpyAsync(landing, o4, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  LENS_HIP(hipMemcpyAsync(landing, o5, (count_box ? 5 : 4) * sizeof(double), hipMemcpyDeviceToHost, st));
   LENS_HIP(hipStreamSynchronize(st));
   std::copy(landing, landing + 4, out);
+  if (count_box) {
+    uint64_t c;
+    std::memcpy(&c, landing + 4, 8);
+    *count = (int64_t)c;
+  }
   for (int c = 0; c < 4; ++c)
     if (!is_finite(out[c])) fail(LENS_EINVAL, "non-finite coordinates in the input positions");
 }
@@ -179,12 +192,38 @@ double preferred_leaf_side(double rho, double rays_density, double side, int p) 
   return s;
 }
 
-int level_for_side(double side, double s, int p) {
+// Device bytes of a plan with leaf level L: the leaf starts (4^L + 1),
+// dense multipole levels down to where boxes hold ~512 sources, and below
+// them windows around the rays' box rb (w x h) grown by 4 boxes a side,
+// FP64 plus FP32 copies; the evaluation's locals take about as much again
+// as the windows.
+double plan_bytes(int L, int p, int64_t n_sources, double side, double w, double h) {
+  double bytes = 4.0 * (double)(int64_t(1) << (2 * L));
+  int D = 2;
+  while (D < L && (double)n_sources / (double)(int64_t(1) << (2 * D)) > 512.0) ++D;
+  for (int l = 2; l <= L; ++l) {
+    const double nb = (double)(int64_t(1) << l), s = side / nb;
+    const double win = std::min(nb, w / s + 9.0) * std::min(nb, h / s + 9.0);
+    const double boxes = l <= D ? nb * nb : win;
+    bytes += (boxes * 2.0 + win) * p * 16.0 * 1.5;
+  }
+  return bytes;
+}
+constexpr double kPlanBytesMax = 16e9;
+
+int level_for_side(double side, double s, int p, int64_t n_sources, double w, double h) {
   int L = (int)std::ceil(std::log2(side / s) - 1e-9);
-  L = std::max(2, std::min(L, 13));
-  // keep the multipole storage (all levels) under ~8 GB
-  while (L > 2 && (double)(int64_t(1) << (2 * L)) * p * 16.0 * 1.34 > 8e9) --L;
+  L = std::max(2, std::min(L, LENS_MAX_LEVEL));
+  while (L > 2 && plan_bytes(L, p, n_sources, side, w, h) > kPlanBytesMax) --L;
   return L;
+}
+
+// Stars per unit area inside the rays' box, from a count of them (or -1 when
+// the count is too small to say: the mean density is used then).
+double local_density(int64_t count, const double rb[4]) {
+  const double area = (rb[2] - rb[0]) * (rb[3] - rb[1]);
+  if (!(area > 0) || count < 32) return -1.0;
+  return (double)count / area;
 }
 
 double star_density(int64_t n_stars, const double sb[4]) {
@@ -198,7 +237,7 @@ double star_density(int64_t n_stars, const double sb[4]) {
 // the smallest such box that lets 2^L boxes cover the domain; otherwise the
 // candidate with the lowest eval_cost.  Returns false if no candidate fits.
 bool aligned_geometry(const lens_grid &g, const double dom[4], int leaf_level, double rho, int p,
-                      Geometry *out) {
+                      int64_t n_sources, Geometry *out) {
   struct Cand {
     double s;
     int kx, ky;
@@ -224,7 +263,7 @@ bool aligned_geometry(const lens_grid &g, const double dom[4], int leaf_level, d
     const double x0 = g.x0 - mx * c.s, y0 = g.y0 - my * c.s;
     const double need = std::max(dom[2] - x0, dom[3] - y0) * (1.0 + 1e-12);
     int L = 2;
-    while (L < 13 && std::ldexp(c.s, L) <= need) ++L;
+    while (L < LENS_MAX_LEVEL && std::ldexp(c.s, L) <= need) ++L;
     if (std::ldexp(c.s, L) <= need) continue;
     if (leaf_level > 0) {
       if (L > leaf_level) continue;  // box too small for this depth
@@ -232,7 +271,8 @@ bool aligned_geometry(const lens_grid &g, const double dom[4], int leaf_level, d
       *out = Geometry{x0, y0, std::ldexp(c.s, L), L};
       return true;  // smallest fitting box
     }
-    if ((double)(int64_t(1) << (2 * L)) * p * 16.0 * 1.34 > 8e9) continue;
+    const double gw = (double)g.nx * g.dx, gh = (double)g.ny * g.dy;
+    if (plan_bytes(L, p, n_sources, std::ldexp(c.s, L), gw, gh) > kPlanBytesMax) continue;
     const double cost = eval_cost(rho, c.s, (double)c.kx * c.ky, p);
     if (!found || cost < best_cost) {
       found = true;
@@ -307,8 +347,11 @@ void source_windows(lens_plan *P) {
 
 // Plan phase 1 (host): domain = star bounding box sb (if any) united with
 // ray_box, root square and leaf level (aligned with `align` if possible).
+// rho_local >= 0: the stars' density where the rays are (else the mean
+// density over the stars' bounding box is used for the leaf choice).
 void plan_geometry(lens_plan *P, int64_t n_sources, const double *sb, const double *ray_box,
-                   const lens_grid *align, double rays_density, const lens_opts &o) {
+                   const lens_grid *align, double rays_density, const lens_opts &o,
+                   double rho_local = -1.0) {
   P->p = o.order_p;
   P->precision = o.precision;
   P->fine_levels = o.fp32_levels;
@@ -329,18 +372,21 @@ void plan_geometry(lens_plan *P, int64_t n_sources, const double *sb, const doub
   double side = std::max(dom[2] - dom[0], dom[3] - dom[1]);
   if (!(side > 0)) side = 1.0;
   side *= 1.0 + 1.0 / 1024;
-  const double rho = star_density(n_sources, sb ? sb : dom);
+  const double rho = rho_local >= 0.0 ? rho_local : star_density(n_sources, sb ? sb : dom);
   bool aligned = false;
   if (align && align->nx > 0 && align->ny > 0 && n_sources > 0)
-    aligned = aligned_geometry(*align, dom, o.leaf_level, rho, P->p, &P->g);
+    aligned = aligned_geometry(*align, dom, o.leaf_level, rho, P->p, n_sources, &P->g);
   if (!aligned) {
     const double cxm = 0.5 * (dom[0] + dom[2]), cym = 0.5 * (dom[1] + dom[3]);
     P->g.side = side;
     P->g.x0 = cxm - 0.5 * side;
     P->g.y0 = cym - 0.5 * side;
+    const double rw = ray_box ? ray_box[2] - ray_box[0] : side;
+    const double rh = ray_box ? ray_box[3] - ray_box[1] : side;
     P->g.L = o.leaf_level > 0
                  ? o.leaf_level
-                 : level_for_side(side, preferred_leaf_side(rho, rays_density, side, P->p), P->p);
+                 : level_for_side(side, preferred_leaf_side(rho, rays_density, side, P->p), P->p,
+                                  n_sources, rw, rh);
   }
   if (ray_box)
     std::copy(ray_box, ray_box + 4, P->target);
@@ -431,7 +477,8 @@ void plan_enqueue(lens_plan *P, const double *xy, const double *q, hipStream_t s
 // if already known (else it is read back from the device).
 lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_grid *align,
                       double rays_density, const lens_opts &o, hipStream_t st,
-                      const double *qc = nullptr, const double *sb_known = nullptr) {
+                      const double *qc = nullptr, const double *sb_known = nullptr,
+                      double rho_known = -1.0) {
   auto *P = new lens_plan();
   P->qdim = qc ? 2 : 1;
   try {
@@ -440,15 +487,22 @@ lens_plan *build_plan(const lens_field &f, const double *ray_box, const lens_gri
     P->gamma = f.gamma;
     double sb[4];
     const double *sbp = nullptr;
+    double rho_local = -1.0;
     if (f.n_stars > 0) {
-      if (sb_known)
+      if (sb_known) {
         std::copy(sb_known, sb_known + 4, sb);
-      else
+        rho_local = rho_known;
+      } else if (ray_box) {
+        int64_t cnt = 0;
+        device_bbox(f.xy, f.n_stars, st, sb, ray_box, &cnt);
+        rho_local = local_density(cnt, ray_box);
+      } else {
         device_bbox(f.xy, f.n_stars, st, sb);
+      }
       sbp = sb;
       std::copy(sb, sb + 4, P->star_bb);
     }
-    plan_geometry(P, f.n_stars, sbp, ray_box, align, rays_density, o);
+    plan_geometry(P, f.n_stars, sbp, ray_box, align, rays_density, o, rho_local);
     (void)op_tables(o.order_p, st);
     plan_alloc(P, st);
     plan_enqueue(P, f.xy, qc ? qc : f.m, st);
@@ -1477,14 +1531,16 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
                    double c2, double *y_out, const lens_map_desc *map, double S,
                    hipStream_t st,
                    double *dfdz = nullptr) {
-  double sb[4];
-  device_bbox(f.xy, f.n_stars, st, sb);
   double bb[4];
   grid_bbox(grid, 0, grid.ny, bb);
+  double sb[4];
+  int64_t cnt = 0;
+  device_bbox(f.xy, f.n_stars, st, sb, bb, &cnt);
+  const double rho_local = local_density(cnt, bb);
   const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
   const double density = (double)(grid.nx * grid.ny) / area;
   auto eager = [&] {
-    lens_plan *P = build_plan(f, bb, &grid, density, o, st, nullptr, sb);
+    lens_plan *P = build_plan(f, bb, &grid, density, o, st, nullptr, sb, rho_local);
     try {
       fmm_grid_rows(*P, grid, 0, grid.ny, c1, c2, y_out, map, S, st, dfdz);
     } catch (...) {
@@ -1497,7 +1553,7 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   // host-side geometry only, to form the key
   lens_plan probe;
   LENS_HIP(hipGetDevice(&probe.device));
-  plan_geometry(&probe, f.n_stars, sb, bb, &grid, density, o);
+  plan_geometry(&probe, f.n_stars, sb, bb, &grid, density, o, rho_local);
   auto key = call_key(f, grid, o, y_out, map, probe, st);
   key_push(key, (const void *)dfdz);
   std::lock_guard<std::mutex> lk(g_call_mu);
@@ -1522,7 +1578,7 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   P->device = probe.device;
   P->kappa_s = f.kappa_s;
   P->gamma = f.gamma;
-  plan_geometry(P, f.n_stars, sb, bb, &grid, density, o);
+  plan_geometry(P, f.n_stars, sb, bb, &grid, density, o, rho_local);
   std::copy(sb, sb + 4, P->star_bb);
   (void)op_tables(o.order_p, st);
   plan_alloc(P, st);
@@ -1865,8 +1921,6 @@ lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_gr
       fail(LENS_EINVAL, "map placement must be finite with side > 0");
     if (!map->mu) fail(LENS_EINVAL, "map.mu is NULL");
     const int64_t nx = grid->nx, ny = grid->ny;
-    if (nx * ny > (int64_t)std::numeric_limits<uint32_t>::max() - 1)
-      fail(LENS_EINVAL, "a grid may hold at most 2^32-2 rays");
     if (nx < 2 || ny < 2) return;  // no cells
     const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
     const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
@@ -1877,8 +1931,12 @@ lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, const lens_gr
       const lens_map_desc md{map->y1min, map->y2min, map->side, map->npix, nullptr};
       o = auto_opts(fv.f, *grid, &md, *opts, st);
     }
-    // cell rows per pass (each pass deflects its rows plus the next one)
-    const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(ny - 1, o.max_rays_per_chunk / nx - 1));
+    // cell rows per pass (each pass deflects its rows plus the next one):
+    // by default passes of about kIpmPassRays rays, and never more cells than
+    // a pass's 32-bit cell indices can name
+    const int64_t chunk = opts && opts->max_rays_per_chunk > 0 ? o.max_rays_per_chunk : kIpmPassRays;
+    const int64_t rows = std::max<int64_t>(
+        1, std::min<int64_t>({ny - 1, chunk / nx - 1, kIpmPassCellsMax / (nx - 1)}));
     Scratch sc(st);
     const int64_t npx = (int64_t)map->npix * map->npix;
     const int64_t ndiff = (int64_t)map->npix * (map->npix + 1);

@@ -85,6 +85,9 @@ struct Window {
 void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, double *out4,
                  hipStream_t stream);
 int bbox_parts(int64_t n);
+// *count = number of points of xy inside the closed rectangle box (host array)
+void launch_count_in_box(const double *xy, int64_t n, const double box[4], unsigned long long *count,
+                         hipStream_t stream);
 struct BBoxSet {
   const double *xy;
   int64_t n;

@@ -72,6 +72,28 @@ __global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restric
   if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Number of points inside the closed rectangle box = {x1min, x2min, x1max,
+// x2max}, added to *count (the density of stars where the rays are).
+__global__ __launch_bounds__(kThreads) void k_count_in_box(const double *__restrict__ xy, int64_t n,
+                                                           double b0, double b1, double b2,
+                                                           double b3,
+                                                           unsigned long long *__restrict__ count) {
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double a = xy[2 * i], b = xy[2 * i + 1];
+    c += (a >= b0 && a <= b2 && b >= b1 && b <= b3) ? 1ull : 0ull;
+  }
+  __shared__ unsigned long long red[kThreads];
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(count, red[0]);
+}
+
 // Bounding boxes of several point sets at once: blockIdx.y = set; partial
 // results [set][part][4], then one workgroup per set reduces its parts.
 __global__ __launch_bounds__(kThreads) void k_bbox_multi_partial(const BBoxSet *__restrict__ sets,
@@ -430,6 +452,16 @@ void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, doubl
                  hipStream_t stream) {
   hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(kThreads), 0, stream, xy, n, partial);
   hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kThreads), 0, stream, partial, nparts, out4);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_count_in_box(const double *xy, int64_t n, const double box[4], unsigned long long *count,
+                         hipStream_t stream) {
+  launch_fill_u32(reinterpret_cast<uint32_t *>(count), 2, 0u, stream);
+  if (n == 0) return;
+  const int nb = bbox_parts(n);
+  hipLaunchKernelGGL(k_count_in_box, dim3(nb), dim3(kThreads), 0, stream, xy, n, box[0], box[1],
+                     box[2], box[3], count);
   LENS_HIP(hipGetLastError());
 }
 

@@ -208,3 +208,76 @@ def random_field(n: int, radius: float, seed: int, kappa_s=0.0, gamma=0.0, masse
     m = np.ones(n) if masses == "unit" else powerlaw_masses(rng, n)
     xy = uniform_disk(rng, n, radius)
     return Field(xy=xy, m=m, kappa_s=kappa_s, gamma=gamma, radius=radius)
+
+
+def synthetic_halo(n_dm: int = 10_800_000, n_gas: int = 3_760_000, n_star: int = 1_190_000,
+                   n_bh: int = 128, n_side: int = 4000, half_width: float = 45.0,
+                   seed: int = 8):
+    """A synthetic galaxy halo standing in for the cosmological-simulation
+    lens of Section 2.5 (whose particle data is not available): the same
+    particle counts (1.08e7 dark matter, 3.76e6 gas, 1.19e6 stars, 128 black
+    holes; 1.575e7 in all), projected on the lens plane, in Einstein-radius
+    units of unit mass.
+
+    * dark matter: surface density ~ 1/r (a projected isothermal halo) out to
+      R = 1500, axis ratio 0.75;
+    * gas: cored, ~ 1/sqrt(r^2 + 40^2), same extent and flattening;
+    * stars: exponential disk of scale 6, axis ratio 0.6;
+    * black holes: Gaussian of width 1 about the centre;
+    * all rotated by 30 degrees; masses 80% / 15% / 5% of a total of 43500
+      (dark matter / gas / stars), black holes 0.1 each, so that the mass
+      inside r = 30 is ~pi 30^2 (an Einstein radius of ~30, where the inner
+      region holds the critical curves); kappa_s = 0, external shear 0.03.
+
+    Rays: an n_side x n_side grid over [-half_width, half_width]^2 (the inner
+    region, where the caustics and the multiple images are)."""
+    rng = np.random.default_rng(seed)
+    R, rc, rs = 1500.0, 40.0, 6.0
+
+    def place(r, q):
+        th = 2.0 * math.pi * rng.random(r.size)
+        x, y = r * np.cos(th), q * r * np.sin(th)
+        c, s = math.cos(math.pi / 6), math.sin(math.pi / 6)
+        return np.stack([c * x - s * y, s * x + c * y], 1)
+
+    r_dm = R * rng.random(n_dm)
+    a = math.sqrt(R * R + rc * rc) - rc
+    r_gas = np.sqrt((rng.random(n_gas) * a + rc) ** 2 - rc * rc)
+    r_st = -rs * np.log(rng.random(n_star) * rng.random(n_star))
+    r_st = np.minimum(r_st, R)
+    xy = np.concatenate([place(r_dm, 0.75), place(r_gas, 0.75), place(r_st, 0.6),
+                         rng.standard_normal((n_bh, 2))])
+    M = 43500.0
+    m = np.concatenate([np.full(n_dm, 0.80 * M / n_dm), np.full(n_gas, 0.15 * M / n_gas),
+                        np.full(n_star, 0.05 * M / n_star), np.full(n_bh, 0.1)])
+    f = Field(xy=xy, m=m, kappa_s=0.0, gamma=0.03, radius=R,
+              meta={"components": {"dark": n_dm, "gas": n_gas, "stars": n_star, "bh": n_bh}})
+    g = centred_grid(2 * half_width, 2 * half_width, n_side, n_side)
+    return f, g
+
+
+def anamorphic_arc(n_stars: int = 1_800_000, mass: float = 0.2, width: float = 15000.0,
+                   height: float = 10.0, nx: int = 15_000_000, ny: int = 10_000, npix: int = 4000,
+                   seed: int = 9):
+    """A highly anamorphic shooting region like the magnified star of
+    Section 3.3: a macro model with magnification ~4200 and an axis ratio of
+    ~1500 (eigenvalues 1 - kappa - gamma = 3.98e-4 and 1 - kappa + gamma =
+    0.597), a 15000 x 10 Einstein-radius region of rays, and 1.8e6
+    deflectors of mass 0.2 filling the circle that circumscribes it
+    (diameter 15000: kappa_* = 6.4e-3, the rest of the convergence smooth).
+    The map covers 4 x 4 Einstein radii of the source plane at 0.001 per
+    pixel.  Rays: nx x ny over the region; the default, 1.5e7 x 1e4 = 1.5e11
+    rays 0.001 apart, is one ray per unlensed pixel."""
+    rng = np.random.default_rng(seed)
+    lam1, lam2 = 3.98e-4, 0.597
+    kappa = 1.0 - 0.5 * (lam1 + lam2)
+    gamma = 0.5 * (lam2 - lam1)
+    R = 0.5 * math.hypot(width, height)
+    xy = uniform_disk(rng, n_stars, R)
+    m = np.full(n_stars, mass)
+    kappa_star = m.sum() / R ** 2
+    f = Field(xy=xy, m=m, kappa_s=kappa - kappa_star, gamma=gamma, radius=R,
+              meta={"kappa_star": kappa_star, "mu_macro": 1.0 / (lam1 * lam2)})
+    g = centred_grid(width, height, nx, ny)
+    mp = MapDesc(y1min=-2.0, y2min=-2.0, side=4.0, npix=npix)
+    return f, g, mp
