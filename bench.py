@@ -92,10 +92,17 @@ def ray_error_stats(y, y_ref, alpha_ref):
 
 
 def eval_source_hash():
+    """Hash of what the evaluation kernel is compiled from: eval.hip, the
+    device helpers and the EvalArgs declaration (the rest of the internal
+    header does not change the kernel)."""
     h = hashlib.sha256()
-    for fn in ("eval.hip", "device_common.h", "lens_internal.h"):
-        with open(os.path.join(ROOT, "paper_2211_00354_amd", "csrc", fn), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2211_00354_amd", "csrc")
+    for fn in ("eval.hip", "device_common.h"):
+        with open(os.path.join(csrc, fn), "rb") as fh:
             h.update(fh.read())
+    txt = open(os.path.join(csrc, "lens_internal.h")).read()
+    i = txt.index("struct EvalArgs")
+    h.update(txt[i:txt.index("};", i)].encode())
     return h.hexdigest()[:16]
 
 

@@ -260,6 +260,85 @@ LENS_API lens_status lens_map_ipm(lens_plan *plan, const lens_field *field, cons
                                   const lens_ipm_desc *map, const lens_opts *opts, void *stream);
 
 /*
+ * Images of point sources: every x of the grid's region with y(x) =
+ * sources[s] (the inverse lens equation; Section 2.5 finds the images of a
+ * source behind a particle halo this way).  The grid rays are the corners
+ * of (nx-1)(ny-1) cells, each split along its (i,j)-(i+1,j+1) diagonal into
+ * two triangles; a triangle whose mapped corners contain a source seeds a
+ * candidate at the source's preimage under the triangle's linear map.  Each
+ * candidate is refined by up to max_iter Newton steps
+ *     x <- x + A(x)^-1 (beta - y(x)),
+ *     A = [[c1 - Re f', Im f'], [Im f', c2 + Re f']],  f' = -sum m/(z - z_i)^2,
+ * with c1 = 1 - kappa_s - gamma, c2 = 1 - kappa_s + gamma (the derivative of
+ * the expansions, Appendix A); a step is at most 4 cell diagonals long and x
+ * stays inside the grid's rays' box.  A candidate whose |y(x) - beta| <= tol
+ * is an image; images of one source closer than max(1e-3 min(dx, dy),
+ * 1e3 tol) are one.  Every image inside the grid's box whose triangle sees
+ * its source is found; two images closer than about a cell (a source within
+ * a cell's image of a caustic) may come out as one, and the tiny images
+ * next to each lens that no grid resolves are found only where a triangle
+ * holds them.  Deflections are computed as lens_deflect computes them
+ * (plan, method, precision and order from opts; the grid is deflected in
+ * passes of whole rows as in lens_map_ipm), so tol should exceed the
+ * evaluation's own error (~1e-6 |alpha| for LENS_MIXED).
+ *   sources    [n_sources][2] FP64 (device)
+ *   images     [cap][4] FP64 (device): x1, x2, magnification 1/det A
+ *              (signed: negative for saddle images), residual |y - beta|;
+ *              ordered by source, then x1
+ *   image_src  [cap] int32 (device): the source of each image
+ *   n_images   (host) number of images found; only the first cap are
+ *              written
+ * Synchronises `stream` (reads back candidate counts).  LENS_EINVAL for bad
+ * arguments (tol <= 0, max_iter outside [0, 1000], NULL pointers).
+ */
+LENS_API lens_status lens_find_images(lens_plan *plan, const lens_field *field,
+                                      const lens_grid *grid, const double *sources,
+                                      int32_t n_sources, double tol, int32_t max_iter,
+                                      double *images, int32_t *image_src, int64_t cap,
+                                      int64_t *n_images, const lens_opts *opts, void *stream);
+
+/*
+ * Critical curves (det A = 0) over the grid's region, and optionally their
+ * caustics.  det A = (c1 - Re f')(c2 + Re f') - (Im f')^2 at every grid ray
+ * (f' as lens_deflect's dfdz_out); on each cell a corner-to-corner edge whose
+ * end values differ in sign is cut where the linear interpolant of det A
+ * vanishes and the cuts are joined into segments (marching squares; a cell
+ * cut on all four edges is split by the sign of the mean of its corners).
+ *   seg_out      [cap][4] FP64 (device): x1a, x2a, x1b, x2b per segment,
+ *                in no particular order
+ *   caustic_out  [cap][4] FP64 (device) or NULL: the images y of the same
+ *                end points (the caustics)
+ *   n_seg        (host) segments found; only the first cap are written
+ * The segments' end points are within O(dx^2) of the curve where det A is
+ * smooth on the scale of a cell.  Synchronises `stream`.
+ */
+LENS_API lens_status lens_critical_curves(lens_plan *plan, const lens_field *field,
+                                          const lens_grid *grid, double *seg_out,
+                                          double *caustic_out, int64_t cap, int64_t *n_seg,
+                                          const lens_opts *opts, void *stream);
+
+/*
+ * Multi-plane ray tracing: a thick lens as a chain of thin planes (the
+ * extension noted in the introduction).  Plane 0 is nearest the observer;
+ * a ray starts at x_0 (grid or explicit rays, as lens_deflect) and reaches
+ * plane j at
+ *     x_j = x_0 - sum_{i<j} beta[j*n_planes + i] alpha_i(x_i),
+ * and the source plane at y = x_0 - sum_i alpha_i(x_i), where alpha_i(x) =
+ * x - y_i(x) is plane i's full deflection (its stars and its kappa_s and
+ * gamma, y_i as lens_deflect computes it) and beta_ij = D_ij D_s / (D_j D_is)
+ * are the distance ratios, plane deflections being scaled to the source
+ * plane.  fields[n_planes]; beta: host, [n_planes][n_planes], only i < j
+ * read (may be NULL for one plane); n_planes <= 64.  Each plane is
+ * evaluated by lens_deflect with `opts` and no plan (planes after the first
+ * see explicit rays, so each such call reads back a bounding box).  Scratch:
+ * 16 (n_planes + 2) bytes per ray.
+ */
+LENS_API lens_status lens_deflect_multiplane(int32_t n_planes, const lens_field *fields,
+                                             const double *beta, const lens_grid *grid,
+                                             const double *rays_xy, int64_t n_rays,
+                                             double *y_out, const lens_opts *opts, void *stream);
+
+/*
  * Empirical autotuner for one field and ray grid: the expansion order p, the
  * leaf level and, for LENS_MIXED, fp32_levels (Appendix A leaves p and the
  * tree depth to the user; here they are measured).  A strided sample of at

@@ -5,15 +5,19 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 two share no code: this is the plain definition (eq. 1 of the paper, Section
 1, summed directly in FP64) that the GPU's fast multipole evaluation must
 reproduce, plus inverse-ray-shooting binning (Section 2.3) and the gradient
-of eq. 1 with respect to the lens parameters.
+of eq. 1 with respect to the lens parameters, and the multi-plane chain of
+thin lenses built on eq. 1.
 
-Every function below is a thin ctypes marshaller around ``lens_oracle.c``;
-the arithmetic lives there and is documented there.
+Every function below but ``multiplane`` is a thin ctypes marshaller around
+``lens_oracle.c``; the arithmetic lives there and is documented there.
+``multiplane`` composes ``deflect`` plane by plane in numpy.
 
 Parity status: every function here is pinned by ``tests/test_oracle_pins.py``
 against closed forms (point lens, Chang-Refsdal shear lens, Gauss's law for
 the deflection flux, far-field Laurent moments, exact rational arithmetic on
-tiny inputs, finite differences and scaling invariants).
+tiny inputs, finite differences and scaling invariants; for the chain of
+planes, its reductions to one plane, to superposition and to products of
+linear maps).
 """
 from __future__ import annotations
 
@@ -172,3 +176,26 @@ def grad(star_xy, star_m, rays_xy, grad_y, nthreads=0):
     if rc != 0:
         raise ValueError("oracle_grad rejected its arguments")
     return gxy, gm
+
+
+def multiplane(planes, beta, rays_xy, nthreads=0):
+    """Multi-plane ray tracing by the thin-lens chain (the introduction's
+    footnote: a thick lens as a collection of thin planes), written from its
+    definition: plane j (0 nearest the observer) is reached at
+        x_j = x_0 - sum_{i<j} beta[j][i] alpha_i(x_i)
+    and the source plane at y = x_0 - sum_i alpha_i(x_i), where
+    alpha_i(x) = x - y_i(x) is plane i's whole deflection, y_i the one-plane
+    lens mapping of ``deflect`` with that plane's smooth terms.  ``planes``
+    lists (star_xy, star_m, kappa_s, gamma).  Returns y [n, 2]."""
+    x0 = _f64(rays_xy, 2).reshape(-1, 2)
+    alphas = []
+    for j, (sxy, sm, ks, g) in enumerate(planes):
+        xj = x0.copy()
+        for i in range(j):
+            xj = xj - float(beta[j][i]) * alphas[i]
+        yj, _, _ = deflect(sxy, sm, xj, ks, g, nthreads=nthreads)
+        alphas.append(xj - yj)
+    y = x0.copy()
+    for a in alphas:
+        y = y - a
+    return y

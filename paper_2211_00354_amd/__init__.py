@@ -254,6 +254,105 @@ def ipm_map(star_xy=None, star_m=None, grid: Grid = None, map: MapDesc = None, k
     return mu
 
 
+def find_images(star_xy=None, star_m=None, grid: Grid = None, sources=None, kappa_s=0.0,
+                gamma=0.0, tol=1e-10, max_iter=40, method="fmm", precision="fp64", p=24,
+                leaf_level=0, plan: Optional[Plan] = None, cap=1 << 16, fp32_levels=0,
+                max_rays_per_chunk=0):
+    """Images of point sources inside the grid's region (lens_find_images).
+    ``sources`` is a [n_src, 2] float64 GPU tensor.  Returns (images [k, 4]
+    float64 = x1, x2, signed magnification, residual; src [k] int32), both on
+    the GPU, ordered by source then x1.  Raises if more than ``cap`` images
+    are found."""
+    torch = _torch()
+    lib = _lib.load()
+    _check_tensor(sources, "sources", 2)
+    ns = sources.numel() // 2
+    if plan is None:
+        f = _field(star_xy, star_m, kappa_s, gamma)
+    else:
+        f = LensField(0, None, None, float(kappa_s), float(gamma))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    images = torch.empty((cap, 4), dtype=torch.float64, device=dev)
+    src = torch.empty((cap,), dtype=torch.int32, device=dev)
+    n = ctypes.c_int64()
+    g = grid.c()
+    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk, fp32_levels)
+    _lib.check(lib.lens_find_images(plan.handle if plan else None, ctypes.byref(f), ctypes.byref(g),
+                                    sources.data_ptr() if ns else None, ns, float(tol),
+                                    int(max_iter), images.data_ptr(), src.data_ptr(), cap,
+                                    ctypes.byref(n), ctypes.byref(o), _stream()))
+    if n.value > cap:
+        raise ValueError(f"{n.value} images found, more than cap={cap}")
+    return images[: n.value], src[: n.value]
+
+
+def critical_curves(star_xy=None, star_m=None, grid: Grid = None, kappa_s=0.0, gamma=0.0,
+                    method="fmm", precision="fp64", p=24, leaf_level=0,
+                    plan: Optional[Plan] = None, cap=1 << 20, caustics=True, fp32_levels=0,
+                    max_rays_per_chunk=0):
+    """Critical-curve segments over the grid's region (lens_critical_curves):
+    returns seg [k, 4] float64 (x1a, x2a, x1b, x2b) and, with ``caustics``,
+    their images [k, 4] (else None), on the GPU.  Raises if more than ``cap``
+    segments are found."""
+    torch = _torch()
+    lib = _lib.load()
+    if plan is None:
+        f = _field(star_xy, star_m, kappa_s, gamma)
+    else:
+        f = LensField(0, None, None, float(kappa_s), float(gamma))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    seg = torch.empty((cap, 4), dtype=torch.float64, device=dev)
+    cau = torch.empty((cap, 4), dtype=torch.float64, device=dev) if caustics else None
+    n = ctypes.c_int64()
+    g = grid.c()
+    o = _opts(method, precision, p, leaf_level, max_rays_per_chunk, fp32_levels)
+    _lib.check(lib.lens_critical_curves(plan.handle if plan else None, ctypes.byref(f),
+                                        ctypes.byref(g), seg.data_ptr(),
+                                        cau.data_ptr() if caustics else None, cap, ctypes.byref(n),
+                                        ctypes.byref(o), _stream()))
+    if n.value > cap:
+        raise ValueError(f"{n.value} segments found, more than cap={cap}")
+    return seg[: n.value], (cau[: n.value] if caustics else None)
+
+
+def deflect_multiplane(planes, beta=None, grid: Optional[Grid] = None, rays=None, out=None,
+                       method="fmm", precision="mixed", p=12, leaf_level=0, fp32_levels=0):
+    """Multi-plane ray tracing (lens_deflect_multiplane).  ``planes`` is a list
+    of (star_xy, star_m, kappa_s, gamma), nearest the observer first;
+    ``beta`` an [n, n] array-like of distance ratios (only i < j read).
+    Returns the source-plane positions y [n_rays, 2] float64 on the GPU."""
+    torch = _torch()
+    lib = _lib.load()
+    npl = len(planes)
+    fields = (LensField * npl)()
+    for j, (xy, m, ks, g) in enumerate(planes):
+        fields[j] = _field(xy, m, ks, g)
+    bp = None
+    if beta is not None:
+        b = [float(v) for row in beta for v in row]
+        if len(b) != npl * npl:
+            raise ValueError("beta must be [n_planes, n_planes]")
+        bp = (ctypes.c_double * (npl * npl))(*b)
+    if (grid is None) == (rays is None):
+        raise ValueError("give exactly one of grid and rays")
+    if grid is not None:
+        n = int(grid.nx) * int(grid.ny)
+        g = grid.c()
+        gp, rp = ctypes.byref(g), None
+    else:
+        _check_tensor(rays, "rays", 2)
+        n = rays.numel() // 2
+        gp, rp = None, rays.data_ptr() if n else None
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    o = _opts(method, precision, p, leaf_level, fp32_levels=fp32_levels)
+    _lib.check(lib.lens_deflect_multiplane(npl, fields, bp, gp, rp, n,
+                                           out.data_ptr() if n else None, ctypes.byref(o),
+                                           _stream()))
+    return out
+
+
 def irs_map_batched(fields, grids, maps, counts=None, method="fmm", precision="mixed", p=12,
                     leaf_level=0, fp32_levels=0, tol=0.0):
     """Inverse ray shooting for many independent fields in one captured HIP

@@ -97,6 +97,15 @@ def load(path: str = LIB_PATH):
     lib.lens_map_batched.restype = ctypes.c_int
     lib.lens_map_ipm.argtypes = [V, P(LensField), P(LensGrid), P(LensIpmDesc), P(LensOpts), V]
     lib.lens_map_ipm.restype = ctypes.c_int
+    lib.lens_find_images.argtypes = [V, P(LensField), P(LensGrid), V, I32, D, I32, V, V, I64, P(I64),
+                                     P(LensOpts), V]
+    lib.lens_find_images.restype = ctypes.c_int
+    lib.lens_critical_curves.argtypes = [V, P(LensField), P(LensGrid), V, V, I64, P(I64), P(LensOpts),
+                                         V]
+    lib.lens_critical_curves.restype = ctypes.c_int
+    lib.lens_deflect_multiplane.argtypes = [I32, P(LensField), P(D), P(LensGrid), V, I64, V,
+                                            P(LensOpts), V]
+    lib.lens_deflect_multiplane.restype = ctypes.c_int
     lib.lens_autotune.argtypes = [P(LensField), P(LensGrid), P(LensMapDesc), D, P(LensOpts), V,
                                   P(LensOpts), P(D), P(D)]
     lib.lens_autotune.restype = ctypes.c_int

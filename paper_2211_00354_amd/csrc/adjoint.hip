@@ -24,6 +24,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kThreads = 256;
+constexpr int32_t kFlushSources = 128;  // LENS_MIXED near-field partials per FP64 flush
 
 // One source (position, complex charge) against the R targets of a lane:
 // h += q/d, hp -= q/d^2 with d = z_target - z_source.  A coincident pair has
@@ -110,11 +111,30 @@ __global__ __launch_bounds__(kWave) void k_eval_adj(
         ty[r] = txy[2 * (int64_t)id[r] + 1];
         hr[r] = hi[r] = pr[r] = pi[r] = 0;
       }
+      // LENS_MIXED: the FP32 partial sums move into FP64 ones every
+      // kFlushSources sources, so a neighbourhood of thousands of rays does
+      // not accumulate thousands of FP32 roundings
+      double Sr[R], Si[R], Tr[R], Ti[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) Sr[r] = Si[r] = Tr[r] = Ti[r] = 0.0;
+      int32_t since = 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        for (int32_t i = rs[d]; i < re[d]; ++i)
+        for (int32_t i = rs[d]; i < re[d]; ++i) {
           adj_pair<MIXED, R>(tx, ty, sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1],
                              sq[2 * (int64_t)i], sq[2 * (int64_t)i + 1], hr, hi, pr, pi);
+          if (MIXED && ++since == kFlushSources) {
+            since = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              Sr[r] += (double)hr[r];
+              Si[r] += (double)hi[r];
+              Tr[r] += (double)pr[r];
+              Ti[r] += (double)pi[r];
+              hr[r] = hi[r] = pr[r] = pi[r] = 0;
+            }
+          }
+        }
 
       const double *lb = loc + 2 * (int64_t)b * p;
 #pragma unroll
@@ -128,8 +148,9 @@ __global__ __launch_bounds__(kWave) void k_eval_adj(
             df = cmad(df, w, f);
             f = cmad(f, w, cplx{lb[2 * l], lb[2 * l + 1]});
           }
-        const double Hr = f.re + (double)hr[r], Hi = f.im + (double)hi[r];
-        const double Pr = df.re * inv_s + (double)pr[r], Pi = df.im * inv_s + (double)pi[r];
+        const double Hr = f.re + (Sr[r] + (double)hr[r]), Hi = f.im + (Si[r] + (double)hi[r]);
+        const double Pr = df.re * inv_s + (Tr[r] + (double)pr[r]);
+        const double Pi = df.im * inv_s + (Ti[r] + (double)pi[r]);
         (void)Hi;
         if (!act[r]) continue;
         const uint32_t o = tperm[id[r]];

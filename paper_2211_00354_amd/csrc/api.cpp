@@ -450,7 +450,9 @@ void plan_enqueue(lens_plan *P, const double *xy, const double *q, hipStream_t s
     for (int l = L; l >= 2;) {
       if (P->direct[l]) {
         launch_p2m(P->g, l, P->swin[l], sxy, sm, P->qdim, leaf_start, P->p,
-                   static_cast<double *>(P->mp[l].ptr), static_cast<float *>(P->mp32[l].ptr), N, st);
+                   static_cast<double *>(P->mp[l].ptr), static_cast<float *>(P->mp32[l].ptr), N,
+                   l < L ? P->swin[l + 1] : Window{0, 0, 0, 0}, l < L ? P->mp_at(l + 1) : nullptr,
+                   st);
         --l;
         continue;
       }
@@ -787,14 +789,25 @@ void fmm_grid_rows(lens_plan &P, const lens_grid &grid, int64_t j0, int64_t j1, 
 }
 
 // Explicit rays: sorted by leaf box of the window, evaluated box by box,
-// written back in the caller's order.
-void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4], double c1, double c2,
-                  double *y_out, hipStream_t st,
-                  double *dfdz = nullptr) {
-  Scratch sc(st);
-  check_inside(P, bb);
+// written back in the caller's order.  The downward pass over the window of
+// bb is separate, so that repeated evaluations at moving points inside bb
+// (Newton steps) share it.
+struct ExplicitLocals {
+  Window wl;
   double *loc = nullptr;
-  const Window wl = downward(P, bb, sc, st, &loc);
+};
+
+ExplicitLocals explicit_locals(lens_plan &P, const double bb[4], Scratch &sc, hipStream_t st) {
+  check_inside(P, bb);
+  ExplicitLocals e;
+  e.wl = downward(P, bb, sc, st, &e.loc);
+  return e;
+}
+
+void fmm_explicit_eval(lens_plan &P, const ExplicitLocals &e, const double *rays, int64_t n,
+                       double c1, double c2, double *y_out, hipStream_t st, double *dfdz = nullptr) {
+  Scratch sc(st);
+  const Window wl = e.wl;
   uint32_t *k = sc.get<uint32_t>(n), *v = sc.get<uint32_t>(n);
   uint32_t *kt = sc.get<uint32_t>(n), *vt = sc.get<uint32_t>(n);
   const size_t ncnt = radix_counts_len(n);
@@ -810,7 +823,7 @@ void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4
   int32_t *rstart = sc.get<int32_t>(wl.count() + 1);
   launch_box_starts(ks, n, wl.count(), rstart, sc.get<int32_t>(box_starts_coarse_len(wl.count())), st);
   EvalArgs ea{};
-  fill_star_side(P, wl, loc, ea);
+  fill_star_side(P, wl, e.loc, ea);
   ea.grid_mode = 0;
   ea.rxy = srays;
   ea.rperm = vs;
@@ -824,6 +837,14 @@ void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4
   eval_shape(std::max<int64_t>(per, 1), &ea.rays_per_lane, &ea.chunks_per_box);
   launch_eval_checked(ea, P.precision, st);
   P.last_stream = st;
+}
+
+void fmm_explicit(lens_plan &P, const double *rays, int64_t n, const double bb[4], double c1, double c2,
+                  double *y_out, hipStream_t st,
+                  double *dfdz = nullptr) {
+  Scratch sc(st);
+  const ExplicitLocals e = explicit_locals(P, bb, sc, st);
+  fmm_explicit_eval(P, e, rays, n, c1, c2, y_out, st, dfdz);
 }
 
 void release_owned(lens_plan *owned, hipStream_t st) {
@@ -2050,6 +2071,68 @@ void zero_f64(double *p, int64_t n, hipStream_t st) {
   launch_fill_u32(reinterpret_cast<uint32_t *>(p), 2 * n, 0u, st);
 }
 
+// ---------------------------------------------- images, critical curves
+
+// A ray grid deflected in passes of whole rows (by the plan or directly),
+// each pass holding its cell rows plus the next ray row: the common frame of
+// lens_find_images and lens_critical_curves.
+struct GridPasses {
+  const FieldView &fv;
+  const lens_grid &grid;
+  lens_plan *P;   // nullptr: direct sum
+  double c1, c2;
+  int64_t rows;   // cell rows per pass
+  double *ybuf, *dbuf;
+
+  // Deflect the ray rows [j0, j1] (y, and f' if dbuf) so that row j0 starts
+  // the buffers.
+  void deflect(int64_t j0, int64_t j1, hipStream_t st) {
+    const int64_t nx = grid.nx;
+    auto shifted = [&](double *b) {
+      return b ? reinterpret_cast<double *>(reinterpret_cast<uintptr_t>(b) -
+                                            (uintptr_t)(j0 * nx) * 2 * sizeof(double))
+               : nullptr;
+    };
+    double *y_out = shifted(ybuf), *d_out = shifted(dbuf);
+    if (!P) {
+      DirectArgs d{};
+      d.n_stars = fv.f.n_stars;
+      d.sxy = fv.f.xy;
+      d.sm = fv.f.m;
+      d.grid_mode = 1;
+      d.grid = grid;
+      d.n_rays = (j1 + 1 - j0) * nx;
+      d.ray_offset = j0 * nx;
+      d.c1 = c1;
+      d.c2 = c2;
+      d.y_out = y_out;
+      d.dfdz_out = d_out;
+      StageTimer tm("direct", st);
+      launch_direct(d, st);
+    } else {
+      fmm_grid_rows(*P, grid, j0, j1 + 1, c1, c2, y_out, nullptr, 0.0, st, d_out);
+    }
+  }
+};
+
+int64_t pass_rows(const lens_opts *opts, int64_t nx, int64_t ny) {
+  const int64_t chunk = opts && opts->max_rays_per_chunk > 0 ? opts->max_rays_per_chunk : kIpmPassRays;
+  return std::max<int64_t>(1, std::min<int64_t>({ny - 1, chunk / nx - 1, kIpmPassCellsMax / (nx - 1)}));
+}
+
+template <typename T>
+T read_scalar(const T *d, hipStream_t st) {
+  T v{};
+  LENS_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, st));
+  LENS_HIP(hipStreamSynchronize(st));
+  return v;
+}
+
+// Re-raise a failed inner library call with its own status and message.
+void check_inner(lens_status r) {
+  if (r != LENS_OK) fail(r, last_error());
+}
+
 }  // namespace
 
 extern "C" {
@@ -2273,6 +2356,298 @@ lens_status lens_autotune(const lens_field *field, const lens_grid *grid, const 
     if (!t.met)
       fail(LENS_EUNSUPPORTED, "no expansion order up to " + std::to_string(LENS_MAX_ORDER) +
                                   " reaches tol (best sampled error " + std::to_string(t.err) + ")");
+  });
+}
+
+lens_status lens_find_images(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                             const double *sources, int32_t n_sources, double tol, int32_t max_iter,
+                             double *images, int32_t *image_src, int64_t cap, int64_t *n_images,
+                             const lens_opts *opts, void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    lens_opts o = resolve_opts(opts);
+    FieldView fv = field_for(plan, field);
+    if (plan) check_plan_device(plan);
+    if (!grid) fail(LENS_EINVAL, "grid is NULL");
+    check_grid(grid);
+    if (!n_images) fail(LENS_EINVAL, "n_images is NULL");
+    if (n_sources < 0) fail(LENS_EINVAL, "n_sources < 0");
+    if (n_sources > 0 && !sources) fail(LENS_EINVAL, "sources is NULL");
+    if (cap < 0) fail(LENS_EINVAL, "cap < 0");
+    if (cap > 0 && (!images || !image_src)) fail(LENS_EINVAL, "images / image_src is NULL");
+    if (!(tol > 0) || !is_finite(tol)) fail(LENS_EINVAL, "tol must be finite and > 0");
+    if (max_iter < 0 || max_iter > 1000) fail(LENS_EINVAL, "max_iter must be in [0, 1000]");
+    *n_images = 0;
+    const int64_t nx = grid->nx, ny = grid->ny;
+    if (nx < 2 || ny < 2 || n_sources == 0) return;
+    const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
+    const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
+    const bool direct = o.method == LENS_DIRECT || fv.f.n_stars == 0;
+    if (!plan && !direct && wants_auto(opts)) o = auto_opts(fv.f, *grid, nullptr, *opts, st);
+    const int64_t rows = pass_rows(opts, nx, ny);
+    double gbb[4];
+    grid_bbox(*grid, 0, ny, gbb);
+    lens_plan *P = direct ? nullptr : plan;
+    lens_plan *owned = nullptr;
+    if (!direct && !P) {
+      const double area = std::max((gbb[2] - gbb[0]) * (gbb[3] - gbb[1]), 1e-300);
+      owned = P = build_plan(fv.f, gbb, grid, (double)(nx * ny) / area, o, st);
+    }
+    try {
+      Scratch sc(st);
+      GridPasses gp{fv, *grid, P, c1, c2, rows, sc.get<double>((size_t)(rows + 1) * nx * 2), nullptr};
+      auto *count = sc.get<unsigned long long>(1);
+      // seeds: every mapped triangle that holds a source (a second sweep
+      // with room for all of them if the first overflowed)
+      int64_t capc = std::max<int64_t>(4096, 64 * (int64_t)n_sources);
+      std::vector<DevBuf> cbufs;
+      double *cand_x = nullptr;
+      int32_t *cand_s = nullptr;
+      int64_t n = 0;
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        Scratch cs(st);
+        cand_x = cs.get<double>((size_t)capc * 2);
+        cand_s = cs.get<int32_t>((size_t)capc);
+        launch_ipm_zero(count, 1, st);
+        for (int64_t j0 = 0; j0 < ny - 1; j0 += rows) {
+          const int64_t j1 = std::min(ny - 1, j0 + rows);
+          gp.deflect(j0, j1, st);
+          ImageCellArgs a{gp.ybuf, nx, j0, j0, j1, *grid, sources, n_sources, count, cand_x, cand_s, capc};
+          StageTimer tm("images", st);
+          launch_image_cells(a, st);
+        }
+        n = (int64_t)read_scalar(count, st);
+        if (n <= capc) {
+          cbufs.swap(cs.bufs);  // keep the candidates
+          break;
+        }
+        capc = n;
+      }
+      struct Keep {
+        std::vector<DevBuf> b;
+        hipStream_t s;
+        ~Keep() {
+          std::vector<DevBuf *> ps;
+          for (auto &x : b) ps.push_back(&x);
+          pool_put_batch(ps.data(), ps.size(), s);
+        }
+      } keep{std::move(cbufs), st};
+      if (n == 0) return;
+      // Newton refinement
+      double *yc = sc.get<double>((size_t)n * 2), *dc = sc.get<double>((size_t)n * 2);
+      double *res = sc.get<double>((size_t)n), *det = sc.get<double>((size_t)n);
+      uint32_t *unconv = sc.get<uint32_t>(1);
+      ExplicitLocals el;
+      if (P) el = explicit_locals(*P, gbb, sc, st);
+      NewtonArgs na{n, cand_x, cand_s, sources, yc, dc, c1, c2, tol,
+                    4.0 * std::hypot(grid->dx, grid->dy), {gbb[0], gbb[1], gbb[2], gbb[3]},
+                    res, det, unconv, 1};
+      for (int it = 0; it <= max_iter; ++it) {
+        if (P) {
+          fmm_explicit_eval(*P, el, cand_x, n, c1, c2, yc, st, dc);
+        } else {
+          DirectArgs d{};
+          d.n_stars = fv.f.n_stars;
+          d.sxy = fv.f.xy;
+          d.sm = fv.f.m;
+          d.rxy = cand_x;
+          d.n_rays = n;
+          d.c1 = c1;
+          d.c2 = c2;
+          d.y_out = yc;
+          d.dfdz_out = dc;
+          launch_direct(d, st);
+        }
+        launch_fill_u32(unconv, 1, 0u, st);
+        na.step = it < max_iter;
+        StageTimer tm("images", st);
+        launch_newton(na, st);
+        if (read_scalar(unconv, st) == 0) break;
+      }
+      // merge the converged candidates of each source (host: images are few)
+      std::vector<double> hx((size_t)n * 2), hr((size_t)n), hd((size_t)n);
+      std::vector<int32_t> hs((size_t)n);
+      LENS_HIP(hipMemcpyAsync(hx.data(), cand_x, hx.size() * 8, hipMemcpyDeviceToHost, st));
+      LENS_HIP(hipMemcpyAsync(hr.data(), res, hr.size() * 8, hipMemcpyDeviceToHost, st));
+      LENS_HIP(hipMemcpyAsync(hd.data(), det, hd.size() * 8, hipMemcpyDeviceToHost, st));
+      LENS_HIP(hipMemcpyAsync(hs.data(), cand_s, hs.size() * 4, hipMemcpyDeviceToHost, st));
+      LENS_HIP(hipStreamSynchronize(st));
+      std::vector<int64_t> ord;
+      for (int64_t k = 0; k < n; ++k)
+        if (hr[k] <= tol && std::isfinite(hd[k]) && hd[k] != 0.0) ord.push_back(k);
+      std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+        if (hs[a] != hs[b]) return hs[a] < hs[b];
+        if (hx[2 * a] != hx[2 * b]) return hx[2 * a] < hx[2 * b];
+        if (hx[2 * a + 1] != hx[2 * b + 1]) return hx[2 * a + 1] < hx[2 * b + 1];
+        return a < b;
+      });
+      const double eps = std::max(1e-3 * std::min(grid->dx, grid->dy), 1e3 * tol);
+      std::vector<int64_t> kept;
+      size_t first_of_src = 0;
+      for (int64_t k : ord) {
+        if (!kept.empty() && hs[kept.back()] != hs[k]) first_of_src = kept.size();
+        bool dup = false;
+        for (size_t q = kept.size(); q-- > first_of_src;) {
+          const int64_t c = kept[q];
+          if (hx[2 * k] - hx[2 * c] > eps) break;
+          if (std::hypot(hx[2 * k] - hx[2 * c], hx[2 * k + 1] - hx[2 * c + 1]) <= eps) {
+            if (hr[k] < hr[c]) kept[q] = k;  // the better-converged copy
+            dup = true;
+            break;
+          }
+        }
+        if (!dup) kept.push_back(k);
+      }
+      // merging may have swapped in a copy at a slightly different x1: the
+      // output stays ordered by source, then x1 to within eps
+      *n_images = (int64_t)kept.size();
+      const int64_t m = std::min<int64_t>(cap, (int64_t)kept.size());
+      if (m > 0) {
+        std::vector<double> out((size_t)m * 4);
+        std::vector<int32_t> osrc((size_t)m);
+        for (int64_t q = 0; q < m; ++q) {
+          const int64_t k = kept[q];
+          out[4 * q] = hx[2 * k];
+          out[4 * q + 1] = hx[2 * k + 1];
+          out[4 * q + 2] = 1.0 / hd[k];
+          out[4 * q + 3] = hr[k];
+          osrc[q] = hs[k];
+        }
+        LENS_HIP(hipMemcpyAsync(images, out.data(), out.size() * 8, hipMemcpyHostToDevice, st));
+        LENS_HIP(hipMemcpyAsync(image_src, osrc.data(), osrc.size() * 4, hipMemcpyHostToDevice, st));
+        LENS_HIP(hipStreamSynchronize(st));
+      }
+    } catch (...) {
+      if (owned) lens_plan_destroy(owned);
+      throw;
+    }
+    if (owned) release_owned(owned, st);
+  });
+}
+
+lens_status lens_critical_curves(lens_plan *plan, const lens_field *field, const lens_grid *grid,
+                                 double *seg_out, double *caustic_out, int64_t cap, int64_t *n_seg,
+                                 const lens_opts *opts, void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    lens_opts o = resolve_opts(opts);
+    FieldView fv = field_for(plan, field);
+    if (plan) check_plan_device(plan);
+    if (!grid) fail(LENS_EINVAL, "grid is NULL");
+    check_grid(grid);
+    if (!n_seg) fail(LENS_EINVAL, "n_seg is NULL");
+    if (cap < 0) fail(LENS_EINVAL, "cap < 0");
+    if (cap > 0 && !seg_out) fail(LENS_EINVAL, "seg_out is NULL");
+    *n_seg = 0;
+    const int64_t nx = grid->nx, ny = grid->ny;
+    if (nx < 2 || ny < 2) return;
+    const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
+    const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
+    const bool direct = o.method == LENS_DIRECT || fv.f.n_stars == 0;
+    if (!plan && !direct && wants_auto(opts)) o = auto_opts(fv.f, *grid, nullptr, *opts, st);
+    const int64_t rows = pass_rows(opts, nx, ny);
+    double gbb[4];
+    grid_bbox(*grid, 0, ny, gbb);
+    lens_plan *P = direct ? nullptr : plan;
+    lens_plan *owned = nullptr;
+    if (!direct && !P) {
+      const double area = std::max((gbb[2] - gbb[0]) * (gbb[3] - gbb[1]), 1e-300);
+      owned = P = build_plan(fv.f, gbb, grid, (double)(nx * ny) / area, o, st);
+    }
+    try {
+      Scratch sc(st);
+      const size_t nb = (size_t)(rows + 1) * nx * 2;
+      GridPasses gp{fv, *grid, P, c1, c2, rows, sc.get<double>(nb), sc.get<double>(nb)};
+      auto *count = sc.get<unsigned long long>(1);
+      launch_ipm_zero(count, 1, st);
+      for (int64_t j0 = 0; j0 < ny - 1; j0 += rows) {
+        const int64_t j1 = std::min(ny - 1, j0 + rows);
+        gp.deflect(j0, j1, st);
+        CritArgs a{gp.dbuf, nx, j0, j0, j1, *grid, c1, c2, seg_out, count, cap};
+        StageTimer tm("critical", st);
+        launch_crit_cells(a, st);
+      }
+      const int64_t n = (int64_t)read_scalar(count, st);
+      *n_seg = n;
+      const int64_t m = std::min(n, cap);
+      if (caustic_out && m > 0) {
+        // the segments' end points are 2m rays inside the grid's box
+        if (P) {
+          fmm_explicit(*P, seg_out, 2 * m, gbb, c1, c2, caustic_out, st);
+        } else {
+          DirectArgs d{};
+          d.n_stars = fv.f.n_stars;
+          d.sxy = fv.f.xy;
+          d.sm = fv.f.m;
+          d.rxy = seg_out;
+          d.n_rays = 2 * m;
+          d.c1 = c1;
+          d.c2 = c2;
+          d.y_out = caustic_out;
+          launch_direct(d, st);
+        }
+        LENS_HIP(hipStreamSynchronize(st));
+      }
+    } catch (...) {
+      if (owned) lens_plan_destroy(owned);
+      throw;
+    }
+    if (owned) release_owned(owned, st);
+  });
+}
+
+lens_status lens_deflect_multiplane(int32_t n_planes, const lens_field *fields, const double *beta,
+                                    const lens_grid *grid, const double *rays_xy, int64_t n_rays,
+                                    double *y_out, const lens_opts *opts, void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    resolve_opts(opts);
+    if (n_planes < 1 || n_planes > kMaxPlanes)
+      fail(LENS_EINVAL, "n_planes must be in [1, " + std::to_string(kMaxPlanes) + "]");
+    if (!fields) fail(LENS_EINVAL, "fields is NULL");
+    for (int32_t j = 0; j < n_planes; ++j) check_field(&fields[j]);
+    if (n_planes > 1 && !beta) fail(LENS_EINVAL, "beta is NULL");
+    for (int32_t j = 1; j < n_planes; ++j)
+      for (int32_t i = 0; i < j; ++i)
+        if (!is_finite(beta[(size_t)j * n_planes + i])) fail(LENS_EINVAL, "beta must be finite");
+    if ((grid == nullptr) == (rays_xy == nullptr) && !(grid == nullptr && n_rays == 0))
+      fail(LENS_EINVAL, "give exactly one of grid and rays_xy");
+    if (n_rays < 0) fail(LENS_EINVAL, "n_rays < 0");
+    if (grid) {
+      check_grid(grid);
+      if (n_rays != grid->nx * grid->ny) fail(LENS_EINVAL, "n_rays must equal grid.nx * grid.ny");
+    }
+    if (n_rays > (int64_t)std::numeric_limits<uint32_t>::max() - 1)
+      fail(LENS_EINVAL, "n_rays exceeds 2^32-2");
+    if (n_rays > 0 && !y_out) fail(LENS_EINVAL, "y_out is NULL");
+    if (n_rays == 0) return;
+    Scratch sc(st);
+    const int64_t n = n_rays;
+    double *alpha = sc.get<double>((size_t)n_planes * n * 2);
+    double *x = sc.get<double>((size_t)n * 2);
+    double *y = sc.get<double>((size_t)n * 2);
+    MultiPlaneArgs a{};
+    a.n = n;
+    a.grid_mode = grid != nullptr;
+    if (grid) a.grid = *grid;
+    a.rays = rays_xy;
+    a.alpha = alpha;
+    for (int32_t j = 0; j < n_planes; ++j) {
+      a.j = j;
+      for (int32_t i = 0; i < j; ++i) a.beta[i] = beta[(size_t)j * n_planes + i];
+      a.x_out = x;
+      launch_mp_positions(a, st);  // x_j (x_0 itself for j = 0)
+      if (j == 0 && grid)
+        check_inner(lens_deflect(nullptr, &fields[0], grid, nullptr, n, y, nullptr, opts, stream));
+      else
+        check_inner(lens_deflect(nullptr, &fields[j], nullptr, x, n, y, nullptr, opts, stream));
+      launch_mp_alpha(x, y, alpha + (size_t)j * n * 2, n, st);
+    }
+    // the source plane: every plane's deflection at full weight
+    a.j = n_planes;
+    for (int32_t i = 0; i < n_planes; ++i) a.beta[i] = 1.0;
+    a.x_out = y_out;
+    launch_mp_positions(a, st);
   });
 }
 

@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kXcd = 8;
+constexpr int32_t kFlushStars = 128;  // LENS_MIXED near-field partials per FP64 flush
 constexpr int kThreads = 256;  // helper kernels
 
 
@@ -141,6 +142,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && 
                                                 int32_t *__restrict__ counts) {
   // the box's local expansion, read by every lane (LDS broadcast)
   __shared__ double2 lds_loc[PMAX];
+  // LENS_MIXED: FP64 sums of the lanes' FP32 near-field partials, flushed
+  // every kFlushStars stars (alpha; f' with DERIV)
+  __shared__ double2 lds_acc[MIXED ? kWave * R * (DERIV ? 2 : 1) : 1];
   __shared__ int32_t hkey[MAP ? kMapTable : 1];
   __shared__ uint32_t hval[MAP ? kMapTable : 1];
   const int lane = threadIdx.x;
@@ -259,6 +263,33 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && 
       auto star = [&](double x, double y, double mass) {
         pair_update<MIXED, DERIV, R>(rx, ry, x, y, mass, ax, ay, dre, dim);
       };
+      // LENS_MIXED: every kFlushStars stars the FP32 partial sums move into
+      // FP64 ones in LDS (a wave-uniform count), so a ray with thousands
+      // of near stars (a cluster's core) does not accumulate thousands of
+      // FP32 roundings; a box of fewer stars never flushes
+      int32_t since = 0;
+      bool flushed = false;
+      auto flush = [&]() {
+        if constexpr (MIXED) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            double2 &acc = lds_acc[r * kWave + lane];
+            const double2 old = flushed ? acc : make_double2(0.0, 0.0);
+            acc = make_double2(old.x + (double)ax[r], old.y + (double)ay[r]);
+            ax[r] = 0;
+            ay[r] = 0;
+            if (DERIV) {
+              double2 &acd = lds_acc[(R + r) * kWave + lane];
+              const double2 od = flushed ? acd : make_double2(0.0, 0.0);
+              acd = make_double2(od.x + (double)dre[r], od.y + (double)dim[r]);
+              dre[r] = 0;
+              dim[r] = 0;
+            }
+          }
+          flushed = true;
+          since = 0;
+        }
+      };
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         int32_t i = rs[d];
@@ -273,6 +304,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && 
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) star(sx[q], sy[q], mm[q]);
+          if (MIXED) {
+            since += 4;
+            if (since >= kFlushStars) flush();
+          }
         }
         for (; i < re[d]; ++i) star(sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i]);
       }
@@ -326,8 +361,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && 
       int32_t key[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double al1 = f[r].re + (double)ax[r];
-        const double al2 = (double)ay[r] - f[r].im;
+        // the FP64 near-field sum: the FP32 partial plus, where a flush
+        // happened, the flushed ones
+        double nx = (double)ax[r], ny = (double)ay[r];
+        if (MIXED && flushed) {
+          const double2 acc = lds_acc[r * kWave + lane];
+          nx += acc.x;
+          ny += acc.y;
+        }
+        const double al1 = f[r].re + nx;
+        const double al2 = ny - f[r].im;
         const double y1 = a.c1 * rx[r] - al1;
         const double y2 = a.c2 * ry[r] - al2;
         if (MAP) {
@@ -341,9 +384,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && 
           }
         } else if (act[r]) {
           *reinterpret_cast<double2 *>(y_out + 2 * oidx[r]) = make_double2(y1, y2);
-          if (DERIV)
+          if (DERIV) {
+            double nre = (double)dre[r], nim = (double)dim[r];
+            if (MIXED && flushed) {
+              const double2 acd = lds_acc[(R + r) * kWave + lane];
+              nre += acd.x;
+              nim += acd.y;
+            }
             *reinterpret_cast<double2 *>(a.dfdz_out + 2 * oidx[r]) =
-                make_double2(fma(gd[r].re, inv_s, (double)dre[r]), fma(gd[r].im, inv_s, (double)dim[r]));
+                make_double2(fma(gd[r].re, inv_s, nre), fma(gd[r].im, inv_s, nim));
+          }
         }
       }
       if (MAP) {

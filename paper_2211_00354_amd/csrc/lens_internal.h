@@ -148,9 +148,12 @@ void build_l2l_bfrag(int p, int ks_count, int nt_count, std::vector<double> &out
 // Upward pass (upward.hip)
 // (mp32 outputs are optional FP32 copies of the same coefficients)
 // n_sources (all levels) picks a wave per box when boxes hold many sources.
+// child_win / child_mp: the level below, already formed ([child_win][p] FP64;
+// child_mp nullptr at the leaf level): boxes of more than 32 sources whose
+// children it holds are formed from them by M2M.
 void launch_p2m(Geometry g, int level, Window win, const double *sxy, const double *sq, int qdim,
                 const int32_t *leaf_start, int p, double *mp, float *mp32, int64_t n_sources,
-                hipStream_t stream);
+                Window child_win, const double *child_mp, hipStream_t stream);
 // M2M of levels level, level-1, ..., level-nlev+1 in one launch; the child
 // level (level+1) is dense, [n][n][p] complex; out[i] / out32[i] (optional)
 // receive level - i, dense.
@@ -303,6 +306,58 @@ struct IpmPass {
   unsigned long long *acc, *diff;
   uint32_t *queue, *qcount;
 };
+// Image finding, critical curves, multi-plane chaining (images.hip).  Cells
+// of grid rows [j0, j1) of a deflected grid held from row ybase on.
+struct ImageCellArgs {
+  const double *y;
+  int64_t nx, ybase, j0, j1;
+  lens_grid grid;
+  const double *src;      // [n_src][2] source positions (device)
+  int32_t n_src;
+  unsigned long long *count;  // candidates found so far
+  double *cand_x;         // [cap][2] seeds
+  int32_t *cand_s;        // [cap] source index
+  int64_t cap;
+};
+void launch_image_cells(const ImageCellArgs &a, hipStream_t stream);
+
+struct NewtonArgs {
+  int64_t n;
+  double *cand_x;
+  const int32_t *cand_s;
+  const double *src, *y, *dfdz;
+  double c1, c2, tol, max_step;
+  double box[4];
+  double *res, *det;
+  uint32_t *unconverged;
+  int step;               // 0: residual and det only
+};
+void launch_newton(const NewtonArgs &a, hipStream_t stream);
+
+struct CritArgs {
+  const double *dfdz;
+  int64_t nx, ybase, j0, j1;
+  lens_grid grid;
+  double c1, c2;
+  double *seg;            // [cap][4]
+  unsigned long long *count;
+  int64_t cap;
+};
+void launch_crit_cells(const CritArgs &a, hipStream_t stream);
+
+constexpr int kMaxPlanes = 64;
+struct MultiPlaneArgs {
+  int64_t n;
+  int grid_mode;
+  lens_grid grid;
+  const double *rays;     // explicit x_0 (grid_mode 0)
+  const double *alpha;    // [j][n][2] deflections of planes 0..j-1
+  double beta[kMaxPlanes];  // beta_ij, i < j
+  int32_t j;
+  double *x_out;          // [n][2]
+};
+void launch_mp_positions(const MultiPlaneArgs &a, hipStream_t stream);
+void launch_mp_alpha(const double *x, const double *y, double *alpha, int64_t n, hipStream_t stream);
 void launch_ipm_zero(unsigned long long *acc, int64_t n, hipStream_t stream);
 void launch_ipm_cells(const IpmPass &p, hipStream_t stream);
 void launch_ipm_finish(const unsigned long long *acc, const unsigned long long *diff, int32_t npix,

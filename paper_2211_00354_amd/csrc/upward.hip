@@ -71,84 +71,21 @@ __global__ __launch_bounds__(kThreads) void k_p2m(Geometry g, int level, Window 
   }
 }
 
-// P2M for boxes holding few sources: one thread per box of `win` with all p
-// coefficients in registers (running powers m w^k); the wave's 64 boxes are
-// staged in LDS so that the [64][p] block is written with coalesced stores.
+// Wave-cooperative P2M of one box (wave-uniform ix, iy): the box's leaf rows
+// are taken 64 at a time, their source counts scanned across the wave so
+// that the lanes share the rows' sources evenly (lane t takes sources t,
+// t+64, ... of the concatenated rows), each lane accumulating all p
+// coefficients with running powers m w^k into acc; the 64 partial
+// expansions are then summed by a fixed cross-lane butterfly (every lane
+// ends with the total, in the same order on every run).
 template <int PMAX, int QDIM>
-__global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window win,
-                                                   const double *__restrict__ sxy,
-                                                   const double *__restrict__ sq,
-                                                   const int32_t *__restrict__ leaf_start, int p,
-                                                   double *__restrict__ mp, float *__restrict__ mp32) {
-  constexpr int STR = 2 * PMAX + 1;
-  __shared__ double stage[kWave * STR];
+__device__ __forceinline__ void p2m_wave_box(const Geometry &g, int level, int64_t ix, int64_t iy,
+                                             const double *__restrict__ sxy,
+                                             const double *__restrict__ sq,
+                                             const int32_t *__restrict__ leaf_start, int p,
+                                             int32_t *row_first, int32_t *row_pre,
+                                             cplx (&acc)[PMAX]) {
   const int lane = threadIdx.x;
-  const int64_t nbox = win.count();
-  const int64_t b0 = (int64_t)blockIdx.x * kWave;
-  const int64_t b = b0 + lane;
-  cplx acc[PMAX];
-#pragma unroll
-  for (int k = 0; k < PMAX; ++k) acc[k] = cplx{0.0, 0.0};
-  if (b < nbox) {
-    const int64_t ix = win.bx0 + b % win.nbx, iy = win.by0 + b / win.nbx;
-    const double s = ldexp(g.side, -level);
-    const double inv_s = 1.0 / s;
-    const double cx = g.x0 + ((double)ix + 0.5) * s;
-    const double cy = g.y0 + ((double)iy + 0.5) * s;
-    const int sh = g.L - level;
-    const int64_t nL = int64_t(1) << g.L;
-    const int64_t span = int64_t(1) << sh;
-    for (int64_t r = 0; r < span; ++r) {
-      const int64_t row = (iy << sh) + r;
-      const int32_t i0 = leaf_start[row * nL + (ix << sh)];
-      const int32_t i1 = leaf_start[row * nL + (ix << sh) + span];
-      for (int32_t i = i0; i < i1; ++i) {
-        const cplx w = {(sxy[2 * (int64_t)i] - cx) * inv_s, (sxy[2 * (int64_t)i + 1] - cy) * inv_s};
-        cplx pw = QDIM == 1 ? cplx{sq[i], 0.0} : cplx{sq[2 * (int64_t)i], sq[2 * (int64_t)i + 1]};
-#pragma unroll
-        for (int k = 0; k < PMAX; ++k)
-          if (k < p) {
-            acc[k].re += pw.re;
-            acc[k].im += pw.im;
-            pw = cmul(pw, w);
-          }
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < PMAX; ++k)
-    if (k < p) {
-      stage[lane * STR + 2 * k] = acc[k].re;
-      stage[lane * STR + 2 * k + 1] = acc[k].im;
-    }
-  __syncthreads();
-  const int twop = 2 * p;
-  const int64_t nb = nbox - b0 < kWave ? nbox - b0 : kWave;
-  for (int e = lane; e < nb * twop; e += kWave) {
-    const int bl = e / twop, c = e - bl * twop;
-    const double v = stage[bl * STR + c];
-    mp[b0 * twop + e] = v;
-    if (mp32) mp32[b0 * twop + e] = (float)v;
-  }
-}
-
-// P2M for boxes holding many sources: one wave per box of `win`.  The box's
-// leaf rows are taken 64 at a time; their source counts are scanned across
-// the wave so that the lanes share the rows' sources evenly (lane t takes
-// sources t, t+64, ... of the concatenated rows), each lane accumulating all
-// p coefficients with running powers m w^k.  The 64 partial expansions are
-// then summed by a fixed cross-lane butterfly, so the result is
-// deterministic (and no LDS buffer limits the waves per CU).
-template <int PMAX, int QDIM>
-__global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Window win,
-                                                    const double *__restrict__ sxy,
-                                                    const double *__restrict__ sq,
-                                                    const int32_t *__restrict__ leaf_start, int p,
-                                                    double *__restrict__ mp, float *__restrict__ mp32) {
-  __shared__ int32_t row_first[kWave], row_pre[kWave];
-  const int lane = threadIdx.x;
-  const int64_t b = blockIdx.x;
-  const int64_t ix = win.bx0 + b % win.nbx, iy = win.by0 + b / win.nbx;
   const double s = ldexp(g.side, -level);
   const double inv_s = 1.0 / s;
   const double cx = g.x0 + ((double)ix + 0.5) * s;
@@ -156,10 +93,8 @@ __global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Windo
   const int sh = g.L - level;
   const int64_t nL = int64_t(1) << g.L;
   const int64_t span = int64_t(1) << sh;
-  cplx acc[PMAX];
 #pragma unroll
   for (int k = 0; k < PMAX; ++k) acc[k] = cplx{0.0, 0.0};
-
   for (int64_t rb = 0; rb < span; rb += kWave) {
     int32_t first = 0, cnt = 0;
     if (rb + lane < span) {
@@ -199,8 +134,6 @@ __global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Windo
         }
     }
   }
-  // sum of the lanes' partial expansions by a fixed butterfly (the same
-  // order on every run), no LDS buffer
 #pragma unroll
   for (int k = 0; k < PMAX; ++k)
     if (k < p) {
@@ -210,15 +143,220 @@ __global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Windo
         re += __shfl_xor(re, d);
         im += __shfl_xor(im, d);
       }
-      if (lane == 0) {
-        mp[b * 2 * p + 2 * k] = re;
-        mp[b * 2 * p + 2 * k + 1] = im;
-        if (mp32) {
-          mp32[b * 2 * p + 2 * k] = (float)re;
-          mp32[b * 2 * p + 2 * k + 1] = (float)im;
-        }
+      acc[k] = cplx{re, im};
+    }
+}
+
+// The level below a P2M level, when it is already formed: its window (in its
+// own box coordinates) and its [window][p] FP64 multipoles.  A crowded box
+// whose four children are all in that window is formed from them by M2M
+// (4 p(p-1)/2 shift updates) instead of from its stars.
+struct ChildLevel {
+  Window win;
+  const double *mp;  // nullptr: no child level
+};
+
+__device__ __forceinline__ bool children_ready(const ChildLevel &c, int64_t ix, int64_t iy) {
+  return c.mp != nullptr && 2 * ix >= c.win.bx0 && 2 * ix + 1 < c.win.bx0 + c.win.nbx &&
+         2 * iy >= c.win.by0 && 2 * iy + 1 < c.win.by0 + c.win.nby;
+}
+
+// Coefficient l of a parent's rescaled multipole from its four children
+// (M2M; one lane per coefficient): in child-size units child q's centre sits
+// at d = (qa - 1/2) + i (qc - 1/2) from the parent's, and
+//     a_l = 2^-l sum_q sum_{j<=l} C(l, j) d^j a_(l-j)(q),
+// summed by Horner in d with the binomials of row l formed on the way
+// (C(l, j-1) = C(l, j) j / (l - j + 1): integers below 2^53, so exact).
+__device__ __forceinline__ cplx m2m_coeff(const ChildLevel &c, int64_t ix, int64_t iy, int p, int l) {
+  cplx sum = {0.0, 0.0};
+  for (int q = 0; q < 4; ++q) {
+    const int qa = q & 1, qc = q >> 1;
+    const double dr = qa - 0.5, di = qc - 0.5;
+    const int64_t cb = (2 * iy + qc - c.win.by0) * c.win.nbx + (2 * ix + qa - c.win.bx0);
+    const double2 *src = reinterpret_cast<const double2 *>(c.mp) + cb * p;
+    double bin = 1.0;  // C(l, l)
+    double2 v = src[0];
+    cplx acc = {v.x, v.y};  // C(l, l) a_0
+    for (int jj = l; jj >= 1; --jj) {
+      // acc <- acc d + C(l, jj - 1) a_(l - jj + 1)
+      bin = bin * (double)jj / (double)(l - jj + 1);
+      v = src[l - jj + 1];
+      const double re = fma(acc.re, dr, fma(-acc.im, di, bin * v.x));
+      const double im = fma(acc.re, di, fma(acc.im, dr, bin * v.y));
+      acc = cplx{re, im};
+    }
+    sum.re += acc.re;
+    sum.im += acc.im;
+  }
+  return cplx{ldexp(sum.re, -l), ldexp(sum.im, -l)};
+}
+
+// A box holding more than this many sources is formed by the whole wave
+// (p2m_wave_box) rather than by its own lane.
+constexpr int64_t kCrowdedBox = 32;
+
+// P2M for levels whose boxes hold few sources on average: one thread per box
+// of `win` with all p coefficients in registers (running powers m w^k).
+// Occupancy is heavy-tailed in clustered fields (a galaxy's centre, a
+// cluster of lenses): a lane whose box holds more than kCrowdedBox sources
+// forms it by M2M from its children when the level below has them all, and
+// otherwise leaves it to the whole wave, which then forms the wave's
+// remaining crowded boxes one after another.  The wave's 64 boxes are staged
+// in LDS so that the [64][p] block is written with coalesced stores.
+template <int PMAX, int QDIM>
+__global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window win,
+                                                   const double *__restrict__ sxy,
+                                                   const double *__restrict__ sq,
+                                                   const int32_t *__restrict__ leaf_start, int p,
+                                                   double *__restrict__ mp, float *__restrict__ mp32,
+                                                   ChildLevel child) {
+  constexpr int STR = 2 * PMAX + 1;
+  __shared__ double stage[kWave * STR];
+  __shared__ int32_t row_first[kWave], row_pre[kWave];
+  const int lane = threadIdx.x;
+  const int64_t nbox = win.count();
+  const int64_t b0 = (int64_t)blockIdx.x * kWave;
+  const int64_t b = b0 + lane;
+  const int sh = g.L - level;
+  const int64_t nL = int64_t(1) << g.L;
+  const int64_t span = int64_t(1) << sh;
+  const int64_t ix = b < nbox ? win.bx0 + b % win.nbx : 0;
+  const int64_t iy = b < nbox ? win.by0 + b / win.nbx : 0;
+  int64_t count = 0;
+  if (b < nbox)
+    for (int64_t r = 0; r < span; ++r) {
+      const int64_t row = (iy << sh) + r;
+      count += leaf_start[row * nL + (ix << sh) + span] - leaf_start[row * nL + (ix << sh)];
+    }
+  const bool crowded = count > kCrowdedBox;
+  const bool by_m2m = crowded && b < nbox && children_ready(child, ix, iy);
+  cplx acc[PMAX];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) acc[k] = cplx{0.0, 0.0};
+  if (b < nbox && !crowded) {
+    const double s = ldexp(g.side, -level);
+    const double inv_s = 1.0 / s;
+    const double cx = g.x0 + ((double)ix + 0.5) * s;
+    const double cy = g.y0 + ((double)iy + 0.5) * s;
+    for (int64_t r = 0; r < span; ++r) {
+      const int64_t row = (iy << sh) + r;
+      const int32_t i0 = leaf_start[row * nL + (ix << sh)];
+      const int32_t i1 = leaf_start[row * nL + (ix << sh) + span];
+      for (int32_t i = i0; i < i1; ++i) {
+        const cplx w = {(sxy[2 * (int64_t)i] - cx) * inv_s, (sxy[2 * (int64_t)i + 1] - cy) * inv_s};
+        cplx pw = QDIM == 1 ? cplx{sq[i], 0.0} : cplx{sq[2 * (int64_t)i], sq[2 * (int64_t)i + 1]};
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k)
+          if (k < p) {
+            acc[k].re += pw.re;
+            acc[k].im += pw.im;
+            pw = cmul(pw, w);
+          }
       }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k)
+    if (k < p) {
+      stage[lane * STR + 2 * k] = acc[k].re;
+      stage[lane * STR + 2 * k + 1] = acc[k].im;
+    }
+  // the wave's crowded boxes whose children are formed: M2M by the wave,
+  // one coefficient per lane
+  uint64_t todo_m2m = __ballot(by_m2m);
+  while (todo_m2m) {
+    const int owner = __builtin_ctzll(todo_m2m);
+    todo_m2m &= todo_m2m - 1;
+    const int64_t ob = b0 + owner;
+    if (lane < p) {
+      const cplx a = m2m_coeff(child, win.bx0 + ob % win.nbx, win.by0 + ob / win.nbx, p, lane);
+      stage[owner * STR + 2 * lane] = a.re;
+      stage[owner * STR + 2 * lane + 1] = a.im;
+    }
+  }
+  // the other crowded boxes, one at a time (a wave-uniform loop)
+  uint64_t todo = __ballot(b < nbox && crowded && !by_m2m);
+  while (todo) {
+    const int owner = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    const int64_t ob = b0 + owner;
+    p2m_wave_box<PMAX, QDIM>(g, level, win.bx0 + ob % win.nbx, win.by0 + ob / win.nbx, sxy, sq,
+                             leaf_start, p, row_first, row_pre, acc);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < PMAX; ++k)
+        if (k < p) {
+          stage[owner * STR + 2 * k] = acc[k].re;
+          stage[owner * STR + 2 * k + 1] = acc[k].im;
+        }
+    }
+  }
+  __syncthreads();
+  const int twop = 2 * p;
+  const int64_t nb = nbox - b0 < kWave ? nbox - b0 : kWave;
+  for (int e = lane; e < nb * twop; e += kWave) {
+    const int bl = e / twop, c = e - bl * twop;
+    const double v = stage[bl * STR + c];
+    mp[b0 * twop + e] = v;
+    if (mp32) mp32[b0 * twop + e] = (float)v;
+  }
+}
+
+// P2M for levels whose boxes hold many sources on average: one wave per box
+// of `win` (p2m_wave_box; deterministic, and no LDS buffer limits the waves
+// per CU beyond the 512-byte row table).
+template <int PMAX, int QDIM>
+__global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Window win,
+                                                    const double *__restrict__ sxy,
+                                                    const double *__restrict__ sq,
+                                                    const int32_t *__restrict__ leaf_start, int p,
+                                                    double *__restrict__ mp, float *__restrict__ mp32,
+                                                    ChildLevel child) {
+  __shared__ int32_t row_first[kWave], row_pre[kWave];
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const int64_t ix = win.bx0 + b % win.nbx, iy = win.by0 + b / win.nbx;
+  cplx acc[PMAX];
+  bool by_m2m = false;
+  if (children_ready(child, ix, iy)) {
+    // the box's source count, its leaf rows spread over the wave
+    const int sh = g.L - level;
+    const int64_t nL = int64_t(1) << g.L;
+    const int64_t span = int64_t(1) << sh;
+    int64_t cnt = 0;
+    for (int64_t r = lane; r < span; r += kWave) {
+      const int64_t row = (iy << sh) + r;
+      cnt += leaf_start[row * nL + (ix << sh) + span] - leaf_start[row * nL + (ix << sh)];
+    }
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d);
+    by_m2m = cnt > kCrowdedBox;  // wave-uniform
+  }
+  if (by_m2m) {  // from the children, one coefficient per lane
+    if (lane < p) {
+      const cplx a = m2m_coeff(child, ix, iy, p, lane);
+      mp[b * 2 * p + 2 * lane] = a.re;
+      mp[b * 2 * p + 2 * lane + 1] = a.im;
+      if (mp32) {
+        mp32[b * 2 * p + 2 * lane] = (float)a.re;
+        mp32[b * 2 * p + 2 * lane + 1] = (float)a.im;
+      }
+    }
+    return;
+  }
+  p2m_wave_box<PMAX, QDIM>(g, level, ix, iy, sxy, sq, leaf_start, p, row_first, row_pre, acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k)
+      if (k < p) {
+        mp[b * 2 * p + 2 * k] = acc[k].re;
+        mp[b * 2 * p + 2 * k + 1] = acc[k].im;
+        if (mp32) {
+          mp32[b * 2 * p + 2 * k] = (float)acc[k].re;
+          mp32[b * 2 * p + 2 * k + 1] = (float)acc[k].im;
+        }
+      }
+  }
 }
 
 // M2M for up to four consecutive levels in one launch.  A 256-thread
@@ -319,7 +457,8 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 
 void launch_p2m(Geometry g, int level, Window win, const double *sxy, const double *sq, int qdim,
                 const int32_t *leaf_start, int p, double *mp, float *mp32, int64_t n_sources,
-                hipStream_t stream) {
+                Window child_win, const double *child_mp, hipStream_t stream) {
+  const ChildLevel child{child_win, child_mp};
   const int64_t n = win.count() * p;
   if (n == 0) return;
   // boxes of ~16 sources or more (on average over the level): a wave per box
@@ -327,10 +466,12 @@ void launch_p2m(Geometry g, int level, Window win, const double *sxy, const doub
     const unsigned nb = (unsigned)win.count();
     if (qdim == 2)
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_wave<PM, 2>), dim3(nb), dim3(kWave), 0, stream,
-                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32));
+                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32,
+                                               child));
     else
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_wave<PM, 1>), dim3(nb), dim3(kWave), 0, stream,
-                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32));
+                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32,
+                                               child));
     LENS_HIP(hipGetLastError());
     return;
   }
@@ -340,10 +481,12 @@ void launch_p2m(Geometry g, int level, Window win, const double *sxy, const doub
     const unsigned nb = (unsigned)((win.count() + kWave - 1) / kWave);
     if (qdim == 2)
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_box<PM, 2>), dim3(nb), dim3(kWave), 0, stream,
-                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32));
+                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32,
+                                               child));
     else
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_box<PM, 1>), dim3(nb), dim3(kWave), 0, stream,
-                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32));
+                                               g, level, win, sxy, sq, leaf_start, p, mp, mp32,
+                                               child));
     LENS_HIP(hipGetLastError());
     return;
   }

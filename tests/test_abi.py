@@ -175,3 +175,78 @@ def test_ipm_map_rejects_bad_maps(npix, side, mu, msg):
                           None)
     assert st == _lib.LENS_EINVAL
     assert msg in lib.lens_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tol=0.0), "tol"),
+    (dict(tol=float("nan")), "tol"),
+    (dict(max_iter=-1), "max_iter"),
+    (dict(max_iter=1001), "max_iter"),
+    (dict(n_images=False), "n_images"),
+    (dict(grid=False), "grid"),
+    (dict(n_src=-1), "n_sources"),
+    (dict(sources=False), "sources"),
+    (dict(out=False), "images"),
+])
+def test_find_images_rejects_bad_arguments(kw, msg):
+    lib = _lib.load()
+    f = _lib.LensField(0, None, None, 0.0, 0.0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 4, 4)
+    n = ctypes.c_int64(-7)
+    st = lib.lens_find_images(None, ctypes.byref(f), ctypes.byref(g) if kw.get("grid", True) else None,
+                              ctypes.c_void_p(8) if kw.get("sources", True) else None,
+                              kw.get("n_src", 1), kw.get("tol", 1e-9), kw.get("max_iter", 10),
+                              ctypes.c_void_p(8) if kw.get("out", True) else None,
+                              ctypes.c_void_p(8) if kw.get("out", True) else None, 16,
+                              ctypes.byref(n) if kw.get("n_images", True) else None, None, None)
+    assert st == _lib.LENS_EINVAL
+    assert msg in lib.lens_last_error().decode()
+
+
+def test_find_images_and_critical_curves_of_a_cell_free_grid_are_empty():
+    lib = _lib.load()
+    f = _lib.LensField(0, None, None, 0.0, 0.0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 1, 7)   # one column: no cells
+    n = ctypes.c_int64(-7)
+    assert lib.lens_find_images(None, ctypes.byref(f), ctypes.byref(g), ctypes.c_void_p(8), 1, 1e-9, 10,
+                                None, None, 0, ctypes.byref(n), None, None) == _lib.LENS_OK
+    assert n.value == 0
+    n.value = -7
+    assert lib.lens_critical_curves(None, ctypes.byref(f), ctypes.byref(g), None, None, 0,
+                                    ctypes.byref(n), None, None) == _lib.LENS_OK
+    assert n.value == 0
+
+
+@pytest.mark.parametrize("cap,seg,nseg,msg", [(-1, True, True, "cap"), (4, False, True, "seg_out"),
+                                              (4, True, False, "n_seg")])
+def test_critical_curves_rejects_bad_arguments(cap, seg, nseg, msg):
+    lib = _lib.load()
+    f = _lib.LensField(0, None, None, 0.0, 0.0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 4, 4)
+    n = ctypes.c_int64()
+    st = lib.lens_critical_curves(None, ctypes.byref(f), ctypes.byref(g),
+                                  ctypes.c_void_p(8) if seg else None, None, cap,
+                                  ctypes.byref(n) if nseg else None, None, None)
+    assert st == _lib.LENS_EINVAL
+    assert msg in lib.lens_last_error().decode()
+
+
+@pytest.mark.parametrize("npl,beta,grid,rays,msg", [
+    (0, None, True, False, "n_planes"),
+    (65, None, True, False, "n_planes"),
+    (2, None, True, False, "beta"),
+    (2, [0.0, 0.0, float("nan"), 0.0], True, False, "beta"),
+    (1, None, True, True, "exactly one"),
+    (1, None, False, False, "exactly one"),
+])
+def test_multiplane_rejects_bad_arguments(npl, beta, grid, rays, msg):
+    lib = _lib.load()
+    k = max(npl, 1)
+    fields = (_lib.LensField * k)(*[_lib.LensField(0, None, None, 0.0, 0.0) for _ in range(k)])
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2)
+    b = (ctypes.c_double * len(beta))(*beta) if beta else None
+    st = lib.lens_deflect_multiplane(npl, fields, b, ctypes.byref(g) if grid else None,
+                                     ctypes.c_void_p(8) if rays else None, 4, ctypes.c_void_p(8),
+                                     None, None)
+    assert st == _lib.LENS_EINVAL
+    assert msg in lib.lens_last_error().decode()

@@ -425,6 +425,37 @@ def test_small_ray_region_in_wide_field(lf, prec, p, fl, tol):
     check(yd[idx], yo, ao, 1e-13)
 
 
+@pytest.mark.parametrize("prec,p,fl,tol", [("fp64", 30, 0, 1e-10), ("mixed", 16, -1, 1e-5)])
+def test_crowded_boxes_formed_by_m2m(lf, prec, p, fl, tol):
+    """A cusp inside a sparse field: 2e5 stars in a Gaussian cluster
+    (sigma 0.3) plus 5e4 spread over a disk of radius 300, rays over the
+    cluster.  The leaf level follows the cluster's density, so the coarser
+    windowed levels hold boxes of thousands of stars, which are formed by
+    M2M from their children, and the rest from their stars.  Against the
+    FP64 direct sum (itself pinned to the oracle on a few rays).  As for any
+    small ray region in a wide field, the coarse levels carry large partial
+    fields, so FP32 M2L levels would leave ~3e-5 on the worst rays: the
+    mixed case keeps every M2L level in FP64."""
+    rng = np.random.default_rng(78)
+    xy_h = np.concatenate([0.3 * rng.standard_normal((200_000, 2)),
+                           wl.uniform_disk(rng, 50_000, 300.0)])
+    m_h = np.concatenate([np.full(200_000, 1e-4), wl.powerlaw_masses(rng, 50_000)])
+    g = wl.centred_grid(6.0, 6.0, 512, 512)
+    xy, m = dev_tensor(xy_h), dev_tensor(m_h)
+    kw = dict(kappa_s=0.0, gamma=0.1)
+    _say("crowded boxes", prec, p)
+    yd = host(lf.deflect(xy, m, grid=lfgrid(g), method="direct", **kw))
+    ad = g.rays() * [0.9, 1.1] - yd
+    plan = lf.Plan(xy, m, grid=lfgrid(g), precision=prec, p=p, fp32_levels=fl, **kw)
+    print(f"[plan] crowded boxes: {plan.info()}", flush=True)
+    y = host(lf.deflect(grid=lfgrid(g), plan=plan, **kw))
+    plan.close()
+    check(y, yd, ad, tol, f"crowded boxes {prec} p={p}")
+    idx = g.strided(61, 7)
+    yo, ao, _ = oracle.deflect(xy_h, m_h, g.rays(idx), **kw)
+    check(yd[idx], yo, ao, 1e-13)
+
+
 def test_plan_rejects_rays_outside_its_ray_box(lf):
     f = wl.random_field(2000, 30.0, seed=5)
     plan = lf.Plan(dev_tensor(f.xy), dev_tensor(f.m), ray_box=(-5, -5, 5, 5))

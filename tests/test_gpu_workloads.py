@@ -36,7 +36,7 @@ def _lfgrid(lf, g):
 
 def test_synthetic_halo_full_size(lf):
     """1.575e7 particles of four kinds (dark matter, gas, stars, black holes)
-    with masses spanning 1e-3 to 0.1 and densities from a cusp to a sparse
+    with masses from 5e-4 to 0.03 and densities from a cusp to a sparse
     envelope 1500 Einstein radii out, 4000^2 rays over the central 90 x 90:
     mixed precision with the order chosen for 1e-5 and FP64 at p = 30,
     against the oracle on ~1000 strided rays, per ray."""

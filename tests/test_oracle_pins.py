@@ -627,3 +627,55 @@ def test_ipm_point_lens_matches_analytic_magnification():
                 continue   # near the caustic point
             ana = ((uu ** 2 + 2) / (uu * np.sqrt(uu ** 2 + 4))).mean()
             assert abs(mu[v, u] / ana - 1) < 2e-3, (u, v, mu[v, u], ana)
+
+
+# ------------------------------------------------------------- multi-plane
+
+def _plane(seed, n, R, ks, g):
+    f = wl.random_field(n, R, seed=seed, masses="powerlaw")
+    return (f.xy, f.m, ks, g)
+
+
+def test_multiplane_one_plane_is_the_single_plane_map():
+    pl = _plane(31, 40, 3.0, 0.2, 0.1)
+    rays = np.random.default_rng(32).uniform(-4, 4, (300, 2))
+    y = oracle.multiplane([pl], None, rays)
+    y1, _, _ = oracle.deflect(pl[0], pl[1], rays, pl[2], pl[3])
+    np.testing.assert_allclose(y, y1, rtol=0, atol=1e-13)   # x - (x - y1) rounds once
+
+
+def test_multiplane_without_coupling_is_superposition():
+    """beta_10 = 0: the second plane sees the unlensed ray, so the two planes
+    act as one plane holding both sets of stars, with the smooth terms
+    added.  The unused upper triangle of beta holds garbage on purpose."""
+    a, b = _plane(33, 30, 3.0, 0.1, 0.2), _plane(34, 25, 2.0, 0.15, -0.05)
+    rays = np.random.default_rng(35).uniform(-4, 4, (300, 2))
+    y = oracle.multiplane([a, b], [[0.0, 0.9], [0.0, 0.0]], rays)
+    yu, _, _ = oracle.deflect(np.concatenate([a[0], b[0]]), np.concatenate([a[1], b[1]]), rays,
+                              a[2] + b[2], a[3] + b[3])
+    np.testing.assert_allclose(y, yu, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("b10", [0.3, 0.75])
+def test_multiplane_smooth_sheets_compose_as_linear_maps(b10):
+    """Two planes of smooth convergence and shear only, K_j = diag(kappa_j +
+    gamma_j, kappa_j - gamma_j) (alpha_j(x) = K_j x): y = (I - K0 - K1 +
+    beta_10 K1 K0) x, the two-plane cross term of the recursion."""
+    k0, g0, k1, g1 = 0.3, 0.12, 0.2, -0.07
+    K0, K1 = np.diag([k0 + g0, k0 - g0]), np.diag([k1 + g1, k1 - g1])
+    rays = np.random.default_rng(36).uniform(-5, 5, (50, 2))
+    empty = (np.zeros((0, 2)), np.zeros(0))
+    y = oracle.multiplane([(*empty, k0, g0), (*empty, k1, g1)], [[0.0, -3.0], [b10, 0.0]], rays)
+    M = np.eye(2) - K0 - K1 + b10 * K1 @ K0
+    np.testing.assert_allclose(y, rays @ M.T, rtol=1e-14, atol=1e-14)
+
+
+def test_multiplane_two_point_lenses_on_the_axis():
+    """Point masses m0, m1 at the origin of two planes, a ray on the x1 axis
+    at r: x_1 = r - beta m0 / r and y = r - m0 / r - m1 / x_1."""
+    m0, m1, b, r = 0.7, 1.3, 0.4, 1.7
+    y = oracle.multiplane([(np.zeros((1, 2)), np.array([m0]), 0.0, 0.0),
+                           (np.zeros((1, 2)), np.array([m1]), 0.0, 0.0)],
+                          [[0.0, 0.0], [b, 0.0]], np.array([[r, 0.0]]))
+    x1 = r - b * m0 / r
+    np.testing.assert_allclose(y[0], [r - m0 / r - m1 / x1, 0.0], rtol=1e-15, atol=1e-15)

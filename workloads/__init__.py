@@ -224,10 +224,11 @@ def synthetic_halo(n_dm: int = 10_800_000, n_gas: int = 3_760_000, n_star: int =
     * gas: cored, ~ 1/sqrt(r^2 + 40^2), same extent and flattening;
     * stars: exponential disk of scale 6, axis ratio 0.6;
     * black holes: Gaussian of width 1 about the centre;
-    * all rotated by 30 degrees; masses 80% / 15% / 5% of a total of 43500
-      (dark matter / gas / stars), black holes 0.1 each, so that the mass
-      inside r = 30 is ~pi 30^2 (an Einstein radius of ~30, where the inner
-      region holds the critical curves); kappa_s = 0, external shear 0.03.
+    * all rotated by 30 degrees; masses 80% / 15% / 5% of a total of 13050
+      (dark matter / gas / stars), black holes 0.03 each, so that the mass
+      inside r = 30 is ~30^2 (a mean convergence M(<r)/r^2 of 1 there: an
+      Einstein radius of ~30, inside the ray region with the critical
+      curves); kappa_s = 0, external shear 0.03.
 
     Rays: an n_side x n_side grid over [-half_width, half_width]^2 (the inner
     region, where the caustics and the multiple images are)."""
@@ -247,9 +248,9 @@ def synthetic_halo(n_dm: int = 10_800_000, n_gas: int = 3_760_000, n_star: int =
     r_st = np.minimum(r_st, R)
     xy = np.concatenate([place(r_dm, 0.75), place(r_gas, 0.75), place(r_st, 0.6),
                          rng.standard_normal((n_bh, 2))])
-    M = 43500.0
+    M = 13050.0
     m = np.concatenate([np.full(n_dm, 0.80 * M / n_dm), np.full(n_gas, 0.15 * M / n_gas),
-                        np.full(n_star, 0.05 * M / n_star), np.full(n_bh, 0.1)])
+                        np.full(n_star, 0.05 * M / n_star), np.full(n_bh, 0.03)])
     f = Field(xy=xy, m=m, kappa_s=0.0, gamma=0.03, radius=R,
               meta={"components": {"dark": n_dm, "gas": n_gas, "stars": n_star, "bh": n_bh}})
     g = centred_grid(2 * half_width, 2 * half_width, n_side, n_side)
