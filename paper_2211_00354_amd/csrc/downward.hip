@@ -29,6 +29,9 @@
 // locals.  Orders whose tile does not fit the LDS budget use the VALU kernel.
 #include <type_traits>
 
+#include <mutex>
+#include <vector>
+
 #include "device_common.h"
 
 namespace lensfmm {
@@ -532,11 +535,28 @@ void mfma_dispatch_tile(M2LBatch &b, const T *bfrag, const double *l2l_frag, hip
     mfma_batch<T, 8, KS, FUSE>(b, bfrag, l2l_frag, stream);
 }
 
+// The device's LDS per workgroup (160 KB on gfx950), read once per device.
+size_t lds_per_block() {
+  static std::mutex mu;
+  static std::vector<size_t> known;
+  int dev = 0;
+  LENS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((size_t)dev >= known.size()) known.resize(dev + 1, 0);
+  if (!known[dev]) {
+    int v = 0;
+    LENS_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    known[dev] = v > 0 ? (size_t)v : kLdsBudget;
+  }
+  return known[dev];
+}
+
 template <typename T, bool FUSE>
 bool mfma_dispatch(M2LBatch &b, const T *bfrag, const double *l2l_frag, int ks,
                    hipStream_t stream) {
-  // the tile must fit the LDS budget at TILE = 8
-  if ((size_t)12 * 12 * (4 * ks + 1) * sizeof(T) > kLdsBudget) return false;
+  // the tile must fit the workgroup's LDS at TILE = 8 (the larger tile is
+  // taken only within kLdsBudget, which keeps two or more workgroups per CU)
+  if ((size_t)12 * 12 * (4 * ks + 1) * sizeof(T) > lds_per_block()) return false;
   switch (ks) {
     case 2: mfma_dispatch_tile<T, 2, FUSE>(b, bfrag, l2l_frag, stream); return true;
     case 4: mfma_dispatch_tile<T, 4, FUSE>(b, bfrag, l2l_frag, stream); return true;

@@ -148,6 +148,22 @@ void build_l2l_bfrag(int p, int ks_count, int nt_count, std::vector<double> &out
 // Upward pass (upward.hip)
 // (mp32 outputs are optional FP32 copies of the same coefficients)
 // n_sources (all levels) picks a wave per box when boxes hold many sources.
+// Trees of several fields sorted together (batched maps): field j's sources
+// xy/q ([n][2], [n]) occupy elements [off, off + n) of the combined arrays;
+// its sorted sources go to sxy/sq.
+struct TreeJob {
+  const double *xy, *q;
+  double *sxy, *sq;
+  Geometry g;
+  int64_t off, n;
+};
+// keys (j << shift) | leaf key, values the field-local index
+void launch_leaf_keys_multi(const TreeJob *jobs, int njobs, int64_t total, int shift, uint32_t *keys,
+                            uint32_t *vals, hipStream_t stream);
+// after the sort: gather each field's sources, keys &= mask (leaf keys)
+void launch_gather_multi(const TreeJob *jobs, int njobs, int64_t total, uint32_t mask, uint32_t *keys,
+                         const uint32_t *perm, hipStream_t stream);
+
 // child_win / child_mp: the level below, already formed ([child_win][p] FP64;
 // child_mp nullptr at the leaf level): boxes of more than 32 sources whose
 // children it holds are formed from them by M2M.

@@ -379,6 +379,55 @@ __global__ __launch_bounds__(kThreads) void k_gather_stars(const uint32_t *__res
   for (int c = 0; c < qdim; ++c) sq[qdim * j + c] = q[qdim * i + c];
 }
 
+// Several fields' trees in one pass (batched maps): field j's sources are
+// elements [off_j, off_j + n_j) of the combined key/value arrays, keyed
+// (j << shift) | leaf key, so one stable sort orders every field by leaf box
+// (within a field exactly as its own sort would).
+__device__ __forceinline__ int tree_job_of(const TreeJob *__restrict__ jobs, int njobs, int64_t g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].off <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_leaf_keys_multi(const TreeJob *__restrict__ jobs,
+                                                              int njobs, int64_t total, int shift,
+                                                              uint32_t *__restrict__ keys,
+                                                              uint32_t *__restrict__ vals) {
+  const int64_t gi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (gi >= total) return;
+  const int j = tree_job_of(jobs, njobs, gi);
+  const TreeJob &t = jobs[j];
+  const int64_t i = gi - t.off;
+  const int64_t nb = int64_t(1) << t.g.L;
+  const double s = ldexp(t.g.side, -t.g.L);
+  const int64_t ix = box_coord(t.xy[2 * i], t.g.x0, s, nb);
+  const int64_t iy = box_coord(t.xy[2 * i + 1], t.g.y0, s, nb);
+  keys[gi] = ((uint32_t)j << shift) | (uint32_t)(iy * nb + ix);
+  vals[gi] = (uint32_t)i;
+}
+
+// Sorted position gi of the combined arrays: field j's source perm[gi]
+// (a field-local index) into that field's sorted arrays; the key loses its
+// field bits.
+__global__ __launch_bounds__(kThreads) void k_gather_multi(const TreeJob *__restrict__ jobs, int njobs,
+                                                           int64_t total, uint32_t mask,
+                                                           uint32_t *__restrict__ keys,
+                                                           const uint32_t *__restrict__ perm) {
+  const int64_t gi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (gi >= total) return;
+  const int j = tree_job_of(jobs, njobs, gi);
+  const TreeJob &t = jobs[j];
+  const int64_t k = gi - t.off;
+  const int64_t i = perm[gi];
+  t.sxy[2 * k] = t.xy[2 * i];
+  t.sxy[2 * k + 1] = t.xy[2 * i + 1];
+  t.sq[k] = t.q[i];
+  keys[gi] &= mask;
+}
+
 __global__ __launch_bounds__(kThreads) void k_gather_rays(const uint32_t *__restrict__ perm,
                                                           const double *__restrict__ xy, int64_t n,
                                                           double *__restrict__ sxy) {
@@ -546,6 +595,22 @@ void launch_gather_stars(const uint32_t *perm, const double *xy, const double *q
   if (n == 0) return;
   hipLaunchKernelGGL(k_gather_stars, dim3(blocks_for(n)), dim3(kThreads), 0, stream, perm, xy, q,
                      qdim, n, sxy, sq);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_leaf_keys_multi(const TreeJob *jobs, int njobs, int64_t total, int shift, uint32_t *keys,
+                            uint32_t *vals, hipStream_t stream) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_leaf_keys_multi, dim3(blocks_for(total)), dim3(kThreads), 0, stream, jobs,
+                     njobs, total, shift, keys, vals);
+  LENS_HIP(hipGetLastError());
+}
+
+void launch_gather_multi(const TreeJob *jobs, int njobs, int64_t total, uint32_t mask, uint32_t *keys,
+                         const uint32_t *perm, hipStream_t stream) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_gather_multi, dim3(blocks_for(total)), dim3(kThreads), 0, stream, jobs, njobs,
+                     total, mask, keys, perm);
   LENS_HIP(hipGetLastError());
 }
 
