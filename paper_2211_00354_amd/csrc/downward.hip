@@ -565,6 +565,7 @@ bool mfma_dispatch(M2LBatch &b, const T *bfrag, const double *l2l_frag, int ks,
     case 10: mfma_dispatch_tile<T, 10, FUSE>(b, bfrag, l2l_frag, stream); return true;
     case 12: mfma_dispatch_tile<T, 12, FUSE>(b, bfrag, l2l_frag, stream); return true;
     case 16: mfma_dispatch_tile<T, 16, FUSE>(b, bfrag, l2l_frag, stream); return true;
+    case 20: mfma_dispatch_tile<T, 20, FUSE>(b, bfrag, l2l_frag, stream); return true;
     default: return false;
   }
 }

@@ -357,6 +357,19 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
       } else if (hits) {
         if (u0 == u1 && v0 == v1 && inside) {
           table_add(tkey, tval, a.acc, (int32_t)(v0 * npix + u0), q_cell);  // wholly inside
+        } else if (npx == 2 && inside && c.kind == 0) {
+          // across one pixel edge: the first pixel's overlap by Green's
+          // theorem, the second takes the rest of the cell (in fixed point,
+          // so the cell's total is exact)
+          double k[4], kinv[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) edge_slope(c.q[e], c.q[(e + 1) & 3], k[e], kinv[e]);
+          const double ov = cell_pixel_overlap(c.q, c.X, 0, k, kinv, (double)u0, (double)v0);
+          const double f = fmin(fmax(ov / c.area, 0.0), 1.0);
+          const unsigned long long q0 = to_fix(a.cell_px * f);
+          const unsigned long long q1 = q_cell >= q0 ? q_cell - q0 : 0ull;
+          if (q0) table_add(tkey, tval, a.acc, (int32_t)(v0 * npix + u0), q0);
+          if (q1) table_add(tkey, tval, a.acc, (int32_t)(v1 * npix + u1), q1);
         } else if (npx > kPairMax) {
           const uint32_t slot = atomicAdd(a.qcount, 1u);
           a.queue[slot] = (uint32_t)((j - a.j0) * ncx + i);
