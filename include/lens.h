@@ -166,8 +166,9 @@ LENS_API lens_status lens_plan_info(const lens_plan *plan, int32_t *order_p, int
  * d(alpha1, alpha2)/d(x1, x2) = [[Re f', -Im f'], [-Im f', -Re f']], so the
  * lens map's Jacobian determinant is (1 - kappa_s)^2 - |gamma + conj(f')|^2
  * (for the shear along x1).  A ray exactly on a star skips that pair in f'
- * too; LENS_MIXED sums the near field of f' in FP32 (valid for pairs farther
- * apart than ~1e-9 Einstein radii).  Rays come from `grid` (then rays_xy must
+ * too; LENS_MIXED forms the near-field pairs of f' in FP32 (partial sums
+ * carried into FP64 every 128 stars; valid for pairs farther apart than
+ * ~1e-9 Einstein radii).  Rays come from `grid` (then rays_xy must
  * be NULL and n_rays = grid->nx * grid->ny) or from the explicit device array
  * rays_xy[n_rays][2] (then grid must be NULL).
  * `plan` may be NULL: the library then builds the star tree for this call,
@@ -176,7 +177,11 @@ LENS_API lens_status lens_plan_info(const lens_plan *plan, int32_t *order_p, int
  * the second call with the same stream, input addresses and sizes, options,
  * smooth terms and resulting tree geometry on, the call's kernels run as one
  * captured HIP graph (its buffers stay allocated until lens_release_cached;
- * calls made while the stage profiler is on run uncached).
+ * calls made while the stage profiler is on run uncached).  Such a call
+ * launches its latest graph before the bounding box has come back and then
+ * waits for the bounding-box reduction only; if the tree geometry has
+ * changed (the stars moved), it recomputes, so y_out and dfdz_out always
+ * hold this call's result.
  * With a plan, the plan's (sorted) stars, expansion order, leaf level and
  * precision are used and opts->method still selects FMM or direct; `field`
  * may then be NULL (the plan's kappa_s and gamma apply) or supply only

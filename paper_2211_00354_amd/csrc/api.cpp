@@ -11,6 +11,7 @@
 // All device work goes to the caller's stream; plan creation and explicit-ray
 // calls read one bounding box back from the device.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -145,9 +146,25 @@ double *bbox_landing() {
 }
 
 // Bounding box of the points (one read-back); with count_box, also the
-// number of points inside that rectangle (same read-back).
-void device_bbox(const double *xy, int64_t n, hipStream_t st, double out[4],
-                 const double *count_box = nullptr, int64_t *count = nullptr) {
+// number of points inside that rectangle (same read-back).  In two halves:
+// bbox_enqueue puts the reductions and the copy to the calling thread's
+// pinned landing buffer on the stream and records an event; bbox_finish
+// waits for that event only (not for work enqueued after it).
+struct BBoxRead {
+  hipEvent_t ev = nullptr;
+  bool with_count = false;
+};
+
+hipEvent_t bbox_event() {
+  thread_local std::vector<hipEvent_t> evs;
+  int dev = 0;
+  LENS_HIP(hipGetDevice(&dev));
+  if ((size_t)dev >= evs.size()) evs.resize(dev + 1, nullptr);
+  if (!evs[dev]) LENS_HIP(hipEventCreateWithFlags(&evs[dev], hipEventDisableTiming));
+  return evs[dev];
+}
+
+BBoxRead bbox_enqueue(const double *xy, int64_t n, hipStream_t st, const double *count_box = nullptr) {
   Scratch sc(st);
   const int parts = bbox_parts(n);
   double *partial = sc.get<double>((size_t)parts * 4);
@@ -156,15 +173,29 @@ void device_bbox(const double *xy, int64_t n, hipStream_t st, double out[4],
   if (count_box) launch_count_in_box(xy, n, count_box, reinterpret_cast<unsigned long long *>(o5 + 4), st);
   double *landing = bbox_landing();
   LENS_HIP(hipMemcpyAsync(landing, o5, (count_box ? 5 : 4) * sizeof(double), hipMemcpyDeviceToHost, st));
-  LENS_HIP(hipStreamSynchronize(st));
+  BBoxRead r;
+  r.ev = bbox_event();
+  r.with_count = count_box != nullptr;
+  LENS_HIP(hipEventRecord(r.ev, st));
+  return r;
+}
+
+void bbox_finish(const BBoxRead &r, double out[4], int64_t *count = nullptr) {
+  LENS_HIP(hipEventSynchronize(r.ev));
+  const double *landing = bbox_landing();
   std::copy(landing, landing + 4, out);
-  if (count_box) {
+  if (r.with_count && count) {
     uint64_t c;
     std::memcpy(&c, landing + 4, 8);
     *count = (int64_t)c;
   }
   for (int c = 0; c < 4; ++c)
     if (!is_finite(out[c])) fail(LENS_EINVAL, "non-finite coordinates in the input positions");
+}
+
+void device_bbox(const double *xy, int64_t n, hipStream_t st, double out[4],
+                 const double *count_box = nullptr, int64_t *count = nullptr) {
+  bbox_finish(bbox_enqueue(xy, n, st, count_box), out, count);
 }
 
 // Cost model of the evaluation per ray, in VALU lane-instructions: 9 q near
@@ -1568,8 +1599,11 @@ namespace {
 // buffers it uses kept alive) and from then on replayed with one launch.
 // The stage profiler needs eager launches, so calls made while it is on run
 // eagerly.
+std::atomic<uint64_t> g_call_ids{1};
+
 struct CallExec {
-  std::vector<uint64_t> key;
+  std::vector<uint64_t> key, skey;  // full key; its part independent of star positions
+  uint64_t id = g_call_ids.fetch_add(1);  // never reused
   lens_plan *P = nullptr;
   GridExec ge;
   hipStream_t origin = nullptr;
@@ -1595,11 +1629,12 @@ std::mutex g_call_mu;
 std::vector<std::unique_ptr<CallExec>> g_calls;        // most recently used last
 std::vector<std::vector<uint64_t>> g_call_seen;         // keys seen once
 
-std::vector<uint64_t> call_key(const lens_field &f, const lens_grid &g, const lens_opts &o,
-                               const double *y_out, const lens_map_desc *map, const lens_plan &P,
-                               hipStream_t st) {
+// The parts of a call's key that do not depend on the stars' positions.
+std::vector<uint64_t> call_key_static(const lens_field &f, const lens_grid &g, const lens_opts &o,
+                                      const double *y_out, const lens_map_desc *map, int device,
+                                      hipStream_t st) {
   std::vector<uint64_t> k;
-  key_push(k, (int64_t)P.device);
+  key_push(k, (int64_t)device);
   key_push(k, (const void *)st);  // replays on one stream are ordered; others get their own
   key_push(k, (const void *)f.xy);
   key_push(k, (const void *)f.m);
@@ -1624,6 +1659,13 @@ std::vector<uint64_t> call_key(const lens_field &f, const lens_grid &g, const le
     key_push(k, (int64_t)map->npix);
     key_push(k, (const void *)map->counts);
   }
+  return k;
+}
+
+std::vector<uint64_t> call_key(const lens_field &f, const lens_grid &g, const lens_opts &o,
+                               const double *y_out, const lens_map_desc *map, const lens_plan &P,
+                               hipStream_t st) {
+  std::vector<uint64_t> k = call_key_static(f, g, o, y_out, map, P.device, st);
   key_push(k, P.g.x0);
   key_push(k, P.g.y0);
   key_push(k, P.g.side);
@@ -1640,7 +1682,30 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   grid_bbox(grid, 0, grid.ny, bb);
   double sb[4];
   int64_t cnt = 0;
-  device_bbox(f.xy, f.n_stars, st, sb, bb, &cnt);
+  const BBoxRead rd = bbox_enqueue(f.xy, f.n_stars, st, bb);
+  // Speculation (outputs that the call overwrites, not maps that it adds
+  // to): replay the latest graph of this call's arrays and parameters right
+  // behind the bounding-box reduction, and check its tree against the
+  // read-back while it runs; if the stars have moved out of it, the call
+  // below runs again and overwrites the outputs.
+  int dev = 0;
+  LENS_HIP(hipGetDevice(&dev));
+  std::vector<uint64_t> skey;
+  uint64_t spec = 0;  // id of the graph replayed speculatively
+  std::unique_lock<std::mutex> lk(g_call_mu);
+  if (!map && !profiling_enabled()) {
+    skey = call_key_static(f, grid, o, y_out, map, dev, st);
+    key_push(skey, (const void *)dfdz);
+    for (size_t i = g_calls.size(); i-- > 0;)
+      if (g_calls[i]->skey == skey) {
+        spec = g_calls[i]->id;
+        LENS_HIP(hipGraphLaunch(g_calls[i]->exec, st));
+        g_calls[i]->last = st;
+        break;
+      }
+  }
+  lk.unlock();
+  bbox_finish(rd, sb, &cnt);
   const double rho_local = local_density(cnt, bb);
   const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
   const double density = (double)(grid.nx * grid.ny) / area;
@@ -1661,12 +1726,12 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   plan_geometry(&probe, f.n_stars, sb, bb, &grid, density, o, rho_local);
   auto key = call_key(f, grid, o, y_out, map, probe, st);
   key_push(key, (const void *)dfdz);
-  std::lock_guard<std::mutex> lk(g_call_mu);
+  lk.lock();
   for (size_t i = 0; i < g_calls.size(); ++i)
     if (g_calls[i]->key == key) {
       std::unique_ptr<CallExec> c = std::move(g_calls[i]);
       g_calls.erase(g_calls.begin() + (long)i);
-      LENS_HIP(hipGraphLaunch(c->exec, st));
+      if (c->id != spec) LENS_HIP(hipGraphLaunch(c->exec, st));  // else it already ran
       c->last = st;
       g_calls.push_back(std::move(c));
       return;
@@ -1678,6 +1743,7 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   }
   auto c = std::make_unique<CallExec>();
   c->key = key;
+  c->skey = skey;
   auto *P = new lens_plan();
   c->P = P;
   P->device = probe.device;

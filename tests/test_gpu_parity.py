@@ -1167,6 +1167,46 @@ def test_call_graph_replays_match_eager(lf):
     lf.release_cached()
 
 
+def test_speculative_replay_recovers_when_stars_move(lf):
+    """A repeated plan-less deflection replays its graph before the stars'
+    bounding box has come back; when the stars have moved (in place) so
+    that the tree changes, the call must detect it and recompute: every
+    output equals the eager result of the stars it was called with, with and
+    without f'(z), and across alternating star sets."""
+    import torch
+    from paper_2211_00354_amd import _lib
+    f = wl.random_field(20000, 60.0, seed=93, masses="powerlaw")
+    g = wl.centred_grid(80.0, 80.0, 512, 512)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    xy0 = xy.clone()
+    y = torch.empty((g.n, 2), dtype=torch.float64, device="cuda")
+    d = torch.empty((g.n, 2), dtype=torch.float64, device="cuda")
+    kw = dict(kappa_s=0.2, gamma=0.1, precision="mixed", p=12)
+
+    def eager(want):
+        _lib.profile_enable(True)   # the profiler forces eager launches
+        r = lf.deflect(xy, m, grid=lfgrid(g), out=y, dfdz_out=d if want else None, **kw)
+        r = (host(r[0]), host(r[1])) if want else host(r)
+        _lib.profile_enable(False)
+        return r
+
+    lf.release_cached()
+    for want in (False, True):
+        for rep, scale in enumerate((1.0, 1.0, 1.0, 1.3, 1.3, 1.0, 0.8, 1.0)):
+            _say("speculative replay", want, rep, scale)
+            xy.copy_(xy0 * scale)   # a wider or narrower field: another root box
+            ref = eager(want)
+            y.fill_(float("nan"))
+            d.fill_(float("nan"))
+            out = lf.deflect(xy, m, grid=lfgrid(g), out=y, dfdz_out=d if want else None, **kw)
+            if want:
+                np.testing.assert_array_equal(host(out[0]), ref[0], err_msg=f"y {rep}")
+                np.testing.assert_array_equal(host(out[1]), ref[1], err_msg=f"dfdz {rep}")
+            else:
+                np.testing.assert_array_equal(host(out), ref, err_msg=f"y {rep}")
+    lf.release_cached()
+
+
 # ----------------------------------------------------------------------- IPM
 
 def _ipm_case():
