@@ -64,6 +64,61 @@ def near_pairs(info, f, g):
     return float(cy @ n3 @ cx)
 
 
+PEAK_MFMA_FP32 = 157.3e12      # MI355X dense FP32 matrix, FLOP/s
+PEAK_MFMA_FP64 = 78.6e12       # dense FP64 matrix
+
+
+def stage_rooflines(info, f, g, p, stage_ms, fp32_levels=2):
+    """Algorithmic work of the non-evaluation stages of one call against the
+    roofline that bounds each (per call, from the stage profiler's times):
+      * downward: M2L, 27 source boxes x p^2 complex MACs (8 real FLOPs) per
+        target box of every level (the boxes that cover the ray grid), FP32
+        MFMA on the finest fp32_levels levels, FP64 MFMA above; the peak is
+        the two peaks weighted by the levels' FLOPs (the L2L the stage also
+        runs is not counted);
+      * upward: P2M, p complex MACs per star at each level formed from the
+        stars, is small; the stage moves the sorted stars (24 B each) and
+        writes the multipoles (16 p B per box): HBM;
+      * tree: keys and values (8 B) read and written by each radix pass
+        (3 passes for keys of 2L <= 24 bits), the stars gathered (24 B read,
+        24 B written) and the leaf starts written (4 B per leaf box): HBM."""
+    import math as _m
+    L = info["leaf_level"]
+    out = {}
+    x0, y0, side = info["root_x0"], info["root_y0"], info["root_side"]
+    gx0, gx1 = g.x0 + 0.5 * g.dx, g.x0 + (g.nx - 0.5) * g.dx
+    gy0, gy1 = g.y0 + 0.5 * g.dy, g.y0 + (g.ny - 0.5) * g.dy
+    f32 = f64 = 0.0
+    boxes_total = 0
+    for lv in range(2, L + 1):
+        n = 1 << lv
+        s = _m.ldexp(side, -lv)
+        nx = min(n - 1, int((gx1 - x0) // s)) - max(0, int((gx0 - x0) // s)) + 1
+        ny = min(n - 1, int((gy1 - y0) // s)) - max(0, int((gy0 - y0) // s)) + 1
+        boxes = nx * ny
+        boxes_total += n * n
+        flops = boxes * 27 * 8.0 * p * p
+        if lv > L - fp32_levels:
+            f32 += flops
+        else:
+            f64 += flops
+    t_dn = stage_ms.get("downward", float("nan")) * 1e-3
+    peak_dn = (f32 + f64) / (f32 / PEAK_MFMA_FP32 + f64 / PEAK_MFMA_FP64)
+    out["downward_m2l"] = {"bound": "mfma", "flops": f32 + f64, "achieved_tflops": (f32 + f64) / t_dn / 1e12,
+                           "peak_tflops": peak_dn / 1e12, "frac": (f32 + f64) / t_dn / peak_dn}
+    n_st = f.n
+    up_bytes = n_st * 24.0 + boxes_total * 16.0 * p
+    t_up = stage_ms.get("upward", float("nan")) * 1e-3
+    out["upward"] = {"bound": "hbm", "bytes": up_bytes, "achieved_gbs": up_bytes / t_up / 1e9,
+                     "peak_gbs": PEAK_HBM / 1e9, "frac": up_bytes / t_up / PEAK_HBM}
+    passes = max(1, _m.ceil(2 * L / 8))
+    tree_bytes = n_st * (16.0 * passes + 48.0) + 4.0 * (1 << (2 * L))
+    t_tr = stage_ms.get("tree", float("nan")) * 1e-3
+    out["tree"] = {"bound": "hbm", "bytes": tree_bytes, "achieved_gbs": tree_bytes / t_tr / 1e9,
+                   "peak_gbs": PEAK_HBM / 1e9, "frac": tree_bytes / t_tr / PEAK_HBM}
+    return out
+
+
 def host_threads():
     """Threads for the CPU oracle: the cores this process may run on, capped
     by OMP_NUM_THREADS when set (a GPU machine grants each GPU a share of its
@@ -114,8 +169,9 @@ def main():
     ap.add_argument("--leaf", type=int, default=0, help="leaf level (0 = the library's choice)")
     ap.add_argument("--tune", action="store_true", help="time leaf levels 9-11 and use the fastest")
     ap.add_argument("--p", type=int, default=12)
-    ap.add_argument("--p-fp64", type=int, default=30,
-                    help="order of the FP64 FMM run at the 1e-10 target (reported in extra)")
+    ap.add_argument("--p-fp64", type=int, default=0,
+                    help="order of the FP64 FMM run at the 1e-10 target (reported in extra); "
+                         "0: the autotuner's order and leaf level for a 1e-10 per-ray error")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-direct", action="store_true", help="skip the FP64 direct comparator")
     ap.add_argument("--profile-only", action="store_true",
@@ -247,6 +303,7 @@ def main():
              "leaf_box_side": math.ldexp(info["root_side"], -leaf),
              "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
              "eval_flops_per_launch": flops, "profiled_eager_ms_per_step": ms_prof}
+    extra["stage_rooflines"] = stage_rooflines(info, f, g, args.p, extra["stage_ms_per_step"])
 
     # FP64 direct sum on the same GPU, on 128 full rows of the grid (rays/s is
     # exactly linear in the ray count for a direct sum)
@@ -268,13 +325,21 @@ def main():
         fms = timed(lambda: run(prec="fp64", leaf=leaf), 3)
         extra["fp64_fmm_rays_per_s"] = n_rays / (fms * 1e-3)
         yf = y[torch.from_numpy(idx).cuda()].cpu().numpy()
-        # FP64 FMM at the order that reaches the 1e-10 target
+        # FP64 FMM at the 1e-10 target: the autotuner's order and leaf level
+        # for a 1e-10 per-ray error on its 256^2 sample (or --p-fp64)
+        p_hi, leaf_hi = args.p_fp64, leaf
+        if p_hi == 0:
+            t_hi = lf.autotune(xy, m, grid, tol=1e-10, kappa_s=f.kappa_s, gamma=f.gamma,
+                               precision="fp64")
+            p_hi, leaf_hi = t_hi["p"], t_hi["leaf_level"]
+            extra["fp64_fmm_1e-10_autotune"] = t_hi
         for _ in range(2):
-            run(prec="fp64", p=args.p_fp64, leaf=leaf)
-        fms_hi = timed(lambda: run(prec="fp64", p=args.p_fp64, leaf=leaf), 3)
-        extra[f"fp64_fmm_p{args.p_fp64}_rays_per_s"] = n_rays / (fms_hi * 1e-3)
+            run(prec="fp64", p=p_hi, leaf=leaf_hi)
+        fms_hi = timed(lambda: run(prec="fp64", p=p_hi, leaf=leaf_hi), 3)
+        extra["fp64_fmm_1e-10"] = {"p": p_hi, "leaf_level": leaf_hi,
+                                   "rays_per_s": n_rays / (fms_hi * 1e-3), "ms": fms_hi}
         yf_hi = y[torch.from_numpy(idx).cuda()].cpu().numpy()
-        log(f"FP64 FMM p={args.p}: {fms:.3f} ms; p={args.p_fp64}: {fms_hi:.3f} ms")
+        log(f"FP64 FMM p={args.p}: {fms:.3f} ms; p={p_hi} leaf {leaf_hi}: {fms_hi:.3f} ms")
         run(leaf=leaf)   # restore the mixed output (not timed)
 
     cpu = None
@@ -301,7 +366,7 @@ def main():
         extra["rel_l2_err_alpha_mixed"] = st["rel_l2"]
         if not args.no_direct:
             extra["err_fp64_fmm_p%d" % args.p] = ray_error_stats(yf, yo, ao)
-            extra["err_fp64_fmm_p%d" % args.p_fp64] = ray_error_stats(yf_hi, yo, ao)
+            extra["fp64_fmm_1e-10"]["err"] = ray_error_stats(yf_hi, yo, ao)
         log(f"oracle: {dt:.1f} s on {nthr} threads ({host_desc()}), 1 thread "
             f"{len(idx1) / dt1:.1f} rays/s; mixed errors {st}")
 

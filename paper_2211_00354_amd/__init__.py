@@ -387,11 +387,13 @@ def irs_map_batched(fields, grids, maps, counts=None, method="fmm", precision="m
 
 def autotune(star_xy, star_m, grid: Grid, map: Optional[MapDesc] = None, tol=1e-5, kappa_s=0.0,
              gamma=0.0, precision="mixed", leaf_level=0) -> dict:
-    """Choose p, leaf level and FP32 levels by measurement: the sampled error
-    against the FP64 direct sum (relative l2 of alpha, or with ``map`` the
-    expected bin-reassignment fraction) must reach ``tol``, and the fastest
-    such whole call wins.  Returns {"p", "leaf_level", "fp32_levels",
-    "error", "ms"}; raises LensError if no p up to 40 reaches tol."""
+    """Choose p, leaf level and FP32 levels by measurement (lens_autotune):
+    on up to 256^2 strided rays the error against the FP64 direct sum (the
+    largest per-ray |dalpha_k| / max(|alpha_k|, 1e-3 rms alpha), or with
+    ``map`` the expected bin-reassignment fraction) must be at most half of
+    ``tol``, and the fastest such whole call wins.  Returns {"p",
+    "leaf_level", "fp32_levels", "error", "ms"}; raises LensError if no p up
+    to 40 reaches tol."""
     lib = _lib.load()
     f = _field(star_xy, star_m, kappa_s, gamma)
     g = grid.c()
