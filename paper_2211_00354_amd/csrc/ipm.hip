@@ -683,7 +683,7 @@ unsigned grid_for(int64_t n) {
 }
 
 // workgroups of the wide-cell kernel
-constexpr unsigned kWideBlocks = 1024;
+constexpr unsigned kWideBlocks = 1536;  // six waves per SIMD (its register limit)
 
 }  // namespace
 
