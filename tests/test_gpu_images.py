@@ -260,3 +260,102 @@ def test_multiplane_against_oracle(lf, nplanes, prec, p, tol):
     assert np.percentile(err, 99) <= tol and np.percentile(erre, 99) <= tol
     assert err.max() <= 50 * tol and erre.max() <= 50 * tol
     torch.cuda.synchronize()
+
+
+def test_images_through_a_plan_and_in_mixed_precision(lf):
+    """The same point-lens images with a plan built over the grid (FP64) and
+    in mixed precision (tol 1e-6: the evaluation's own error); for a distant
+    source only the faint image next to the lens, and nothing for no
+    source at all."""
+    import ctypes
+    import torch
+    from paper_2211_00354_amd import _lib
+    zl, m = np.array([[0.0312, -0.0187]]), np.ones(1)
+    g, grid = _grid(lf, 3.0, 1024)
+    src = np.array([[0.4, 0.1], [1.2, -0.7]])
+    plan = lf.Plan(_dev(zl), _dev(m), grid=grid, precision="fp64", p=36)
+    _say("images through a plan")
+    im_p, s_p = lf.find_images(grid=grid, sources=_dev(src), plan=plan, tol=1e-12)
+    im_n, s_n = lf.find_images(_dev(zl), _dev(m), grid=grid, sources=_dev(src), precision="fp64",
+                               p=36, tol=1e-12)
+    plan.close()
+    np.testing.assert_array_equal(s_p.cpu().numpy(), s_n.cpu().numpy())
+    np.testing.assert_allclose(im_p.cpu().numpy()[:, :3], im_n.cpu().numpy()[:, :3], rtol=0,
+                               atol=1e-12)
+    _say("images mixed")
+    im_m, s_m = lf.find_images(_dev(zl), _dev(m), grid=grid, sources=_dev(src), precision="mixed",
+                               p=16, tol=1e-6)
+    im_m, s_m = im_m.cpu().numpy(), s_m.cpu().numpy()
+    assert len(im_m) == 4
+    res = _residual_oracle(zl, m, im_m[:, :2], src[s_m], 0.0, 0.0)
+    print(f"[img] mixed: residual against the oracle up to {res.max():.2e}", flush=True)
+    assert res.max() <= 5e-6
+    # a source far outside: its bright image lies outside the grid's region,
+    # the faint one next to the lens (at distance ~1/u) inside it
+    far = np.array([[40.0, 40.0]])
+    im_f, _ = lf.find_images(_dev(zl), _dev(m), grid=grid, sources=_dev(far), method="direct",
+                             tol=1e-12)
+    im_f = im_f.cpu().numpy()
+    d = far[0] - zl[0]
+    u = np.hypot(*d)
+    x_in = zl[0] + (u - math.sqrt(u * u + 4)) / 2 * d / u
+    assert len(im_f) == 1
+    np.testing.assert_allclose(im_f[0, :2], x_in, rtol=0, atol=1e-9)
+    # no sources at all, through the C ABI
+    lib = _lib.load()
+    zl_d, m_d = _dev(zl), _dev(m)
+    f = _lib.LensField(1, ctypes.c_void_p(zl_d.data_ptr()), ctypes.c_void_p(m_d.data_ptr()), 0.0, 0.0)
+    n = ctypes.c_int64(-1)
+    g_c = grid.c()
+    assert lib.lens_find_images(None, ctypes.byref(f), ctypes.byref(g_c), None, 0, 1e-9, 10, None,
+                                None, 0, ctypes.byref(n), None, None) == _lib.LENS_OK
+    assert n.value == 0
+    torch.cuda.synchronize()
+
+
+def test_critical_curves_mixed_and_cap(lf):
+    """Mixed precision gives the same Einstein ring to O(dx^2); a segment
+    buffer smaller than the curve reports the full count and fills the
+    buffer only."""
+    import ctypes
+    import torch
+    from paper_2211_00354_amd import _lib
+    g, grid = _grid(lf, 2.0, 512)
+    xy, m = _dev(np.zeros((1, 2))), _dev(np.ones(1))
+    seg, _ = lf.critical_curves(xy, m, grid=grid, precision="mixed", p=16, caustics=False)
+    r = np.hypot(*seg.cpu().numpy().reshape(-1, 2).T)
+    print(f"[crit] mixed: {len(seg)} segments, |r - 1| max {np.abs(r - 1).max():.2e}", flush=True)
+    assert np.abs(r - 1).max() <= 3 * g.dx ** 2
+    lib = _lib.load()
+    f = _lib.LensField(1, ctypes.c_void_p(xy.data_ptr()), ctypes.c_void_p(m.data_ptr()), 0.0, 0.0)
+    buf = torch.full((10, 4), float("nan"), dtype=torch.float64, device="cuda")
+    n = ctypes.c_int64(-1)
+    g_c = grid.c()
+    o = lf._opts("direct", "fp64", 12)
+    assert lib.lens_critical_curves(None, ctypes.byref(f), ctypes.byref(g_c),
+                                    ctypes.c_void_p(buf.data_ptr()), None, 10, ctypes.byref(n),
+                                    ctypes.byref(o), None) == _lib.LENS_OK
+    assert n.value == len(seg)
+    assert bool(torch.isfinite(buf).all())
+    r10 = np.hypot(*buf.cpu().numpy().reshape(-1, 2).T)
+    assert np.abs(r10 - 1).max() <= 3 * g.dx ** 2
+
+
+def test_multiplane_single_plane_and_no_coupling_on_gpu(lf):
+    """On the GPU too: one plane equals lens_deflect, and two planes with
+    beta = 0 equal one plane holding both star sets with the smooth terms
+    added (explicit rays, FP64 direct sums)."""
+    pl = _planes(90)[:2]
+    dpl = [(_dev(a), _dev(b), ks, gm) for a, b, ks, gm in pl]
+    rays = np.random.default_rng(91).uniform(-8, 8, (3000, 2))
+    y1 = lf.deflect_multiplane(dpl[:1], None, rays=_dev(rays), method="direct").cpu().numpy()
+    yd = lf.deflect(dpl[0][0], dpl[0][1], rays=_dev(rays), kappa_s=pl[0][2], gamma=pl[0][3],
+                    method="direct").cpu().numpy()
+    np.testing.assert_allclose(y1, yd, rtol=0, atol=1e-12)
+    y2 = lf.deflect_multiplane(dpl, [[0.0, 0.0], [0.0, 0.0]], rays=_dev(rays),
+                               method="direct").cpu().numpy()
+    xy = np.concatenate([pl[0][0], pl[1][0]])
+    mm = np.concatenate([pl[0][1], pl[1][1]])
+    yu = lf.deflect(_dev(xy), _dev(mm), rays=_dev(rays), kappa_s=pl[0][2] + pl[1][2],
+                    gamma=pl[0][3] + pl[1][3], method="direct").cpu().numpy()
+    np.testing.assert_allclose(y2, yu, rtol=0, atol=1e-11)
