@@ -124,6 +124,18 @@ typedef struct {
                            ($LENS_TUNE_CACHE, "off" to disable; default
                            ~/.cache/lensfmm/autotune.txt) keyed by a coarse
                            description of the problem.  Unused otherwise */
+  void *workspace;      /* NULL (default): per-call device memory comes from
+                           the library's pool.  Otherwise a caller-owned
+                           device buffer, 256-byte aligned, of
+                           workspace_bytes bytes that lens_deflect with a plan
+                           and a ray grid carves its per-call memory from
+                           (local expansions of every level over the grid,
+                           ray ranges): the grid then runs in bands of whole
+                           rows that fit it, no device allocation is made,
+                           and one row that does not fit gives LENS_ENOMEM.
+                           Calls on one stream may share it; calls that
+                           overlap in time must not.  Other calls ignore it. */
+  size_t workspace_bytes;
 } lens_opts;
 
 /* Fill *o with the defaults (FMM, mixed, p = 12, automatic leaf level). */

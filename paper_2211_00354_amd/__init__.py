@@ -150,7 +150,7 @@ class Plan:
 def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, kappa_s=0.0,
             gamma=0.0, method="fmm", precision="mixed", p=12, leaf_level=0,
             plan: Optional[Plan] = None, out=None, fp32_levels=0, want_dfdz=False, dfdz_out=None,
-            tol=0.0):
+            tol=0.0, workspace=None):
     """Lens-map rays: returns y [n, 2] float64 on the GPU (eq. 1 + smooth term).
 
     Rays come from ``grid`` or from the explicit tensor ``rays`` [n, 2].  With
@@ -159,7 +159,9 @@ def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, k
     dfdz [n, 2] holds f'(z) = -sum m/(z - z_i)^2 (real, imaginary).
     ``p=0`` with ``tol > 0`` lets the library's autotuner choose p, the leaf
     level and the FP32 levels for that per-ray deflection error (measured
-    once, then cached in-process and on disk).
+    once, then cached in-process and on disk).  ``workspace`` (a contiguous
+    uint8 GPU tensor, with ``plan`` and ``grid``): the call's device memory
+    is carved from it, in bands of rows that fit, and nothing is allocated.
     """
     torch = _torch()
     lib = _lib.load()
@@ -193,6 +195,11 @@ def deflect(star_xy=None, star_m=None, grid: Optional[Grid] = None, rays=None, k
             if dfdz_out.numel() != 2 * n:
                 raise ValueError("dfdz_out must be [n, 2]")
     o = _opts(method, precision, p, leaf_level, fp32_levels=fp32_levels, tol=tol)
+    if workspace is not None:
+        if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 GPU tensor")
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel()
     _lib.check(lib.lens_deflect(plan.handle if plan else None, ctypes.byref(f), gp, rp, n,
                                 out.data_ptr() if n else None,
                                 dfdz_out.data_ptr() if (want and n) else None, ctypes.byref(o),

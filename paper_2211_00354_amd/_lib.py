@@ -50,7 +50,8 @@ class LensOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("order_p", ctypes.c_int32), ("leaf_level", ctypes.c_int32),
                 ("max_rays_per_chunk", ctypes.c_int64), ("fp32_levels", ctypes.c_int32),
-                ("tol", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 _lib = None

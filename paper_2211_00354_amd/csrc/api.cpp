@@ -95,6 +95,8 @@ void check_opts(const lens_opts &o) {
   if (o.max_rays_per_chunk < 0) fail(LENS_EINVAL, "opts.max_rays_per_chunk must be >= 0");
   if (o.fp32_levels < -1 || o.fp32_levels > LENS_MAX_LEVEL)
     fail(LENS_EINVAL, "opts.fp32_levels must be in [-1, " + std::to_string(LENS_MAX_LEVEL) + "]");
+  if (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) % 256 != 0 || o.workspace_bytes == 0))
+    fail(LENS_EINVAL, "opts.workspace must be 256-byte aligned with workspace_bytes > 0");
 }
 
 lens_opts resolve_opts(const lens_opts *o) {
@@ -1794,7 +1796,7 @@ namespace lensfmm {
 // Every band is planned on the host before anything is enqueued.
 void deflect_grid_no_alloc(lens_plan *plan, const lens_field *field, const lens_grid *grid,
                            double *y_out, const lens_opts *opts, char *region, size_t bytes,
-                           hipStream_t st) {
+                           hipStream_t st, double *dfdz) {
   if (!plan) fail(LENS_EINVAL, "plan is NULL (the allocation-free deflection needs a plan)");
   const lens_opts o = resolve_opts(opts);
   FieldView fv = field_for(plan, field);
@@ -1819,6 +1821,7 @@ void deflect_grid_no_alloc(lens_plan *plan, const lens_field *field, const lens_
     d.c1 = c1;
     d.c2 = c2;
     d.y_out = y_out;
+    d.dfdz_out = dfdz;
     launch_direct(d, st);
     return;
   }
@@ -1832,8 +1835,8 @@ void deflect_grid_no_alloc(lens_plan *plan, const lens_field *field, const lens_
     const size_t one = gridexec_bytes(*plan, *grid, j0, j0 + 1);
     if (one > bytes)
       fail(LENS_ENOMEM, "one grid row needs " + std::to_string(one) +
-                            " bytes of scratch, more than the allocation-free entry point's " +
-                            std::to_string(bytes) + " (use lens_deflect)");
+                            " bytes of scratch, more than the " + std::to_string(bytes) +
+                            " bytes of the allocation-free workspace");
     int64_t lo = j0 + 1, hi = grid->ny;
     while (lo < hi) {
       const int64_t mid = lo + (hi - lo + 1) / 2;
@@ -1845,7 +1848,7 @@ void deflect_grid_no_alloc(lens_plan *plan, const lens_field *field, const lens_
   for (const auto &b : bands) {
     GridExec ge;
     gridexec_alloc(*plan, *grid, b.first, b.second, ge, st, region);
-    gridexec_enqueue(*plan, ge, c1, c2, y_out, nullptr, st);
+    gridexec_enqueue(*plan, ge, c1, c2, y_out, nullptr, st, dfdz);
   }
   plan->last_stream = st;
 }
@@ -1952,6 +1955,12 @@ lens_status lens_deflect(lens_plan *plan, const lens_field *field, const lens_gr
     const double c1 = (1.0 - fv.f.kappa_s) - fv.f.gamma;
     const double c2 = (1.0 - fv.f.kappa_s) + fv.f.gamma;
 
+    if (plan && grid && o.workspace && o.method == LENS_FMM && fv.f.n_stars > 0) {
+      // the caller's workspace instead of the pool, in bands of rows that fit
+      deflect_grid_no_alloc(plan, field, grid, y_out, &o, static_cast<char *>(o.workspace),
+                            o.workspace_bytes, st, dfdz_out);
+      return;
+    }
     if (o.method == LENS_DIRECT || fv.f.n_stars == 0) {
       DirectArgs d{};
       d.n_stars = fv.f.n_stars;

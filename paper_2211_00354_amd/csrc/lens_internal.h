@@ -398,10 +398,11 @@ struct NoTiming {
 };
 
 // Grid deflection with a plan into a caller-provided device region of
-// `bytes` bytes (allocates no device memory); see lens_deflect_noalloc.
+// `bytes` bytes (allocates no device memory); see lens_deflect_noalloc and
+// lens_opts.workspace.  dfdz: f'(z) as in lens_deflect, or nullptr.
 void deflect_grid_no_alloc(lens_plan *plan, const lens_field *field, const lens_grid *grid,
                            double *y_out, const lens_opts *opts, char *region, size_t bytes,
-                           hipStream_t st);
+                           hipStream_t st, double *dfdz = nullptr);
 struct StageTimer {
   const char *name;
   hipStream_t stream;

@@ -250,3 +250,17 @@ def test_multiplane_rejects_bad_arguments(npl, beta, grid, rays, msg):
                                      None, None)
     assert st == _lib.LENS_EINVAL
     assert msg in lib.lens_last_error().decode()
+
+
+@pytest.mark.parametrize("addr,size", [(8, 1 << 20), (256, 0)])
+def test_workspace_must_be_aligned_and_sized(addr, size):
+    lib = _lib.load()
+    f = _lib.LensField(n_stars=0)
+    g = _lib.LensGrid(0.0, 0.0, 1.0, 1.0, 2, 2)
+    o = _opts()
+    o.workspace = addr
+    o.workspace_bytes = size
+    st = lib.lens_deflect(None, ctypes.byref(f), ctypes.byref(g), None, 4, ctypes.c_void_p(8), None,
+                          ctypes.byref(o), None)
+    assert st == _lib.LENS_EINVAL
+    assert "workspace" in lib.lens_last_error().decode()

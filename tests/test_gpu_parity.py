@@ -395,6 +395,35 @@ def test_fmm_determinism_and_plan_reuse(lf):
     plan.close()
 
 
+def test_caller_workspace_matches_pooled_call(lf):
+    """lens_opts.workspace: a plan + grid deflection whose per-call memory is
+    carved from a caller's buffer equals the pooled call bit for bit, with and
+    without f'(z), also when the buffer holds only a few rows at a time; a
+    buffer too small for one row is refused with ENOMEM."""
+    import torch
+    from paper_2211_00354_amd import _lib
+    f = wl.random_field(20000, 60.0, seed=37, masses="powerlaw")
+    g = wl.centred_grid(80.0, 80.0, 1024, 777)
+    xy, m = dev_tensor(f.xy), dev_tensor(f.m)
+    kw = dict(grid=lfgrid(g), kappa_s=0.25, gamma=-0.1)
+    for prec, p in (("mixed", 12), ("fp64", 24)):
+        plan = lf.Plan(xy, m, precision=prec, p=p, **kw)
+        ref = lf.deflect(plan=plan, want_dfdz=True, **kw)
+        yref, dref = host(ref[0]), host(ref[1])
+        for mib in (256, 3):
+            _say("workspace", prec, p, f"{mib} MiB")
+            ws = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+            y, d = lf.deflect(plan=plan, want_dfdz=True, workspace=ws, **kw)
+            np.testing.assert_array_equal(host(y), yref)
+            np.testing.assert_array_equal(host(d), dref)
+            np.testing.assert_array_equal(host(lf.deflect(plan=plan, workspace=ws, **kw)), yref)
+        tiny = torch.empty(4096, dtype=torch.uint8, device="cuda")
+        with pytest.raises(_lib.LensError) as e:
+            lf.deflect(plan=plan, workspace=tiny, **kw)
+        assert e.value.status == _lib.LENS_ENOMEM
+        plan.close()
+
+
 @pytest.mark.parametrize("prec,p,fl,tol", [("fp64", 36, 0, 1e-10), ("mixed", 20, 0, 1e-5),
                                            ("mixed", 20, -1, 1e-5)])
 def test_small_ray_region_in_wide_field(lf, prec, p, fl, tol):
