@@ -18,45 +18,32 @@ constexpr int kWaves = kThreads / 64;
 
 // ------------------------------------------------------------ bounding box
 
-__global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restrict__ xy, int64_t n,
-                                                           double *__restrict__ partial) {
-  double mn0 = DBL_MAX, mn1 = DBL_MAX, mx0 = -DBL_MAX, mx1 = -DBL_MAX;
+// v = {x1min, x2min, x1max, x2max} of the grid-strided points of xy[0, n).
+__device__ inline void bbox_accumulate(const double *__restrict__ xy, int64_t n, double v[4]) {
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads) {
     const double a = xy[2 * i], b = xy[2 * i + 1];
-    mn0 = fmin(mn0, a);
-    mx0 = fmax(mx0, a);
-    mn1 = fmin(mn1, b);
-    mx1 = fmax(mx1, b);
+    v[0] = fmin(v[0], a);
+    v[1] = fmin(v[1], b);
+    v[2] = fmax(v[2], a);
+    v[3] = fmax(v[3], b);
   }
-  __shared__ double red[4][kThreads];
-  red[0][threadIdx.x] = mn0;
-  red[1][threadIdx.x] = mn1;
-  red[2][threadIdx.x] = mx0;
-  red[3][threadIdx.x] = mx1;
-  __syncthreads();
-  for (int o = kThreads / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
-      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + o]);
-      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + o]);
-      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 4) partial[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restrict__ partial,
-                                                         int nparts, double *__restrict__ out4) {
-  __shared__ double red[4][kThreads];
-  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
+// v = min/max over the parts [0, nparts) of partial boxes laid out [part][4].
+__device__ inline void bbox_merge_parts(const double *__restrict__ pp, int nparts, double v[4]) {
   for (int i = threadIdx.x; i < nparts; i += kThreads) {
-    v[0] = fmin(v[0], partial[4 * i + 0]);
-    v[1] = fmin(v[1], partial[4 * i + 1]);
-    v[2] = fmax(v[2], partial[4 * i + 2]);
-    v[3] = fmax(v[3], partial[4 * i + 3]);
+    v[0] = fmin(v[0], pp[4 * i + 0]);
+    v[1] = fmin(v[1], pp[4 * i + 1]);
+    v[2] = fmax(v[2], pp[4 * i + 2]);
+    v[3] = fmax(v[3], pp[4 * i + 3]);
   }
+}
+
+// Reduces every thread's box v over the workgroup (a fixed tree order) and
+// writes the result to out[0..3].
+__device__ inline void bbox_block_store(const double v[4], double *__restrict__ out) {
+  __shared__ double red[4][kThreads];
   for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
   __syncthreads();
   for (int o = kThreads / 2; o > 0; o >>= 1) {
@@ -68,8 +55,22 @@ __global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restric
     }
     __syncthreads();
   }
-  // out4 = {x1min, x2min, x1max, x2max}
-  if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restrict__ xy, int64_t n,
+                                                           double *__restrict__ partial) {
+  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
+  bbox_accumulate(xy, n, v);
+  bbox_block_store(v, partial + 4 * blockIdx.x);
+}
+
+// out4 = {x1min, x2min, x1max, x2max}
+__global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restrict__ partial,
+                                                         int nparts, double *__restrict__ out4) {
+  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
+  bbox_merge_parts(partial, nparts, v);
+  bbox_block_store(v, out4);
 }
 
 // Number of points inside the closed rectangle box = {x1min, x2min, x1max,
@@ -100,57 +101,16 @@ __global__ __launch_bounds__(kThreads) void k_bbox_multi_partial(const BBoxSet *
                                                                  int nparts,
                                                                  double *__restrict__ partial) {
   const BBoxSet S = sets[blockIdx.y];
-  double mn0 = DBL_MAX, mn1 = DBL_MAX, mx0 = -DBL_MAX, mx1 = -DBL_MAX;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < S.n;
-       i += (int64_t)gridDim.x * kThreads) {
-    const double a = S.xy[2 * i], b = S.xy[2 * i + 1];
-    mn0 = fmin(mn0, a);
-    mx0 = fmax(mx0, a);
-    mn1 = fmin(mn1, b);
-    mx1 = fmax(mx1, b);
-  }
-  __shared__ double red[4][kThreads];
-  red[0][threadIdx.x] = mn0;
-  red[1][threadIdx.x] = mn1;
-  red[2][threadIdx.x] = mx0;
-  red[3][threadIdx.x] = mx1;
-  __syncthreads();
-  for (int o = kThreads / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
-      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + o]);
-      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + o]);
-      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 4)
-    partial[((size_t)blockIdx.y * nparts + blockIdx.x) * 4 + threadIdx.x] = red[threadIdx.x][0];
+  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
+  bbox_accumulate(S.xy, S.n, v);
+  bbox_block_store(v, partial + ((size_t)blockIdx.y * nparts + blockIdx.x) * 4);
 }
 
 __global__ __launch_bounds__(kThreads) void k_bbox_multi_final(const double *__restrict__ partial,
                                                                int nparts, double *__restrict__ out) {
   double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
-  const double *pp = partial + (size_t)blockIdx.x * nparts * 4;
-  for (int i = threadIdx.x; i < nparts; i += kThreads) {
-    v[0] = fmin(v[0], pp[4 * i + 0]);
-    v[1] = fmin(v[1], pp[4 * i + 1]);
-    v[2] = fmax(v[2], pp[4 * i + 2]);
-    v[3] = fmax(v[3], pp[4 * i + 3]);
-  }
-  __shared__ double red[4][kThreads];
-  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
-  __syncthreads();
-  for (int o = kThreads / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + o]);
-      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + o]);
-      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + o]);
-      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + o]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 4) out[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+  bbox_merge_parts(partial + (size_t)blockIdx.x * nparts * 4, nparts, v);
+  bbox_block_store(v, out + (size_t)blockIdx.x * 4);
 }
 
 // --------------------------------------------------------------- leaf keys
