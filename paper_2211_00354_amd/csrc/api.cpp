@@ -138,19 +138,28 @@ int64_t box_coord_host(double x, double origin, double s, int64_t nbox) {
   return (int64_t)std::floor(t);
 }
 
-// Pinned host landing buffer for the bounding-box read-back (one per host
-// thread, kept for the process): a direct DMA, no staging through pageable
-// memory on the one wait of a plan-less call.
-double *bbox_landing() {
-  thread_local double *buf = nullptr;
-  if (!buf) LENS_HIP(hipHostMalloc(reinterpret_cast<void **>(&buf), 5 * sizeof(double), hipHostMallocDefault));
-  return buf;
+// Pinned, coherent host landing buffer for the bounding-box read-back (one
+// per host thread, kept for the process): the final reduction kernel writes
+// it directly, so the one wait of a plan-less call needs no copy.
+struct Landing {
+  double *host = nullptr;
+  double *dev = nullptr;  // the same memory as the device addresses it
+};
+
+const Landing &bbox_landing() {
+  thread_local Landing l;
+  if (!l.host) {
+    LENS_HIP(hipHostMalloc(reinterpret_cast<void **>(&l.host), 8 * sizeof(double),
+                           hipHostMallocCoherent));
+    LENS_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&l.dev), l.host, 0));
+  }
+  return l;
 }
 
 // Bounding box of the points (one read-back); with count_box, also the
 // number of points inside that rectangle (same read-back).  In two halves:
-// bbox_enqueue puts the reductions and the copy to the calling thread's
-// pinned landing buffer on the stream and records an event; bbox_finish
+// bbox_enqueue puts the reductions, the last of which writes the calling
+// thread's landing buffer, on the stream and records an event; bbox_finish
 // waits for that event only (not for work enqueued after it).
 struct BBoxRead {
   hipEvent_t ev = nullptr;
@@ -169,12 +178,8 @@ hipEvent_t bbox_event() {
 BBoxRead bbox_enqueue(const double *xy, int64_t n, hipStream_t st, const double *count_box = nullptr) {
   Scratch sc(st);
   const int parts = bbox_parts(n);
-  double *partial = sc.get<double>((size_t)parts * 4);
-  double *o5 = sc.get<double>(5);
-  launch_bbox(xy, n, partial, parts, o5, st);
-  if (count_box) launch_count_in_box(xy, n, count_box, reinterpret_cast<unsigned long long *>(o5 + 4), st);
-  double *landing = bbox_landing();
-  LENS_HIP(hipMemcpyAsync(landing, o5, (count_box ? 5 : 4) * sizeof(double), hipMemcpyDeviceToHost, st));
+  double *partial = sc.get<double>((size_t)parts * 5);
+  launch_bbox(xy, n, partial, parts, count_box, bbox_landing().dev, st);
   BBoxRead r;
   r.ev = bbox_event();
   r.with_count = count_box != nullptr;
@@ -184,7 +189,7 @@ BBoxRead bbox_enqueue(const double *xy, int64_t n, hipStream_t st, const double 
 
 void bbox_finish(const BBoxRead &r, double out[4], int64_t *count = nullptr) {
   LENS_HIP(hipEventSynchronize(r.ev));
-  const double *landing = bbox_landing();
+  const double *landing = bbox_landing().host;
   std::copy(landing, landing + 4, out);
   if (r.with_count && count) {
     uint64_t c;

@@ -82,12 +82,13 @@ struct Window {
 // (each returns after enqueueing on `stream`; sizes already validated)
 
 // Tree build (tree.hip)
-void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, double *out4,
-                 hipStream_t stream);
+// out[0..4) = bounding box {x1min, x2min, x1max, x2max} of xy[0, n); with
+// count_box (a host array {x1min, x2min, x1max, x2max}), out[4] holds the
+// bits of the number of points inside that closed rectangle.  partial:
+// device scratch of 5 * nparts doubles; out may be host-mapped memory.
+void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, const double *count_box,
+                 double *out, hipStream_t stream);
 int bbox_parts(int64_t n);
-// *count = number of points of xy inside the closed rectangle box (host array)
-void launch_count_in_box(const double *xy, int64_t n, const double box[4], unsigned long long *count,
-                         hipStream_t stream);
 struct BBoxSet {
   const double *xy;
   int64_t n;

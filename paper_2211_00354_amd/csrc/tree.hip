@@ -58,33 +58,11 @@ __device__ inline void bbox_block_store(const double v[4], double *__restrict__ 
   if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restrict__ xy, int64_t n,
-                                                           double *__restrict__ partial) {
-  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
-  bbox_accumulate(xy, n, v);
-  bbox_block_store(v, partial + 4 * blockIdx.x);
-}
-
-// out4 = {x1min, x2min, x1max, x2max}
-__global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restrict__ partial,
-                                                         int nparts, double *__restrict__ out4) {
-  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
-  bbox_merge_parts(partial, nparts, v);
-  bbox_block_store(v, out4);
-}
-
-// Number of points inside the closed rectangle box = {x1min, x2min, x1max,
-// x2max}, added to *count (the density of stars where the rays are).
-__global__ __launch_bounds__(kThreads) void k_count_in_box(const double *__restrict__ xy, int64_t n,
-                                                           double b0, double b1, double b2,
-                                                           double b3,
-                                                           unsigned long long *__restrict__ count) {
-  unsigned long long c = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    const double a = xy[2 * i], b = xy[2 * i + 1];
-    c += (a >= b0 && a <= b2 && b >= b1 && b <= b3) ? 1ull : 0ull;
-  }
+// Per-workgroup bounding box of xy[0, n) (partial[part][4]) and, with
+// has_box, the number of points inside the closed rectangle {b0, b1, b2, b3}
+// (pcount[part]): one read of the points for both.
+// Sum of one value per thread over the workgroup (the result in every thread).
+__device__ inline unsigned long long block_sum_u64(unsigned long long c) {
   __shared__ unsigned long long red[kThreads];
   red[threadIdx.x] = c;
   __syncthreads();
@@ -92,7 +70,47 @@ __global__ __launch_bounds__(kThreads) void k_count_in_box(const double *__restr
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(count, red[0]);
+  return red[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restrict__ xy, int64_t n,
+                                                           int has_box, double b0, double b1,
+                                                           double b2, double b3,
+                                                           double *__restrict__ partial,
+                                                           unsigned long long *__restrict__ pcount) {
+  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double a = xy[2 * i], b = xy[2 * i + 1];
+    v[0] = fmin(v[0], a);
+    v[1] = fmin(v[1], b);
+    v[2] = fmax(v[2], a);
+    v[3] = fmax(v[3], b);
+    c += (a >= b0 && a <= b2 && b >= b1 && b <= b3) ? 1ull : 0ull;
+  }
+  bbox_block_store(v, partial + 4 * blockIdx.x);
+  if (has_box) {
+    c = block_sum_u64(c);
+    if (threadIdx.x == 0) pcount[blockIdx.x] = c;
+  }
+}
+
+// out = {x1min, x2min, x1max, x2max} and, with has_box, the count as the
+// bits of out[4]; out may be host-mapped memory (the read-back landing).
+__global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restrict__ partial,
+                                                         const unsigned long long *__restrict__ pcount,
+                                                         int nparts, int has_box,
+                                                         double *__restrict__ out) {
+  double v[4] = {DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX};
+  bbox_merge_parts(partial, nparts, v);
+  bbox_block_store(v, out);
+  if (has_box) {
+    unsigned long long c = 0;
+    for (int i = threadIdx.x; i < nparts; i += kThreads) c += pcount[i];
+    c = block_sum_u64(c);
+    if (threadIdx.x == 0) reinterpret_cast<unsigned long long *>(out)[4] = c;
+  }
 }
 
 // Bounding boxes of several point sets at once: blockIdx.y = set; partial
@@ -457,20 +475,16 @@ int bbox_parts(int64_t n) {
   return (int)b;
 }
 
-void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, double *out4,
-                 hipStream_t stream) {
-  hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(kThreads), 0, stream, xy, n, partial);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kThreads), 0, stream, partial, nparts, out4);
-  LENS_HIP(hipGetLastError());
-}
-
-void launch_count_in_box(const double *xy, int64_t n, const double box[4], unsigned long long *count,
-                         hipStream_t stream) {
-  launch_fill_u32(reinterpret_cast<uint32_t *>(count), 2, 0u, stream);
-  if (n == 0) return;
-  const int nb = bbox_parts(n);
-  hipLaunchKernelGGL(k_count_in_box, dim3(nb), dim3(kThreads), 0, stream, xy, n, box[0], box[1],
-                     box[2], box[3], count);
+void launch_bbox(const double *xy, int64_t n, double *partial, int nparts, const double *count_box,
+                 double *out, hipStream_t stream) {
+  const bool has = count_box != nullptr;
+  const double b0 = has ? count_box[0] : 0.0, b1 = has ? count_box[1] : 0.0;
+  const double b2 = has ? count_box[2] : -1.0, b3 = has ? count_box[3] : -1.0;
+  auto *pcount = reinterpret_cast<unsigned long long *>(partial + 4 * (size_t)nparts);
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(kThreads), 0, stream, xy, n, (int)has, b0,
+                     b1, b2, b3, partial, pcount);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kThreads), 0, stream, partial, pcount, nparts,
+                     (int)has, out);
   LENS_HIP(hipGetLastError());
 }
 
