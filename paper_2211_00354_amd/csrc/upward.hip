@@ -201,8 +201,11 @@ constexpr int64_t kCrowdedBox = 32;
 // cluster of lenses): a lane whose box holds more than kCrowdedBox sources
 // forms it by M2M from its children when the level below has them all, and
 // otherwise leaves it to the whole wave, which then forms the wave's
-// remaining crowded boxes one after another.  The wave's 64 boxes are staged
-// in LDS so that the [64][p] block is written with coalesced stores.
+// remaining crowded boxes one after another.  The kernel is bound by memory
+// latency (a few sources per lane): a box of one or two leaf rows keeps its
+// source ranges in registers and the next source's loads are issued before
+// the current one's powers are summed.  The wave's 64 boxes are staged in
+// LDS so that the [64][p] block is written with coalesced stores.
 template <int PMAX, int QDIM>
 __global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window win,
                                                    const double *__restrict__ sxy,
@@ -222,37 +225,72 @@ __global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window
   const int64_t span = int64_t(1) << sh;
   const int64_t ix = b < nbox ? win.bx0 + b % win.nbx : 0;
   const int64_t iy = b < nbox ? win.by0 + b / win.nbx : 0;
+  // source ranges of the box's (first two) leaf rows, and its source count
+  int32_t a0 = 0, e0 = 0, a1 = 0, e1 = 0;
   int64_t count = 0;
-  if (b < nbox)
-    for (int64_t r = 0; r < span; ++r) {
+  if (b < nbox) {
+    const int64_t c0 = (iy << sh) * nL + (ix << sh);
+    a0 = leaf_start[c0];
+    e0 = leaf_start[c0 + span];
+    if (span >= 2) {
+      a1 = leaf_start[c0 + nL];
+      e1 = leaf_start[c0 + nL + span];
+    }
+    count = (int64_t)(e0 - a0) + (e1 - a1);
+    for (int64_t r = 2; r < span; ++r) {
       const int64_t row = (iy << sh) + r;
       count += leaf_start[row * nL + (ix << sh) + span] - leaf_start[row * nL + (ix << sh)];
     }
+  }
   const bool crowded = count > kCrowdedBox;
   const bool by_m2m = crowded && b < nbox && children_ready(child, ix, iy);
   cplx acc[PMAX];
 #pragma unroll
   for (int k = 0; k < PMAX; ++k) acc[k] = cplx{0.0, 0.0};
+  auto add_source = [&](double x, double y, cplx pw, const cplx &c, double inv_s) {
+    const cplx w = {(x - c.re) * inv_s, (y - c.im) * inv_s};
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k)
+      if (k < p) {
+        acc[k].re += pw.re;
+        acc[k].im += pw.im;
+        pw = cmul(pw, w);
+      }
+  };
+  auto charge = [&](int64_t i) {
+    return QDIM == 1 ? cplx{sq[i], 0.0} : cplx{sq[2 * i], sq[2 * i + 1]};
+  };
   if (b < nbox && !crowded) {
     const double s = ldexp(g.side, -level);
     const double inv_s = 1.0 / s;
-    const double cx = g.x0 + ((double)ix + 0.5) * s;
-    const double cy = g.y0 + ((double)iy + 0.5) * s;
-    for (int64_t r = 0; r < span; ++r) {
+    const cplx c = {g.x0 + ((double)ix + 0.5) * s, g.y0 + ((double)iy + 0.5) * s};
+    // the first two rows as one run of n0 + n1 sources, software-pipelined
+    const int32_t n0 = e0 - a0, n = n0 + (e1 - a1);
+    auto src = [&](int32_t t) { return (int64_t)(t < n0 ? a0 + t : a1 + (t - n0)); };
+    double nx = 0.0, ny = 0.0;
+    cplx nq = {0.0, 0.0};
+    if (n > 0) {
+      const int64_t i = src(0);
+      nx = sxy[2 * i];
+      ny = sxy[2 * i + 1];
+      nq = charge(i);
+    }
+    for (int32_t t = 0; t < n; ++t) {
+      const double x = nx, y = ny;
+      const cplx q = nq;
+      if (t + 1 < n) {
+        const int64_t i = src(t + 1);
+        nx = sxy[2 * i];
+        ny = sxy[2 * i + 1];
+        nq = charge(i);
+      }
+      add_source(x, y, q, c, inv_s);
+    }
+    for (int64_t r = 2; r < span; ++r) {
       const int64_t row = (iy << sh) + r;
       const int32_t i0 = leaf_start[row * nL + (ix << sh)];
       const int32_t i1 = leaf_start[row * nL + (ix << sh) + span];
-      for (int32_t i = i0; i < i1; ++i) {
-        const cplx w = {(sxy[2 * (int64_t)i] - cx) * inv_s, (sxy[2 * (int64_t)i + 1] - cy) * inv_s};
-        cplx pw = QDIM == 1 ? cplx{sq[i], 0.0} : cplx{sq[2 * (int64_t)i], sq[2 * (int64_t)i + 1]};
-#pragma unroll
-        for (int k = 0; k < PMAX; ++k)
-          if (k < p) {
-            acc[k].re += pw.re;
-            acc[k].im += pw.im;
-            pw = cmul(pw, w);
-          }
-      }
+      for (int32_t i = i0; i < i1; ++i) add_source(sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], charge(i), c, inv_s);
     }
   }
 #pragma unroll
