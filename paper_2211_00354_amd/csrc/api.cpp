@@ -48,6 +48,7 @@ struct lens_plan {
   std::vector<Window> swin;  // index = level
   std::vector<char> direct;  // index = level: multipoles formed from the stars (else M2M)
   DevBuf sxy, sm, leaf_start;
+  DevBuf sm32;               // FP32 copies of real masses (mixed-precision near field)
   std::vector<DevBuf> mp;    // index = level, FP64 multipoles
   std::vector<DevBuf> mp32;  // index = level, FP32 copies (fine levels, mixed)
   DevBuf keys, vals, keys_tmp, vals_tmp, cnt, scan_tmp, box_coarse;  // tree-build scratch
@@ -59,8 +60,8 @@ struct lens_plan {
   }
   // return every buffer to the pool, ordered after the work on `st`
   void put_all(hipStream_t st) {
-    std::vector<DevBuf *> ps = {&sxy, &sm, &leaf_start, &keys, &vals, &keys_tmp, &vals_tmp, &cnt,
-                                &scan_tmp, &box_coarse};
+    std::vector<DevBuf *> ps = {&sxy, &sm, &sm32, &leaf_start, &keys, &vals, &keys_tmp, &vals_tmp,
+                                &cnt, &scan_tmp, &box_coarse};
     for (auto &b : mp) ps.push_back(&b);
     for (auto &b : mp32) ps.push_back(&b);
     pool_put_batch(ps.data(), ps.size(), st);
@@ -443,6 +444,7 @@ void plan_alloc(lens_plan *P, hipStream_t st) {
   P->leaf_start = pool_get((size_t)(nbox + 1) * sizeof(int32_t), st);
   P->sxy = pool_get((size_t)N * 16, st);
   P->sm = pool_get((size_t)N * 8 * P->qdim, st);
+  if (P->qdim == 1) P->sm32 = pool_get((size_t)N * 4, st);
   for (DevBuf *b : {&P->keys, &P->vals, &P->keys_tmp, &P->vals_tmp})
     *b = pool_get((size_t)N * sizeof(uint32_t), st);
   const size_t ncnt = radix_counts_len(N);
@@ -475,7 +477,7 @@ void plan_tree(lens_plan *P, const double *xy, const double *q, hipStream_t st) 
   const uint32_t *ks = in_tmp ? kt : k, *vs = in_tmp ? vt : v;
   P->perm = vs;
   launch_gather_stars(vs, xy, q, P->qdim, N, static_cast<double *>(P->sxy.ptr),
-                      static_cast<double *>(P->sm.ptr), st);
+                      static_cast<double *>(P->sm.ptr), static_cast<float *>(P->sm32.ptr), st);
   // all zero when N = 0
   launch_box_starts(ks, N, nbox, static_cast<int32_t *>(P->leaf_start.ptr),
                     static_cast<int32_t *>(P->box_coarse.ptr), st);
@@ -676,6 +678,7 @@ void fill_star_side(const lens_plan &P, Window wl, double *loc, EvalArgs &ea) {
   ea.loc = loc;
   ea.sxy = static_cast<const double *>(P.sxy.ptr);
   ea.sm = static_cast<const double *>(P.sm.ptr);
+  ea.sm32 = static_cast<const float *>(P.sm32.ptr);
   ea.leaf_start = static_cast<const int32_t *>(P.leaf_start.ptr);
 }
 
@@ -1480,6 +1483,7 @@ std::unique_ptr<BatchExec> batch_build(int n, const lens_field *f, const lens_gr
     t.q = f[i].m;
     t.sxy = static_cast<double *>(P->sxy.ptr);
     t.sq = static_cast<double *>(P->sm.ptr);
+    t.sq32 = static_cast<float *>(P->sm32.ptr);
     t.g = P->g;
     t.off = total;
     t.n = P->n_stars;
@@ -2384,7 +2388,7 @@ lens_status lens_deflect_backward(lens_plan *plan, const lens_field *field, cons
         const bool in_tmp = radix_sort_pairs(k, v, kt, vt, N, bits, cnt, stmp, st);
         const uint32_t *ks = in_tmp ? kt : k;
         v = in_tmp ? vt : v;
-        launch_gather_stars(v, field->xy, field->m, 1, N, txy, tm, st);
+        launch_gather_stars(v, field->xy, field->m, 1, N, txy, tm, nullptr, st);
         launch_box_starts(ks, N, wl.count(), tstart,
                           sc.get<int32_t>(box_starts_coarse_len(wl.count())), st);
       }

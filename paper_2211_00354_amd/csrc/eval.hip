@@ -45,12 +45,12 @@ constexpr int kThreads = 256;  // helper kernels
 // 1/dz^2 = (dx^2 - dy^2 - 2i dx dy) / r^4, so f' gains -t (dx - dy)(dx + dy)
 // (real) and 2 t dx dy (imaginary), t = m / r^4; a coincident pair has
 // r2 = tiny exactly and gets t = 0.
-template <bool MIXED, bool DERIV, int R, typename A>
+template <bool MIXED, bool DERIV, int R, typename A, typename M>
 __device__ __forceinline__ void pair_update(const double (&rx)[R], const double (&ry)[R], double sx,
-                                            double sy, double mm, A (&ax)[R], A (&ay)[R],
+                                            double sy, M mm, A (&ax)[R], A (&ay)[R],
                                             A (&dre)[R], A (&dim)[R]) {
   if constexpr (MIXED) {
-    const float m = (float)mm;
+    const float m = mm;  // the mass, rounded to FP32 when the stars were sorted
     constexpr float tiny = 0x1p-100f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -132,6 +132,7 @@ template <int PMAX, bool MIXED, bool MAP, bool GRID, int R, bool DERIV>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && !DERIV ? 5 : 1))) void k_eval(EvalArgs a, const double *__restrict__ loc,
                                                 const double *__restrict__ sxy,
                                                 const double *__restrict__ sm,
+                                                const float *__restrict__ sm32,
                                                 const int32_t *__restrict__ leaf_start,
                                                 const int32_t *__restrict__ col_start,
                                                 const int32_t *__restrict__ row_start,
@@ -260,8 +261,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && 
         dim[r] = 0;
       }
 
-      auto star = [&](double x, double y, double mass) {
-        pair_update<MIXED, DERIV, R>(rx, ry, x, y, mass, ax, ay, dre, dim);
+      // LENS_MIXED reads the masses' FP32 copies (no conversion per star)
+      using mass_t = typename std::conditional<MIXED, float, double>::type;
+      auto mass = [&](int32_t i) -> mass_t {
+        if constexpr (MIXED) return sm32[i]; else return sm[i];
+      };
+      auto star = [&](double x, double y, mass_t m) {
+        pair_update<MIXED, DERIV, R>(rx, ry, x, y, m, ax, ay, dre, dim);
       };
       // LENS_MIXED: every kFlushStars stars the FP32 partial sums move into
       // FP64 ones in LDS (a wave-uniform count), so a ray with thousands
@@ -295,12 +301,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && 
         int32_t i = rs[d];
         // four stars per step: their scalar loads issue together
         for (; i + 4 <= re[d]; i += 4) {
-          double sx[4], sy[4], mm[4];
+          double sx[4], sy[4];
+          mass_t mm[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             sx[q] = sxy[2 * (int64_t)(i + q)];
             sy[q] = sxy[2 * (int64_t)(i + q) + 1];
-            mm[q] = sm[i + q];
+            mm[q] = mass(i + q);
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) star(sx[q], sy[q], mm[q]);
@@ -309,7 +316,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED && 
             if (since >= kFlushStars) flush();
           }
         }
-        for (; i < re[d]; ++i) star(sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], sm[i]);
+        for (; i < re[d]; ++i) star(sxy[2 * (int64_t)i], sxy[2 * (int64_t)i + 1], mass(i));
       }
 
       // ray offsets from the box centre (FP64) for the far field; grid rays'
@@ -457,7 +464,7 @@ void eval_launch_r(const EvalArgs &a, hipStream_t stream) {
   int64_t nblk = units < kMaxEvalBlocks ? units : kMaxEvalBlocks;
   if (nblk > kXcd) nblk = nblk / kXcd * kXcd;
   hipLaunchKernelGGL((k_eval<PM, MIXED, MAP, GRID, R, DERIV>), dim3((unsigned)nblk), dim3(kWave), 0, stream,
-                     a, a.loc, a.sxy, a.sm, a.leaf_start, a.col_start, a.row_start, a.rxy, a.rperm,
+                     a, a.loc, a.sxy, a.sm, a.sm32, a.leaf_start, a.col_start, a.row_start, a.rxy, a.rperm,
                      a.ray_start, a.y_out, a.counts);
 }
 
@@ -544,6 +551,8 @@ void grid_tile_shape(int64_t W, int64_t H, int *shift, int64_t *tiles) {
 
 void launch_eval(const EvalArgs &a, int precision, hipStream_t stream) {
   if (a.win.count() == 0) return;
+  if (precision == LENS_MIXED && !a.sm32)
+    fail(LENS_EINVAL, "mixed-precision evaluation needs the plan's FP32 masses");
   LENS_PMAX_DISPATCH(a.p, eval_dispatch<PM>(a, precision, stream));
   LENS_HIP(hipGetLastError());
 }

@@ -110,9 +110,10 @@ size_t scan_tmp_len(size_t n);
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp,
                         hipStream_t stream);
 // sources (stars, or rays with complex charges) sorted by leaf box:
-// positions [n][2] and charges [n][qdim] (qdim 1: real masses; 2: complex)
+// positions [n][2] and charges [n][qdim] (qdim 1: real masses; 2: complex);
+// with sq32 (qdim 1), also the masses rounded to FP32
 void launch_gather_stars(const uint32_t *perm, const double *xy, const double *q, int qdim,
-                         int64_t n, double *sxy, double *sq, hipStream_t stream);
+                         int64_t n, double *sxy, double *sq, float *sq32, hipStream_t stream);
 void launch_gather_rays(const uint32_t *perm, const double *xy, int64_t n, double *sxy,
                         hipStream_t stream);
 // start[b] = first sorted index with key >= b, for b in [0, nbox]
@@ -155,6 +156,7 @@ void build_l2l_bfrag(int p, int ks_count, int nt_count, std::vector<double> &out
 struct TreeJob {
   const double *xy, *q;
   double *sxy, *sq;
+  float *sq32;  // FP32 copies of the sorted charges (or nullptr)
   Geometry g;
   int64_t off, n;
 };
@@ -243,6 +245,7 @@ struct EvalArgs {
   const double *loc;     // [win][p] complex locals
   const double *sxy;     // sorted stars
   const double *sm;
+  const float *sm32;     // their masses in FP32 (LENS_MIXED near field)
   const int32_t *leaf_start;  // [4^L + 1]
   // rays: grid or sorted explicit
   int grid_mode;

@@ -348,13 +348,15 @@ __global__ __launch_bounds__(kThreads) void k_gather_stars(const uint32_t *__res
                                                            const double *__restrict__ xy,
                                                            const double *__restrict__ q, int qdim,
                                                            int64_t n, double *__restrict__ sxy,
-                                                           double *__restrict__ sq) {
+                                                           double *__restrict__ sq,
+                                                           float *__restrict__ sq32) {
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (j >= n) return;
   const int64_t i = perm[j];
   sxy[2 * j] = xy[2 * i];
   sxy[2 * j + 1] = xy[2 * i + 1];
   for (int c = 0; c < qdim; ++c) sq[qdim * j + c] = q[qdim * i + c];
+  if (sq32) sq32[j] = (float)q[i];
 }
 
 // Several fields' trees in one pass (batched maps): field j's sources are
@@ -403,6 +405,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_multi(const TreeJob *__rest
   t.sxy[2 * k] = t.xy[2 * i];
   t.sxy[2 * k + 1] = t.xy[2 * i + 1];
   t.sq[k] = t.q[i];
+  if (t.sq32) t.sq32[k] = (float)t.q[i];
   keys[gi] &= mask;
 }
 
@@ -565,10 +568,10 @@ bool radix_sort_pairs(uint32_t *k, uint32_t *v, uint32_t *k_tmp, uint32_t *v_tmp
 }
 
 void launch_gather_stars(const uint32_t *perm, const double *xy, const double *q, int qdim,
-                         int64_t n, double *sxy, double *sq, hipStream_t stream) {
+                         int64_t n, double *sxy, double *sq, float *sq32, hipStream_t stream) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_gather_stars, dim3(blocks_for(n)), dim3(kThreads), 0, stream, perm, xy, q,
-                     qdim, n, sxy, sq);
+                     qdim, n, sxy, sq, qdim == 1 ? sq32 : nullptr);
   LENS_HIP(hipGetLastError());
 }
 
