@@ -45,6 +45,7 @@ struct lens_plan {
   // those of its source window swin[l] (the boxes that can be M2L sources
   // for targets in the box above), each formed straight from the stars.
   int dense_top = 0;
+  double rho_local = -1.0;   // sources per unit area where the rays are (< 0: unknown)
   std::vector<Window> swin;  // index = level
   std::vector<char> direct;  // index = level: multipoles formed from the stars (else M2M)
   DevBuf sxy, sm, leaf_start;
@@ -412,6 +413,7 @@ void plan_geometry(lens_plan *P, int64_t n_sources, const double *sb, const doub
   if (!(side > 0)) side = 1.0;
   side *= 1.0 + 1.0 / 1024;
   const double rho = rho_local >= 0.0 ? rho_local : star_density(n_sources, sb ? sb : dom);
+  P->rho_local = rho_local;
   bool aligned = false;
   if (align && align->nx > 0 && align->ny > 0 && n_sources > 0)
     aligned = aligned_geometry(*align, dom, o.leaf_level, rho, P->p, n_sources, &P->g);
@@ -501,8 +503,17 @@ void plan_upward(lens_plan *P, hipStream_t st) {
     // levels go up to four levels per launch
     for (int l = L; l >= 2;) {
       if (P->direct[l]) {
-        launch_p2m(P->g, l, P->swin[l], sxy, sm, P->qdim, leaf_start, P->p,
-                   static_cast<double *>(P->mp[l].ptr), static_cast<float *>(P->mp32[l].ptr), N,
+        // sources expected in the level's window: from the density where
+        // the rays are for a window that is not the whole level
+        const int64_t nl = int64_t(1) << l;
+        const Window &w = P->swin[l];
+        double n_win = (double)N;
+        if (P->rho_local >= 0.0 && w.count() < nl * nl) {
+          const double s = std::ldexp(P->g.side, -l);
+          n_win = std::min((double)N, P->rho_local * s * s * (double)w.count());
+        }
+        launch_p2m(P->g, l, w, sxy, sm, P->qdim, leaf_start, P->p,
+                   static_cast<double *>(P->mp[l].ptr), static_cast<float *>(P->mp32[l].ptr), n_win,
                    l < L ? P->swin[l + 1] : Window{0, 0, 0, 0}, l < L ? P->mp_at(l + 1) : nullptr,
                    st);
         --l;

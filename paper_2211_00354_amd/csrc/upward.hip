@@ -191,17 +191,65 @@ __device__ __forceinline__ cplx m2m_coeff(const ChildLevel &c, int64_t ix, int64
   return cplx{ldexp(sum.re, -l), ldexp(sum.im, -l)};
 }
 
-// A box holding more than this many sources is formed by the whole wave
+// A box holding more than kCrowdedBox sources is formed by M2M from its
+// four children when the level below has them; one holding more than
+// kWaveBox sources (and no formed children) is formed by the whole wave
 // (p2m_wave_box) rather than by its own lane.
 constexpr int64_t kCrowdedBox = 32;
+constexpr int64_t kWaveBox = 256;
+
+// The rescaled multipole of a box from its four formed children, in one
+// lane: each child's coefficients are shifted to the parent's centre by the
+// synthetic division of k_m2m_tile below (p(p-1)/2 updates
+// a_j += d a_(j-1), d = (+-1/2, +-1/2) in child-size units) and the four
+// are summed, then scaled by 2^-l.
+template <int PMAX>
+__device__ __forceinline__ void m2m_lane(const ChildLevel &c, int64_t ix, int64_t iy, int p,
+                                         cplx (&acc)[PMAX]) {
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) acc[k] = cplx{0.0, 0.0};
+  for (int q = 0; q < 4; ++q) {
+    const int qa = q & 1, qc = q >> 1;
+    const double dr = qa - 0.5, di = qc - 0.5;
+    const int64_t cb = (2 * iy + qc - c.win.by0) * c.win.nbx + (2 * ix + qa - c.win.bx0);
+    const double2 *src = reinterpret_cast<const double2 *>(c.mp) + cb * p;
+    cplx a[PMAX];
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k)
+      if (k < p) {
+        const double2 v = src[k];
+        a[k] = cplx{v.x, v.y};
+      }
+#pragma unroll
+    for (int k = 0; k + 1 < PMAX; ++k)
+      if (k + 1 < p) {
+#pragma unroll
+        for (int j = PMAX - 1; j > k; --j)
+          if (j < p) {
+            a[j].re = fma(dr, a[j - 1].re, fma(-di, a[j - 1].im, a[j].re));
+            a[j].im = fma(dr, a[j - 1].im, fma(di, a[j - 1].re, a[j].im));
+          }
+      }
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k)
+      if (k < p) {
+        acc[k].re += a[k].re;
+        acc[k].im += a[k].im;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k)
+    if (k < p) acc[k] = cplx{ldexp(acc[k].re, -k), ldexp(acc[k].im, -k)};
+}
 
 // P2M for levels whose boxes hold few sources on average: one thread per box
 // of `win` with all p coefficients in registers (running powers m w^k).
 // Occupancy is heavy-tailed in clustered fields (a galaxy's centre, a
 // cluster of lenses): a lane whose box holds more than kCrowdedBox sources
-// forms it by M2M from its children when the level below has them all, and
-// otherwise leaves it to the whole wave, which then forms the wave's
-// remaining crowded boxes one after another.  The kernel is bound by memory
+// forms it by M2M from its children when the level below has them all (in
+// its own lane, so a wave of crowded boxes shifts them side by side), and a
+// box of more than kWaveBox sources without them is left to the whole wave,
+// which forms such boxes one after another.  The kernel is bound by memory
 // latency (a few sources per lane): a box of one or two leaf rows keeps its
 // source ranges in registers and the next source's loads are issued before
 // the current one's powers are summed.  The wave's 64 boxes are staged in
@@ -212,7 +260,7 @@ __global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window
                                                    const double *__restrict__ sq,
                                                    const int32_t *__restrict__ leaf_start, int p,
                                                    double *__restrict__ mp, float *__restrict__ mp32,
-                                                   ChildLevel child) {
+                                                   ChildLevel child, int defer) {
   constexpr int STR = 2 * PMAX + 1;
   __shared__ double stage[kWave * STR];
   __shared__ int32_t row_first[kWave], row_pre[kWave];
@@ -242,8 +290,8 @@ __global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window
       count += leaf_start[row * nL + (ix << sh) + span] - leaf_start[row * nL + (ix << sh)];
     }
   }
-  const bool crowded = count > kCrowdedBox;
-  const bool by_m2m = crowded && b < nbox && children_ready(child, ix, iy);
+  const bool by_m2m = count > kCrowdedBox && b < nbox && children_ready(child, ix, iy);
+  const bool by_wave = count > kWaveBox && !by_m2m;
   cplx acc[PMAX];
 #pragma unroll
   for (int k = 0; k < PMAX; ++k) acc[k] = cplx{0.0, 0.0};
@@ -260,7 +308,8 @@ __global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window
   auto charge = [&](int64_t i) {
     return QDIM == 1 ? cplx{sq[i], 0.0} : cplx{sq[2 * i], sq[2 * i + 1]};
   };
-  if (b < nbox && !crowded) {
+  if (by_m2m) m2m_lane<PMAX>(child, ix, iy, p, acc);
+  if (b < nbox && !by_m2m && !by_wave) {
     const double s = ldexp(g.side, -level);
     const double inv_s = 1.0 / s;
     const cplx c = {g.x0 + ((double)ix + 0.5) * s, g.y0 + ((double)iy + 0.5) * s};
@@ -299,21 +348,9 @@ __global__ __launch_bounds__(kWave) void k_p2m_box(Geometry g, int level, Window
       stage[lane * STR + 2 * k] = acc[k].re;
       stage[lane * STR + 2 * k + 1] = acc[k].im;
     }
-  // the wave's crowded boxes whose children are formed: M2M by the wave,
-  // one coefficient per lane
-  uint64_t todo_m2m = __ballot(by_m2m);
-  while (todo_m2m) {
-    const int owner = __builtin_ctzll(todo_m2m);
-    todo_m2m &= todo_m2m - 1;
-    const int64_t ob = b0 + owner;
-    if (lane < p) {
-      const cplx a = m2m_coeff(child, win.bx0 + ob % win.nbx, win.by0 + ob / win.nbx, p, lane);
-      stage[owner * STR + 2 * lane] = a.re;
-      stage[owner * STR + 2 * lane + 1] = a.im;
-    }
-  }
-  // the other crowded boxes, one at a time (a wave-uniform loop)
-  uint64_t todo = __ballot(b < nbox && crowded && !by_m2m);
+  // the boxes left to the whole wave, one at a time (a wave-uniform loop),
+  // unless a second pass (k_p2m_wave) forms them, a wave each, afterwards
+  uint64_t todo = defer ? 0ull : __ballot(b < nbox && by_wave);
   while (todo) {
     const int owner = __builtin_ctzll(todo);
     todo &= todo - 1;
@@ -349,14 +386,18 @@ __global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Windo
                                                     const double *__restrict__ sq,
                                                     const int32_t *__restrict__ leaf_start, int p,
                                                     double *__restrict__ mp, float *__restrict__ mp32,
-                                                    ChildLevel child) {
+                                                    ChildLevel child, int64_t only_above) {
   __shared__ int32_t row_first[kWave], row_pre[kWave];
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
   const int64_t ix = win.bx0 + b % win.nbx, iy = win.by0 + b / win.nbx;
   cplx acc[PMAX];
   bool by_m2m = false;
-  if (children_ready(child, ix, iy)) {
+  const bool ready = children_ready(child, ix, iy);
+  // only_above >= 0: the second pass behind k_p2m_box, which left this
+  // kernel its boxes of more than only_above sources without formed children
+  if (only_above >= 0 && ready) return;
+  if (ready || only_above >= 0) {
     // the box's source count, its leaf rows spread over the wave
     const int sh = g.L - level;
     const int64_t nL = int64_t(1) << g.L;
@@ -368,7 +409,8 @@ __global__ __launch_bounds__(kWave) void k_p2m_wave(Geometry g, int level, Windo
     }
 #pragma unroll
     for (int d = kWave / 2; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d);
-    by_m2m = cnt > kCrowdedBox;  // wave-uniform
+    if (cnt <= only_above) return;  // wave-uniform
+    by_m2m = ready && cnt > kCrowdedBox;
   }
   if (by_m2m) {  // from the children, one coefficient per lane
     if (lane < p) {
@@ -494,38 +536,50 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 
 
 void launch_p2m(Geometry g, int level, Window win, const double *sxy, const double *sq, int qdim,
-                const int32_t *leaf_start, int p, double *mp, float *mp32, int64_t n_sources,
+                const int32_t *leaf_start, int p, double *mp, float *mp32, double win_sources,
                 Window child_win, const double *child_mp, hipStream_t stream) {
   const ChildLevel child{child_win, child_mp};
   const int64_t n = win.count() * p;
   if (n == 0) return;
-  // boxes of ~16 sources or more (on average over the level): a wave per box
-  if ((double)n_sources > 16.0 * (double)(int64_t(1) << (2 * level))) {
+  // boxes of ~128 sources or more (on average over the window): a wave per
+  // box (below that a thread per box, crowded boxes by M2M in their lanes,
+  // measured faster on a galaxy halo's levels of 24 and 91 stars per box)
+  auto wave_per_box = [&](int64_t only_above) {
     const unsigned nb = (unsigned)win.count();
     if (qdim == 2)
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_wave<PM, 2>), dim3(nb), dim3(kWave), 0, stream,
                                                g, level, win, sxy, sq, leaf_start, p, mp, mp32,
-                                               child));
+                                               child, only_above));
     else
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_wave<PM, 1>), dim3(nb), dim3(kWave), 0, stream,
                                                g, level, win, sxy, sq, leaf_start, p, mp, mp32,
-                                               child));
+                                               child, only_above));
     LENS_HIP(hipGetLastError());
+  };
+  const double mean = win_sources / (double)win.count();
+  if (mean > 128.0) {
+    wave_per_box(-1);
     return;
   }
   // otherwise a thread per box (all coefficients), unless p exceeds the
-  // register budget of that kernel's largest instance
+  // register budget of that kernel's largest instance.  Where leaf boxes
+  // hold a few sources on average (a clustered field), those of more than
+  // kWaveBox sources get a wave each in a second pass rather than their
+  // lane's wave one after another (above the leaf level such boxes are
+  // formed from their children).
   if (p <= 24) {
+    const int defer = (mean > 2.0 && child_mp == nullptr) ? 1 : 0;
     const unsigned nb = (unsigned)((win.count() + kWave - 1) / kWave);
     if (qdim == 2)
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_box<PM, 2>), dim3(nb), dim3(kWave), 0, stream,
                                                g, level, win, sxy, sq, leaf_start, p, mp, mp32,
-                                               child));
+                                               child, defer));
     else
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_box<PM, 1>), dim3(nb), dim3(kWave), 0, stream,
                                                g, level, win, sxy, sq, leaf_start, p, mp, mp32,
-                                               child));
+                                               child, defer));
     LENS_HIP(hipGetLastError());
+    if (defer) wave_per_box(kWaveBox);
     return;
   }
   if (qdim == 2)
