@@ -497,6 +497,11 @@ void plan_upward(lens_plan *P, hipStream_t st) {
   auto *sxy = static_cast<double *>(P->sxy.ptr);
   auto *sm = static_cast<double *>(P->sm.ptr);
   const OpTables &T = op_tables(P->p, st);
+  // clustered: the sources are much denser where the rays are than over
+  // their bounding box (a galaxy's centre), so some leaf boxes may hold
+  // hundreds of them
+  const double bb_area = std::max((P->star_bb[2] - P->star_bb[0]) * (P->star_bb[3] - P->star_bb[1]), 1e-300);
+  const bool clustered = P->rho_local > 4.0 * (double)N / bb_area;
   {
     StageTimer tm("upward", st);
     // from the stars or by M2M, as source_windows decided; runs of M2M
@@ -514,8 +519,8 @@ void plan_upward(lens_plan *P, hipStream_t st) {
         }
         launch_p2m(P->g, l, w, sxy, sm, P->qdim, leaf_start, P->p,
                    static_cast<double *>(P->mp[l].ptr), static_cast<float *>(P->mp32[l].ptr), n_win,
-                   l < L ? P->swin[l + 1] : Window{0, 0, 0, 0}, l < L ? P->mp_at(l + 1) : nullptr,
-                   st);
+                   clustered, l < L ? P->swin[l + 1] : Window{0, 0, 0, 0},
+                   l < L ? P->mp_at(l + 1) : nullptr, st);
         --l;
         continue;
       }

@@ -170,10 +170,11 @@ void launch_gather_multi(const TreeJob *jobs, int njobs, int64_t total, uint32_t
 // child_win / child_mp: the level below, already formed ([child_win][p] FP64;
 // child_mp nullptr at the leaf level): boxes of more than 32 sources whose
 // children it holds are formed from them by M2M.  win_sources: the sources
-// expected in `win` (chooses a thread or a wave per box).
+// expected in `win` (chooses a thread or a wave per box); clustered: some
+// boxes may hold far more than that average.
 void launch_p2m(Geometry g, int level, Window win, const double *sxy, const double *sq, int qdim,
                 const int32_t *leaf_start, int p, double *mp, float *mp32, double win_sources,
-                Window child_win, const double *child_mp, hipStream_t stream);
+                bool clustered, Window child_win, const double *child_mp, hipStream_t stream);
 // M2M of levels level, level-1, ..., level-nlev+1 in one launch; the child
 // level (level+1) is dense, [n][n][p] complex; out[i] / out32[i] (optional)
 // receive level - i, dense.

@@ -420,19 +420,24 @@ __global__ __launch_bounds__(kThreads) void k_gather_rays(const uint32_t *__rest
 }
 
 // start[b] = lower_bound of box b in the sorted keys, b = 0..nbox, in two
-// steps: every kBoxStride-th box searches the whole array; then a workgroup
-// per stride of boxes counts the keys between its two coarse bounds per box
+// steps: every stride-th box searches the whole array; then a workgroup per
+// stride of boxes counts the keys between its two coarse bounds per box
 // (LDS histogram) and writes their exclusive prefix, so each key is read once
-// and each entry written once, with no per-box search.
-constexpr int64_t kBoxStride = kThreads;
+// and each entry written once, with no per-box search.  The stride is 256
+// boxes (one per thread: more workgroups in flight) for trees of up to 2^22
+// leaves and 4096 (16 per thread, so the per-workgroup cost stays small
+// against its 16 KB of output) beyond; a stride without keys only fills its
+// entries (the deep, mostly empty trees of clustered fields: 2.7e8 boxes).
+constexpr int64_t kWideStartsFrom = int64_t(1) << 22;
 
 __global__ __launch_bounds__(kThreads) void k_box_starts_coarse(const uint32_t *__restrict__ keys,
                                                                 int64_t n, int64_t nbox,
+                                                                int64_t stride,
                                                                 int32_t *__restrict__ coarse) {
   const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t nc = nbox / kBoxStride + 1;
+  const int64_t nc = nbox / stride + 1;
   if (c > nc) return;
-  const int64_t b = c * kBoxStride < nbox ? c * kBoxStride : nbox;
+  const int64_t b = c * stride < nbox ? c * stride : nbox;
   int64_t lo = 0, hi = n;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -444,23 +449,42 @@ __global__ __launch_bounds__(kThreads) void k_box_starts_coarse(const uint32_t *
   coarse[c] = (int32_t)lo;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_box_starts(const uint32_t *__restrict__ keys,
                                                          int64_t nbox,
                                                          const int32_t *__restrict__ coarse,
                                                          int32_t *__restrict__ start) {
-  __shared__ uint32_t cnt[kBoxStride];
+  constexpr int64_t STRIDE = (int64_t)kThreads * ITEMS;
+  __shared__ uint32_t cnt[STRIDE];
   __shared__ uint32_t sh[kWaves];
   const int t = threadIdx.x;
-  const int64_t c = blockIdx.x, b0 = c * kBoxStride;
-  cnt[t] = 0;
-  __syncthreads();
+  const int64_t c = blockIdx.x, b0 = c * STRIDE;
   // the keys in [lo, hi) are those of boxes [b0, b0 + stride)
   const int32_t lo = coarse[c], hi = coarse[c + 1];
+  const int64_t nb = nbox + 1 - b0 < STRIDE ? nbox + 1 - b0 : STRIDE;
+  if (lo == hi) {  // no keys: every start is lo (workgroup-uniform)
+    for (int64_t j = t; j < nb; j += kThreads) start[b0 + j] = lo;
+    return;
+  }
+  for (int j = t; j < STRIDE; j += kThreads) cnt[j] = 0;
+  __syncthreads();
   for (int64_t j = (int64_t)lo + t; j < hi; j += kThreads) atomicAdd(&cnt[keys[j] - b0], 1u);
   __syncthreads();
+  // thread t: boxes [t * ITEMS, (t + 1) * ITEMS), prefixed within the
+  // thread, then across the workgroup; the prefixes go back to LDS for
+  // coalesced stores
+  uint32_t v[ITEMS], sum = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    v[i] = sum;
+    sum += cnt[t * ITEMS + i];
+  }
   uint32_t tot;
-  const uint32_t ex = block_excl_scan(cnt[t], sh, &tot);
-  if (b0 + t <= nbox) start[b0 + t] = lo + (int32_t)ex;
+  const uint32_t ex = block_excl_scan(sum, sh, &tot);
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) cnt[t * ITEMS + i] = ex + v[i];
+  __syncthreads();
+  for (int64_t j = t; j < nb; j += kThreads) start[b0 + j] = lo + (int32_t)cnt[j];
 }
 
 inline unsigned blocks_for(int64_t n, int per = kThreads) {
@@ -601,14 +625,19 @@ void launch_gather_rays(const uint32_t *perm, const double *xy, int64_t n, doubl
 
 void launch_box_starts(const uint32_t *sorted_keys, int64_t n, int64_t nbox, int32_t *start,
                        int32_t *coarse, hipStream_t stream) {
-  const int64_t nc = nbox / kBoxStride + 2;
+  const bool wide = nbox >= kWideStartsFrom;
+  const int64_t stride = wide ? (int64_t)kThreads * 16 : kThreads;
+  const int64_t nc = nbox / stride + 2;
   hipLaunchKernelGGL(k_box_starts_coarse, dim3(blocks_for(nc)), dim3(kThreads), 0, stream,
-                     sorted_keys, n, nbox, coarse);
-  hipLaunchKernelGGL(k_box_starts, dim3((unsigned)(nbox / kBoxStride + 1)), dim3(kThreads), 0,
-                     stream, sorted_keys, nbox, coarse, start);
+                     sorted_keys, n, nbox, stride, coarse);
+  const dim3 grid((unsigned)(nbox / stride + 1));
+  if (wide)
+    hipLaunchKernelGGL(k_box_starts<16>, grid, dim3(kThreads), 0, stream, sorted_keys, nbox, coarse, start);
+  else
+    hipLaunchKernelGGL(k_box_starts<1>, grid, dim3(kThreads), 0, stream, sorted_keys, nbox, coarse, start);
   LENS_HIP(hipGetLastError());
 }
 
-int64_t box_starts_coarse_len(int64_t nbox) { return nbox / kBoxStride + 2; }
+int64_t box_starts_coarse_len(int64_t nbox) { return nbox / kThreads + 2; }
 
 }  // namespace lensfmm

@@ -537,7 +537,7 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 
 void launch_p2m(Geometry g, int level, Window win, const double *sxy, const double *sq, int qdim,
                 const int32_t *leaf_start, int p, double *mp, float *mp32, double win_sources,
-                Window child_win, const double *child_mp, hipStream_t stream) {
+                bool clustered, Window child_win, const double *child_mp, hipStream_t stream) {
   const ChildLevel child{child_win, child_mp};
   const int64_t n = win.count() * p;
   if (n == 0) return;
@@ -562,13 +562,13 @@ void launch_p2m(Geometry g, int level, Window win, const double *sxy, const doub
     return;
   }
   // otherwise a thread per box (all coefficients), unless p exceeds the
-  // register budget of that kernel's largest instance.  Where leaf boxes
-  // hold a few sources on average (a clustered field), those of more than
-  // kWaveBox sources get a wave each in a second pass rather than their
+  // register budget of that kernel's largest instance.  In a clustered
+  // field whose leaf boxes hold a few sources on average, those of more
+  // than kWaveBox sources get a wave each in a second pass rather than their
   // lane's wave one after another (above the leaf level such boxes are
   // formed from their children).
   if (p <= 24) {
-    const int defer = (mean > 2.0 && child_mp == nullptr) ? 1 : 0;
+    const int defer = (clustered && mean > 2.0 && child_mp == nullptr) ? 1 : 0;
     const unsigned nb = (unsigned)((win.count() + kWave - 1) / kWave);
     if (qdim == 2)
       LENS_PMAX_DISPATCH(p, hipLaunchKernelGGL((k_p2m_box<PM, 2>), dim3(nb), dim3(kWave), 0, stream,
