@@ -164,8 +164,11 @@ def eval_source_hash():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    # defaults per workload (None): a deflection step takes ~1.2 ms, so 50
+    # timed steps after 20 untimed ones (the GPU's clocks settle over the
+    # first ~10) run in well under a second; an arc map takes ~4 s
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--leaf", type=int, default=0, help="leaf level (0 = the library's choice)")
     ap.add_argument("--tune", action="store_true", help="time leaf levels 9-11 and use the fastest")
     ap.add_argument("--p", type=int, default=12)
@@ -188,9 +191,15 @@ def main():
                     help="with --profile-only: also run one device-to-device copy of this many "
                          "MiB, the reference for scaling FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
+    dsteps, dwarm = {"deflect": (50, 20), "map": (20, 5), "ipm": (10, 3), "batch": (20, 5),
+                     "halo": (20, 5), "arc": (1, 0)}[args.workload]
+    if args.steps is None:
+        args.steps = dsteps
+    if args.warmup is None:
+        args.warmup = dwarm
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the ray grid would shard into bands, one per GPU; see DESIGN.md)", file=sys.stderr)
+              "(the ray grid would shard into bands of rows, one per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
