@@ -253,20 +253,25 @@ __global__ __launch_bounds__(kThreads) void k_scan_tiles(const uint32_t *__restr
 
 // ------------------------------------------------------------- radix sort
 
-// 2048 keys per tile: twice as many workgroups as 4096-key tiles, which
-// measured faster for 1e6 keys (more waves in flight per CU)
-constexpr int kSortItems = 8;
+// Tiles of kThreads * ITEMS keys: 2048 (twice as many workgroups as 4096-key
+// tiles, which measured faster for 1e6 keys: more waves in flight per CU)
+// up to kLongSort keys, 4096 beyond (a digit's run in a tile is then twice
+// as long, so the scatter writes fuller cache lines).
+constexpr int kSortItems = 8, kLongSortItems = 16;
 constexpr int kSortTile = kThreads * kSortItems;
+constexpr int64_t kLongSort = int64_t(1) << 23;
 
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_count(const uint32_t *__restrict__ keys,
                                                           int64_t n, int shift,
                                                           uint32_t *__restrict__ counts,
                                                           int nblocks) {
+  constexpr int TILE = kThreads * ITEMS;
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int it = 0; it < kSortItems; ++it) {
+  const int64_t base = (int64_t)blockIdx.x * TILE;
+  for (int it = 0; it < ITEMS; ++it) {
     const int64_t i = base + (int64_t)it * kThreads + threadIdx.x;
     if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
   }
@@ -281,25 +286,27 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(const uint32_t *__rest
 // bits).  Every item of the tile is ranked first, the per-(round, wave,
 // digit) counts are turned into offsets by one thread per digit, and only
 // then are the items written: three barriers per tile.
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offsets,
     int nblocks) {
+  constexpr int TILE = kThreads * ITEMS;
   __shared__ uint32_t run[256];
-  // counts, then offsets within the tile (<= kSortTile, fits 16 bits)
-  __shared__ uint16_t cnt[kSortItems][kWaves][256];
+  // counts, then offsets within the tile (<= TILE, fits 16 bits)
+  __shared__ uint16_t cnt[ITEMS][kWaves][256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   run[t] = offsets[(size_t)t * nblocks + blockIdx.x];
   {
     uint32_t *c32 = reinterpret_cast<uint32_t *>(&cnt[0][0][0]);
-    for (int e = t; e < kSortItems * kWaves * 256 / 2; e += kThreads) c32[e] = 0u;
+    for (int e = t; e < ITEMS * kWaves * 256 / 2; e += kThreads) c32[e] = 0u;
   }
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * TILE;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+  uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
+  for (int it = 0; it < ITEMS; ++it) {
     const int64_t i = base + (int64_t)it * kThreads + t;
     const bool valid = i < n;
     key[it] = valid ? kin[i] : 0u;
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
   {
     // thread t: exclusive prefix of digit t's counts over (round, wave)
     uint32_t pre = 0;
-    for (int it = 0; it < kSortItems; ++it)
+    for (int it = 0; it < ITEMS; ++it)
 #pragma unroll
       for (int q = 0; q < kWaves; ++q) {
         const uint32_t c = cnt[it][q][t];
@@ -330,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
   }
   __syncthreads();
 #pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
+  for (int it = 0; it < ITEMS; ++it) {
     const int64_t i = base + (int64_t)it * kThreads + t;
     if (i < n) {
       const uint32_t d = (key[it] >> shift) & 255u;
@@ -573,22 +580,32 @@ size_t radix_counts_len(int64_t n) {
   return (size_t)(nb < 1 ? 1 : nb) * 256;
 }
 
-bool radix_sort_pairs(uint32_t *k, uint32_t *v, uint32_t *k_tmp, uint32_t *v_tmp, int64_t n,
-                      int bits, uint32_t *counts, uint32_t *scan_tmp, hipStream_t stream) {
-  if (n <= 1 || bits <= 0) return false;
-  const int nb = (int)((n + kSortTile - 1) / kSortTile);
+template <int ITEMS>
+static bool radix_passes(uint32_t *k, uint32_t *v, uint32_t *k_tmp, uint32_t *v_tmp, int64_t n,
+                         int bits, uint32_t *counts, uint32_t *scan_tmp, hipStream_t stream) {
+  constexpr int64_t TILE = kThreads * ITEMS;
+  const int nb = (int)((n + TILE - 1) / TILE);
   bool in_tmp = false;
   for (int shift = 0; shift < bits; shift += 8) {
     uint32_t *ki = in_tmp ? k_tmp : k, *vi = in_tmp ? v_tmp : v;
     uint32_t *ko = in_tmp ? k : k_tmp, *vo = in_tmp ? v : v_tmp;
-    hipLaunchKernelGGL(k_radix_count, dim3(nb), dim3(kThreads), 0, stream, ki, n, shift, counts, nb);
+    hipLaunchKernelGGL((k_radix_count<ITEMS>), dim3(nb), dim3(kThreads), 0, stream, ki, n, shift,
+                       counts, nb);
     exclusive_scan_u32(counts, counts, (size_t)nb * 256, scan_tmp, stream);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kThreads), 0, stream, ki, vi, ko, vo, n,
-                       shift, counts, nb);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS>), dim3(nb), dim3(kThreads), 0, stream, ki, vi, ko, vo,
+                       n, shift, counts, nb);
     LENS_HIP(hipGetLastError());
     in_tmp = !in_tmp;
   }
   return in_tmp;
+}
+
+bool radix_sort_pairs(uint32_t *k, uint32_t *v, uint32_t *k_tmp, uint32_t *v_tmp, int64_t n,
+                      int bits, uint32_t *counts, uint32_t *scan_tmp, hipStream_t stream) {
+  if (n <= 1 || bits <= 0) return false;
+  if (n > kLongSort)
+    return radix_passes<kLongSortItems>(k, v, k_tmp, v_tmp, n, bits, counts, scan_tmp, stream);
+  return radix_passes<kSortItems>(k, v, k_tmp, v_tmp, n, bits, counts, scan_tmp, stream);
 }
 
 void launch_gather_stars(const uint32_t *perm, const double *xy, const double *q, int qdim,
