@@ -260,6 +260,17 @@ def main():
     t0 = time.perf_counter()
     ms = timed(lambda: run(leaf=leaf), args.steps)
     wall = time.perf_counter() - t0
+    # per-call times of the same steps (an event pair around each call):
+    # their median, outside the timed region above
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record()
+        run(leaf=leaf)
+        e1.record()
+    torch.cuda.synchronize()
+    per_call = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    ms_median = per_call[len(per_call) // 2]
     # the same steps once more with the stage profiler on (HIP events around
     # every stage on its stream; the profiler runs the calls eagerly), for the
     # evaluation kernel's duration
@@ -309,6 +320,7 @@ def main():
             traffic = None
 
     extra = {"leaf_level": leaf, "p": args.p, "near_pairs_per_ray": pairs / n_rays,
+             "median_ms_per_call": ms_median, "median_rays_per_s": n_rays / (ms_median * 1e-3),
              "leaf_box_side": math.ldexp(info["root_side"], -leaf),
              "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
              "eval_flops_per_launch": flops, "profiled_eager_ms_per_step": ms_prof}
