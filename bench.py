@@ -8,7 +8,9 @@ plan, so each step runs the whole path: star quadtree build, P2M, M2M, the
 downward pass and the fused evaluation, writing y [8192^2, 2] FP64.  Stars
 are resident in HBM before the timed region; grid rays need no input bytes.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
+
+(K, W default per workload: 50 and 20 for the deflection benchmark.)
 
 --workload map runs the high-magnification map instead: 5e6 equal-mass
 stars (kappa_* = 0.1, kappa_s = 0.75, gamma = 0.05, mu = 50), a 16384^2 ray
