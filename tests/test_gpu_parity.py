@@ -458,9 +458,10 @@ def test_small_ray_region_in_wide_field(lf, prec, p, fl, tol):
 def test_crowded_boxes_formed_by_m2m(lf, prec, p, fl, tol):
     """A cusp inside a sparse field: 2e5 stars in a Gaussian cluster
     (sigma 0.3) plus 5e4 spread over a disk of radius 300, rays over the
-    cluster.  The leaf level follows the cluster's density, so the coarser
-    windowed levels hold boxes of thousands of stars, which are formed by
-    M2M from their children, and the rest from their stars.  Against the
+    cluster.  The leaf level follows the mean density over the rays' box, so
+    the core's leaf boxes hold hundreds of stars (formed a wave each) and the
+    coarser windowed levels thousands (formed by M2M from their children in
+    the boxes' own lanes), the rest from their stars.  Against the
     FP64 direct sum (itself pinned to the oracle on a few rays).  As for any
     small ray region in a wide field, the coarse levels carry large partial
     fields, so FP32 M2L levels would leave ~3e-5 on the worst rays: the
@@ -476,7 +477,17 @@ def test_crowded_boxes_formed_by_m2m(lf, prec, p, fl, tol):
     yd = host(lf.deflect(xy, m, grid=lfgrid(g), method="direct", **kw))
     ad = g.rays() * [0.9, 1.1] - yd
     plan = lf.Plan(xy, m, grid=lfgrid(g), precision=prec, p=p, fp32_levels=fl, **kw)
-    print(f"[plan] crowded boxes: {plan.info()}", flush=True)
+    info = plan.info()
+    print(f"[plan] crowded boxes: {info}", flush=True)
+    # the cluster's core fills leaf boxes with more than 256 stars, which the
+    # upward pass forms a wave each in its second pass
+    L = info["leaf_level"]
+    s = math.ldexp(info["root_side"], -L)
+    keys = (np.floor((xy_h[:, 1] - info["root_y0"]) / s).astype(np.int64) << L) + \
+        np.floor((xy_h[:, 0] - info["root_x0"]) / s).astype(np.int64)
+    fullest = int(np.unique(keys, return_counts=True)[1].max())
+    print(f"[plan] fullest leaf box: {fullest} stars", flush=True)
+    assert fullest > 256
     y = host(lf.deflect(grid=lfgrid(g), plan=plan, **kw))
     plan.close()
     check(y, yd, ad, tol, f"crowded boxes {prec} p={p}")
