@@ -1656,6 +1656,36 @@ std::mutex g_call_mu;
 std::vector<std::unique_ptr<CallExec>> g_calls;        // most recently used last
 std::vector<std::vector<uint64_t>> g_call_seen;         // keys seen once
 
+// A non-blocking stream beside a caller's stream (default priority) and an
+// event to start it behind the caller's work: the speculative replay's
+// bounding-box reduction runs there.  One per (device, stream) of the
+// calling host thread, kept for the thread's life (a few at most).
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t start = nullptr;
+};
+
+const SideStream &side_stream_for(hipStream_t st) {
+  thread_local std::vector<std::pair<std::pair<int, hipStream_t>, SideStream>> sides;
+  int dev = 0;
+  LENS_HIP(hipGetDevice(&dev));
+  for (auto &e : sides)
+    if (e.first.first == dev && e.first.second == st) return e.second;
+  if (sides.size() >= 8) {
+    // stale entries (streams the caller may have destroyed): drop the oldest
+    SideStream &old = sides.front().second;
+    (void)hipStreamSynchronize(old.stream);
+    (void)hipEventDestroy(old.start);
+    (void)hipStreamDestroy(old.stream);
+    sides.erase(sides.begin());
+  }
+  SideStream s;
+  LENS_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+  LENS_HIP(hipEventCreateWithFlags(&s.start, hipEventDisableTiming));
+  sides.emplace_back(std::make_pair(dev, st), s);
+  return sides.back().second;
+}
+
 // The parts of a call's key that do not depend on the stars' positions.
 std::vector<uint64_t> call_key_static(const lens_field &f, const lens_grid &g, const lens_opts &o,
                                       const double *y_out, const lens_map_desc *map, int device,
@@ -1709,16 +1739,17 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
   grid_bbox(grid, 0, grid.ny, bb);
   double sb[4];
   int64_t cnt = 0;
-  const BBoxRead rd = bbox_enqueue(f.xy, f.n_stars, st, bb);
   // Speculation (outputs that the call overwrites, not maps that it adds
-  // to): replay the latest graph of this call's arrays and parameters right
-  // behind the bounding-box reduction, and check its tree against the
-  // read-back while it runs; if the stars have moved out of it, the call
-  // below runs again and overwrites the outputs.
+  // to): replay the latest graph of this call's arrays and parameters at
+  // once, and check its tree against the stars' bounding box, reduced on a
+  // side stream (it only reads the stars) while the graph runs; if the stars
+  // have moved out of the tree, the call below runs again and overwrites the
+  // outputs.  Without a graph to replay the reduction runs on the stream.
   int dev = 0;
   LENS_HIP(hipGetDevice(&dev));
   std::vector<uint64_t> skey;
   uint64_t spec = 0;  // id of the graph replayed speculatively
+  BBoxRead rd;
   std::unique_lock<std::mutex> lk(g_call_mu);
   if (!map && !profiling_enabled()) {
     skey = call_key_static(f, grid, o, y_out, map, dev, st);
@@ -1726,12 +1757,17 @@ void fmm_grid_call(const lens_field &f, const lens_grid &grid, const lens_opts &
     for (size_t i = g_calls.size(); i-- > 0;)
       if (g_calls[i]->skey == skey) {
         spec = g_calls[i]->id;
+        const SideStream &side = side_stream_for(st);
+        LENS_HIP(hipEventRecord(side.start, st));
+        LENS_HIP(hipStreamWaitEvent(side.stream, side.start, 0));
+        rd = bbox_enqueue(f.xy, f.n_stars, side.stream, bb);
         LENS_HIP(hipGraphLaunch(g_calls[i]->exec, st));
         g_calls[i]->last = st;
         break;
       }
   }
   lk.unlock();
+  if (!spec) rd = bbox_enqueue(f.xy, f.n_stars, st, bb);
   bbox_finish(rd, sb, &cnt);
   const double rho_local = local_density(cnt, bb);
   const double area = std::max((bb[2] - bb[0]) * (bb[3] - bb[1]), 1e-300);
