@@ -249,7 +249,9 @@ __device__ __forceinline__ void m2m_lane(const ChildLevel &c, int64_t ix, int64_
 // forms it by M2M from its children when the level below has them all (in
 // its own lane, so a wave of crowded boxes shifts them side by side), and a
 // box of more than kWaveBox sources without them is left to the whole wave,
-// which forms such boxes one after another.  The kernel is bound by memory
+// which forms such boxes one after another -- or, with `defer`, to a second
+// pass of k_p2m_wave (a wave per box), this pass storing zeros for them.
+// The kernel is bound by memory
 // latency (a few sources per lane): a box of one or two leaf rows keeps its
 // source ranges in registers and the next source's loads are issued before
 // the current one's powers are summed.  The wave's 64 boxes are staged in
