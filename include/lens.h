@@ -134,7 +134,9 @@ typedef struct {
                            rows that fit it, no device allocation is made,
                            and one row that does not fit gives LENS_ENOMEM.
                            Calls on one stream may share it; calls that
-                           overlap in time must not.  Other calls ignore it. */
+                           overlap in time must not.  Other calls, and the
+                           direct method or a field without stars (which
+                           need no per-call memory), ignore it. */
   size_t workspace_bytes;
 } lens_opts;
 
