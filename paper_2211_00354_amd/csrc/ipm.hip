@@ -241,9 +241,11 @@ __device__ __forceinline__ bool load_quad(const IpmArgs &a, int64_t i, int64_t j
   return finite;
 }
 
-// Pixel bounding box of q clamped to the map; false if it misses the map.
-__device__ __forceinline__ bool quad_bbox(const double (&q)[4][2], int32_t npix, int64_t &u0,
-                                          int64_t &v0, int64_t &u1, int64_t &v1, bool &inside) {
+// Pixel bounding box of q clamped to the map; false if it misses the map
+// (the box is then of no use).  The corners are clamped to the map before
+// the conversion, so it is a 32-bit one.
+__device__ __forceinline__ bool quad_bbox(const double (&q)[4][2], int32_t npix, int32_t &u0,
+                                          int32_t &v0, int32_t &u1, int32_t &v1, bool &inside) {
   double lo0 = q[0][0], hi0 = q[0][0], lo1 = q[0][1], hi1 = q[0][1];
 #pragma unroll
   for (int k = 1; k < 4; ++k) {
@@ -252,12 +254,13 @@ __device__ __forceinline__ bool quad_bbox(const double (&q)[4][2], int32_t npix,
     lo1 = fmin(lo1, q[k][1]);
     hi1 = fmax(hi1, q[k][1]);
   }
-  u0 = lo0 < 0.0 ? 0 : (int64_t)floor(lo0);
-  v0 = lo1 < 0.0 ? 0 : (int64_t)floor(lo1);
-  u1 = hi0 >= (double)npix ? npix - 1 : (int64_t)floor(hi0);
-  v1 = hi1 >= (double)npix ? npix - 1 : (int64_t)floor(hi1);
-  inside = lo0 >= 0.0 && lo1 >= 0.0 && hi0 < (double)npix && hi1 < (double)npix;
-  return !(hi0 < 0.0 || hi1 < 0.0 || lo0 >= (double)npix || lo1 >= (double)npix);
+  const double top = (double)npix, last = top - 1.0;
+  u0 = (int32_t)floor(fmin(fmax(lo0, 0.0), last));
+  v0 = (int32_t)floor(fmin(fmax(lo1, 0.0), last));
+  u1 = (int32_t)floor(fmin(fmax(hi0, 0.0), last));
+  v1 = (int32_t)floor(fmin(fmax(hi1, 0.0), last));
+  inside = lo0 >= 0.0 && lo1 >= 0.0 && hi0 < top && hi1 < top;
+  return !(hi0 < 0.0 || hi1 < 0.0 || lo0 >= top || lo1 >= top);
 }
 
 __device__ __forceinline__ unsigned long long to_fix(double x) {
@@ -317,7 +320,9 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t *wsum, int
 // time, one thread per cell.  The (cell, pixel) pairs of the batch's
 // multi-pixel cells are numbered by a scan and shared out evenly over the
 // workgroup's threads, so a few cells near a star do not hold a whole wave.
-__global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
+// Four waves per SIMD (at most 128 VGPRs), as many as its LDS allows.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ipm(
+    IpmArgs a) {
   __shared__ int32_t tkey[kTable];
   __shared__ unsigned long long tval[kTable];
   __shared__ double sq[kThreads][10];       // multi-pixel cells of the batch: corners, X,
@@ -345,10 +350,10 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
     Cell c;
     if (i < ncx && j < a.j1 && load_quad(a, i, j, c.q)) {
       classify(c);
-      int64_t u0, v0, u1, v1;
+      int32_t u0, v0, u1, v1;
       bool inside;
       const bool hits = quad_bbox(c.q, npix, u0, v0, u1, v1, inside);
-      const int64_t npx = (u1 - u0 + 1) * (v1 - v0 + 1);
+      const int64_t npx = (int64_t)(u1 - u0 + 1) * (v1 - v0 + 1);
       if (!(c.area > 0.0)) {
         // no shape: a quarter of the cell to each corner's pixel
 #pragma unroll
@@ -358,7 +363,7 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
         }
       } else if (hits) {
         if (u0 == u1 && v0 == v1 && inside) {
-          table_add(tkey, tval, a.acc, (int32_t)(v0 * npix + u0), q_cell);  // wholly inside
+          table_add(tkey, tval, a.acc, v0 * npix + u0, q_cell);  // wholly inside
         } else if (npx == 2 && inside && c.kind == 0) {
           // across one pixel edge: the first pixel's overlap by Green's
           // theorem, the second takes the rest of the cell (in fixed point,
@@ -370,8 +375,8 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
           const double f = fmin(fmax(ov / c.area, 0.0), 1.0);
           const unsigned long long q0 = to_fix(a.cell_px * f);
           const unsigned long long q1 = q_cell >= q0 ? q_cell - q0 : 0ull;
-          if (q0) table_add(tkey, tval, a.acc, (int32_t)(v0 * npix + u0), q0);
-          if (q1) table_add(tkey, tval, a.acc, (int32_t)(v1 * npix + u1), q1);
+          if (q0) table_add(tkey, tval, a.acc, v0 * npix + u0, q0);
+          if (q1) table_add(tkey, tval, a.acc, v1 * npix + u1, q1);
         } else if (npx > kPairMax) {
           const uint32_t slot = atomicAdd(a.qcount, 1u);
           a.queue[slot] = (uint32_t)((j - a.j0) * ncx + i);
@@ -386,9 +391,9 @@ __global__ __launch_bounds__(kThreads) void k_ipm(IpmArgs a) {
           sq[t][9] = c.X[1];
           sinv[t] = 1.0 / c.area;
           sshape[t] = c.kind | ((c.kind == 0 ? convex_orientation(c.q) + 1 : 1) << 2);
-          sbox[t][0] = (int32_t)u0;
-          sbox[t][1] = (int32_t)v0;
-          sbox[t][2] = (int32_t)(u1 - u0 + 1);
+          sbox[t][0] = u0;
+          sbox[t][1] = v0;
+          sbox[t][2] = u1 - u0 + 1;
         }
       }
     }
