@@ -46,13 +46,9 @@ __device__ __forceinline__ double orient2(double ax, double ay, double bx, doubl
   return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
 }
 
-__device__ __forceinline__ bool segments_cross(const double (&a)[2], const double (&b)[2],
-                                               const double (&c)[2], const double (&d)[2]) {
-  const double o1 = orient2(a[0], a[1], b[0], b[1], c[0], c[1]);
-  const double o2 = orient2(a[0], a[1], b[0], b[1], d[0], d[1]);
-  const double o3 = orient2(c[0], c[1], d[0], d[1], a[0], a[1]);
-  const double o4 = orient2(c[0], c[1], d[0], d[1], b[0], b[1]);
-  return ((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) && ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0));
+// Strictly opposite signs (a zero is neither).
+__device__ __forceinline__ bool opposite(double u, double v) {
+  return (u > 0 && v < 0) || (u < 0 && v > 0);
 }
 
 __device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
@@ -121,8 +117,22 @@ __device__ __forceinline__ double tri_area(const double (&a)[2], const double (&
 }
 
 __device__ __forceinline__ void classify(Cell &c) {
-  const bool c01 = segments_cross(c.q[0], c.q[1], c.q[2], c.q[3]);
-  const bool c12 = !c01 && segments_cross(c.q[1], c.q[2], c.q[3], c.q[0]);
+  // Twice the signed areas of four corner triangles, on differences of
+  // corners (a small image far from the map origin keeps its digits):
+  // A = o(q0,q1,q2), B = o(q0,q1,q3), C = o(q2,q3,q0), D = o(q2,q3,q1),
+  // o(a,b,c) = (b - a) x (c - a), unchanged by a cyclic shift of a, b, c.
+  // Segments 0-1 and 2-3 cross iff A, B and C, D have opposite signs;
+  // segments 1-2 and 3-0 iff D, A and B, C do; and A + C is twice the
+  // signed area of q (its triangles q0 q1 q2 and q0 q2 q3).
+  const double(&q)[4][2] = c.q;
+  const double e01x = q[1][0] - q[0][0], e01y = q[1][1] - q[0][1];
+  const double e23x = q[3][0] - q[2][0], e23y = q[3][1] - q[2][1];
+  const double A = e01x * (q[2][1] - q[0][1]) - e01y * (q[2][0] - q[0][0]);
+  const double B = e01x * (q[3][1] - q[0][1]) - e01y * (q[3][0] - q[0][0]);
+  const double C = e23x * (q[0][1] - q[2][1]) - e23y * (q[0][0] - q[2][0]);
+  const double D = e23x * (q[1][1] - q[2][1]) - e23y * (q[1][0] - q[2][0]);
+  const bool c01 = opposite(A, B) && opposite(C, D);
+  const bool c12 = !c01 && opposite(D, A) && opposite(B, C);
   if (c01 || c12) {
     const int ia = c01 ? 0 : 1;
     const double(&a)[2] = c.q[ia];
@@ -136,19 +146,9 @@ __device__ __forceinline__ void classify(Cell &c) {
     c.kind = c01 ? 1 : 2;
     c.area = tri_area(c.X, b, cc) + tri_area(a, c.X, d);
   } else {
-    // shoelace on coordinates relative to the first corner (a small image
-    // far from the map origin keeps its digits)
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int k1 = (k + 1) & 3;
-      const double x0 = c.q[k][0] - c.q[0][0], y0 = c.q[k][1] - c.q[0][1];
-      const double x1 = c.q[k1][0] - c.q[0][0], y1 = c.q[k1][1] - c.q[0][1];
-      s += x0 * y1 - x1 * y0;
-    }
     c.X[0] = c.X[1] = 0.0;
     c.kind = 0;
-    c.area = fabs(0.5 * s);
+    c.area = fabs(0.5 * (A + C));
   }
 }
 
