@@ -178,6 +178,33 @@ __device__ double cell_pixel_overlap(const double (&q)[4][2], const double (&X)[
   return fabs(t1) + fabs(t2);
 }
 
+// Area of the part of the simple quadrilateral q with x < xs (across_x) or
+// y < ys, for a cell whose image spans two pixels that share that line.  By
+// Green's theorem the area of q n {w < 0}, w = x - xs, is |the line integral
+// of min(w, 0) dy| around q (with w = y - ys and x in the place of y for the
+// other split).  min(w, 0) is linear along an edge except where the edge
+// crosses w = 0, at t = wa / (wa - wb) of its length, so the trapezoid rule
+// on the one or two pieces is exact.
+__device__ __forceinline__ double split_area(const double (&q)[4][2], bool across_x, double xs,
+                                             double ys) {
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double(&a)[2] = q[e];
+    const double(&b)[2] = q[(e + 1) & 3];
+    const double wa = across_x ? a[0] - xs : a[1] - ys, wb = across_x ? b[0] - xs : b[1] - ys;
+    const double dz = across_x ? b[1] - a[1] : b[0] - a[0];
+    const double ma = fmin(wa, 0.0), mb = fmin(wb, 0.0);
+    double m = ma + mb;
+    if ((wa < 0.0) != (wb < 0.0)) {
+      const double t = wa * rcp_f64(wa - wb);
+      m = ma * t + mb * (1.0 - t);
+    }
+    s += m * dz;
+  }
+  return fabs(0.5 * s);
+}
+
 // Orientation of a convex q (+1 counter-clockwise, -1 clockwise), or 0 if q
 // is not convex.
 __device__ __forceinline__ int convex_orientation(const double (&q)[4][2]) {
@@ -368,10 +395,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           // across one pixel edge: the first pixel's overlap by Green's
           // theorem, the second takes the rest of the cell (in fixed point,
           // so the cell's total is exact)
-          double k[4], kinv[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) edge_slope(c.q[e], c.q[(e + 1) & 3], k[e], kinv[e]);
-          const double ov = cell_pixel_overlap(c.q, c.X, 0, k, kinv, (double)u0, (double)v0);
+          const double ov = split_area(c.q, u1 != u0, (double)(u0 + 1), (double)(v0 + 1));
           const double f = fmin(fmax(ov / c.area, 0.0), 1.0);
           const unsigned long long q0 = to_fix(a.cell_px * f);
           const unsigned long long q1 = q_cell >= q0 ? q_cell - q0 : 0ull;
