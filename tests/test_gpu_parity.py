@@ -1282,6 +1282,31 @@ def test_ipm_kernel_matches_oracle_on_the_same_rays(lf, npix, side):
     np.testing.assert_array_equal(mu, mu2)
 
 
+@pytest.mark.parametrize("a1,a2,cell_px", [(0.7, 0.45, 0.4), (0.7, -0.45, 2.5), (-0.6, 0.5, 9.0)])
+def test_ipm_linear_lens_gives_inverse_determinant(lf, a1, a2, cell_px):
+    """No stars: y = diag(a1, a2) x maps every cell to a rectangle of area
+    |a1 a2| dx dy, and cells tile the map, so exact apportioning puts
+    1/|a1 a2| in every pixel the grid's image covers (Section 2.3; the
+    magnification of a linear lens).  cell_px, the cells' image width in
+    pixels, picks the kernel path: cells inside one pixel and across one
+    pixel edge (0.4), (cell, pixel) pairs (2.5) and the wide-cell rasteriser
+    (9); a negative a reverses the images' orientation."""
+    import torch
+    n = 512
+    g = lf.Grid(-1.0, -1.0, 2.0 / n, 2.0 / n, n, n)
+    side = 0.8 * min(abs(a1), abs(a2))
+    npix = int(round(side / (abs(a1) * g.dx / cell_px)))
+    md = lf_mapdesc(-side / 2, -side / 2, side, npix)
+    kappa, gamma = 1.0 - 0.5 * (a1 + a2), 0.5 * (a2 - a1)
+    empty = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    _say("ipm linear lens", a1, a2, npix)
+    mu = host(lf.ipm_map(empty, empty[:, 0], grid=g, map=md, kappa_s=kappa, gamma=gamma))
+    want = 1.0 / abs(a1 * a2)
+    err = np.abs(mu / want - 1.0).max()
+    print(f"[ipm] linear lens a = ({a1}, {a2}), {npix}^2 pixels: max relative deviation {err:.2e}")
+    assert err <= 1e-9
+
+
 @pytest.mark.parametrize("prec,p", [("fp64", 20), ("mixed", 12)])
 def test_ipm_fmm_against_oracle(lf, prec, p):
     """End to end: FMM deflection + GPU IPM against the oracle's deflection
