@@ -123,7 +123,7 @@ def stage_rooflines(info, f, g, p, stage_ms, fp32_levels=2):
 
 def host_threads():
     """Threads for the CPU oracle: the cores this process may run on, capped
-    by OMP_NUM_THREADS when set (a GPU machine grants each GPU a share of its
+    by OMP_NUM_THREADS when set (a shared machine may grant each GPU a share of its
     host cores through it)."""
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)

@@ -62,7 +62,7 @@ typedef enum {
   LENS_EINVAL = 1,       /* bad argument; nothing enqueued */
   LENS_ENOMEM = 2,       /* device allocation failed; nothing enqueued */
   LENS_EDEVICE = 3,      /* HIP runtime error */
-  LENS_EUNSUPPORTED = 4  /* valid request this build does not implement */
+  LENS_EUNSUPPORTED = 4  /* valid request this library does not implement */
 } lens_status;
 
 enum { LENS_FMM = 0, LENS_DIRECT = 1 };   /* lens_opts.method    */
