@@ -1307,6 +1307,34 @@ def test_ipm_linear_lens_gives_inverse_determinant(lf, a1, a2, cell_px):
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("a1,a2", [(0.5, -0.25), (-0.5, 2.0)])
+def test_ipm_linear_lens_with_corners_on_pixel_lines(lf, a1, a2):
+    """Cell corners exactly on pixel lines (dyadic grid, map and lens): a
+    corner on a pixel's left or lower edge belongs to that pixel, so boxes
+    reach one pixel past cells that end on a line, and those pixels must
+    receive nothing from them.  Every covered pixel still holds 1/|a1 a2|
+    (Section 2.3), for cells of 1 x 0.5 and 1 x 4 pixels."""
+    import torch
+    n = 512
+    g = lf.Grid(-1.0, -1.0, 2.0 / n, 2.0 / n, n, n)
+    px = abs(a1) * g.dx  # one cell's image is one pixel wide
+    npix = 128
+    side = npix * px
+    # corners at y1 = a1 (-1 + (i + 1/2) dx): the map starts on one of them
+    y1min = -side / 2 + 0.5 * px
+    y2min = -side / 2
+    md = lf_mapdesc(y1min, y2min, side, npix)
+    kappa, gamma = 1.0 - 0.5 * (a1 + a2), 0.5 * (a2 - a1)
+    empty = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    _say("ipm linear lens on pixel lines", a1, a2, npix)
+    mu = host(lf.ipm_map(empty, empty[:, 0], grid=g, map=md, kappa_s=kappa, gamma=gamma))
+    want = 1.0 / abs(a1 * a2)
+    err = np.abs(mu / want - 1.0).max()
+    print(f"[ipm] linear lens a = ({a1}, {a2}), corners on pixel lines: max relative deviation "
+          f"{err:.2e}")
+    assert err <= 1e-9
+
+
 @pytest.mark.parametrize("prec,p", [("fp64", 20), ("mixed", 12)])
 def test_ipm_fmm_against_oracle(lf, prec, p):
     """End to end: FMM deflection + GPU IPM against the oracle's deflection
