@@ -882,6 +882,41 @@ def test_batched_maps_equal_single_maps_and_replay(lf):
     lf.release_cached()
 
 
+def test_batched_maps_with_empty_and_single_star_fields(lf):
+    """A batch holding a field without stars (only the smooth term; the
+    direct kernel's path) and a one-star field beside ordinary ones, with
+    more fields than graph branches: every map equals its single-field map,
+    and the star-free field's map is the binning of the smooth term alone."""
+    import torch
+    cases = _batch_fields(19, 128, 32, 41, (200, 3000))
+    f0, g0, m0 = cases[0]
+    cases[0] = (wl.Field(xy=np.zeros((0, 2)), m=np.zeros(0), kappa_s=0.3, gamma=0.2,
+                         radius=f0.radius), g0, m0)
+    f1, g1, m1 = cases[1]
+    cases[1] = (wl.Field(xy=f1.xy[:1].copy(), m=f1.m[:1].copy(), kappa_s=f1.kappa_s,
+                         gamma=f1.gamma, radius=f1.radius), g1, m1)
+    fields, grids, maps = [], [], []
+    for f, g, mp in cases:
+        fields.append((dev_tensor(f.xy).reshape(-1, 2), dev_tensor(f.m), f.kappa_s, f.gamma))
+        grids.append(lfgrid(g))
+        maps.append(lf.MapDesc(mp.y1min, mp.y2min, mp.side, mp.npix))
+    _say("batched 19 fields, empty and one-star fields")
+    kw = dict(p=16)
+    got = [host(c) for c in lf.irs_map_batched(fields, grids, maps, **kw)]
+    for k, ((xy, m, ks, gm), g, mp) in enumerate(zip(fields, grids, maps)):
+        single = host(lf.irs_map(xy, m, grid=g, map=mp, kappa_s=ks, gamma=gm, **kw))
+        np.testing.assert_array_equal(got[k], single, err_msg=f"field {k}")
+    # the star-free field is the smooth term alone: the GPU's y is the
+    # oracle's, and the map is the binning of it
+    y = host(lf.deflect(fields[0][0], fields[0][1], grid=grids[0], kappa_s=0.3, gamma=0.2, **kw))
+    yo, _, _ = oracle.deflect(np.zeros((0, 2)), np.zeros(0), g0.rays(np.arange(g0.n)), 0.3, 0.2)
+    assert np.abs(y - yo).max() <= 1e-14 * np.abs(yo).max()
+    ref, _ = oracle.bin_rays(y, m0.y1min, m0.y2min, m0.side, m0.npix)
+    np.testing.assert_array_equal(got[0], ref)
+    assert got[0].sum() > 0 and got[1].sum() > 0
+    lf.release_cached()
+
+
 def test_batched_field_batch_full_size(lf):
     """64 fields with N_* log-uniform in [1e4, 2e5], 2048^2 rays each, 512^2
     maps, one captured graph; checked field by field against single maps."""
