@@ -1370,6 +1370,28 @@ def test_ipm_linear_lens_with_corners_on_pixel_lines(lf, a1, a2):
     assert err <= 1e-9
 
 
+def test_ipm_degenerate_lens_sends_cells_to_their_corners(lf):
+    """kappa_s + gamma = 1 with no stars: y1 = 0 for every ray, so every
+    cell's image is a segment of no area and the cell goes to its corners, a
+    quarter to each corner's pixel (the zeroth-order rule the map keeps for
+    images without area).  Equal to the oracle's map of the same corners."""
+    import torch
+    n = 256
+    g = lf.Grid(-1.0, -1.0, 2.0 / n, 2.0 / n, n, n)
+    kappa, gamma = 0.6, 0.4  # y1 = 0, y2 = 0.8 x2
+    md = lf_mapdesc(-0.5, -0.5, 1.0, 37)
+    empty = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    _say("ipm degenerate lens")
+    mu = host(lf.ipm_map(empty, empty[:, 0], grid=g, map=md, kappa_s=kappa, gamma=gamma))
+    y = host(lf.deflect(empty, empty[:, 0], grid=g, kappa_s=kappa, gamma=gamma))
+    assert np.all(y[:, 0] == 0.0)
+    ref = oracle.ipm(y.reshape(n, n, 2), g.dx * g.dy, md.y1min, md.y2min, md.side, md.npix)
+    assert np.abs(mu - ref).max() <= 1e-9 * ref.max()
+    # the whole grid's area lands in the pixel column holding y1 = 0
+    col = int(np.floor((0.0 - md.y1min) * md.npix / md.side))
+    assert mu[:, col].sum() > 0 and np.count_nonzero(np.delete(mu, col, axis=1)) == 0
+
+
 @pytest.mark.parametrize("prec,p", [("fp64", 20), ("mixed", 12)])
 def test_ipm_fmm_against_oracle(lf, prec, p):
     """End to end: FMM deflection + GPU IPM against the oracle's deflection
